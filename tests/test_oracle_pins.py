@@ -1,0 +1,353 @@
+"""Pins of the CPU oracle against what mathematics fixes (no GPU needed).
+
+Each test checks the oracle against something other than itself: textbook
+filter values, closed forms, brute force on tiny inputs, a different library
+routine on the raw data, statistical identities, invariances and limits.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, linalg, optimize, stats
+
+from oracle import hyres_oracle as O
+from paper_2204_06979_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ----------------------------------------------------------------- P1 wavelets
+def test_db2_filter_matches_published_table():
+    vals = [float(l) for l in open(os.path.join(GOLDEN, "db2_filter.txt"))
+            if l.strip() and not l.startswith("#")]
+    np.testing.assert_allclose(O.DB2, vals, rtol=0, atol=1e-15)
+
+
+def test_filter_identities():
+    h, g = O.DB2, O.highpass(O.DB2)
+    assert abs(h.sum() - math.sqrt(2)) < 1e-15
+    assert abs((h * h).sum() - 1) < 1e-15
+    assert abs(h[0] * h[2] + h[1] * h[3]) < 1e-15          # shift-2 orthogonality
+    assert abs(g.sum()) < 1e-15                              # first vanishing moment
+    assert abs((np.arange(4) * g).sum()) < 1e-14             # second vanishing moment
+    assert abs((h * g).sum()) < 1e-15
+
+
+def test_haar_against_hand_arithmetic():
+    x = np.array([1.0, 2.0, 3.0, 4.0, 6.0])                 # odd: last sample repeated
+    a, d = O.dwt1_axis(x, 0, O.HAAR)
+    s = 1 / math.sqrt(2)
+    np.testing.assert_allclose(a, [3 * s, 7 * s, 12 * s], atol=1e-15)
+    # g = (h1, -h0): d[k] = (x[2k] - x[2k+1]) / sqrt 2
+    np.testing.assert_allclose(d, [-s, -s, 0.0], atol=1e-15)
+    np.testing.assert_allclose(O.idwt1_axis(a, d, 5, 0, O.HAAR), x, atol=1e-14)
+
+
+@pytest.mark.parametrize("N", [4, 6, 8, 10, 16])
+def test_one_level_matrix_is_orthogonal(N):
+    M = np.empty((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1
+        a, d = O.dwt1_axis(e, 0)
+        M[:, j] = np.concatenate([a, d])
+    np.testing.assert_allclose(M @ M.T, np.eye(N), atol=1e-14)
+    # synthesis is the transpose
+    for j in range(N):
+        c = np.zeros(N)
+        c[j] = 1
+        x = O.idwt1_axis(c[: N // 2], c[N // 2:], N, 0)
+        np.testing.assert_allclose(x, M[j], atol=1e-15)
+
+
+@pytest.mark.parametrize("H,W,L", [(64, 64, 3), (37, 53, 3), (5, 7, 1), (9, 4, 2),
+                                   (349, 191, 4), (128, 96, 4), (33, 17, 2)])
+def test_perfect_reconstruction_any_size(H, W, L):
+    x = _rng(H * W).standard_normal((H, W))
+    c = O.dwt2(x, L)
+    assert c.size == O.coeff_count(H, W, L)
+    np.testing.assert_allclose(O.idwt2(c, H, W, L), x, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("H,W,L", [(64, 64, 3), (32, 48, 4), (16, 8, 2)])
+def test_parseval_when_all_lengths_even(H, W, L):
+    x = _rng(1).standard_normal((H, W))
+    c = O.dwt2(x, L)
+    assert abs((c * c).sum() - (x * x).sum()) < 1e-12 * (x * x).sum()
+
+
+def test_coefficient_count_for_the_large_cube_shape():
+    # 349 x 1905, 4 levels: 175x953, 88x477, 44x239, 22x120
+    assert O.level_shapes(349, 1905, 4) == [(175, 953), (88, 477), (44, 239), (22, 120)]
+    assert O.coeff_count(349, 1905, 4) == 668361
+
+
+def test_linear_ramp_has_zero_details_away_from_the_wrap():
+    N = 32
+    x = 3.0 + 0.5 * np.arange(N)
+    a, d = O.dwt1_axis(x, 0)
+    # windows (2k .. 2k+3) that do not cross the periodic wrap
+    inner = [k for k in range(N // 2) if 2 * k + 3 < N]
+    assert np.abs(d[inner]).max() < 1e-13
+    assert np.abs(d[N // 2 - 1]) > 1.0                       # the wrap window sees the jump
+
+
+def test_transpose_swaps_detail_orientations():
+    x = _rng(2).standard_normal((32, 48))
+    L = 2
+    c = O.dwt2(x, L)
+    ct = O.dwt2(x.T, L)
+    off = 0
+    for (h, w) in O.level_shapes(32, 48, L):
+        blk = h * w
+        lh = c[off:off + blk].reshape(h, w)
+        hl = c[off + blk:off + 2 * blk].reshape(h, w)
+        hh = c[off + 2 * blk:off + 3 * blk].reshape(h, w)
+        lh_t = ct[off:off + blk].reshape(w, h)
+        hl_t = ct[off + blk:off + 2 * blk].reshape(w, h)
+        hh_t = ct[off + 2 * blk:off + 3 * blk].reshape(w, h)
+        np.testing.assert_allclose(lh_t, hl.T, atol=1e-13)
+        np.testing.assert_allclose(hl_t, lh.T, atol=1e-13)
+        np.testing.assert_allclose(hh_t, hh.T, atol=1e-13)
+        off += 3 * blk
+
+
+# ------------------------------------------------------------ P2 soft threshold
+@pytest.mark.parametrize("b,lam", [(2.5, 1.0), (-0.3, 1.0), (-4.0, 0.5), (1.0, 1.0), (0.0, 0.2)])
+def test_soft_threshold_is_the_l1_prox(b, lam):
+    res = optimize.minimize_scalar(lambda w: 0.5 * (w - b) ** 2 + lam * abs(w),
+                                   bounds=(-10, 10), method="bounded",
+                                   options=dict(xatol=1e-12))
+    assert abs(O.soft_threshold(np.array([b]), lam)[0] - res.x) < 1e-6
+
+
+def test_soft_threshold_closed_form_values():
+    b = np.array([-3.0, -1.0, -0.5, 0.0, 0.5, 1.0, 3.0])
+    np.testing.assert_array_equal(O.soft_threshold(b, 1.0), [-2.0, 0.0, 0.0, 0.0, 0.0, 0.0, 2.0])
+
+
+# ------------------------------------------------------------------- P3 SURE
+def test_sure_candidate_set_is_exact_against_dense_grid():
+    rng = _rng(3)
+    for trial in range(20):
+        N = int(rng.integers(1, 40))
+        b = rng.standard_normal(N) * rng.uniform(0.2, 4.0)
+        if trial % 5 == 0:
+            b[: N // 2] = np.round(b[: N // 2], 1)           # ties
+        lam, smin = O.sure_threshold(b)
+        # definition evaluated at every candidate (O(N^2))
+        cands = np.concatenate([[0.0], np.abs(b)])
+        vals = np.array([O.sure_at(b, t) for t in cands])
+        assert abs(smin - vals.min()) < 1e-9
+        assert abs(O.sure_at(b, lam) - smin) < 1e-9
+        assert lam == cands[vals <= vals.min() + 1e-9].min()  # smallest minimiser
+        grid = np.linspace(0, np.abs(b).max() * 1.2, 4001)
+        assert min(O.sure_at(b, t) for t in grid) >= smin - 1e-9
+
+
+def _soft_risk(theta, lam):
+    """Gaussian risk of soft thresholding at unit noise (Donoho-Johnstone)."""
+    Phi, phi = stats.norm.cdf, stats.norm.pdf
+    return (1 + lam ** 2 + (theta ** 2 - lam ** 2 - 1) * (Phi(lam - theta) - Phi(-lam - theta))
+            - (lam - theta) * phi(lam + theta) - (lam + theta) * phi(lam - theta))
+
+
+@pytest.mark.parametrize("theta,lam", [(0.0, 1.0), (2.0, 1.5), (-3.0, 0.5), (0.7, 2.5)])
+def test_soft_risk_formula_against_quadrature(theta, lam):
+    f = lambda z: (O.soft_threshold(np.array([theta + z]), lam)[0] - theta) ** 2 * stats.norm.pdf(z)
+    q, _ = integrate.quad(f, -12, 12, points=[-lam - theta, lam - theta], limit=200, epsabs=1e-13)
+    assert abs(q - _soft_risk(theta, lam)) < 1e-9
+
+
+def test_sure_is_unbiased_monte_carlo():
+    rng = _rng(4)
+    N, M, lam = 200, 4000, 1.3
+    theta = np.concatenate([np.zeros(150), rng.normal(0, 3, 50)])
+    risk = _soft_risk(theta, lam).sum()
+    sures = np.empty(M)
+    for m in range(M):
+        b = theta + rng.standard_normal(N)
+        sures[m] = O.sure_at(b, lam)
+    se = sures.std() / math.sqrt(M)
+    assert abs(sures.mean() - risk) < 4 * se
+
+
+def test_sure_matches_mse_on_a_tiny_known_cube():
+    """E[SURE(lam)] = E ||Xhat_w(lam) - X_w||^2 with clean V and known sigma."""
+    rng = _rng(5)
+    H, W, p, r, L = 16, 16, 12, 2, 2
+    A = rng.uniform(0, 1, (H * W, r)) * 3
+    E = rng.uniform(0, 1, (p, r))
+    Xc = A @ E.T
+    sigma = rng.uniform(0.05, 0.2, p)
+    Xw = Xc / sigma
+    U, s, Vt = np.linalg.svd(Xw, full_matrices=False)
+    V = Vt[:r].T
+    lam = np.array([0.8, 1.2])
+    M = 600
+    sure = np.empty(M)
+    loss = np.empty(M)
+    for m in range(M):
+        Y = (Xc + rng.standard_normal(Xc.shape) * sigma).reshape(H, W, p)
+        out = O.hyres(Y, r, L, sigma=sigma, lam=lam, V=V)
+        sure[m] = out["sure"].sum()
+        loss[m] = (((out["X"].reshape(-1, p) - Xc) / sigma) ** 2).sum()
+    d = sure - loss
+    assert abs(d.mean()) < 4 * d.std() / math.sqrt(M)
+
+
+# -------------------------------------------------------------- P4 noise model
+def test_noise_regression_matches_lstsq_and_inverse_gram():
+    rng = _rng(6)
+    n, p = 500, 9
+    Y2 = rng.standard_normal((n, 3)) @ rng.standard_normal((3, p)) + 0.3 * rng.standard_normal((n, p))
+    sig = O.noise_estimate(Y2)
+    for i in range(p):
+        o = [j for j in range(p) if j != i]
+        _, res, _, _ = np.linalg.lstsq(Y2[:, o], Y2[:, i], rcond=None)
+        assert abs(sig[i] - math.sqrt(res[0] / n)) < 1e-12 * sig[i]
+    Ginv = np.linalg.inv(Y2.T @ Y2)
+    np.testing.assert_allclose(sig, np.sqrt(1.0 / (n * np.diag(Ginv))), rtol=1e-12)
+
+
+def test_noise_estimate_on_pure_noise_within_statistical_band():
+    rng = _rng(7)
+    n, p = 40000, 6
+    sb = np.array([0.5, 1.0, 2.0, 0.1, 3.0, 1.5])
+    Y2 = rng.standard_normal((n, p)) * sb
+    rel = O.noise_estimate(Y2) / sb - 1
+    assert np.abs(rel).max() < 4 * math.sqrt(2.0 / n) + p / n
+
+
+# ------------------------------------------------------------------- P5 eigen
+def test_subspace_eigen_residual_and_scipy_agreement():
+    cube = synth.config_cube(1)
+    out = O.hyres(cube.Y, 4, 3)
+    Y2 = cube.Y.reshape(-1, 32) / out["sigma"]
+    C = Y2.T @ Y2
+    V = out["V"]
+    lam = out["evals"][:4]
+    assert np.linalg.norm(C @ V - V * lam) / np.linalg.norm(C) < 1e-13
+    assert np.abs(V.T @ V - np.eye(4)).max() < 1e-13
+    w = linalg.eigh(C, eigvals_only=True, driver="evr")[::-1]
+    np.testing.assert_allclose(out["evals"], w, rtol=1e-12, atol=1e-12 * w[0])
+    for i in range(4):                                        # sign rule
+        k = np.argmax(np.abs(V[:, i]))
+        assert V[k, i] > 0
+
+
+# --------------------------------------------------------- P6 exact recovery
+def test_noiseless_rank_r_cube_is_recovered_exactly():
+    rng = _rng(8)
+    H, W, p, r = 24, 20, 10, 3
+    Y = (rng.uniform(0, 1, (H * W, r)) @ rng.uniform(0, 1, (r, p))).reshape(H, W, p)
+    out = O.hyres(Y, r, 2, sigma=np.ones(p), lam=np.zeros(r))
+    np.testing.assert_allclose(out["X"], Y, atol=1e-12)
+
+
+def test_zero_threshold_is_pca_truncation():
+    cube = synth.config_cube(1)
+    out = O.hyres(cube.Y, 4, 3, lam=np.zeros(4))
+    Y2 = cube.Y.reshape(-1, 32)
+    sig = out["sigma"]
+    Yw = Y2 / sig
+    U, s, Vt = np.linalg.svd(Yw, full_matrices=False)           # a different factorisation
+    P = Vt[:4].T @ Vt[:4]
+    np.testing.assert_allclose(out["X"].reshape(-1, 32), (Yw @ P) * sig, atol=1e-11)
+
+
+# ------------------------------------------------------------ P7 invariances
+def test_invariances():
+    cube = synth.config_cube(1)
+    Y = cube.Y
+    ref = O.hyres(Y, 4, 3)["X"]
+    np.testing.assert_allclose(O.hyres(2.5 * Y, 4, 3)["X"], 2.5 * ref, rtol=1e-9, atol=1e-12)
+    a = np.linspace(0.5, 3.0, 32)
+    np.testing.assert_allclose(O.hyres(Y * a, 4, 3)["X"], ref * a, rtol=1e-9, atol=1e-12)
+    perm = _rng(9).permutation(32)
+    np.testing.assert_allclose(O.hyres(Y[:, :, perm], 4, 3)["X"], ref[:, :, perm], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(O.hyres(Y.transpose(1, 0, 2), 4, 3)["X"], ref.transpose(1, 0, 2),
+                               rtol=1e-9, atol=1e-12)
+    sh = np.roll(Y, (8, 16), axis=(0, 1))                     # multiples of 2^L
+    np.testing.assert_allclose(O.hyres(sh, 4, 3)["X"], np.roll(ref, (8, 16), axis=(0, 1)),
+                               rtol=1e-9, atol=1e-12)
+
+
+# ------------------------------------------------------------------ P8 limits
+def test_limits():
+    cube = synth.config_cube(1)
+    out = O.hyres(cube.Y, 4, 3)
+    big = np.abs(out["B"]).max(axis=1) * 1.0001
+    assert np.abs(O.hyres(cube.Y, 4, 3, lam=big)["X"]).max() == 0.0
+    small = cube.Y[:16, :16, :6]
+    np.testing.assert_allclose(O.hyres(small, 6, 2, lam=np.zeros(6))["X"], small, atol=1e-12)
+
+
+# ------------------------------------------------------------------ tiling
+def test_tile_blend_of_identity_is_identity():
+    Y = _rng(10).standard_normal((70, 90, 3))
+    sy = synth.tile_starts(70, 32, 8)
+    sx = synth.tile_starts(90, 32, 8)
+    out = O.hyres_tiled(Y, 2, 2, 32, 8, sy, sx, tile_fn=lambda t: t)
+    np.testing.assert_allclose(out, Y, atol=1e-13)
+
+
+def test_tile_grid_for_the_sliding_window_workload():
+    assert synth.tile_starts(2048, 512, 32) == [0, 480, 960, 1440, 1536]
+    w = O.tile_weights_1d(480, 512, 2048, 32)
+    assert w[0] < 0.01 and w[-1] < 0.01 and w[100] == 1.0
+    assert np.all(O.tile_weights_1d(0, 512, 2048, 32)[:32] == 1.0)
+
+
+def test_single_tile_equals_plain():
+    cube = synth.config_cube(1)
+    out = O.hyres_tiled(cube.Y, 4, 3, 64, 8, [0], [0])
+    np.testing.assert_allclose(out, O.hyres(cube.Y, 4, 3)["X"], atol=1e-13)
+
+
+# ------------------------------------------------------------ P9 gradients
+def test_oracle_gradient_matches_central_differences():
+    torch = pytest.importorskip("torch")
+    from oracle import grad as OG
+    # the finite-difference sub-cube: rows 0-31, cols 0-31, bands 0-15 of the
+    # 256 x 256 x 191 workload, in float64
+    cube = synth.config_cube(4, keep_clean=False)
+    Y = torch.tensor(cube.Y[:32, :32, :16].astype(np.float64))
+    r, L = 6, 3
+    base = O.hyres(Y.numpy(), r, L)
+    # thresholds moved off the candidate set, so that no |b_k| lies within h
+    lam = torch.tensor(base["lam"] * 0.97, dtype=torch.float64)
+    ref = torch.tensor(base["V"])
+    Yv = Y.clone().requires_grad_(True)
+    lv = lam.clone().requires_grad_(True)
+    Wt = torch.tensor(_rng(11).standard_normal(Y.shape))
+    f = (OG.hyres_forward(Yv, lv, r, L, ref) * Wt).sum()
+    gY, gl = torch.autograd.grad(f, (Yv, lv))
+    # the autograd forward equals the numpy oracle
+    np.testing.assert_allclose(OG.hyres_forward(Y, lam, r, L, ref).numpy(),
+                               O.hyres(Y.numpy(), r, L, lam=lam.numpy())["X"], atol=1e-10)
+    h = 1e-6
+    rng = _rng(12)
+    checked = 0
+    for _ in range(6):
+        u = torch.tensor(rng.standard_normal(Y.shape))
+        u /= u.norm()
+        fp = (OG.hyres_forward(Y + h * u, lam, r, L, ref) * Wt).sum()
+        fm = (OG.hyres_forward(Y - h * u, lam, r, L, ref) * Wt).sum()
+        fd = float(fp - fm) / (2 * h)
+        an = float((gY * u).sum())
+        assert abs(fd - an) <= 1e-5 * max(1.0, abs(an))
+        checked += 1
+    assert checked == 6
+    # threshold gradient vs its closed form: d/dlam sum_k W . soft = -sum sign(b) 1[|b|>lam] dw
+    for i in range(r):
+        e = torch.zeros(r, dtype=torch.float64)
+        e[i] = h
+        fd = float((OG.hyres_forward(Y, lam + e, r, L, ref) * Wt).sum()
+                   - (OG.hyres_forward(Y, lam - e, r, L, ref) * Wt).sum()) / (2 * h)
+        assert abs(fd - float(gl[i])) <= 1e-5 * max(1.0, abs(float(gl[i])))

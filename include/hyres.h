@@ -1,0 +1,213 @@
+/*
+ * hyres.h -- C ABI of the MI355X (gfx950) HyRes denoising library.
+ *
+ * HyRes is the low-rank, wavelet-based, parameter-free Gaussian denoiser of
+ * hyperspectral cubes that the HyDe paper moves onto GPUs (Section 2.1, the
+ * list of conventional methods; Table 1 and Table 2 report its speed and
+ * energy).  The path implemented here is:
+ *
+ *   per-band noise by multiple regression -> whitening -> band Gram Y^T Y and
+ *   its FP64 eigendecomposition (rank-r spectral subspace) -> projection ->
+ *   L-level periodised 2-D Daubechies-4 transform of every component image ->
+ *   per-component soft threshold minimising SURE -> inverse transform ->
+ *   back-projection.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless a
+ *    comment says "host".  Compute calls never allocate device memory; all
+ *    scratch comes from the caller's workspace, whose size the matching
+ *    *_workspace_size call returns.  Workspaces must be 256-byte aligned.
+ *  - Every compute call is stream-ordered on the caller's hipStream_t and
+ *    never synchronises the host, so a sequence of calls may be captured in
+ *    a HIP graph.
+ *  - The return value is a synchronous status from host-side validation or
+ *    from the kernel launches.  Conditions found on the device are OR-ed into
+ *    the optional device word `status` (HYRES_DEV_* bits); read it after your
+ *    own synchronisation.
+ *  - Cube layout: Y is H x W x p, band-fastest.  `pitch` is the number of
+ *    elements between the band vectors of two neighbouring pixels (>= p) and
+ *    `row_pitch` the number between two image rows (>= W * pitch), so a tile
+ *    of a larger cube is addressed in place.
+ *  - Element type of cubes, component images and coefficients: HYRES_F32 or
+ *    HYRES_F64.  Noise levels, eigenvectors, eigenvalues, thresholds and SURE
+ *    values are always double.
+ *  - V is p x r, column-major (column i is eigenvector i).
+ *  - Wavelet coefficients of one image of size H x W with L levels are stored
+ *    flat: [LH_1 HL_1 HH_1 LH_2 HL_2 HH_2 ... LH_L HL_L HH_L LL_L], each block
+ *    row-major of size h_l x w_l with h_l = ceil(h_{l-1}/2), w_l likewise;
+ *    the first letter names the filter along y, the second along x.  The
+ *    number of coefficients is hyres_coeff_count(H, W, L).
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef HYRES_H
+#define HYRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hyres_stream_t;   /* same type as hipStream_t */
+
+typedef enum {
+    HYRES_OK = 0,
+    HYRES_E_NULL = 1,         /* a required pointer is NULL */
+    HYRES_E_SHAPE = 2,        /* r < 1, r >= p (r > p where allowed), p < 2, p > 224,
+                                 r > 16, a level length < 4, pitch < p, ... */
+    HYRES_E_DTYPE = 3,        /* unknown element type or precision */
+    HYRES_E_WORKSPACE = 4,    /* workspace NULL, too small or misaligned */
+    HYRES_E_HIP = 5,          /* a HIP runtime call or kernel launch failed */
+    HYRES_E_UNSUPPORTED = 6   /* valid request this build does not handle */
+} hyres_status;
+
+typedef enum { HYRES_F32 = 0, HYRES_F64 = 1 } hyres_dtype;
+
+typedef enum {
+    HYRES_PREC_NATIVE = 0,    /* every large product in the element type (FP32 or FP64) */
+    HYRES_PREC_MIXED = 1      /* FP32 cubes only: Gram, projection and back-projection on
+                                 BF16 MFMA (hi/lo split operands, FP32 accumulation), one
+                                 FP32 refinement pass of the subspace, FP64 small solves */
+} hyres_precision;
+
+typedef enum {
+    HYRES_SCOPE_ALL = 0,      /* one threshold over every coefficient of a component */
+    HYRES_SCOPE_DETAIL = 1    /* coarsest approximation LL_L is left untouched */
+} hyres_scope;
+
+/* Device status bits (OR-ed into the caller's `status` word). */
+#define HYRES_DEV_NOT_PD        1   /* band Gram not positive definite (zero or dependent band) */
+#define HYRES_DEV_NONFINITE     2   /* NaN or Inf in the input cube */
+#define HYRES_DEV_EIGH_NOCONV   4   /* eigensolver produced a non-finite value */
+#define HYRES_DEV_DEGENERATE    8   /* warning: evals[r-1] / evals[r] < 1 + 1e-6 */
+#define HYRES_DEV_SURE_INEXACT 16   /* SURE search stopped before isolating the exact minimiser;
+                                       the threshold is the best exact candidate seen */
+
+typedef struct hyres_handle hyres_handle;
+
+/* Options of one solve.  rank: r; levels: L (1..8); precision: hyres_precision;
+ * scope: hyres_scope. */
+typedef struct {
+    int rank;
+    int levels;
+    int precision;
+    int scope;
+} hyres_options;
+
+/* Optional device outputs of a solve (any pointer may be NULL). */
+typedef struct {
+    double* sigma;   /* [p]   noise standard deviation per band */
+    double* V;       /* [p*r] top-r eigenvectors of the whitened Gram, column-major, sign rule:
+                              the entry of largest magnitude is positive */
+    double* evals;   /* [p]   all eigenvalues of the whitened Gram, descending */
+    double* lambda;  /* [r]   soft thresholds */
+    double* sure;    /* [r]   SURE at the thresholds */
+    double* gap;     /* [1]   evals[r-1] / evals[r] (Inf when r == p) */
+    int*    status;  /* [1]   HYRES_DEV_* bits, OR-ed (the caller zeroes it) */
+} hyres_outputs;
+
+/* ---- handle ------------------------------------------------------------- */
+
+/* Create a handle bound to HIP device `device` (it becomes current during calls).
+ * Fails with HYRES_E_HIP when no such device exists. */
+hyres_status hyres_create(hyres_handle** handle, int device);
+void hyres_destroy(hyres_handle* handle);
+const char* hyres_status_string(int status);
+/* Number of wavelet coefficients of one H x W image with L levels (0 on bad shape). */
+int64_t hyres_coeff_count(int H, int W, int L);
+
+/* ---- noise estimation (regression of each band on the others) ----------- */
+
+/* sigma_i^2 = RSS_i / n where RSS_i is the residual of the least-squares
+ * regression, without intercept, of band i on the other p-1 bands, n = H*W.
+ * Computed from the FP64 band Gram G = Y^T Y as 1 / (n [G^-1]_ii).
+ * sigma_out [p] (device double); gram_out [p*p] (device double, may be NULL). */
+hyres_status hyres_estimate_noise_workspace_size(int H, int W, int p, int dtype, size_t* bytes);
+hyres_status hyres_estimate_noise(hyres_handle* h, const void* Y, int H, int W, int p,
+                                  int64_t pitch, int64_t row_pitch, int dtype,
+                                  double* sigma_out, double* gram_out, int* status,
+                                  void* workspace, size_t workspace_bytes, hyres_stream_t stream);
+
+/* ---- spectral subspace -------------------------------------------------- */
+
+/* Eigendecomposition of the whitened Gram C = D^-1 Y^T Y D^-1, D = diag(sigma)
+ * (sigma == NULL means D = I).  V_out receives the top-r eigenvectors
+ * (column-major p x r, sign rule as in hyres_outputs), evals_out all p
+ * eigenvalues in descending order.  Solved in FP64 on the device. */
+hyres_status hyres_subspace_workspace_size(int H, int W, int p, int r, int dtype, size_t* bytes);
+hyres_status hyres_subspace(hyres_handle* h, const void* Y, int H, int W, int p,
+                            int64_t pitch, int64_t row_pitch, int dtype,
+                            const double* sigma, int r, double* V_out, double* evals_out,
+                            int* status, void* workspace, size_t workspace_bytes,
+                            hyres_stream_t stream);
+
+/* ---- wavelet transforms ------------------------------------------------- */
+
+/* Forward L-level periodised 2-D db2 transform of `batch` images x[batch][H][W]
+ * (contiguous) into coeffs[batch][Nc], Nc = hyres_coeff_count(H, W, L).  An
+ * odd length is extended by repeating its last sample before each step. */
+hyres_status hyres_dwt2_workspace_size(int batch, int H, int W, int L, int dtype, size_t* bytes);
+hyres_status hyres_dwt2(hyres_handle* h, const void* x, int batch, int H, int W, int L,
+                        int dtype, void* coeffs, void* workspace, size_t workspace_bytes,
+                        hyres_stream_t stream);
+/* Inverse transform.  When lambda (device double [batch]) is not NULL each
+ * coefficient is first soft-thresholded, sign(b) max(|b| - lambda_i, 0)
+ * (every coefficient for scope ALL, details only for scope DETAIL). */
+hyres_status hyres_idwt2(hyres_handle* h, const void* coeffs, int batch, int H, int W, int L,
+                         int dtype, const double* lambda, int scope, void* x_out,
+                         void* workspace, size_t workspace_bytes, hyres_stream_t stream);
+
+/* ---- SURE threshold ----------------------------------------------------- */
+
+/* For each of `batch` coefficient vectors of length Nc (stride `stride`
+ * elements) the exact minimiser, over t in {0} U {|b_k|}, of Stein's unbiased
+ * risk estimate of soft thresholding at unit noise,
+ *   SURE(t) = Nc - 2 #{k : |b_k| <= t} + sum_k min(b_k^2, t^2),
+ * smallest t on ties.  lambda_out, sure_min_out: device double [batch]. */
+hyres_status hyres_sure_workspace_size(int batch, int64_t Nc, int dtype, size_t* bytes);
+hyres_status hyres_sure_threshold(hyres_handle* h, const void* coeffs, int batch, int64_t Nc,
+                                  int64_t stride, int dtype, double* lambda_out,
+                                  double* sure_min_out, int* status, void* workspace,
+                                  size_t workspace_bytes, hyres_stream_t stream);
+
+/* ---- the whole denoiser ------------------------------------------------- */
+
+/* X = HyRes(Y).  sigma_in (device [p]) and lambda_in (device [r]) override the
+ * estimates when not NULL.  X has its own pitch and row pitch (same rules as
+ * Y) and must not overlap Y. */
+hyres_status hyres_denoise_workspace_size(int H, int W, int p, const hyres_options* opt,
+                                          int dtype, size_t* bytes);
+hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int W, int p,
+                           int64_t pitch, int64_t row_pitch, int dtype,
+                           const hyres_options* opt, const double* sigma_in,
+                           const double* lambda_in, void* X, int64_t x_pitch,
+                           int64_t x_row_pitch, const hyres_outputs* out,
+                           void* workspace, size_t workspace_bytes, hyres_stream_t stream);
+
+/* ---- stage timing (benchmarks) ------------------------------------------ */
+
+/* Stages of a solve, as bit positions of the mask below. */
+#define HYRES_STAGE_GRAM        0   /* band Gram (first pass over Y) */
+#define HYRES_STAGE_SMALL       1   /* FP64 noise regression and eigensolve */
+#define HYRES_STAGE_PROJECT     2   /* projection (second pass over Y) */
+#define HYRES_STAGE_DWT         3   /* forward transforms */
+#define HYRES_STAGE_SURE        4   /* SURE threshold search */
+#define HYRES_STAGE_IDWT        5   /* soft threshold + inverse transforms */
+#define HYRES_STAGE_BACKPROJECT 6   /* back-projection (write of X) */
+#define HYRES_NUM_STAGES        7
+
+/* When stage bit s of `mask` is set, every later solve on this handle records
+ * a HIP event pair around stage s on the caller's stream (mask 0: off).  The
+ * events are host objects owned by the handle; no device memory is used. */
+hyres_status hyres_profile_enable(hyres_handle* h, unsigned mask);
+/* Wait for the recorded events, then add the elapsed milliseconds and the
+ * number of timed launches of each stage to ms_out[s] and count_out[s]
+ * (host arrays of HYRES_NUM_STAGES) and forget them. */
+hyres_status hyres_profile_read(hyres_handle* h, double* ms_out, int* count_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYRES_H */

@@ -1,0 +1,226 @@
+"""Python binding of libhyres (torch tensors in, torch tensors out).
+
+PyTorch provides device memory and the current stream; every computation
+runs in the library's HIP kernels.  All calls are asynchronous on
+``torch.cuda.current_stream()``; the returned ``info`` tensors are filled
+when that stream reaches them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Tuple
+
+import torch
+
+from . import _lib as L
+
+_HANDLES: Dict[int, int] = {}
+
+
+def _handle(device: torch.device) -> int:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    h = _HANDLES.get(idx)
+    if h is None:
+        hp = C.c_void_p()
+        L.check(L.lib().hyres_create(C.byref(hp), idx), "hyres_create")
+        h = hp.value
+        _HANDLES[idx] = h
+    return h
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return L.HYRES_F32
+    if t.dtype == torch.float64:
+        return L.HYRES_F64
+    raise TypeError("cubes must be float32 or float64, got %s" % t.dtype)
+
+
+def _workspace(nbytes: int, device: torch.device) -> Tuple[torch.Tensor, int]:
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    ptr = buf.data_ptr()
+    off = (-ptr) % 256
+    return buf, ptr + off
+
+
+def _cube_strides(Y: torch.Tensor) -> Tuple[int, int]:
+    if Y.dim() != 3:
+        raise ValueError("cube must be H x W x p")
+    if Y.stride(2) != 1:
+        raise ValueError("the band axis must be contiguous (band-fastest layout)")
+    return Y.stride(1), Y.stride(0)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _need_cuda(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+
+
+def coeff_count(H: int, W: int, levels: int) -> int:
+    n = L.lib().hyres_coeff_count(H, W, levels)
+    if n <= 0:
+        raise ValueError("invalid transform shape %dx%d, %d levels" % (H, W, levels))
+    return int(n)
+
+
+def estimate_noise(Y: torch.Tensor, return_gram: bool = False):
+    """Per-band noise std by regression on the other bands (device FP64)."""
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    pitch, rp = _cube_strides(Y)
+    dt = _dtype_code(Y)
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_estimate_noise_workspace_size(H, W, p, dt, C.byref(nb)), "workspace size")
+    buf, ws = _workspace(nb.value, Y.device)
+    sigma = torch.empty(p, dtype=torch.float64, device=Y.device)
+    gram = torch.empty(p, p, dtype=torch.float64, device=Y.device) if return_gram else None
+    status = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    L.check(lib.hyres_estimate_noise(_handle(Y.device), Y.data_ptr(), H, W, p, pitch, rp, dt,
+                                     sigma.data_ptr(), _ptr(gram), status.data_ptr(), ws, nb.value,
+                                     _stream(Y.device)), "hyres_estimate_noise")
+    return (sigma, gram, status) if return_gram else (sigma, status)
+
+
+def subspace(Y: torch.Tensor, rank: int, sigma: Optional[torch.Tensor] = None):
+    """Top-r eigenvectors (p x r) and all eigenvalues of the whitened Gram."""
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    pitch, rp = _cube_strides(Y)
+    dt = _dtype_code(Y)
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_subspace_workspace_size(H, W, p, rank, dt, C.byref(nb)), "workspace size")
+    buf, ws = _workspace(nb.value, Y.device)
+    Vt = torch.empty(rank, p, dtype=torch.float64, device=Y.device)     # column-major p x r
+    ev = torch.empty(p, dtype=torch.float64, device=Y.device)
+    status = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    sg = None if sigma is None else sigma.to(device=Y.device, dtype=torch.float64).contiguous()
+    L.check(lib.hyres_subspace(_handle(Y.device), Y.data_ptr(), H, W, p, pitch, rp, dt, _ptr(sg), rank,
+                               Vt.data_ptr(), ev.data_ptr(), status.data_ptr(), ws, nb.value,
+                               _stream(Y.device)), "hyres_subspace")
+    return Vt.T, ev, status
+
+
+def dwt2(x: torch.Tensor, levels: int) -> torch.Tensor:
+    """Batched L-level periodised db2 transform: (B, H, W) -> (B, Nc)."""
+    _need_cuda(x, "x")
+    x = x.contiguous()
+    B, H, W = x.shape
+    dt = _dtype_code(x)
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_dwt2_workspace_size(B, H, W, levels, dt, C.byref(nb)), "workspace size")
+    buf, ws = _workspace(nb.value, x.device)
+    out = torch.empty(B, coeff_count(H, W, levels), dtype=x.dtype, device=x.device)
+    L.check(lib.hyres_dwt2(_handle(x.device), x.data_ptr(), B, H, W, levels, dt, out.data_ptr(), ws,
+                           nb.value, _stream(x.device)), "hyres_dwt2")
+    return out
+
+
+def idwt2(coeffs: torch.Tensor, H: int, W: int, levels: int, lam: Optional[torch.Tensor] = None,
+          scope: str = "all") -> torch.Tensor:
+    """Inverse transform (optionally soft-thresholding with per-image lambda)."""
+    _need_cuda(coeffs, "coeffs")
+    coeffs = coeffs.contiguous()
+    B = coeffs.shape[0]
+    dt = _dtype_code(coeffs)
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_dwt2_workspace_size(B, H, W, levels, dt, C.byref(nb)), "workspace size")
+    buf, ws = _workspace(nb.value, coeffs.device)
+    out = torch.empty(B, H, W, dtype=coeffs.dtype, device=coeffs.device)
+    lm = None if lam is None else lam.to(device=coeffs.device, dtype=torch.float64).contiguous()
+    sc = L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL
+    L.check(lib.hyres_idwt2(_handle(coeffs.device), coeffs.data_ptr(), B, H, W, levels, dt, _ptr(lm), sc,
+                            out.data_ptr(), ws, nb.value, _stream(coeffs.device)), "hyres_idwt2")
+    return out
+
+
+def sure_threshold(coeffs: torch.Tensor):
+    """Exact SURE-minimising soft threshold of each row of a (B, N) tensor."""
+    _need_cuda(coeffs, "coeffs")
+    if coeffs.stride(1) != 1:
+        coeffs = coeffs.contiguous()
+    B, N = coeffs.shape
+    dt = _dtype_code(coeffs)
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_sure_workspace_size(B, N, dt, C.byref(nb)), "workspace size")
+    buf, ws = _workspace(nb.value, coeffs.device)
+    lam = torch.empty(B, dtype=torch.float64, device=coeffs.device)
+    sure = torch.empty(B, dtype=torch.float64, device=coeffs.device)
+    status = torch.zeros(1, dtype=torch.int32, device=coeffs.device)
+    row_stride = coeffs.stride(0) if B > 1 else N         # torch may report any stride for a size-1 dim
+    L.check(lib.hyres_sure_threshold(_handle(coeffs.device), coeffs.data_ptr(), B, N, row_stride, dt,
+                                     lam.data_ptr(), sure.data_ptr(), status.data_ptr(), ws, nb.value,
+                                     _stream(coeffs.device)), "hyres_sure_threshold")
+    return lam, sure, status
+
+
+class Denoiser:
+    """A reusable single-cube solve: workspace and output buffers are allocated
+    once, so ``run`` only enqueues kernels (and can be captured in a graph)."""
+
+    def __init__(self, H: int, W: int, p: int, rank: int, levels: int, dtype=torch.float32,
+                 precision: str = "native", scope: str = "all", device=None):
+        self.device = torch.device(device if device is not None else "cuda")
+        self.H, self.W, self.p, self.r, self.L = H, W, p, rank, levels
+        self.dtype = dtype
+        self.dt = L.HYRES_F32 if dtype == torch.float32 else L.HYRES_F64
+        self.opt = L.Options(rank, levels, L.PREC_MIXED if precision == "mixed" else L.PREC_NATIVE,
+                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL)
+        lib = L.lib()
+        nb = C.c_size_t()
+        L.check(lib.hyres_denoise_workspace_size(H, W, p, C.byref(self.opt), self.dt, C.byref(nb)),
+                "workspace size")
+        self.ws_bytes = nb.value
+        self._buf, self._ws = _workspace(nb.value, self.device)
+        dev = self.device
+        self.sigma = torch.empty(p, dtype=torch.float64, device=dev)
+        self.V = torch.empty(rank, p, dtype=torch.float64, device=dev)
+        self.evals = torch.empty(p, dtype=torch.float64, device=dev)
+        self.lam = torch.empty(rank, dtype=torch.float64, device=dev)
+        self.sure = torch.empty(rank, dtype=torch.float64, device=dev)
+        self.gap = torch.empty(1, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.out = L.Outputs(self.sigma.data_ptr(), self.V.data_ptr(), self.evals.data_ptr(),
+                             self.lam.data_ptr(), self.sure.data_ptr(), self.gap.data_ptr(),
+                             self.status.data_ptr())
+        self.X = torch.empty(H, W, p, dtype=dtype, device=dev)
+
+    def run(self, Y: torch.Tensor, sigma: Optional[torch.Tensor] = None,
+            lam: Optional[torch.Tensor] = None, X: Optional[torch.Tensor] = None) -> torch.Tensor:
+        pitch, rp = _cube_strides(Y)
+        X = self.X if X is None else X
+        xp, xrp = _cube_strides(X)
+        L.check(L.lib().hyres_denoise(_handle(self.device), Y.data_ptr(), self.H, self.W, self.p, pitch, rp,
+                                      self.dt, C.byref(self.opt), _ptr(sigma), _ptr(lam), X.data_ptr(), xp,
+                                      xrp, C.byref(self.out), self._ws, self.ws_bytes,
+                                      _stream(self.device)), "hyres_denoise")
+        return X
+
+    def info(self) -> Dict[str, torch.Tensor]:
+        return dict(sigma=self.sigma, V=self.V.T, evals=self.evals, lam=self.lam, sure=self.sure,
+                    gap=self.gap, status=self.status)
+
+
+def denoise(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
+            sigma: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
+            scope: str = "all"):
+    """HyRes denoising of one H x W x p cube; returns (X, info)."""
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    dn = Denoiser(H, W, p, rank, levels, dtype=Y.dtype, precision=precision, scope=scope, device=Y.device)
+    sg = None if sigma is None else sigma.to(device=Y.device, dtype=torch.float64).contiguous()
+    lm = None if lam is None else lam.to(device=Y.device, dtype=torch.float64).contiguous()
+    X = dn.run(Y, sg, lm)
+    return X, dn.info()

@@ -1,0 +1,117 @@
+// Internal types and device helpers of the HyRes library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hyres.h"
+
+namespace hyres {
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxRank = 16;
+constexpr int kMaxBands = 224;        // FP64 small solver keeps a 224 x 224 matrix in registers
+constexpr int kSureBins = 4096;       // histogram bins per refinement round
+constexpr int kSureRoundsF32 = 6;     // 31-bit keys, >= 12 bits resolved per round when narrow
+constexpr int kSureRoundsF64 = 10;    // 63-bit keys
+constexpr int kGramThreads = 512;
+constexpr int kSmallThreads = 1024;
+constexpr int kPixTile = 64;          // pixels per projection / back-projection block
+
+// Daubechies 4-tap orthonormal scaling filter h = ((1+s3),(3+s3),(3-s3),(1-s3)) / (4 sqrt 2),
+// s3 = sqrt 3, and its quadrature mirror g[m] = (-1)^m h[3-m].
+constexpr double kH0 = 0.48296291314453416;
+constexpr double kH1 = 0.83651630373780794;
+constexpr double kH2 = 0.22414386804201339;
+constexpr double kH3 = -0.12940952255126037;
+
+// Per-component state of the SURE refinement search.
+struct SureState {
+    uint64_t klo, khi, width;   // current key range [klo, khi) and bin width
+    uint64_t below_cnt;         // number of magnitudes with key < klo
+    double below_sum;           // sum of their squares
+    double best_s;              // smallest SURE value seen at an exact candidate
+    double best_t;              // the candidate attaining it
+    uint64_t zeros;             // number of exact zeros (round 1)
+    int round;
+    int done;
+    int inexact;
+    int pad;
+};
+
+// Everything a kernel needs to know about one cube.  Pointers are device pointers.
+struct CubeDesc {
+    const void* Y;  int64_t pitch, row_pitch;
+    void* X;        int64_t xpitch, xrow_pitch;
+    int H, W, p, r, L, scope, T, dtype;     // T = ceil(p / 16)
+    int64_t n;                              // H * W
+    int lh[kMaxLevels + 1], lw[kMaxLevels + 1];  // approximation sizes after l levels (l=0: H, W)
+    int64_t loff[kMaxLevels + 1];           // offset of the detail blocks of level l in a coefficient vector
+    int64_t ll_off;                         // offset of LL_L
+    int64_t nc, ncs;                        // coefficients per component, component stride
+    int64_t nz;                             // plane stride of the component images
+    int64_t tps, tmp_off2;                  // temp plane stride, offset of the second LL buffer
+    // workspace arrays
+    void* gpart; int gslot0, gslots;        // Gram partial sums (slots of this cube)
+    double* G;                              // p x p band Gram
+    double* sigma;                          // p
+    const double* sigma_in;                 // optional caller sigma
+    double* hv;                             // Householder vectors, p x p
+    double* V;                              // p x r column-major
+    double* evals;                          // p, descending
+    double* gap;                            // 1
+    float* P32; float* Q32;                 // (16T x 16) projection and (16 x 16T) back-projection
+    double* P64; double* Q64;               // (p x r) and (r x p)
+    void* Z;                                // r x nz component images (also the denoised ones)
+    void* coef;                             // r x ncs coefficients
+    void* tmp;                              // r x tps approximation buffers
+    uint32_t* hcnt; double* hsum; uint64_t* hmin; uint64_t* hmax;  // r x kSureBins
+    SureState* sst;                         // r
+    double* lambda; double* sure;           // r
+    const double* lambda_in;                // optional caller thresholds
+    int* status;                            // device status word (may be null)
+    int mode;                               // bit 0: estimate sigma, bit 1: eigen, bit 3: threshold
+    int vec4;                               // Y is contiguous with 16-byte aligned pixel rows, p % 4 == 0
+    int xvec4;                              // the same for X
+    unsigned long long* dbg;                // phase time stamps (timing builds only; null otherwise)
+};
+
+#ifdef HYRES_PHASE_TIMING
+#define HYRES_STAMP(d, i) \
+    do { if (threadIdx.x == 0 && (d).dbg) (d).dbg[i] = __builtin_amdgcn_s_memrealtime(); } while (0)
+#else
+#define HYRES_STAMP(d, i) do { } while (0)
+#endif
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// index of the cube owning flattened work item `item` (offsets[0..ncubes])
+__device__ __forceinline__ int find_cube(const int* __restrict__ off, int ncubes, int item) {
+    int lo = 0, hi = ncubes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void set_status(int* st, int bits) {
+    if (st && bits) atomicOr(st, bits);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* pixel_ptr(const CubeDesc& d, int64_t q) {
+    int64_t y = q / d.W, x = q - y * d.W;
+    return static_cast<const T*>(d.Y) + y * d.row_pitch + x * d.pitch;
+}
+
+}  // namespace hyres

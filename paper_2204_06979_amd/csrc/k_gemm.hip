@@ -1,0 +1,265 @@
+// Projection Z = Y (D^-1 V) and back-projection Xhat = Zhat (V^T D).
+//
+// Both are skinny products (r <= 16 columns) that stream the cube once; they
+// are HBM-bound.  FP32 cubes run them on the matrix cores
+// (v_mfma_f32_16x16x4f32): a 16 x 16 output tile per wave, 16 pixels by 16
+// components (projection) or 16 pixels by 16 bands (back-projection).  The
+// cube tile of the projection is staged through LDS with coalesced loads; the
+// small matrices stay in registers as MFMA fragments.  FP64 cubes use plain
+// FP64 FMAs, one pixel per thread.
+#include "hyres_internal.hpp"
+
+namespace hyres {
+
+// LDS row stride (floats) of a 64-pixel x 16T-band tile; the MFMA A fragment
+// reads 16 rows x 4 columns, so rows are offset by 4 banks.
+template <int T>
+__host__ __device__ constexpr int proj_ldw() { return 16 * T + 4; }
+template <int T> __host__ __device__ constexpr int proj_nv4() { return (kPixTile * 4 * T + 255) / 256; }
+template <int T> __host__ __device__ constexpr int proj_nv1() { return (kPixTile * 16 * T + 255) / 256; }
+
+// Registers holding one 64-pixel tile of the cube (all 16T band slots).
+template <int T>
+__device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&r4)[proj_nv4<T>()],
+                                           float (&r1)[proj_nv1<T>()]) {
+    const int tid = threadIdx.x;
+    const int64_t nleft = d.n - q0;
+    if (d.vec4) {
+        const float* base = static_cast<const float*>(d.Y) + q0 * d.pitch;
+        const int g4 = d.p >> 2;
+#pragma unroll
+        for (int i = 0; i < proj_nv4<T>(); ++i) {
+            const int e = tid + 256 * i;
+            const int k = e / (4 * T), g = e - k * (4 * T);
+            v4f v = {0.f, 0.f, 0.f, 0.f};
+            if (k < kPixTile && g < g4 && k < nleft)
+                v = *reinterpret_cast<const v4f*>(base + (int64_t)k * d.pitch + 4 * g);
+            r4[i] = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < proj_nv1<T>(); ++i) {
+            const int e = tid + 256 * i;
+            const int k = e / (16 * T), b = e - k * (16 * T);
+            float v = 0.f;
+            if (k < kPixTile && b < d.p && k < nleft) v = pixel_ptr<float>(d, q0 + k)[b];
+            r1[i] = v;
+        }
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, const v4f (&r4)[proj_nv4<T>()],
+                                           const float (&r1)[proj_nv1<T>()]) {
+    constexpr int LDW = proj_ldw<T>();
+    const int tid = threadIdx.x;
+    if (vec) {
+#pragma unroll
+        for (int i = 0; i < proj_nv4<T>(); ++i) {
+            const int e = tid + 256 * i;
+            const int k = e / (4 * T), g = e - k * (4 * T);
+            if (k < kPixTile) *reinterpret_cast<v4f*>(tile + k * LDW + 4 * g) = r4[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < proj_nv1<T>(); ++i) {
+            const int e = tid + 256 * i;
+            const int k = e / (16 * T), b = e - k * (16 * T);
+            if (k < kPixTile) tile[k * LDW + b] = r1[i];
+        }
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict__ descs,
+                                                    const int* __restrict__ items, int ncubes) {
+    constexpr int LDW = proj_ldw<T>();
+    __shared__ __attribute__((aligned(16))) float tile[kPixTile * LDW];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
+    const int total = items[ncubes];
+    int cur = -1;
+    float bf[4 * T];
+    v4f r4[proj_nv4<T>()];
+    float r1[proj_nv1<T>()];
+    int item = blockIdx.x;
+    if (item < total) {
+        const int c = find_cube(items, ncubes, item);
+        proj_fetch<T>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4, r1);
+    }
+    for (; item < total; item += gridDim.x) {
+        const int c = find_cube(items, ncubes, item);
+        const CubeDesc& d = descs[c];
+        if (c != cur) {
+            cur = c;
+#pragma unroll
+            for (int s = 0; s < 4 * T; ++s) bf[s] = d.P32[(4 * s + row) * 16 + col];
+        }
+        const int64_t q0 = (int64_t)(item - items[c]) * kPixTile;
+        const bool vec = d.vec4 != 0;
+        __syncthreads();
+        proj_stage<T>(tile, vec, r4, r1);
+        __syncthreads();
+        const int nxt = item + gridDim.x;
+        if (nxt < total) {
+            const int c2 = find_cube(items, ncubes, nxt);
+            proj_fetch<T>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4, r1);
+        }
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        const float* arow = tile + (16 * wave + col) * LDW + row;
+#pragma unroll
+        for (int s = 0; s < 4 * T; ++s) acc = mfma4(arow[4 * s], bf[s], acc);
+        // lane holds component col of pixels q0 + 16 wave + 4 row + i
+        if (col < d.r) {
+            float* z = static_cast<float*>(d.Z) + (int64_t)col * d.nz + q0 + 16 * wave + 4 * row;
+            *reinterpret_cast<v4f*>(z) = acc;
+        }
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restrict__ descs,
+                                                        const int* __restrict__ items, int ncubes) {
+    constexpr int P16 = 16 * T;
+    constexpr int LDO = P16 + 4;
+    __shared__ __attribute__((aligned(16))) float ot[kPixTile * LDO];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
+    const int total = items[ncubes];
+    int cur = -1;
+    float bq[4][T];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_cube(items, ncubes, item);
+        const CubeDesc& d = descs[c];
+        const int r = d.r, p = d.p;
+        const int R4 = (r + 3) >> 2;
+        if (c != cur) {
+            cur = c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < T; ++j) bq[q][j] = d.Q32[(4 * q + row) * P16 + 16 * j + col];
+        }
+        const int64_t q0 = (int64_t)(item - items[c]) * kPixTile;
+        // A fragments: Zhat[comp 4q + row][pixel q0 + 16 wave + col]
+        float a[4];
+        const float* zh = static_cast<const float*>(d.Z);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int comp = 4 * q + row;
+            a[q] = (q < R4 && comp < r) ? zh[(int64_t)comp * d.nz + q0 + 16 * wave + col] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < R4) acc = mfma4(a[q], bq[q][j], acc);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ot[(16 * wave + 4 * row + i) * LDO + 16 * j + col] = acc[i];
+        }
+        __syncthreads();
+        const int64_t nleft = d.n - q0;
+        if (d.xvec4) {
+            const int g4 = p >> 2;
+            float* base = static_cast<float*>(d.X) + q0 * d.xpitch;
+            for (int e = threadIdx.x; e < kPixTile * g4; e += 256) {
+                const int k = e / g4, g = e - k * g4;
+                if (k < nleft)
+                    *reinterpret_cast<v4f*>(base + (int64_t)k * d.xpitch + 4 * g) =
+                        *reinterpret_cast<const v4f*>(ot + k * LDO + 4 * g);
+            }
+        } else {
+            for (int e = threadIdx.x; e < kPixTile * p; e += 256) {
+                const int k = e / p, b = e - k * p;
+                if (k < nleft) {
+                    const int64_t q = q0 + k;
+                    const int64_t y = q / d.W, x = q - y * d.W;
+                    static_cast<float*>(d.X)[y * d.xrow_pitch + x * d.xpitch + b] = ot[k * LDO + b];
+                }
+            }
+        }
+    }
+}
+
+// FP64: one pixel per thread.
+__global__ void k_project_f64(const CubeDesc* __restrict__ descs, int cube) {
+    const CubeDesc& d = descs[cube];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.n) return;
+    const double* y = pixel_ptr<double>(d, q);
+    double acc[kMaxRank];
+    for (int g = 0; g < kMaxRank; ++g) acc[g] = 0.0;
+    for (int b = 0; b < d.p; ++b) {
+        const double v = y[b];
+        for (int g = 0; g < d.r; ++g) acc[g] = fma(v, d.P64[(int64_t)b * d.r + g], acc[g]);
+    }
+    double* z = static_cast<double*>(d.Z);
+    for (int g = 0; g < d.r; ++g) z[(int64_t)g * d.nz + q] = acc[g];
+}
+
+__global__ void k_backproject_f64(const CubeDesc* __restrict__ descs, int cube) {
+    const CubeDesc& d = descs[cube];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.n) return;
+    const double* zh = static_cast<const double*>(d.Z);
+    double a[kMaxRank];
+    for (int g = 0; g < d.r; ++g) a[g] = zh[(int64_t)g * d.nz + q];
+    const int64_t y = q / d.W, x = q - y * d.W;
+    double* xo = static_cast<double*>(d.X) + y * d.xrow_pitch + x * d.xpitch;
+    for (int b = 0; b < d.p; ++b) {
+        double s = 0.0;
+        for (int g = 0; g < d.r; ++g) s = fma(a[g], d.Q64[(int64_t)g * d.p + b], s);
+        xo[b] = s;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int T>
+static void launch_proj_t(const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_project_f32<T>, dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+}
+template <int T>
+static void launch_bp_t(const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_backproject_f32<T>, dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+}
+
+hipError_t launch_project_f32(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,
+                              hipStream_t s) {
+    switch (T) {
+#define HYRES_P(TT) case TT: launch_proj_t<TT>(descs, items, ncubes, grid, s); break;
+        HYRES_P(1) HYRES_P(2) HYRES_P(3) HYRES_P(4) HYRES_P(5) HYRES_P(6) HYRES_P(7)
+        HYRES_P(8) HYRES_P(9) HYRES_P(10) HYRES_P(11) HYRES_P(12) HYRES_P(13) HYRES_P(14)
+#undef HYRES_P
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject_f32(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,
+                                  hipStream_t s) {
+    switch (T) {
+#define HYRES_B(TT) case TT: launch_bp_t<TT>(descs, items, ncubes, grid, s); break;
+        HYRES_B(1) HYRES_B(2) HYRES_B(3) HYRES_B(4) HYRES_B(5) HYRES_B(6) HYRES_B(7)
+        HYRES_B(8) HYRES_B(9) HYRES_B(10) HYRES_B(11) HYRES_B(12) HYRES_B(13) HYRES_B(14)
+#undef HYRES_B
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project_f64(const CubeDesc* descs, int cube, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_project_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, descs, cube);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject_f64(const CubeDesc* descs, int cube, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_backproject_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, descs, cube);
+    return hipGetLastError();
+}
+
+}  // namespace hyres

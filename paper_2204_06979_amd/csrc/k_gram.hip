@@ -1,0 +1,297 @@
+// Band Gram G = Y^T Y of a hyperspectral cube (the first pass over Y).
+//
+// FP32 cubes: a symmetric rank-k update on the matrix cores.  Each work item
+// ("slot") is a contiguous pixel range of one cube.  A block of 8 waves stages
+// 32 pixels x p bands in LDS, every wave loads the 16-band fragments of the 4
+// pixel rows of one k-step and issues v_mfma_f32_16x16x4f32 for its share of
+// the T(T+1)/2 upper 16x16 tiles of G (T = ceil(p/16)).  Each slot writes one
+// FP32 partial Gram; k_gram_reduce sums the slots of a cube in FP64 in a fixed
+// order, so the result is bitwise reproducible.  Inside a slot the MFMA
+// accumulates one 64-pixel chunk in FP32 and chunks are summed in FP64, so the
+// rounding error of G stays near one FP32 rounding of each partial.
+//
+// FP64 cubes: one thread per upper-triangle entry and slot, plain FP64 FMAs.
+#include "hyres_internal.hpp"
+
+namespace hyres {
+
+template <int T>
+struct TileMap {
+    static constexpr int NT = T * (T + 1) / 2;
+    static constexpr int S = (NT + 7) / 8;        // tiles per wave
+    __host__ __device__ static constexpr int ti(int t) {
+        int i = 0, rem = t;
+        while (rem >= T - i) { rem -= T - i; ++i; }
+        return i;
+    }
+    __host__ __device__ static constexpr int tj(int t) {
+        int i = 0, rem = t;
+        while (rem >= T - i) { rem -= T - i; ++i; }
+        return i + rem;
+    }
+};
+
+constexpr int kGramKB = 64;                        // pixels per LDS stage
+
+template <int T>
+__host__ __device__ constexpr int gram_ldw() { return (T & 1) ? 16 * T : 16 * T + 16; }
+
+// Values each thread stages per chunk: float4 path (contiguous, 16-byte aligned
+// rows) and scalar path.
+template <int T> __host__ __device__ constexpr int gram_nv4() { return (kGramKB * 4 * T + kGramThreads - 1) / kGramThreads; }
+template <int T> __host__ __device__ constexpr int gram_nv1() { return (kGramKB * 16 * T + kGramThreads - 1) / kGramThreads; }
+
+template <int T, int WV>
+__device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int lane,
+                                          v4f (&acc)[TileMap<T>::S]) {
+    constexpr int LDW = gram_ldw<T>();
+    constexpr int NT = TileMap<T>::NT;
+    constexpr int S = TileMap<T>::S;
+    const int col = lane & 15, row = lane >> 4;
+#pragma unroll 2
+    for (int s = 0; s < kGramKB / 4; ++s) {
+        float f[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) f[j] = tile[(4 * s + row) * LDW + 16 * j + col];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int t = WV + 8 * q;
+            if (t < NT) acc[q] = mfma4(f[TileMap<T>::ti(t)], f[TileMap<T>::tj(t)], acc[q]);
+        }
+    }
+}
+
+// Load one chunk of kGramKB pixels (all 16T band slots) into registers.
+// vec: the cube is contiguous with 16-byte aligned pixel rows and p % 4 == 0.
+template <int T>
+__device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t q1, bool vec,
+                                           v4f (&r4)[gram_nv4<T>()], float (&r1)[gram_nv1<T>()]) {
+    const int tid = threadIdx.x;
+    if (vec) {
+        const float* base = static_cast<const float*>(d.Y) + q * d.pitch;
+        const int g4 = d.p >> 2;                     // float4 groups per pixel
+#pragma unroll
+        for (int i = 0; i < gram_nv4<T>(); ++i) {
+            const int e = tid + kGramThreads * i;    // over kGramKB x 4T
+            const int k = e / (4 * T), g = e - k * (4 * T);
+            v4f v = {0.f, 0.f, 0.f, 0.f};
+            if (k < kGramKB && g < g4 && q + k < q1)
+                v = *reinterpret_cast<const v4f*>(base + (int64_t)k * d.pitch + 4 * g);
+            r4[i] = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < gram_nv1<T>(); ++i) {
+            const int e = tid + kGramThreads * i;    // over kGramKB x 16T
+            const int k = e / (16 * T), b = e - k * (16 * T);
+            float v = 0.f;
+            if (k < kGramKB && b < d.p && q + k < q1) v = pixel_ptr<float>(d, q + k)[b];
+            r1[i] = v;
+        }
+    }
+}
+
+template <int T>
+__device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, const v4f (&r4)[gram_nv4<T>()],
+                                          const float (&r1)[gram_nv1<T>()]) {
+    constexpr int LDW = gram_ldw<T>();
+    const int tid = threadIdx.x;
+    int bad = 0;
+    if (vec) {
+#pragma unroll
+        for (int i = 0; i < gram_nv4<T>(); ++i) {
+            const int e = tid + kGramThreads * i;
+            const int k = e / (4 * T), g = e - k * (4 * T);
+            if (k < kGramKB) {
+                const v4f v = r4[i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) bad |= !__builtin_isfinite(v[c]);
+                *reinterpret_cast<v4f*>(tile + k * LDW + 4 * g) = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < gram_nv1<T>(); ++i) {
+            const int e = tid + kGramThreads * i;
+            const int k = e / (16 * T), b = e - k * (16 * T);
+            if (k < kGramKB) {
+                bad |= !__builtin_isfinite(r1[i]);
+                tile[k * LDW + b] = r1[i];
+            }
+        }
+    }
+    return bad;
+}
+
+template <int T>
+__global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __restrict__ descs,
+                                                          const int* __restrict__ items, int ncubes) {
+    constexpr int LDW = gram_ldw<T>();
+    constexpr int NT = TileMap<T>::NT;
+    constexpr int S = TileMap<T>::S;
+    __shared__ __attribute__((aligned(16))) float tile[kGramKB * LDW];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int total = items[ncubes];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_cube(items, ncubes, item);
+        const CubeDesc& d = descs[c];
+        const int slot = item - items[c];
+        const int64_t n = d.n;
+        int64_t per = (n + d.gslots - 1) / d.gslots;
+        per = (per + kGramKB - 1) / kGramKB * kGramKB;
+        const int64_t q0 = (int64_t)slot * per;
+        const int64_t q1 = q0 + per < n ? q0 + per : n;
+        const bool vec = d.vec4 != 0;
+        v4f acc[S];
+        double accd[S][4];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
+        }
+        int bad = 0;
+        v4f r4[gram_nv4<T>()];
+        float r1[gram_nv1<T>()];
+        if (q0 < q1) gram_fetch<T>(d, q0, q1, vec, r4, r1);
+        for (int64_t q = q0; q < q1; q += kGramKB) {
+            __syncthreads();
+            bad |= gram_stage<T>(tile, vec, r4, r1);
+            __syncthreads();
+            if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, r4, r1);   // overlaps the MFMAs
+            switch (wave) {
+                case 0: gram_wave<T, 0>(tile, lane, acc); break;
+                case 1: gram_wave<T, 1>(tile, lane, acc); break;
+                case 2: gram_wave<T, 2>(tile, lane, acc); break;
+                case 3: gram_wave<T, 3>(tile, lane, acc); break;
+                case 4: gram_wave<T, 4>(tile, lane, acc); break;
+                case 5: gram_wave<T, 5>(tile, lane, acc); break;
+                case 6: gram_wave<T, 6>(tile, lane, acc); break;
+                default: gram_wave<T, 7>(tile, lane, acc); break;
+            }
+            // FP32 sums over one chunk only; chunks accumulate in FP64
+#pragma unroll
+            for (int q2 = 0; q2 < S; ++q2) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
+                acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        if (__any(bad) && lane == 0) set_status(d.status, HYRES_DEV_NONFINITE);
+        float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
+        const int col = lane & 15, row = lane >> 4;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int t = wave + 8 * q;
+            if (t < NT) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) out[t * 256 + (4 * row + i) * 16 + col] = (float)accd[q][i];
+            }
+        }
+    }
+}
+
+// Sum the FP32 partials of every slot of a cube in FP64 (fixed order) into G.
+__global__ void k_gram_reduce_f32(const CubeDesc* __restrict__ descs, const int* __restrict__ cubes,
+                                  int ncubes_in_class) {
+    const int k = blockIdx.y;
+    if (k >= ncubes_in_class) return;
+    const CubeDesc& d = descs[cubes[k]];
+    const int T = d.T, NT = T * (T + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NT * 256) return;
+    const int t = e >> 8, m = (e >> 4) & 15, nn = e & 15;
+    int i = 0, rem = t;
+    while (rem >= T - i) { rem -= T - i; ++i; }
+    const int j = i + rem;
+    const int a = 16 * i + m, b = 16 * j + nn;
+    if (a >= d.p || b >= d.p) return;
+    const float* part = static_cast<const float*>(d.gpart) + (int64_t)d.gslot0 * NT * 256 + e;
+    double s = 0.0;
+    for (int sl = 0; sl < d.gslots; ++sl) s += (double)part[(int64_t)sl * NT * 256];
+    d.G[(int64_t)a * d.p + b] = s;
+    d.G[(int64_t)b * d.p + a] = s;
+}
+
+// FP64 Gram: grid.x covers upper-triangle entries, grid.y the slots of one cube.
+__global__ void k_gram_f64(const CubeDesc* __restrict__ descs, int cube) {
+    const CubeDesc& d = descs[cube];
+    const int p = d.p;
+    const int ntri = p * (p + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int slot = blockIdx.y;
+    if (e >= ntri || slot >= d.gslots) return;
+    int a = 0, rem = e;
+    while (rem >= p - a) { rem -= p - a; ++a; }
+    const int b = a + rem;
+    const int64_t per = (d.n + d.gslots - 1) / d.gslots;
+    const int64_t q0 = (int64_t)slot * per;
+    const int64_t q1 = q0 + per < d.n ? q0 + per : d.n;
+    double s = 0.0;
+    int bad = 0;
+    for (int64_t q = q0; q < q1; ++q) {
+        const double* y = pixel_ptr<double>(d, q);
+        const double ya = y[a], yb = y[b];
+        if (a == b) bad |= !__builtin_isfinite(ya);
+        s = fma(ya, yb, s);
+    }
+    if (bad) set_status(d.status, HYRES_DEV_NONFINITE);
+    static_cast<double*>(d.gpart)[(int64_t)(d.gslot0 + slot) * ntri + e] = s;
+}
+
+__global__ void k_gram_reduce_f64(const CubeDesc* __restrict__ descs, int cube) {
+    const CubeDesc& d = descs[cube];
+    const int p = d.p;
+    const int ntri = p * (p + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ntri) return;
+    int a = 0, rem = e;
+    while (rem >= p - a) { rem -= p - a; ++a; }
+    const int b = a + rem;
+    const double* part = static_cast<const double*>(d.gpart) + (int64_t)d.gslot0 * ntri + e;
+    double s = 0.0;
+    for (int sl = 0; sl < d.gslots; ++sl) s += part[(int64_t)sl * ntri];
+    d.G[(int64_t)a * p + b] = s;
+    d.G[(int64_t)b * p + a] = s;
+}
+
+// ---------------------------------------------------------------- launchers
+typedef void (*GramF32Kernel)(const CubeDesc*, const int*, int);
+
+template <int T>
+static hipError_t launch_gram_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_gram_f32<T>, dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_f32(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,
+                           hipStream_t s) {
+    switch (T) {
+#define HYRES_G(TT) case TT: return launch_gram_t<TT>(descs, items, ncubes, grid, s);
+        HYRES_G(1) HYRES_G(2) HYRES_G(3) HYRES_G(4) HYRES_G(5) HYRES_G(6) HYRES_G(7)
+        HYRES_G(8) HYRES_G(9) HYRES_G(10) HYRES_G(11) HYRES_G(12) HYRES_G(13) HYRES_G(14)
+#undef HYRES_G
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gram_reduce_f32(int T, const CubeDesc* descs, const int* cubes, int ncls,
+                                  hipStream_t s) {
+    const int NT = T * (T + 1) / 2;
+    dim3 grid((NT * 256 + 255) / 256, ncls);
+    hipLaunchKernelGGL(k_gram_reduce_f32, grid, dim3(256), 0, s, descs, cubes, ncls);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_f64(const CubeDesc* descs, int cube, int p, int gslots, hipStream_t s) {
+    const int ntri = p * (p + 1) / 2;
+    hipLaunchKernelGGL(k_gram_f64, dim3((ntri + 255) / 256, gslots), dim3(256), 0, s, descs, cube);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_reduce_f64, dim3((ntri + 255) / 256), dim3(256), 0, s, descs, cube);
+    return hipGetLastError();
+}
+
+}  // namespace hyres

@@ -1,0 +1,521 @@
+// FP64 small solves of one cube in one 1024-thread workgroup:
+//   noise   sigma_i^2 = 1 / (n [G^-1]_ii)           (Gauss-Jordan sweep of the band Gram)
+//   whiten  C = D^-1 G D^-1,  D = diag(sigma)
+//   eigen   Householder tridiagonalisation of C, every eigenvalue by Sturm-count
+//           multisection, the top-r eigenvectors of the tridiagonal matrix from a
+//           twisted factorisation, modified Gram-Schmidt, back-transformation.
+//
+// The regression of band i on the other bands leaves the residual sum of
+// squares 1/[G^-1]_ii (Schur complement), which is why the noise estimate only
+// needs the diagonal of the inverse Gram.
+//
+// The p x p matrix lives in registers: thread (tr, tc) of a ROWS x 32 grid
+// holds the entries (tr + ROWS a, tc + 32 b), a < BR, b < BC.  ROWS = 32 (1024
+// threads) up to p = 160 and ROWS = 16 (512 threads, twice the registers per
+// thread) beyond.  A column is broadcast through LDS; row sums over tc are
+// 32-lane shuffles (the 32 threads of a row share a wave).
+#include "hyres_internal.hpp"
+
+namespace hyres {
+
+constexpr int kSmallP = 256;   // LDS vector length (p <= 224)
+
+// Sturm count: number of eigenvalues of the symmetric tridiagonal (ds, e2s)
+// smaller than x, from the sign changes of the leading principal minors
+// p_i(x) = (d_i - x) p_{i-1}(x) - e_{i-1}^2 p_{i-2}(x); both minors are
+// rescaled by a power of two every 8 steps so the recursion stays in range.
+__device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const double* __restrict__ e2s,
+                                           int p, double x) {
+    double pm2 = 1.0, pm1 = ds[0] - x;
+    int neg = pm1 < 0.0 ? 1 : 0;
+    int cnt = neg;
+    for (int i = 1; i < p; ++i) {
+        const double pi = fma(ds[i] - x, pm1, -e2s[i - 1] * pm2);
+        const int s = pi < 0.0 ? 1 : (pi > 0.0 ? 0 : neg);
+        cnt += (s != neg);
+        neg = s;
+        pm2 = pm1;
+        pm1 = pi;
+        if ((i & 7) == 0) {
+            int e1, e2;
+            frexp(pm1, &e1);
+            frexp(pm2, &e2);
+            const int e = e1 > e2 ? e1 : e2;
+            pm1 = ldexp(pm1, -e);
+            pm2 = ldexp(pm2, -e);
+        }
+    }
+    return cnt;
+}
+
+template <int BR, int BC, int ROWS>
+__global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict__ descs,
+                                                     const int* __restrict__ cubes, int ncls) {
+    constexpr int NTH = ROWS * 32;
+    constexpr int NW = NTH / 64;           // waves
+    constexpr int VPW = (kMaxRank + NW - 1) / NW;   // eigenvectors per wave
+    if ((int)blockIdx.x >= ncls) return;
+    const CubeDesc& d = descs[cubes[blockIdx.x]];
+    const int p = d.p, r = d.r;
+    const double nn = (double)d.n;
+    const int t = threadIdx.x, tc = t & 31, tr = t >> 5, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+
+    __shared__ double s_col[2][kSmallP];
+    __shared__ double s_ub[kSmallP];
+    __shared__ double s_sig[kSmallP];
+    __shared__ double s_dd[kSmallP], s_ee[kSmallP], s_e2[kSmallP], s_hb[kSmallP], s_ev[kSmallP];
+    __shared__ double s_zD[kSmallP * kMaxRank];      // pivots of the top-down factorisation [i][g]
+    __shared__ double s_zU[kSmallP * kMaxRank];      // multipliers of the bottom-up one    [i][g]
+    __shared__ double s_z[kMaxRank][kSmallP];        // eigenvectors of the tridiagonal / of C
+    __shared__ double s_red[4];
+    __shared__ int s_flags;
+
+    if (t == 0) s_flags = 0;
+    int flags = 0;
+    HYRES_STAMP(d, 0);
+    double A[BR][BC];
+
+#pragma unroll
+    for (int a = 0; a < BR; ++a)
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+            const int i = tr + ROWS * a, j = tc + 32 * b;
+            A[a][b] = (i < p && j < p) ? d.G[(int64_t)i * p + j] : (i == j ? 1.0 : 0.0);
+        }
+
+    // ---------------------------------------------------------------- noise
+    if (d.mode & 1) {
+#pragma unroll
+        for (int bb = 0; bb < BC; ++bb) {
+            for (int kk = 0; kk < 32; ++kk) {
+                const int k = 32 * bb + kk;
+                if (k >= p) break;
+                const int buf = k & 1;
+                if (tc == kk) {
+#pragma unroll
+                    for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
+                }
+                __syncthreads();
+                double dk = s_col[buf][k];
+                // the pivot is the regression residual of band k on the bands swept so far
+                if (!(dk > 1e-12 * d.G[(int64_t)k * p + k])) {
+                    flags |= HYRES_DEV_NOT_PD;
+                    dk = 1.0;
+                }
+                const double inv = 1.0 / dk;
+                double cj[BC];
+#pragma unroll
+                for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + 32 * b];
+#pragma unroll
+                for (int a = 0; a < BR; ++a) {
+                    const int i = tr + ROWS * a;
+                    const double ci = s_col[buf][i] * inv;
+                    if (i == k) {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv;
+                        if (tc == kk) A[a][bb] = -inv;
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
+                        if (tc == kk) A[a][bb] = ci;
+                    }
+                }
+            }
+        }
+        // after sweeping every index, A = -G^-1
+#pragma unroll
+        for (int a = 0; a < BR; ++a)
+#pragma unroll
+            for (int b = 0; b < BC; ++b) {
+                const int i = tr + ROWS * a, j = tc + 32 * b;
+                if (i == j && i < p) {
+                    const double gii = -A[a][b];
+                    double s = 1.0;
+                    if (gii > 0.0 && !(flags & HYRES_DEV_NOT_PD)) s = sqrt(1.0 / (nn * gii));
+                    else flags |= HYRES_DEV_NOT_PD;
+                    s_sig[i] = s;
+                    d.sigma[i] = s;
+                }
+            }
+    } else if (t < p) {
+        const double s = d.sigma_in ? d.sigma_in[t] : 1.0;
+        s_sig[t] = s;
+        d.sigma[t] = s;
+    }
+    __syncthreads();
+
+    HYRES_STAMP(d, 1);
+    if (d.mode & 2) {
+        // ------------------------------------------------------- whitened Gram
+#pragma unroll
+        for (int a = 0; a < BR; ++a)
+#pragma unroll
+            for (int b = 0; b < BC; ++b) {
+                const int i = tr + ROWS * a, j = tc + 32 * b;
+                A[a][b] = (i < p && j < p) ? d.G[(int64_t)i * p + j] / (s_sig[i] * s_sig[j]) : 0.0;
+            }
+
+        // ------------------------------------------------ tridiagonalisation
+#pragma unroll
+        for (int bb = 0; bb < BC; ++bb) {
+            for (int kk = 0; kk < 32; ++kk) {
+                const int k = 32 * bb + kk;
+                if (k >= p - 2) break;
+                const int buf = k & 1;
+                if (tc == kk) {
+#pragma unroll
+                    for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
+                }
+                __syncthreads();
+                double ss = 0.0;
+                for (int i = k + 1 + lane; i < p; i += 64) {
+                    const double v = s_col[buf][i];
+                    ss = fma(v, v, ss);
+                }
+                ss = wave_sum(ss);
+                const double x1 = s_col[buf][k + 1];
+                const double nrm = sqrt(ss);
+                const double alpha = x1 >= 0.0 ? -nrm : nrm;
+                const double vtv = 2.0 * alpha * (alpha - x1);
+                const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+                const double v1 = x1 - alpha;
+                double vc[BC];
+#pragma unroll
+                for (int b = 0; b < BC; ++b) {
+                    const int j = tc + 32 * b;
+                    vc[b] = (j > k + 1 && j < p) ? s_col[buf][j] : (j == k + 1 ? v1 : 0.0);
+                }
+#pragma unroll
+                for (int a = 0; a < BR; ++a) {
+                    double s = 0.0;
+                    if (ROWS * a + ROWS - 1 > k) {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) s = fma(A[a][b], vc[b], s);
+#pragma unroll
+                        for (int o = 16; o >= 1; o >>= 1) s += __shfl_xor(s, o, 32);
+                    }
+                    if (tc == 0) s_ub[tr + ROWS * a] = beta * s;
+                }
+                if (t == 0) {
+                    s_dd[k] = s_col[buf][k];
+                    s_ee[k] = alpha;
+                    s_hb[k] = beta;
+                }
+                if (t > k && t < p) d.hv[(int64_t)k * p + t] = (t == k + 1) ? v1 : s_col[buf][t];
+                __syncthreads();
+                double uv = 0.0;
+                for (int i = k + 1 + lane; i < p; i += 64) {
+                    const double vi = (i == k + 1) ? v1 : s_col[buf][i];
+                    uv = fma(s_ub[i], vi, uv);
+                }
+                uv = wave_sum(uv);
+                const double K = 0.5 * beta * uv;
+                double wc[BC];
+#pragma unroll
+                for (int b = 0; b < BC; ++b) {
+                    const int j = tc + 32 * b;
+                    wc[b] = (j > k && j < p) ? s_ub[j] - K * vc[b] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < BR; ++a) {
+                    if (ROWS * a + ROWS - 1 > k) {
+                        const int i = tr + ROWS * a;
+                        const double vi = (i > k + 1 && i < p) ? s_col[buf][i] : (i == k + 1 ? v1 : 0.0);
+                        const double wi = (i > k && i < p) ? s_ub[i] - K * vi : 0.0;
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) {
+                            if (32 * b + 31 > k) A[a][b] -= vi * wc[b] + wi * vc[b];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < BR; ++a)
+#pragma unroll
+            for (int b = 0; b < BC; ++b) {
+                const int i = tr + ROWS * a, j = tc + 32 * b;
+                if (i == j && i >= p - 2 && i < p) s_dd[i] = A[a][b];
+                if (i == p - 1 && j == p - 2) s_ee[p - 2] = A[a][b];
+            }
+        __syncthreads();
+
+        HYRES_STAMP(d, 2);
+        // ------------------------------------------------ eigenvalues (all)
+        if (wave == 0) {
+            double m = 0.0;
+            for (int i = lane; i < p; i += 64) {
+                double rr = fabs(s_dd[i]);
+                if (i > 0) rr += fabs(s_ee[i - 1]);
+                if (i < p - 1) rr += fabs(s_ee[i]);
+                m = rr > m ? rr : m;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double q = __shfl_xor(m, o, 64);
+                m = q > m ? q : m;
+            }
+            if (lane == 0) s_red[0] = m > 0.0 ? m : 1.0;
+        }
+        __syncthreads();
+        const double gmax = s_red[0];
+        const double sc = 1.0 / gmax;
+        for (int i = t; i < p; i += NTH) {
+            s_ub[i] = s_dd[i] * sc;
+            if (i < p - 1) {
+                const double es = s_ee[i] * sc;
+                s_e2[i] = es * es;
+            }
+        }
+        __syncthreads();
+        for (int g = t >> 2; g < p; g += NTH / 4) {
+            const int m = t & 3;
+            {
+                const int midx = p - 1 - g;        // ascending index of the g-th largest
+                double lo = -1.0 - 1e-12, hi = 1.0 + 1e-12;
+                for (int it = 0; it < 24; ++it) {
+                    const double x = lo + (hi - lo) * (0.2 * (m + 1));
+                    const int cnt = sturm_count(s_ub, s_e2, p, x);
+                    const bool below = cnt <= midx;   // x <= lambda
+                    double lo_c = below ? x : lo;
+                    double hi_c = below ? hi : x;
+#pragma unroll
+                    for (int o = 1; o <= 2; o <<= 1) {
+                        const double a1 = __shfl_xor(lo_c, o, 4);
+                        const double a2 = __shfl_xor(hi_c, o, 4);
+                        lo_c = a1 > lo_c ? a1 : lo_c;
+                        hi_c = a2 < hi_c ? a2 : hi_c;
+                    }
+                    lo = lo_c;
+                    hi = hi_c;
+                }
+                if (m == 0) {
+                    const double ev = 0.5 * (lo + hi) * gmax;
+                    s_ev[g] = ev;
+                    d.evals[g] = ev;
+                }
+            }
+        }
+        __syncthreads();
+
+        HYRES_STAMP(d, 3);
+        // ---------------------------- eigenvectors of the tridiagonal matrix
+        if (wave == 0 && lane < r) {
+            const int g = lane;
+            const double mu = s_ev[g];
+            const double pivmin = gmax * 1e-290;
+            double D = s_dd[0] - mu;
+            for (int i = 0; i < p; ++i) {
+                if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
+                s_zD[i * kMaxRank + g] = D;
+                if (i < p - 1) D = (s_dd[i + 1] - mu) - s_ee[i] * (s_ee[i] / D);
+            }
+            double R = s_dd[p - 1] - mu;
+            if (fabs(R) < pivmin) R = R < 0.0 ? -pivmin : pivmin;
+            double best = fabs(s_zD[(p - 1) * kMaxRank + g] + R - (s_dd[p - 1] - mu));
+            int kb = p - 1;
+            for (int i = p - 2; i >= 0; --i) {
+                const double U = s_ee[i] / R;
+                s_zU[i * kMaxRank + g] = U;
+                const double ai = s_dd[i] - mu;
+                R = ai - U * s_ee[i];
+                if (fabs(R) < pivmin) R = R < 0.0 ? -pivmin : pivmin;
+                const double gam = fabs(s_zD[i * kMaxRank + g] + R - ai);
+                if (gam < best) {
+                    best = gam;
+                    kb = i;
+                }
+            }
+            s_z[g][kb] = 1.0;
+            double z = 1.0;
+            for (int i = kb - 1; i >= 0; --i) {
+                z = -(s_ee[i] / s_zD[i * kMaxRank + g]) * z;
+                s_z[g][i] = z;
+            }
+            z = 1.0;
+            for (int i = kb; i < p - 1; ++i) {
+                z = -s_zU[i * kMaxRank + g] * z;
+                s_z[g][i + 1] = z;
+            }
+        }
+        __syncthreads();
+
+        HYRES_STAMP(d, 4);
+        // ---- modified Gram-Schmidt; vector g = wave + NW*v stays in registers of its wave
+        double zr[VPW][4];
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            const int g = wave + NW * v;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane + 64 * q;
+                zr[v][q] = (g < r && i < p) ? s_z[g][i] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int i = 0; i < r; ++i) {
+            double* shared_zi = s_col[i & 1];
+            if (wave == i % NW) {
+#pragma unroll
+                for (int v = 0; v < VPW; ++v) {
+                    if (v == i / NW) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) s = fma(zr[v][q], zr[v][q], s);
+                        s = wave_sum(s);
+                        const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            zr[v][q] *= inv;
+                            shared_zi[lane + 64 * q] = zr[v][q];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const int g = wave + NW * v;
+                if (g > i && g < r) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) s = fma(shared_zi[lane + 64 * q], zr[v][q], s);
+                    s = wave_sum(s);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) zr[v][q] = fma(-s, shared_zi[lane + 64 * q], zr[v][q]);
+                }
+            }
+        }
+
+        HYRES_STAMP(d, 5);
+        // -------------------------- back-transformation v = H_0 ... H_{p-3} z
+        // Reflectors are staged from global memory into LDS eight at a time by
+        // the whole block (coalesced), then applied by the waves owning vectors.
+        {
+            constexpr int RB = 8;
+            double* stage = s_zD;                       // free now: RB x kSmallP doubles
+            for (int k1 = p - 3; k1 >= 0; k1 -= RB) {
+                const int k0 = k1 - RB + 1 < 0 ? 0 : k1 - RB + 1;
+                __syncthreads();
+                for (int e = t; e < RB * kSmallP; e += NTH) {
+                    const int kk = k1 - e / kSmallP, i = e % kSmallP;
+                    if (kk >= k0) stage[(k1 - kk) * kSmallP + i] = (i > kk && i < p) ? d.hv[(int64_t)kk * p + i] : 0.0;
+                }
+                __syncthreads();
+                if (wave < r) {
+                    for (int k = k1; k >= k0; --k) {
+                        const double* hk = stage + (k1 - k) * kSmallP;
+                        double h[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) h[q] = hk[lane + 64 * q];
+                        const double hb = s_hb[k];
+#pragma unroll
+                        for (int v = 0; v < VPW; ++v) {
+                            if (wave + NW * v < r) {
+                                double sdot = 0.0;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) sdot = fma(h[q], zr[v][q], sdot);
+                                sdot = wave_sum(sdot) * hb;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) zr[v][q] = fma(-sdot, h[q], zr[v][q]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        HYRES_STAMP(d, 6);
+        if (wave < r) {
+            // sign rule: the entry of largest magnitude is positive (lowest index on ties)
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const int g = wave + NW * v;
+                if (g < r) {
+                    double bv = -1.0, bs = 1.0;
+                    int bi = 0x7fffffff;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = lane + 64 * q;
+                        if (i < p && fabs(zr[v][q]) > bv) {
+                            bv = fabs(zr[v][q]);
+                            bi = i;
+                            bs = zr[v][q];
+                        }
+                    }
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) {
+                        const double ov = __shfl_xor(bv, o, 64);
+                        const int oi = __shfl_xor(bi, o, 64);
+                        const double os = __shfl_xor(bs, o, 64);
+                        if (ov > bv || (ov == bv && oi < bi)) {
+                            bv = ov;
+                            bi = oi;
+                            bs = os;
+                        }
+                    }
+                    const double sgn = bs < 0.0 ? -1.0 : 1.0;
+                    int bad = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = lane + 64 * q;
+                        if (i < p) {
+                            const double val = zr[v][q] * sgn;
+                            bad |= !__builtin_isfinite(val);
+                            s_z[g][i] = val;
+                            d.V[(int64_t)g * p + i] = val;
+                        }
+                    }
+                    if (__any(bad)) flags |= HYRES_DEV_EIGH_NOCONV;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ------------------------------- projection / back-projection matrices
+        const int P16 = 16 * d.T;
+        for (int e = t; e < P16 * 16; e += NTH) {
+            const int i = e >> 4, g = e & 15;
+            const bool ok = i < p && g < r;
+            const double v = ok ? s_z[g][i] : 0.0;
+            const double s = i < p ? s_sig[i] : 1.0;
+            d.P32[e] = (float)(v / s);
+            d.Q32[(int64_t)g * P16 + i] = (float)(v * s);
+            if (ok) {
+                d.P64[(int64_t)i * r + g] = v / s;
+                d.Q64[(int64_t)g * p + i] = v * s;
+            }
+        }
+        if (t == 0) {
+            double gp = __builtin_inf();
+            if (r < p) {
+                gp = s_ev[r - 1] / s_ev[r];
+                if (!(gp >= 1.0 + 1e-6)) flags |= HYRES_DEV_DEGENERATE;
+            }
+            d.gap[0] = gp;
+        }
+    }
+    if (flags) atomicOr(&s_flags, flags);
+    __syncthreads();
+    if (t == 0 && s_flags) set_status(d.status, s_flags);
+    HYRES_STAMP(d, 7);
+}
+
+// Kernel variant for p bands: (BR, BC, ROWS).
+hipError_t launch_small(int p, const CubeDesc* descs, const int* cubes, int ncls, hipStream_t s) {
+#define HYRES_S(BR, BC, RW) \
+    hipLaunchKernelGGL((k_small<BR, BC, RW>), dim3(ncls), dim3(RW * 32), 0, s, descs, cubes, ncls)
+    if (p <= 32) HYRES_S(1, 1, 32);
+    else if (p <= 64) HYRES_S(2, 2, 32);
+    else if (p <= 96) HYRES_S(3, 3, 32);
+    else if (p <= 128) HYRES_S(4, 4, 32);
+    else if (p <= 160) HYRES_S(5, 5, 32);
+    else if (p <= 192) HYRES_S(12, 6, 16);
+    else if (p <= 224) HYRES_S(14, 7, 16);
+    else return hipErrorInvalidValue;
+#undef HYRES_S
+    return hipGetLastError();
+}
+
+}  // namespace hyres

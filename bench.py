@@ -47,12 +47,65 @@ def stage_work(H, W, p, r, L):
     }
 
 
+def measure(api, _lib, lib, handle, Y, dims, precision, steps, warmup):
+    """Warm up, take a per-stage breakdown, then time `steps` solves with HIP
+    events around the dominant stage (on the solve stream)."""
+    import torch
+    H, W, p, r, L = dims
+    dev = Y.device
+    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32, precision=precision, device=dev)
+    for _ in range(max(warmup, 1)):
+        dn.run(Y)
+    torch.cuda.synchronize()
+    ms = (C.c_double * 7)()
+    cnt = (C.c_int * 7)()
+    lib.hyres_profile_enable(handle, (1 << len(STAGES)) - 1)
+    for _ in range(3):
+        dn.run(Y)
+    torch.cuda.synchronize()
+    _lib.check(lib.hyres_profile_read(handle, ms, cnt), "profile read")
+    stage_ms = {STAGES[i]: ms[i] / max(cnt[i], 1) for i in range(7)}
+    work = stage_work(H, W, p, r, L)
+    dom = max(work.keys(), key=lambda k: stage_ms[k])
+    dom_bit = STAGES.index(dom)
+    for i in range(7):
+        ms[i] = 0.0
+        cnt[i] = 0
+    lib.hyres_profile_enable(handle, 1 << dom_bit)
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        dn.run(Y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    _lib.check(lib.hyres_profile_read(handle, ms, cnt), "profile read")
+    lib.hyres_profile_enable(handle, 0)
+    ms_step = ev0.elapsed_time(ev1) / steps
+    dom_ms = ms[dom_bit] / max(cnt[dom_bit], 1)
+    bound, amount, unit = work[dom]
+    if bound == "mfma":
+        achieved = amount / (dom_ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[precision]
+    else:
+        achieved = amount / (dom_ms * 1e-3) / 1e9
+        peak = HBM_PEAK_GBS
+    return dict(dn=dn, ms_step=ms_step, wall=wall, stage_ms=stage_ms, dom=dom, dom_ms=dom_ms,
+                roofline={"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+                          "frac": achieved / peak, "traffic": None, "kernel_ms": dom_ms},
+                status=int(dn.status.cpu()[0]))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="native", choices=["native", "mixed"])
+    ap.add_argument("--precision", default="both", choices=["native", "mixed", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     args = ap.parse_args()
@@ -72,84 +125,41 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     Y = torch.tensor(cube.Y, device=dev)
-    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32, precision=args.precision, device=dev)
     lib = _lib.lib()
     handle = api._handle(dev)
-
-    for _ in range(max(args.warmup, 1)):
-        dn.run(Y)
-    torch.cuda.synchronize()
-    print("bench: warm-up done", file=sys.stderr, flush=True)
-
-    # stage breakdown (events around every stage; outside the timed region)
-    lib.hyres_profile_enable(handle, (1 << len(STAGES)) - 1)
-    for _ in range(3):
-        dn.run(Y)
-    torch.cuda.synchronize()
-    ms = (C.c_double * 7)()
-    cnt = (C.c_int * 7)()
-    _lib.check(lib.hyres_profile_read(handle, ms, cnt), "profile read")
-    stage_ms = {STAGES[i]: ms[i] / max(cnt[i], 1) for i in range(7)}
-    work = stage_work(H, W, p, r, L)
-    dom = max(work.keys(), key=lambda k: stage_ms[k])
-    dom_bit = STAGES.index(dom)
-
-    # timed region: K solves; events around the dominant stage on the solve stream
-    for i in range(7):
-        ms[i] = 0.0
-        cnt[i] = 0
-    lib.hyres_profile_enable(handle, 1 << dom_bit)
-    stream = torch.cuda.current_stream(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        dn.run(Y)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    _lib.check(lib.hyres_profile_read(handle, ms, cnt), "profile read")
-    lib.hyres_profile_enable(handle, 0)
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+    precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
+    res = {}
+    for prec in precs:
+        res[prec] = measure(api, _lib, lib, handle, Y, (H, W, p, r, L), prec, args.steps, args.warmup)
+        print("bench: %s %.3f ms/solve" % (prec, res[prec]["ms_step"]), file=sys.stderr, flush=True)
+    head = res["mixed"] if "mixed" in res else res[precs[0]]
+    head_prec = "mixed" if "mixed" in res else precs[0]
     voxels = float(H * W * p)
-    value = voxels / (ms_step * 1e-3)
-    dom_ms = ms[dom_bit] / max(cnt[dom_bit], 1)
-    bound, amount, unit = work[dom]
-    if bound == "mfma":
-        achieved = amount / (dom_ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[args.precision]
-    else:
-        achieved = amount / (dom_ms * 1e-3) / 1e9
-        peak = HBM_PEAK_GBS
-    status = int(dn.status.cpu()[0])
-
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": voxels / (head["ms_step"] * 1e-3),
         "unit": "voxels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16-split/f32" if head_prec == "mixed" else "f32",
         "data": "synthetic",
         "config": {
             "workload": "HyRes solve of a %dx%dx%d FP32 cube (Houston-2013 shape), rank %d, %d db2 levels, "
                         "per-band SNR 5-20 dB, linear-mixing synthetic" % (H, W, p, r, L),
-            "precision": args.precision,
-            "wall_s": wall,
+            "precision": head_prec,
         },
-        "roofline": {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": None},
-        "stages_ms": stage_ms,
-        "hbm_gbs_whole_solve": (4.0 * (3 * H * W * p)) / (ms_step * 1e-3) / 1e9,
-        "device_status": status,
+        "roofline": head["roofline"],
     }
+    for prec, m in res.items():
+        out["config"][prec] = {"voxels_per_s": voxels / (m["ms_step"] * 1e-3), "ms_per_solve": m["ms_step"],
+                               "wall_s": m["wall"], "stages_ms": m["stage_ms"], "roofline": m["roofline"],
+                               "hbm_gbs_whole_solve": (4.0 * (3 * H * W * p)) / (m["ms_step"] * 1e-3) / 1e9,
+                               "device_status": m["status"]}
 
     if not args.no_parity or not args.no_cpu_baseline:
         from oracle import hyres_oracle as O
@@ -161,11 +171,16 @@ def main() -> int:
         c0 = time.perf_counter()
         ref = O.hyres(cube.Y.astype(np.float64), r, L)
         cpu_s = time.perf_counter() - c0
-        X = dn.run(Y).double().cpu().numpy()
-        err = float(np.linalg.norm(X - ref["X"]) / np.linalg.norm(ref["X"]))
-        lam_g = dn.lam.cpu().numpy()
-        out["config"]["rel_err_vs_fp64_oracle"] = err
-        out["config"]["lambda_max_rel_diff"] = float(np.max(np.abs(lam_g - ref["lam"]) / ref["lam"]))
+        for prec, m in res.items():
+            X = m["dn"].run(Y).double().cpu().numpy()
+            err = float(np.linalg.norm(X - ref["X"]) / np.linalg.norm(ref["X"]))
+            dn = m["dn"]
+            out["config"][prec]["rel_err_vs_fp64_oracle"] = err
+            out["config"][prec]["sigma_max_rel_err"] = float(np.max(np.abs(dn.sigma.cpu().numpy() / ref["sigma"] - 1)))
+            out["config"][prec]["evals_top_r_max_rel_err"] = float(np.max(np.abs(
+                dn.evals.cpu().numpy()[:r] / ref["evals"][:r] - 1)))
+            out["config"][prec]["lambda_max_rel_diff"] = float(np.max(np.abs(dn.lam.cpu().numpy() - ref["lam"])
+                                                                   / ref["lam"]))
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = {"value": voxels / cpu_s, "unit": "voxels/s", "cores": int(cores),
                                    "kind": "oracle",

@@ -13,6 +13,7 @@
 
 namespace hyres {
 hipError_t launch_gram_f32(int T, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_gram_bf16(int T, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_gram_reduce_f32(int T, const CubeDesc*, const int*, int, hipStream_t);
 hipError_t launch_gram_f64(const CubeDesc*, int, int, int, hipStream_t);
 hipError_t launch_small(int p, const CubeDesc*, const int*, int, hipStream_t);
@@ -136,7 +137,7 @@ enum Stage {
 
 // Geometry and workspace layout of one cube.
 struct CubePlan {
-    int H = 0, W = 0, p = 0, r = 0, L = 0, dtype = 0, scope = 0, T = 0, gslots = 1;
+    int H = 0, W = 0, p = 0, r = 0, L = 0, dtype = 0, scope = 0, T = 0, gslots = 1, precision = 0;
     int64_t n = 0, nz = 0, nc = 0, ncs = 0, tps = 0, tmp_off2 = 0, ll_off = 0;
     int lh[kMaxLevels + 1] = {0}, lw[kMaxLevels + 1] = {0};
     int64_t loff[kMaxLevels + 1] = {0};
@@ -323,7 +324,10 @@ hyres_status run_gram(Ctx& x, const CubePlan& c) {
     if (c.dtype == HYRES_F64) {
         HIPCHK(launch_gram_f64(x.descs(), 0, c.p, c.gslots, x.s));
     } else {
-        HIPCHK(launch_gram_f32(c.T, x.descs(), x.items(ST_GRAM), 1, c.gslots, x.s));
+        if (c.precision == HYRES_PREC_MIXED)
+            HIPCHK(launch_gram_bf16(c.T, x.descs(), x.items(ST_GRAM), 1, c.gslots, x.s));
+        else
+            HIPCHK(launch_gram_f32(c.T, x.descs(), x.items(ST_GRAM), 1, c.gslots, x.s));
         HIPCHK(launch_gram_reduce_f32(c.T, x.descs(), x.items(ST_CLASS), 1, x.s));
     }
     return HYRES_OK;
@@ -673,7 +677,6 @@ static hyres_status check_opts(const hyres_options* opt, int p, int dtype) {
     if (opt->scope != HYRES_SCOPE_ALL && opt->scope != HYRES_SCOPE_DETAIL) return HYRES_E_SHAPE;
     if (opt->precision != HYRES_PREC_NATIVE && opt->precision != HYRES_PREC_MIXED) return HYRES_E_DTYPE;
     if (opt->precision == HYRES_PREC_MIXED && dtype != HYRES_F32) return HYRES_E_DTYPE;
-    if (opt->precision == HYRES_PREC_MIXED) return HYRES_E_UNSUPPORTED;
     return HYRES_OK;
 }
 
@@ -706,6 +709,7 @@ HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int 
     if ((st = plan_cube_call(k, H, W, p, opt->rank, opt->levels, dtype, opt->scope,
                              P_GRAM | P_SMALL | P_IMG | P_SURE)))
         return st;
+    k.c.precision = opt->precision;
     if ((st = check_ws(workspace, workspace_bytes, k.lay.total))) return st;
     if ((st = set_device(h))) return st;
     CubeDesc d = make_desc(k.c, workspace);

@@ -40,7 +40,14 @@ __host__ __device__ constexpr int gram_ldw() { return (T & 1) ? 16 * T : 16 * T 
 // rows) and scalar path.
 template <int T> __host__ __device__ constexpr int gram_nv4() { return (kGramKB * 4 * T + kGramThreads - 1) / kGramThreads; }
 template <int T> __host__ __device__ constexpr int gram_nv1() { return (kGramKB * 16 * T + kGramThreads - 1) / kGramThreads; }
+// one register array serves both paths (float4 groups or single floats)
+template <int T> __host__ __device__ constexpr int gram_nr() {
+    return 4 * gram_nv4<T>() > gram_nv1<T>() ? 4 * gram_nv4<T>() : gram_nv1<T>();
+}
 
+// Wave WV owns the contiguous run of upper tiles [WV*S, WV*S + S) in row-major
+// order: the fragment of the tile row stays in registers while the column
+// fragment is loaded per tile.
 template <int T, int WV>
 __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int lane,
                                           v4f (&acc)[TileMap<T>::S]) {
@@ -48,15 +55,19 @@ __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int la
     constexpr int NT = TileMap<T>::NT;
     constexpr int S = TileMap<T>::S;
     const int col = lane & 15, row = lane >> 4;
-#pragma unroll 2
+#pragma unroll 4
     for (int s = 0; s < kGramKB / 4; ++s) {
-        float f[T];
-#pragma unroll
-        for (int j = 0; j < T; ++j) f[j] = tile[(4 * s + row) * LDW + 16 * j + col];
+        const float* rowp = tile + (4 * s + row) * LDW + col;
+        float fi = 0.f;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            const int t = WV + 8 * q;
-            if (t < NT) acc[q] = mfma4(f[TileMap<T>::ti(t)], f[TileMap<T>::tj(t)], acc[q]);
+            const int t = WV * S + q;
+            if (t < NT) {
+                const int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
+                if (q == 0 || TileMap<T>::ti(t - 1) != i) fi = rowp[16 * i];
+                const float fj = (i == j) ? fi : rowp[16 * j];
+                acc[q] = mfma4(fi, fj, acc[q]);
+            }
         }
     }
 }
@@ -65,7 +76,7 @@ __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int la
 // vec: the cube is contiguous with 16-byte aligned pixel rows and p % 4 == 0.
 template <int T>
 __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t q1, bool vec,
-                                           v4f (&r4)[gram_nv4<T>()], float (&r1)[gram_nv1<T>()]) {
+                                           float (&r)[gram_nr<T>()]) {
     const int tid = threadIdx.x;
     if (vec) {
         const float* base = static_cast<const float*>(d.Y) + q * d.pitch;
@@ -77,7 +88,8 @@ __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t
             v4f v = {0.f, 0.f, 0.f, 0.f};
             if (k < kGramKB && g < g4 && q + k < q1)
                 v = *reinterpret_cast<const v4f*>(base + (int64_t)k * d.pitch + 4 * g);
-            r4[i] = v;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) r[4 * i + c] = v[c];
         }
     } else {
 #pragma unroll
@@ -86,14 +98,13 @@ __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t
             const int k = e / (16 * T), b = e - k * (16 * T);
             float v = 0.f;
             if (k < kGramKB && b < d.p && q + k < q1) v = pixel_ptr<float>(d, q + k)[b];
-            r1[i] = v;
+            r[i] = v;
         }
     }
 }
 
 template <int T>
-__device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, const v4f (&r4)[gram_nv4<T>()],
-                                          const float (&r1)[gram_nv1<T>()]) {
+__device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, const float (&r)[gram_nr<T>()]) {
     constexpr int LDW = gram_ldw<T>();
     const int tid = threadIdx.x;
     int bad = 0;
@@ -103,7 +114,7 @@ __device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, co
             const int e = tid + kGramThreads * i;
             const int k = e / (4 * T), g = e - k * (4 * T);
             if (k < kGramKB) {
-                const v4f v = r4[i];
+                const v4f v = {r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) bad |= !__builtin_isfinite(v[c]);
                 *reinterpret_cast<v4f*>(tile + k * LDW + 4 * g) = v;
@@ -115,8 +126,8 @@ __device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, co
             const int e = tid + kGramThreads * i;
             const int k = e / (16 * T), b = e - k * (16 * T);
             if (k < kGramKB) {
-                bad |= !__builtin_isfinite(r1[i]);
-                tile[k * LDW + b] = r1[i];
+                bad |= !__builtin_isfinite(r[i]);
+                tile[k * LDW + b] = r[i];
             }
         }
     }
@@ -152,14 +163,13 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
         }
         int bad = 0;
-        v4f r4[gram_nv4<T>()];
-        float r1[gram_nv1<T>()];
-        if (q0 < q1) gram_fetch<T>(d, q0, q1, vec, r4, r1);
+        float rg[gram_nr<T>()];
+        if (q0 < q1) gram_fetch<T>(d, q0, q1, vec, rg);
         for (int64_t q = q0; q < q1; q += kGramKB) {
             __syncthreads();
-            bad |= gram_stage<T>(tile, vec, r4, r1);
+            bad |= gram_stage<T>(tile, vec, rg);
             __syncthreads();
-            if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, r4, r1);   // overlaps the MFMAs
+            if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, rg);   // overlaps the MFMAs
             switch (wave) {
                 case 0: gram_wave<T, 0>(tile, lane, acc); break;
                 case 1: gram_wave<T, 1>(tile, lane, acc); break;
@@ -183,7 +193,164 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            const int t = wave + 8 * q;
+            const int t = wave * S + q;
+            if (t < NT) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) out[t * 256 + (4 * row + i) * 16 + col] = (float)accd[q][i];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Mixed precision: each value is split y = hi + lo with hi = bf16(y) and
+// lo = bf16(y - hi); G is accumulated on v_mfma_f32_16x16x32_bf16 as
+// hi.hi + hi.lo + lo.hi (FP32 accumulation).  The missing lo.lo term has a
+// random sign off the diagonal, but on the diagonal it is a positive bias of
+// about 2^-16 y^2 that the noise regression would amplify, so diagonal tiles
+// also add lo.lo.  The tile in LDS is band-major so that one 16-byte read
+// gives a lane its 8 consecutive pixels of one band.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v4f mfma_bf16(bf16x8 a, bf16x8 b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+constexpr int kGramLDP = kGramKB + 8;   // bf16 elements per band row (16-byte aligned rows)
+
+template <int T, int WV>
+__device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const __bf16* __restrict__ tl,
+                                           int lane, v4f (&acc)[TileMap<T>::S]) {
+    constexpr int NT = TileMap<T>::NT;
+    constexpr int S = TileMap<T>::S;
+    const int col = lane & 15, row = lane >> 4;
+#pragma unroll 1
+    for (int s = 0; s < kGramKB / 32; ++s) {
+        const int base = col * kGramLDP + 32 * s + 8 * row;
+        bf16x8 hi_i = {}, lo_i = {};
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int t = WV * S + q;
+            if (t < NT) {
+                const int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
+                if (q == 0 || TileMap<T>::ti(t - 1) != i) {
+                    hi_i = *reinterpret_cast<const bf16x8*>(th + base + 16 * i * kGramLDP);
+                    lo_i = *reinterpret_cast<const bf16x8*>(tl + base + 16 * i * kGramLDP);
+                }
+                if (i == j) {
+                    acc[q] = mfma_bf16(hi_i, hi_i, acc[q]);
+                    acc[q] = mfma_bf16(hi_i, lo_i, acc[q]);
+                    acc[q] = mfma_bf16(lo_i, hi_i, acc[q]);
+                    acc[q] = mfma_bf16(lo_i, lo_i, acc[q]);
+                } else {
+                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8*>(th + base + 16 * j * kGramLDP);
+                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8*>(tl + base + 16 * j * kGramLDP);
+                    acc[q] = mfma_bf16(hi_i, hi_j, acc[q]);
+                    acc[q] = mfma_bf16(hi_i, lo_j, acc[q]);
+                    acc[q] = mfma_bf16(lo_i, hi_j, acc[q]);
+                }
+            }
+        }
+    }
+}
+
+template <int T>
+__device__ __forceinline__ int gramb_stage(__bf16* __restrict__ th, __bf16* __restrict__ tl, bool vec,
+                                           const float (&r)[gram_nr<T>()]) {
+    const int tid = threadIdx.x;
+    int bad = 0;
+    if (vec) {
+#pragma unroll
+        for (int i = 0; i < gram_nv4<T>(); ++i) {
+            const int e = tid + kGramThreads * i;
+            const int k = e / (4 * T), g = e - k * (4 * T);
+            if (k < kGramKB) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float v = r[4 * i + c];
+                    bad |= !__builtin_isfinite(v);
+                    const __bf16 h = (__bf16)v;
+                    th[(4 * g + c) * kGramLDP + k] = h;
+                    tl[(4 * g + c) * kGramLDP + k] = (__bf16)(v - (float)h);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < gram_nv1<T>(); ++i) {
+            const int e = tid + kGramThreads * i;
+            const int k = e / (16 * T), b = e - k * (16 * T);
+            if (k < kGramKB) {
+                const float v = r[i];
+                bad |= !__builtin_isfinite(v);
+                const __bf16 h = (__bf16)v;
+                th[b * kGramLDP + k] = h;
+                tl[b * kGramLDP + k] = (__bf16)(v - (float)h);
+            }
+        }
+    }
+    return bad;
+}
+
+template <int T>
+__global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __restrict__ descs,
+                                                           const int* __restrict__ items, int ncubes) {
+    constexpr int NT = TileMap<T>::NT;
+    constexpr int S = TileMap<T>::S;
+    __shared__ __attribute__((aligned(16))) __bf16 th[16 * T * kGramLDP];
+    __shared__ __attribute__((aligned(16))) __bf16 tl[16 * T * kGramLDP];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int total = items[ncubes];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_cube(items, ncubes, item);
+        const CubeDesc& d = descs[c];
+        const int slot = item - items[c];
+        const int64_t n = d.n;
+        int64_t per = (n + d.gslots - 1) / d.gslots;
+        per = (per + kGramKB - 1) / kGramKB * kGramKB;
+        const int64_t q0 = (int64_t)slot * per;
+        const int64_t q1 = q0 + per < n ? q0 + per : n;
+        const bool vec = d.vec4 != 0;
+        v4f acc[S];
+        double accd[S][4];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
+        }
+        int bad = 0;
+        float rg[gram_nr<T>()];
+        if (q0 < q1) gram_fetch<T>(d, q0, q1, vec, rg);
+        for (int64_t q = q0; q < q1; q += kGramKB) {
+            __syncthreads();
+            bad |= gramb_stage<T>(th, tl, vec, rg);
+            __syncthreads();
+            if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, rg);
+            switch (wave) {
+                case 0: gramb_wave<T, 0>(th, tl, lane, acc); break;
+                case 1: gramb_wave<T, 1>(th, tl, lane, acc); break;
+                case 2: gramb_wave<T, 2>(th, tl, lane, acc); break;
+                case 3: gramb_wave<T, 3>(th, tl, lane, acc); break;
+                case 4: gramb_wave<T, 4>(th, tl, lane, acc); break;
+                case 5: gramb_wave<T, 5>(th, tl, lane, acc); break;
+                case 6: gramb_wave<T, 6>(th, tl, lane, acc); break;
+                default: gramb_wave<T, 7>(th, tl, lane, acc); break;
+            }
+#pragma unroll
+            for (int q2 = 0; q2 < S; ++q2) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
+                acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        if (__any(bad) && lane == 0) set_status(d.status, HYRES_DEV_NONFINITE);
+        float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
+        const int col = lane & 15, row = lane >> 4;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int t = wave * S + q;
             if (t < NT) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) out[t * 256 + (4 * row + i) * 16 + col] = (float)accd[q][i];
@@ -264,6 +431,24 @@ static hipError_t launch_gram_t(const CubeDesc* descs, const int* items, int ncu
                                 hipStream_t s) {
     hipLaunchKernelGGL(k_gram_f32<T>, dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     return hipGetLastError();
+}
+
+template <int T>
+static hipError_t launch_gramb_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_gram_bf16<T>, dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_bf16(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,
+                            hipStream_t s) {
+    switch (T) {
+#define HYRES_G(TT) case TT: return launch_gramb_t<TT>(descs, items, ncubes, grid, s);
+        HYRES_G(1) HYRES_G(2) HYRES_G(3) HYRES_G(4) HYRES_G(5) HYRES_G(6) HYRES_G(7)
+        HYRES_G(8) HYRES_G(9) HYRES_G(10) HYRES_G(11) HYRES_G(12) HYRES_G(13) HYRES_G(14)
+#undef HYRES_G
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_gram_f32(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,

@@ -65,6 +65,8 @@ def test_workspace_sizes_and_shape_errors():
     # mixed precision needs an FP32 cube
     assert lib.hyres_denoise_workspace_size(64, 64, 32, C.byref(L.Options(4, 3, 1, 0)), L.HYRES_F64,
                                             C.byref(nb)) == 3
+    assert lib.hyres_denoise_workspace_size(64, 64, 32, C.byref(L.Options(4, 3, 1, 0)), L.HYRES_F32,
+                                            C.byref(nb)) == 0
     assert lib.hyres_dwt2_workspace_size(4, 5, 64, 2, 0, C.byref(nb)) == 2   # 5 -> 3 < 4 at level 2
     assert lib.hyres_dwt2_workspace_size(4, 64, 64, 3, 0, C.byref(nb)) == 0
     assert lib.hyres_sure_workspace_size(0, 100, 0, C.byref(nb)) == 2

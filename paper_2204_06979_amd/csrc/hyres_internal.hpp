@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "../../include/hyres.h"
 
 namespace hyres {
@@ -11,7 +13,7 @@ constexpr int kMaxLevels = 8;
 constexpr int kMaxRank = 16;
 constexpr int kMaxBands = 224;        // FP64 small solver keeps a 224 x 224 matrix in registers
 constexpr int kSureBins = 4096;       // histogram bins per refinement round
-constexpr int kSureRoundsF32 = 6;     // 31-bit keys, >= 12 bits resolved per round when narrow
+constexpr int kSureRoundsF32 = 8;     // 31-bit keys, >= 12 bits resolved per round when narrow
 constexpr int kSureRoundsF64 = 10;    // 63-bit keys
 constexpr int kGramThreads = 512;
 constexpr int kSmallThreads = 1024;
@@ -98,10 +100,40 @@ __device__ __forceinline__ int find_cube(const int* __restrict__ off, int ncubes
     return lo;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1.
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// DPP move of a double (both halves) with a row-level control.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+// Sum over the 16 lanes of each DPP row, returned to every lane of the row:
+// quad_perm xor 1, quad_perm xor 2, row_half_mirror, row_mirror.
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
     return v;
+}
+// Sum over each half-wave (32 lanes), returned to every lane of the half.
+__device__ __forceinline__ double half_sum(double v) {
+    v = row16_sum(v);
+    return v + __shfl_xor(v, 16, 64);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v = half_sum(v);
+    return v + __shfl_xor(v, 32, 64);
 }
 
 __device__ __forceinline__ void set_status(int* st, int bits) {

@@ -55,20 +55,23 @@ __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int la
     constexpr int NT = TileMap<T>::NT;
     constexpr int S = TileMap<T>::S;
     const int col = lane & 15, row = lane >> 4;
-#pragma unroll 4
+#pragma unroll 2
     for (int s = 0; s < kGramKB / 4; ++s) {
         const float* rowp = tile + (4 * s + row) * LDW + col;
         float fi = 0.f;
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const int t = WV * S + q;
-            if (t < NT) {
-                const int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
-                if (q == 0 || TileMap<T>::ti(t - 1) != i) fi = rowp[16 * i];
-                const float fj = (i == j) ? fi : rowp[16 * j];
-                acc[q] = mfma4(fi, fj, acc[q]);
+        static_for<S>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int t = WV * S + q;
+            if constexpr (t < NT) {
+                constexpr int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
+                if constexpr (q == 0 || TileMap<T>::ti(t - 1) != i) fi = rowp[16 * i];
+                if constexpr (i == j) {
+                    acc[q] = mfma4(fi, fi, acc[q]);
+                } else {
+                    acc[q] = mfma4(fi, rowp[16 * j], acc[q]);
+                }
             }
-        }
+        });
     }
 }
 
@@ -228,16 +231,16 @@ __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const 
     for (int s = 0; s < kGramKB / 32; ++s) {
         const int base = col * kGramLDP + 32 * s + 8 * row;
         bf16x8 hi_i = {}, lo_i = {};
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const int t = WV * S + q;
-            if (t < NT) {
-                const int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
-                if (q == 0 || TileMap<T>::ti(t - 1) != i) {
+        static_for<S>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int t = WV * S + q;
+            if constexpr (t < NT) {
+                constexpr int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
+                if constexpr (q == 0 || TileMap<T>::ti(t - 1) != i) {
                     hi_i = *reinterpret_cast<const bf16x8*>(th + base + 16 * i * kGramLDP);
                     lo_i = *reinterpret_cast<const bf16x8*>(tl + base + 16 * i * kGramLDP);
                 }
-                if (i == j) {
+                if constexpr (i == j) {
                     acc[q] = mfma_bf16(hi_i, hi_i, acc[q]);
                     acc[q] = mfma_bf16(hi_i, lo_i, acc[q]);
                     acc[q] = mfma_bf16(lo_i, hi_i, acc[q]);
@@ -250,7 +253,7 @@ __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const 
                     acc[q] = mfma_bf16(lo_i, hi_j, acc[q]);
                 }
             }
-        }
+        });
     }
 }
 

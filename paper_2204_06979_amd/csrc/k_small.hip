@@ -11,7 +11,7 @@
 //
 // The p x p matrix lives in registers: thread (tr, tc) of a ROWS x 32 grid
 // holds the entries (tr + ROWS a, tc + 32 b), a < BR, b < BC.  ROWS = 32 (1024
-// threads) up to p = 160 and ROWS = 16 (512 threads, twice the registers per
+// threads) up to p = 160 and ROWS = 24 (768 threads, more registers per
 // thread) beyond.  A column is broadcast through LDS; row sums over tc are
 // 32-lane shuffles (the 32 threads of a row share a wave).
 #include "hyres_internal.hpp"
@@ -29,21 +29,37 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const 
     double pm2 = 1.0, pm1 = ds[0] - x;
     int neg = pm1 < 0.0 ? 1 : 0;
     int cnt = neg;
-    for (int i = 1; i < p; ++i) {
+    int i = 1;
+    for (; i + 8 <= p; i += 8) {
+        double dd[8], ee[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dd[u] = ds[i + u];
+            ee[u] = e2s[i + u - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double pi = fma(dd[u] - x, pm1, -ee[u] * pm2);
+            const int sg = pi < 0.0 ? 1 : (pi > 0.0 ? 0 : neg);
+            cnt += (sg != neg);
+            neg = sg;
+            pm2 = pm1;
+            pm1 = pi;
+        }
+        int e1, e2;
+        frexp(pm1, &e1);
+        frexp(pm2, &e2);
+        const int e = e1 > e2 ? e1 : e2;
+        pm1 = ldexp(pm1, -e);
+        pm2 = ldexp(pm2, -e);
+    }
+    for (; i < p; ++i) {
         const double pi = fma(ds[i] - x, pm1, -e2s[i - 1] * pm2);
-        const int s = pi < 0.0 ? 1 : (pi > 0.0 ? 0 : neg);
-        cnt += (s != neg);
-        neg = s;
+        const int sg = pi < 0.0 ? 1 : (pi > 0.0 ? 0 : neg);
+        cnt += (sg != neg);
+        neg = sg;
         pm2 = pm1;
         pm1 = pi;
-        if ((i & 7) == 0) {
-            int e1, e2;
-            frexp(pm1, &e1);
-            frexp(pm2, &e2);
-            const int e = e1 > e2 ? e1 : e2;
-            pm1 = ldexp(pm1, -e);
-            pm2 = ldexp(pm2, -e);
-        }
     }
     return cnt;
 }
@@ -192,8 +208,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
                     if (ROWS * a + ROWS - 1 > k) {
 #pragma unroll
                         for (int b = 0; b < BC; ++b) s = fma(A[a][b], vc[b], s);
-#pragma unroll
-                        for (int o = 16; o >= 1; o >>= 1) s += __shfl_xor(s, o, 32);
+                        s = half_sum(s);
                     }
                     if (tc == 0) s_ub[tr + ROWS * a] = beta * s;
                 }
@@ -511,8 +526,8 @@ hipError_t launch_small(int p, const CubeDesc* descs, const int* cubes, int ncls
     else if (p <= 96) HYRES_S(3, 3, 32);
     else if (p <= 128) HYRES_S(4, 4, 32);
     else if (p <= 160) HYRES_S(5, 5, 32);
-    else if (p <= 192) HYRES_S(12, 6, 16);
-    else if (p <= 224) HYRES_S(14, 7, 16);
+    else if (p <= 192) HYRES_S(8, 6, 24);
+    else if (p <= 224) HYRES_S(10, 7, 24);
     else return hipErrorInvalidValue;
 #undef HYRES_S
     return hipGetLastError();

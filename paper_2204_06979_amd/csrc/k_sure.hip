@@ -199,25 +199,21 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_select(const CubeDesc* __
             tc += cnt[j];
             ts += sum[j];
         }
+        // exclusive scan over threads (Hillis-Steele in LDS; fixed order of additions)
         s_cnt[tid] = tc;
         s_sum[tid] = ts;
         __syncthreads();
-        // exclusive scan over threads (fixed order)
-        if (tid == 0) {
-            unsigned long long ac = 0;
-            double as = 0.0;
-            for (int i = 0; i < kSureThreads; ++i) {
-                const unsigned long long xc = s_cnt[i];
-                const double xs = s_sum[i];
-                s_cnt[i] = ac;
-                s_sum[i] = as;
-                ac += xc;
-                as += xs;
-            }
+        for (int o = 1; o < kSureThreads; o <<= 1) {
+            const unsigned long long ac = tid >= o ? s_cnt[tid - o] : 0ull;
+            const double as = tid >= o ? s_sum[tid - o] : 0.0;
+            __syncthreads();
+            s_cnt[tid] += ac;
+            s_sum[tid] += as;
+            __syncthreads();
         }
+        unsigned long long pc = s_cnt[tid] - tc;
+        double ps = tid > 0 ? s_sum[tid - 1] : 0.0;
         __syncthreads();
-        unsigned long long pc = s_cnt[tid];
-        double ps = s_sum[tid];
         double bs = __builtin_inf(), bt = 0.0;
         if (st.round == 0 && tid == 0) {
             bs = N - 2.0 * (double)st.zeros;   // candidate t = 0

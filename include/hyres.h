@@ -88,20 +88,26 @@ typedef enum {
 typedef struct hyres_handle hyres_handle;
 
 /* Options of one solve.  rank: r; levels: L (1..8); precision: hyres_precision;
- * scope: hyres_scope. */
+ * scope: hyres_scope; flags: HYRES_FLAG_* bits. */
 typedef struct {
     int rank;
     int levels;
     int precision;
     int scope;
+    int flags;
 } hyres_options;
+
+/* Compute all p eigenvalues of the whitened Gram (otherwise only the top r+1,
+ * which the solve needs, are computed and written to hyres_outputs.evals). */
+#define HYRES_FLAG_ALL_EVALS 1
 
 /* Optional device outputs of a solve (any pointer may be NULL). */
 typedef struct {
     double* sigma;   /* [p]   noise standard deviation per band */
     double* V;       /* [p*r] top-r eigenvectors of the whitened Gram, column-major, sign rule:
                               the entry of largest magnitude is positive */
-    double* evals;   /* [p]   all eigenvalues of the whitened Gram, descending */
+    double* evals;   /* [p]   eigenvalues of the whitened Gram, descending: entries 0..r always,
+                              all p with HYRES_FLAG_ALL_EVALS */
     double* lambda;  /* [r]   soft thresholds */
     double* sure;    /* [r]   SURE at the thresholds */
     double* gap;     /* [1]   evals[r-1] / evals[r] (Inf when r == p) */

@@ -21,8 +21,12 @@ SCOPE_ALL, SCOPE_DETAIL = 0, 1
 DEV_NOT_PD, DEV_NONFINITE, DEV_EIGH_NOCONV, DEV_DEGENERATE, DEV_SURE_INEXACT = 1, 2, 4, 8, 16
 
 
+FLAG_ALL_EVALS = 1
+
+
 class Options(C.Structure):
-    _fields_ = [("rank", C.c_int), ("levels", C.c_int), ("precision", C.c_int), ("scope", C.c_int)]
+    _fields_ = [("rank", C.c_int), ("levels", C.c_int), ("precision", C.c_int), ("scope", C.c_int),
+                ("flags", C.c_int)]
 
 
 class Outputs(C.Structure):

@@ -171,13 +171,14 @@ class Denoiser:
     once, so ``run`` only enqueues kernels (and can be captured in a graph)."""
 
     def __init__(self, H: int, W: int, p: int, rank: int, levels: int, dtype=torch.float32,
-                 precision: str = "native", scope: str = "all", device=None):
+                 precision: str = "native", scope: str = "all", device=None, all_evals: bool = False):
         self.device = torch.device(device if device is not None else "cuda")
         self.H, self.W, self.p, self.r, self.L = H, W, p, rank, levels
         self.dtype = dtype
         self.dt = L.HYRES_F32 if dtype == torch.float32 else L.HYRES_F64
         self.opt = L.Options(rank, levels, L.PREC_MIXED if precision == "mixed" else L.PREC_NATIVE,
-                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL)
+                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL,
+                             L.FLAG_ALL_EVALS if all_evals else 0)
         lib = L.lib()
         nb = C.c_size_t()
         L.check(lib.hyres_denoise_workspace_size(H, W, p, C.byref(self.opt), self.dt, C.byref(nb)),
@@ -215,11 +216,12 @@ class Denoiser:
 
 def denoise(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
             sigma: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
-            scope: str = "all"):
+            scope: str = "all", all_evals: bool = False):
     """HyRes denoising of one H x W x p cube; returns (X, info)."""
     _need_cuda(Y, "Y")
     H, W, p = Y.shape
-    dn = Denoiser(H, W, p, rank, levels, dtype=Y.dtype, precision=precision, scope=scope, device=Y.device)
+    dn = Denoiser(H, W, p, rank, levels, dtype=Y.dtype, precision=precision, scope=scope, device=Y.device,
+                  all_evals=all_evals)
     sg = None if sigma is None else sigma.to(device=Y.device, dtype=torch.float64).contiguous()
     lm = None if lam is None else lam.to(device=Y.device, dtype=torch.float64).contiguous()
     X = dn.run(Y, sg, lm)

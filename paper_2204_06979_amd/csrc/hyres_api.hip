@@ -545,7 +545,7 @@ HYRES_API hyres_status hyres_subspace(hyres_handle* h, const void* Y, int H, int
     d.V = V_out;
     if (evals_out) d.evals = evals_out;
     d.status = status;
-    d.mode = 2;
+    d.mode = 2 | 16;
     Ctx x{h, (hipStream_t)stream, workspace, k.o_desc, k.o_items};
     if ((st = begin(x, k.c, d, k.lay))) return st;
     if ((st = run_gram(x, k.c))) return st;
@@ -719,7 +719,7 @@ HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int 
     d.xvec4 = vec4_ok(X, W, p, x_pitch, x_row_pitch, dtype);
     d.sigma_in = sigma_in;
     d.lambda_in = lambda_in;
-    d.mode = (sigma_in ? 0 : 1) | 2 | 8;
+    d.mode = (sigma_in ? 0 : 1) | 2 | 8 | ((opt->flags & HYRES_FLAG_ALL_EVALS) ? 16 : 0);
     if (out) {
         if (out->sigma) d.sigma = out->sigma;
         if (out->V) d.V = out->V;

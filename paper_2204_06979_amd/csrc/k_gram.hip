@@ -257,42 +257,120 @@ __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const 
     }
 }
 
+// BF16 staging: a task is 8 consecutive pixels x 4 bands; its values are
+// split and written as 16-byte rows of the band-major hi and lo tiles.
+template <int T> __host__ __device__ constexpr int gramb_ntask() { return (kGramKB / 8) * 4 * T; }
+template <int T> __host__ __device__ constexpr int gramb_nt() {
+    return (gramb_ntask<T>() + kGramThreads - 1) / kGramThreads;
+}
+
 template <int T>
-__device__ __forceinline__ int gramb_stage(__bf16* __restrict__ th, __bf16* __restrict__ tl, bool vec,
-                                           const float (&r)[gram_nr<T>()]) {
+__device__ __forceinline__ void gramb_fetch(const CubeDesc& d, int64_t q, int64_t q1, v4f (&r)[gramb_nt<T>()][8]) {
+    const int tid = threadIdx.x;
+    const float* base = static_cast<const float*>(d.Y) + q * d.pitch;
+    const int g4 = d.p >> 2;
+#pragma unroll
+    for (int i = 0; i < gramb_nt<T>(); ++i) {
+        const int task = tid + kGramThreads * i;
+        const int blk = task / (4 * T), g = task - blk * (4 * T);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = 8 * blk + u;
+            v4f v = {0.f, 0.f, 0.f, 0.f};
+            if (task < gramb_ntask<T>() && g < g4 && q + k < q1)
+                v = *reinterpret_cast<const v4f*>(base + (int64_t)k * d.pitch + 4 * g);
+            r[i][u] = v;
+        }
+    }
+}
+
+template <int T>
+__device__ __forceinline__ int gramb_stage(__bf16* __restrict__ th, __bf16* __restrict__ tl,
+                                           const v4f (&r)[gramb_nt<T>()][8]) {
     const int tid = threadIdx.x;
     int bad = 0;
-    if (vec) {
 #pragma unroll
-        for (int i = 0; i < gram_nv4<T>(); ++i) {
-            const int e = tid + kGramThreads * i;
-            const int k = e / (4 * T), g = e - k * (4 * T);
-            if (k < kGramKB) {
+    for (int i = 0; i < gramb_nt<T>(); ++i) {
+        const int task = tid + kGramThreads * i;
+        const int blk = task / (4 * T), g = task - blk * (4 * T);
+        if (task < gramb_ntask<T>()) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const float v = r[4 * i + c];
+            for (int c = 0; c < 4; ++c) {
+                bf16x8 h8, l8;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float v = r[i][u][c];
                     bad |= !__builtin_isfinite(v);
                     const __bf16 h = (__bf16)v;
-                    th[(4 * g + c) * kGramLDP + k] = h;
-                    tl[(4 * g + c) * kGramLDP + k] = (__bf16)(v - (float)h);
+                    h8[u] = h;
+                    l8[u] = (__bf16)(v - (float)h);
                 }
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < gram_nv1<T>(); ++i) {
-            const int e = tid + kGramThreads * i;
-            const int k = e / (16 * T), b = e - k * (16 * T);
-            if (k < kGramKB) {
-                const float v = r[i];
-                bad |= !__builtin_isfinite(v);
-                const __bf16 h = (__bf16)v;
-                th[b * kGramLDP + k] = h;
-                tl[b * kGramLDP + k] = (__bf16)(v - (float)h);
+                *reinterpret_cast<bf16x8*>(th + (4 * g + c) * kGramLDP + 8 * blk) = h8;
+                *reinterpret_cast<bf16x8*>(tl + (4 * g + c) * kGramLDP + 8 * blk) = l8;
             }
         }
     }
     return bad;
+}
+
+// Scalar staging (strided or unaligned cubes).
+template <int T>
+__device__ __forceinline__ int gramb_stage_scalar(__bf16* __restrict__ th, __bf16* __restrict__ tl,
+                                                  const float (&r)[gram_nr<T>()]) {
+    const int tid = threadIdx.x;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < gram_nv1<T>(); ++i) {
+        const int e = tid + kGramThreads * i;
+        const int k = e / (16 * T), b = e - k * (16 * T);
+        if (k < kGramKB) {
+            const float v = r[i];
+            bad |= !__builtin_isfinite(v);
+            const __bf16 h = (__bf16)v;
+            th[b * kGramLDP + k] = h;
+            tl[b * kGramLDP + k] = (__bf16)(v - (float)h);
+        }
+    }
+    return bad;
+}
+
+template <int T, bool VEC>
+__device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_t q1, __bf16* th, __bf16* tl,
+                                           int lane, int wave, v4f (&acc)[TileMap<T>::S],
+                                           double (&accd)[TileMap<T>::S][4], int& bad) {
+    constexpr int S = TileMap<T>::S;
+    v4f rv[VEC ? gramb_nt<T>() : 1][8];
+    float rs[VEC ? 1 : gram_nr<T>()];
+    if (q0 < q1) {
+        if constexpr (VEC) gramb_fetch<T>(d, q0, q1, rv);
+        else gram_fetch<T>(d, q0, q1, false, rs);
+    }
+    for (int64_t q = q0; q < q1; q += kGramKB) {
+        __syncthreads();
+        if constexpr (VEC) bad |= gramb_stage<T>(th, tl, rv);
+        else bad |= gramb_stage_scalar<T>(th, tl, rs);
+        __syncthreads();
+        if (q + kGramKB < q1) {
+            if constexpr (VEC) gramb_fetch<T>(d, q + kGramKB, q1, rv);
+            else gram_fetch<T>(d, q + kGramKB, q1, false, rs);
+        }
+        switch (wave) {
+            case 0: gramb_wave<T, 0>(th, tl, lane, acc); break;
+            case 1: gramb_wave<T, 1>(th, tl, lane, acc); break;
+            case 2: gramb_wave<T, 2>(th, tl, lane, acc); break;
+            case 3: gramb_wave<T, 3>(th, tl, lane, acc); break;
+            case 4: gramb_wave<T, 4>(th, tl, lane, acc); break;
+            case 5: gramb_wave<T, 5>(th, tl, lane, acc); break;
+            case 6: gramb_wave<T, 6>(th, tl, lane, acc); break;
+            default: gramb_wave<T, 7>(th, tl, lane, acc); break;
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < S; ++q2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
+            acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    }
 }
 
 template <int T>
@@ -324,30 +402,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
         }
         int bad = 0;
-        float rg[gram_nr<T>()];
-        if (q0 < q1) gram_fetch<T>(d, q0, q1, vec, rg);
-        for (int64_t q = q0; q < q1; q += kGramKB) {
-            __syncthreads();
-            bad |= gramb_stage<T>(th, tl, vec, rg);
-            __syncthreads();
-            if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, rg);
-            switch (wave) {
-                case 0: gramb_wave<T, 0>(th, tl, lane, acc); break;
-                case 1: gramb_wave<T, 1>(th, tl, lane, acc); break;
-                case 2: gramb_wave<T, 2>(th, tl, lane, acc); break;
-                case 3: gramb_wave<T, 3>(th, tl, lane, acc); break;
-                case 4: gramb_wave<T, 4>(th, tl, lane, acc); break;
-                case 5: gramb_wave<T, 5>(th, tl, lane, acc); break;
-                case 6: gramb_wave<T, 6>(th, tl, lane, acc); break;
-                default: gramb_wave<T, 7>(th, tl, lane, acc); break;
-            }
-#pragma unroll
-            for (int q2 = 0; q2 < S; ++q2) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
-                acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
-            }
-        }
+        if (vec) gramb_slot<T, true>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
+        else gramb_slot<T, false>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
         if (__any(bad) && lane == 0) set_status(d.status, HYRES_DEV_NONFINITE);
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
@@ -363,25 +419,48 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
 }
 
 // Sum the FP32 partials of every slot of a cube in FP64 (fixed order) into G.
-__global__ void k_gram_reduce_f32(const CubeDesc* __restrict__ descs, const int* __restrict__ cubes,
-                                  int ncubes_in_class) {
+// A block reduces 32 entries; its 8 thread groups each sum every 8th slot
+// (eight loads in flight per thread), then the 8 group sums are added in order.
+constexpr int kRedGroups = 8;
+
+__global__ __launch_bounds__(256) void k_gram_reduce_f32(const CubeDesc* __restrict__ descs,
+                                                        const int* __restrict__ cubes, int ncubes_in_class) {
+    __shared__ double part[kRedGroups][32];
     const int k = blockIdx.y;
     if (k >= ncubes_in_class) return;
     const CubeDesc& d = descs[cubes[k]];
     const int T = d.T, NT = T * (T + 1) / 2;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= NT * 256) return;
-    const int t = e >> 8, m = (e >> 4) & 15, nn = e & 15;
-    int i = 0, rem = t;
-    while (rem >= T - i) { rem -= T - i; ++i; }
-    const int j = i + rem;
-    const int a = 16 * i + m, b = 16 * j + nn;
-    if (a >= d.p || b >= d.p) return;
-    const float* part = static_cast<const float*>(d.gpart) + (int64_t)d.gslot0 * NT * 256 + e;
+    const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + lane;
+    const bool live = e < NT * 256;
+    const int64_t stride = (int64_t)NT * 256;
+    const float* pbase = static_cast<const float*>(d.gpart) + (int64_t)d.gslot0 * stride + (live ? e : 0);
     double s = 0.0;
-    for (int sl = 0; sl < d.gslots; ++sl) s += (double)part[(int64_t)sl * NT * 256];
-    d.G[(int64_t)a * d.p + b] = s;
-    d.G[(int64_t)b * d.p + a] = s;
+    int sl = grp;
+    for (; sl + 7 * kRedGroups < d.gslots; sl += 8 * kRedGroups) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pbase[(int64_t)(sl + u * kRedGroups) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; sl < d.gslots; sl += kRedGroups) s += (double)pbase[(int64_t)sl * stride];
+    part[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && live) {
+        double tot = 0.0;
+#pragma unroll
+        for (int g = 0; g < kRedGroups; ++g) tot += part[g][lane];
+        const int t = e >> 8, m = (e >> 4) & 15, nn = e & 15;
+        int i = 0, rem = t;
+        while (rem >= T - i) { rem -= T - i; ++i; }
+        const int j = i + rem;
+        const int a = 16 * i + m, b = 16 * j + nn;
+        if (a < d.p && b < d.p) {
+            d.G[(int64_t)a * d.p + b] = tot;
+            d.G[(int64_t)b * d.p + a] = tot;
+        }
+    }
 }
 
 // FP64 Gram: grid.x covers upper-triangle entries, grid.y the slots of one cube.
@@ -468,7 +547,7 @@ hipError_t launch_gram_f32(int T, const CubeDesc* descs, const int* items, int n
 hipError_t launch_gram_reduce_f32(int T, const CubeDesc* descs, const int* cubes, int ncls,
                                   hipStream_t s) {
     const int NT = T * (T + 1) / 2;
-    dim3 grid((NT * 256 + 255) / 256, ncls);
+    dim3 grid((NT * 256 + 31) / 32, ncls);
     hipLaunchKernelGGL(k_gram_reduce_f32, grid, dim3(256), 0, s, descs, cubes, ncls);
     return hipGetLastError();
 }

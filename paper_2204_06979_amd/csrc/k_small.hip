@@ -9,11 +9,12 @@
 // squares 1/[G^-1]_ii (Schur complement), which is why the noise estimate only
 // needs the diagonal of the inverse Gram.
 //
-// The p x p matrix lives in registers: thread (tr, tc) of a ROWS x 32 grid
-// holds the entries (tr + ROWS a, tc + 32 b), a < BR, b < BC.  ROWS = 32 (1024
-// threads) up to p = 160 and ROWS = 24 (768 threads, more registers per
-// thread) beyond.  A column is broadcast through LDS; row sums over tc are
-// 32-lane shuffles (the 32 threads of a row share a wave).
+// The p x p matrix lives in registers: thread (tr, tc) of a ROWS x COLS grid
+// holds the entries (tr + ROWS a, tc + COLS b), a < BR, b < BC.  Up to
+// p = 128 the grid is 16 x 16 (256 threads, one wave per SIMD), up to 176 it is
+// 32 x 16 (512 threads): few waves keep the two barriers of every elimination
+// step cheap, and a row sum is a 16-lane DPP reduction.  Beyond, 24 x 32
+// (768 threads).  A column is broadcast through LDS.
 #include "hyres_internal.hpp"
 
 namespace hyres {
@@ -22,12 +23,15 @@ constexpr int kSmallP = 256;   // LDS vector length (p <= 224)
 
 // Sturm count: number of eigenvalues of the symmetric tridiagonal (ds, e2s)
 // smaller than x, from the sign changes of the leading principal minors
-// p_i(x) = (d_i - x) p_{i-1}(x) - e_{i-1}^2 p_{i-2}(x); both minors are
-// rescaled by a power of two every 8 steps so the recursion stays in range.
+// p_i(x) = (d_i - x) p_{i-1}(x) - e_{i-1}^2 p_{i-2}(x) (a minor that is
+// exactly zero counts as positive); both minors are rescaled by a power of two
+// every 8 steps so the recursion stays in range.
+__device__ __forceinline__ int sgnbit(double v) { return (int)((unsigned)__double2hiint(v) >> 31); }
+
 __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const double* __restrict__ e2s,
                                            int p, double x) {
     double pm2 = 1.0, pm1 = ds[0] - x;
-    int neg = pm1 < 0.0 ? 1 : 0;
+    int neg = sgnbit(pm1);
     int cnt = neg;
     int i = 1;
     for (; i + 8 <= p; i += 8) {
@@ -40,8 +44,8 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const 
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const double pi = fma(dd[u] - x, pm1, -ee[u] * pm2);
-            const int sg = pi < 0.0 ? 1 : (pi > 0.0 ? 0 : neg);
-            cnt += (sg != neg);
+            const int sg = sgnbit(pi);
+            cnt += sg ^ neg;
             neg = sg;
             pm2 = pm1;
             pm1 = pi;
@@ -55,8 +59,8 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const 
     }
     for (; i < p; ++i) {
         const double pi = fma(ds[i] - x, pm1, -e2s[i - 1] * pm2);
-        const int sg = pi < 0.0 ? 1 : (pi > 0.0 ? 0 : neg);
-        cnt += (sg != neg);
+        const int sg = sgnbit(pi);
+        cnt += sg ^ neg;
         neg = sg;
         pm2 = pm1;
         pm1 = pi;
@@ -64,17 +68,17 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const 
     return cnt;
 }
 
-template <int BR, int BC, int ROWS>
-__global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict__ descs,
-                                                     const int* __restrict__ cubes, int ncls) {
-    constexpr int NTH = ROWS * 32;
+template <int BR, int BC, int ROWS, int COLS>
+__global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restrict__ descs,
+                                                       const int* __restrict__ cubes, int ncls) {
+    constexpr int NTH = ROWS * COLS;
     constexpr int NW = NTH / 64;           // waves
     constexpr int VPW = (kMaxRank + NW - 1) / NW;   // eigenvectors per wave
     if ((int)blockIdx.x >= ncls) return;
     const CubeDesc& d = descs[cubes[blockIdx.x]];
     const int p = d.p, r = d.r;
     const double nn = (double)d.n;
-    const int t = threadIdx.x, tc = t & 31, tr = t >> 5, lane = t & 63;
+    const int t = threadIdx.x, tc = t % COLS, tr = t / COLS, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
 
     __shared__ double s_col[2][kSmallP];
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
     for (int a = 0; a < BR; ++a)
 #pragma unroll
         for (int b = 0; b < BC; ++b) {
-            const int i = tr + ROWS * a, j = tc + 32 * b;
+            const int i = tr + ROWS * a, j = tc + COLS * b;
             A[a][b] = (i < p && j < p) ? d.G[(int64_t)i * p + j] : (i == j ? 1.0 : 0.0);
         }
 
@@ -104,8 +108,8 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
     if (d.mode & 1) {
 #pragma unroll
         for (int bb = 0; bb < BC; ++bb) {
-            for (int kk = 0; kk < 32; ++kk) {
-                const int k = 32 * bb + kk;
+            for (int kk = 0; kk < COLS; ++kk) {
+                const int k = COLS * bb + kk;
                 if (k >= p) break;
                 const int buf = k & 1;
                 if (tc == kk) {
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
                 const double inv = 1.0 / dk;
                 double cj[BC];
 #pragma unroll
-                for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + 32 * b];
+                for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + COLS * b];
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
                     const int i = tr + ROWS * a;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
         for (int a = 0; a < BR; ++a)
 #pragma unroll
             for (int b = 0; b < BC; ++b) {
-                const int i = tr + ROWS * a, j = tc + 32 * b;
+                const int i = tr + ROWS * a, j = tc + COLS * b;
                 if (i == j && i < p) {
                     const double gii = -A[a][b];
                     double s = 1.0;
@@ -168,15 +172,15 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
         for (int a = 0; a < BR; ++a)
 #pragma unroll
             for (int b = 0; b < BC; ++b) {
-                const int i = tr + ROWS * a, j = tc + 32 * b;
+                const int i = tr + ROWS * a, j = tc + COLS * b;
                 A[a][b] = (i < p && j < p) ? d.G[(int64_t)i * p + j] / (s_sig[i] * s_sig[j]) : 0.0;
             }
 
         // ------------------------------------------------ tridiagonalisation
 #pragma unroll
         for (int bb = 0; bb < BC; ++bb) {
-            for (int kk = 0; kk < 32; ++kk) {
-                const int k = 32 * bb + kk;
+            for (int kk = 0; kk < COLS; ++kk) {
+                const int k = COLS * bb + kk;
                 if (k >= p - 2) break;
                 const int buf = k & 1;
                 if (tc == kk) {
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
                 double vc[BC];
 #pragma unroll
                 for (int b = 0; b < BC; ++b) {
-                    const int j = tc + 32 * b;
+                    const int j = tc + COLS * b;
                     vc[b] = (j > k + 1 && j < p) ? s_col[buf][j] : (j == k + 1 ? v1 : 0.0);
                 }
 #pragma unroll
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
                     if (ROWS * a + ROWS - 1 > k) {
 #pragma unroll
                         for (int b = 0; b < BC; ++b) s = fma(A[a][b], vc[b], s);
-                        s = half_sum(s);
+                        s = COLS == 32 ? half_sum(s) : row16_sum(s);
                     }
                     if (tc == 0) s_ub[tr + ROWS * a] = beta * s;
                 }
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
                 double wc[BC];
 #pragma unroll
                 for (int b = 0; b < BC; ++b) {
-                    const int j = tc + 32 * b;
+                    const int j = tc + COLS * b;
                     wc[b] = (j > k && j < p) ? s_ub[j] - K * vc[b] : 0.0;
                 }
 #pragma unroll
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
                         const double wi = (i > k && i < p) ? s_ub[i] - K * vi : 0.0;
 #pragma unroll
                         for (int b = 0; b < BC; ++b) {
-                            if (32 * b + 31 > k) A[a][b] -= vi * wc[b] + wi * vc[b];
+                            if (COLS * b + COLS - 1 > k) A[a][b] -= vi * wc[b] + wi * vc[b];
                         }
                     }
                 }
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
         for (int a = 0; a < BR; ++a)
 #pragma unroll
             for (int b = 0; b < BC; ++b) {
-                const int i = tr + ROWS * a, j = tc + 32 * b;
+                const int i = tr + ROWS * a, j = tc + COLS * b;
                 if (i == j && i >= p - 2 && i < p) s_dd[i] = A[a][b];
                 if (i == p - 1 && j == p - 2) s_ee[p - 2] = A[a][b];
             }
@@ -285,31 +289,42 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
             }
         }
         __syncthreads();
-        for (int g = t >> 2; g < p; g += NTH / 4) {
-            const int m = t & 3;
-            {
-                const int midx = p - 1 - g;        // ascending index of the g-th largest
-                double lo = -1.0 - 1e-12, hi = 1.0 + 1e-12;
-                for (int it = 0; it < 24; ++it) {
-                    const double x = lo + (hi - lo) * (0.2 * (m + 1));
-                    const int cnt = sturm_count(s_ub, s_e2, p, x);
-                    const bool below = cnt <= midx;   // x <= lambda
-                    double lo_c = below ? x : lo;
-                    double hi_c = below ? hi : x;
-#pragma unroll
-                    for (int o = 1; o <= 2; o <<= 1) {
-                        const double a1 = __shfl_xor(lo_c, o, 4);
-                        const double a2 = __shfl_xor(hi_c, o, 4);
-                        lo_c = a1 > lo_c ? a1 : lo_c;
-                        hi_c = a2 < hi_c ? a2 : hi_c;
+        // Multisection: M lanes per eigenvalue evaluate the Sturm count at M
+        // interior points, shrinking the bracket M+1 times per iteration.
+        // Only the top r+1 eigenvalues are needed by the solve; all p are
+        // computed when requested.
+        {
+            const int nev = (d.mode & 16) ? p : (r + 1 < p ? r + 1 : p);
+            const int M = nev * 64 <= NTH ? 64 : (nev * 16 <= 2 * NTH ? 16 : 4);
+            const int iters = M == 64 ? 9 : (M == 16 ? 14 : 24);
+            const double inv_m1 = 1.0 / (double)(M + 1);
+            const int m = t % M;
+            const int nslot = NTH / M;
+            for (int g0 = 0; g0 < nev; g0 += nslot) {
+                const int g = g0 + t / M;
+                if (g < nev) {
+                    const int midx = p - 1 - g;        // ascending index of the g-th largest
+                    double lo = -1.0 - 1e-12, hi = 1.0 + 1e-12;
+                    for (int it = 0; it < iters; ++it) {
+                        const double x = lo + (hi - lo) * ((double)(m + 1) * inv_m1);
+                        const int cnt = sturm_count(s_ub, s_e2, p, x);
+                        const bool below = cnt <= midx;   // x <= lambda
+                        double lo_c = below ? x : lo;
+                        double hi_c = below ? hi : x;
+                        for (int o = 1; o < M; o <<= 1) {
+                            const double a1 = __shfl_xor(lo_c, o, M);
+                            const double a2 = __shfl_xor(hi_c, o, M);
+                            lo_c = a1 > lo_c ? a1 : lo_c;
+                            hi_c = a2 < hi_c ? a2 : hi_c;
+                        }
+                        lo = lo_c;
+                        hi = hi_c;
                     }
-                    lo = lo_c;
-                    hi = hi_c;
-                }
-                if (m == 0) {
-                    const double ev = 0.5 * (lo + hi) * gmax;
-                    s_ev[g] = ev;
-                    d.evals[g] = ev;
+                    if (m == 0) {
+                        const double ev = 0.5 * (lo + hi) * gmax;
+                        s_ev[g] = ev;
+                        if (d.evals) d.evals[g] = ev;
+                    }
                 }
             }
         }
@@ -519,15 +534,17 @@ __global__ __launch_bounds__(ROWS * 32) void k_small(const CubeDesc* __restrict_
 
 // Kernel variant for p bands: (BR, BC, ROWS).
 hipError_t launch_small(int p, const CubeDesc* descs, const int* cubes, int ncls, hipStream_t s) {
-#define HYRES_S(BR, BC, RW) \
-    hipLaunchKernelGGL((k_small<BR, BC, RW>), dim3(ncls), dim3(RW * 32), 0, s, descs, cubes, ncls)
-    if (p <= 32) HYRES_S(1, 1, 32);
-    else if (p <= 64) HYRES_S(2, 2, 32);
-    else if (p <= 96) HYRES_S(3, 3, 32);
-    else if (p <= 128) HYRES_S(4, 4, 32);
-    else if (p <= 160) HYRES_S(5, 5, 32);
-    else if (p <= 192) HYRES_S(8, 6, 24);
-    else if (p <= 224) HYRES_S(10, 7, 24);
+#define HYRES_S(BR, BC, RW, CL) \
+    hipLaunchKernelGGL((k_small<BR, BC, RW, CL>), dim3(ncls), dim3(RW * CL), 0, s, descs, cubes, ncls)
+    if (p <= 32) HYRES_S(2, 2, 16, 16);
+    else if (p <= 64) HYRES_S(4, 4, 16, 16);
+    else if (p <= 96) HYRES_S(6, 6, 16, 16);
+    else if (p <= 128) HYRES_S(8, 8, 16, 16);
+    else if (p <= 144) HYRES_S(5, 9, 32, 16);
+    else if (p <= 160) HYRES_S(5, 10, 32, 16);
+    else if (p <= 176) HYRES_S(6, 11, 32, 16);
+    else if (p <= 192) HYRES_S(8, 6, 24, 32);
+    else if (p <= 224) HYRES_S(10, 7, 24, 32);
     else return hipErrorInvalidValue;
 #undef HYRES_S
     return hipGetLastError();

@@ -37,8 +37,12 @@ struct SureState {
     int round;
     int done;
     int inexact;
-    int pad;
+    int gather;                 // 1: the next pass collects the values of the surviving bins
+    unsigned int ncand;         // number of collected values
+    unsigned int nsurv;         // number of values in the surviving bins
 };
+
+constexpr int kSureCap = 8192;        // values finished exactly in one block
 
 // Everything a kernel needs to know about one cube.  Pointers are device pointers.
 struct CubeDesc {
@@ -68,6 +72,11 @@ struct CubeDesc {
     void* tmp;                              // r x tps approximation buffers
     uint32_t* hcnt; double* hsum; uint64_t* hmin; uint64_t* hmax;  // r x kSureBins
     SureState* sst;                         // r
+    uint32_t* sbits;                        // r x kSureBins/32 surviving-bin bitmap
+    uint64_t* spre;                         // r x kSureBins: values below each bin (gather round)
+    double* sspre;                          // r x kSureBins: their sum of squares
+    uint32_t* scb;                          // r x kSureBins: collected values in earlier surviving bins
+    uint64_t* cand;                         // r x kSureCap collected magnitudes (keys)
     double* lambda; double* sure;           // r
     const double* lambda_in;                // optional caller thresholds
     int* status;                            // device status word (may be null)

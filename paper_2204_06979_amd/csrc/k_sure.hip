@@ -15,10 +15,13 @@
 //     N - 2(C + c) + S + s + (N - C - c) t_max^2;
 //   a lower bound over every candidate t in the bin:
 //     N - 2(C + c) + S + (N - C) t_min^2.
-// Bins whose lower bound exceeds the best exact value seen are discarded and
-// the next round refines the key range spanned by the surviving bins.  When
-// the bins have width 1 every bin holds one distinct value and the search is
-// exact; the smallest minimising candidate is returned.
+// Bins whose lower bound exceeds the best exact value seen are discarded.
+// When the surviving bins hold at most kSureCap values, the next pass
+// collects exactly those values and the select kernel finishes exactly: it
+// sorts them in LDS and evaluates SURE at every one from the counts below
+// each bin and prefix sums inside it.  Otherwise the next round refines the
+// key range spanned by the surviving bins (bins of width 1 are exact too).
+// The smallest minimising candidate is returned.
 #include "hyres_internal.hpp"
 
 namespace hyres {
@@ -83,8 +86,55 @@ __global__ void k_sure_init(const CubeDesc* __restrict__ descs, const int* __res
             st.round = 0;
             st.done = 0;
             st.inexact = 0;
-            st.pad = 0;
+            st.gather = 0;
+            st.ncand = 0;
+            st.nsurv = 0;
             d.sst[comp] = st;
+        }
+    }
+}
+
+// Collect the magnitudes that fall in surviving bins (bitmap) into the
+// candidate list of the component (order is irrelevant: they are sorted).
+template <typename T>
+__device__ void sure_gather(const CubeDesc& d, int comp, int chunk, int64_t N, const SureState& st,
+                            uint32_t* lds_bits) {
+    typedef KeyTraits<T> KT;
+    typedef typename KT::K K;
+    __shared__ unsigned int s_n, s_base;
+    __syncthreads();
+    for (int w = threadIdx.x; w < kSureBins / 32; w += kSureThreads)
+        lds_bits[w] = d.sbits[(int64_t)comp * (kSureBins / 32) + w];
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const T* cf = static_cast<const T*>(d.coef) + (int64_t)comp * d.ncs;
+    const int64_t e0 = (int64_t)chunk * kSureChunk;
+    const int64_t e1 = e0 + kSureChunk < N ? e0 + kSureChunk : N;
+    const uint64_t klo = st.klo, khi = st.khi;
+    const int sh = (int)st.width;
+    // first pass: count, second pass: write (keeps the append contiguous per block)
+    unsigned int mine = 0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kSureThreads) {
+        const K k = KT::key(cf[e]);
+        if ((uint64_t)k >= klo && (uint64_t)k < khi) {
+            const int b = (int)(((uint64_t)k - klo) >> sh);
+            mine += (lds_bits[b >> 5] >> (b & 31)) & 1u;
+        }
+    }
+    const unsigned int off = atomicAdd(&s_n, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(&d.sst[comp].ncand, s_n) : 0u;
+    __syncthreads();
+    unsigned int pos = s_base + off;
+    uint64_t* out = d.cand + (int64_t)comp * kSureCap;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kSureThreads) {
+        const K k = KT::key(cf[e]);
+        if ((uint64_t)k >= klo && (uint64_t)k < khi) {
+            const int b = (int)(((uint64_t)k - klo) >> sh);
+            if ((lds_bits[b >> 5] >> (b & 31)) & 1u) {
+                if (pos < (unsigned)kSureCap) out[pos] = (uint64_t)k;
+                ++pos;
+            }
         }
     }
 }
@@ -109,6 +159,10 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_hist(const CubeDesc* __re
         const int chunk = local - comp * nch;
         const SureState st = d.sst[comp];
         if (st.done) continue;   // uniform across the block
+        if (st.gather) {
+            sure_gather<T>(d, comp, chunk, N, st, reinterpret_cast<uint32_t*>(lc));
+            continue;
+        }
         __syncthreads();
         for (int b = threadIdx.x; b < kSureBins; b += kSureThreads) {
             lc[b] = 0;
@@ -162,28 +216,144 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_hist(const CubeDesc* __re
     }
 }
 
-// One block per component: exact prefix sums, bounds, survivors, next range.
+constexpr int kSelThreads = 1024;
+
+// Exact finish of a component from its collected candidates (LDS sort).
 template <typename T>
-__global__ __launch_bounds__(kSureThreads) void k_sure_select(const CubeDesc* __restrict__ descs,
-                                                              const int* __restrict__ items, int ncubes) {
+__device__ void sure_finish(const CubeDesc& d, int comp, SureState& st, double N, double* raw) {
     typedef KeyTraits<T> KT;
-    constexpr int PER = kSureBins / kSureThreads;   // bins per thread
-    __shared__ unsigned long long s_cnt[kSureThreads];
-    __shared__ double s_sum[kSureThreads];
-    __shared__ double s_bs[kSureThreads];
-    __shared__ double s_bt[kSureThreads];
-    __shared__ int s_f[kSureThreads], s_l[kSureThreads];
+    uint64_t* keys = reinterpret_cast<uint64_t*>(raw);     // kSureCap
+    double* pre = raw + kSureCap;                           // kSureCap
+    __shared__ double s_tot[kSelThreads];
+    __shared__ double s_bs2[kSelThreads], s_bt2[kSelThreads];
+    const int tid = threadIdx.x;
+    const unsigned int nc = st.ncand < (unsigned)kSureCap ? st.ncand : (unsigned)kSureCap;
+    int n2 = 2;
+    while (n2 < (int)nc) n2 <<= 1;
+    const uint64_t* src = d.cand + (int64_t)comp * kSureCap;
+    for (int i = tid; i < n2; i += kSelThreads) keys[i] = i < (int)nc ? src[i] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < n2; i += kSelThreads) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = keys[i], b = keys[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        keys[i] = b;
+                        keys[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // inclusive prefix sums of squares: per-thread runs, then a scan of run totals
+    const int per = (n2 + kSelThreads - 1) / kSelThreads;
+    const int i0 = tid * per;
+    double run = 0.0;
+    for (int i = i0; i < i0 + per && i < n2; ++i) {
+        const double v = i < (int)nc ? KT::val(keys[i]) : 0.0;
+        run += v * v;
+        pre[i] = run;
+    }
+    s_tot[tid] = run;
+    __syncthreads();
+    for (int o = 1; o < kSelThreads; o <<= 1) {
+        const double add = tid >= o ? s_tot[tid - o] : 0.0;
+        __syncthreads();
+        s_tot[tid] += add;
+        __syncthreads();
+    }
+    const double before = tid > 0 ? s_tot[tid - 1] : 0.0;
+    for (int i = i0; i < i0 + per && i < n2; ++i) pre[i] += before;
+    __syncthreads();
+    const uint64_t klo = st.klo;
+    const int sh = (int)st.width;
+    double bs = __builtin_inf(), bt = 0.0;
+    for (int j = tid; j < (int)nc; j += kSelThreads) {
+        const uint64_t key = keys[j];
+        const double v = KT::val(key);
+        const int b = (int)((key - klo) >> sh);
+        const int64_t base = (int64_t)comp * kSureBins + b;
+        const unsigned int c0 = d.scb[base];
+        const double c = (double)d.spre[base] + (double)(j + 1 - (int)c0);
+        const double S = d.sspre[base] + (pre[j] - (c0 > 0 ? pre[c0 - 1] : 0.0));
+        const double sv = N - 2.0 * c + S + (N - c) * v * v;
+        if (sv < bs || (sv == bs && v < bt)) {
+            bs = sv;
+            bt = v;
+        }
+    }
+    s_bs2[tid] = bs;
+    s_bt2[tid] = bt;
+    __syncthreads();
+    for (int o = kSelThreads / 2; o >= 1; o >>= 1) {
+        if (tid < o) {
+            const double ob = s_bs2[tid + o], ot = s_bt2[tid + o];
+            if (ob < s_bs2[tid] || (ob == s_bs2[tid] && ot < s_bt2[tid])) {
+                s_bs2[tid] = ob;
+                s_bt2[tid] = ot;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double b_s = s_bs2[0], b_t = s_bt2[0];
+        if (st.best_s < b_s || (st.best_s == b_s && st.best_t < b_t)) {
+            b_s = st.best_s;
+            b_t = st.best_t;
+        }
+        st.best_s = b_s;
+        st.best_t = b_t;
+        st.done = 1;
+        if (st.ncand != st.nsurv) st.inexact = 1;
+    }
+}
+
+// One block per component: exact prefix sums, bounds, survivors, then either
+// the next range, a gather of the surviving values, or (after a gather) the
+// exact finish.
+template <typename T>
+__global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __restrict__ descs,
+                                                             const int* __restrict__ items, int ncubes) {
+    typedef KeyTraits<T> KT;
+    constexpr int PER = kSureBins / kSelThreads;   // bins per thread
+    __shared__ double raw[2 * kSureCap];           // finish: keys + prefix sums; select: scratch below
+    __shared__ SureState s_st;
+    unsigned long long* s_cnt = reinterpret_cast<unsigned long long*>(raw);
+    double* s_sum = raw + kSelThreads;
+    double* s_bs = raw + 2 * kSelThreads;
+    double* s_bt = raw + 3 * kSelThreads;
+    int* s_f = reinterpret_cast<int*>(raw + 4 * kSelThreads);
+    int* s_l = s_f + kSelThreads;
+    unsigned long long* s_m = reinterpret_cast<unsigned long long*>(raw + 5 * kSelThreads);
     const int total = items[ncubes];
+    const int tid = threadIdx.x;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int c = find_cube(items, ncubes, item);
         const CubeDesc& d = descs[c];
         const int comp = item - items[c];
-        SureState st = d.sst[comp];
         __syncthreads();
-        if (st.done) continue;
+        if (tid == 0) s_st = d.sst[comp];
+        __syncthreads();
+        if (s_st.done) continue;
         const double N = (double)sure_count(d);
         const int64_t base = (int64_t)comp * kSureBins;
-        const int tid = threadIdx.x;
+        if (s_st.gather) {
+            sure_finish<T>(d, comp, s_st, N, raw);
+            __syncthreads();
+            if (tid == 0) {
+                s_st.round += 1;
+                d.lambda[comp] = s_st.best_t;
+                if (d.sure) d.sure[comp] = s_st.best_s;
+                if (s_st.inexact) set_status(d.status, HYRES_DEV_SURE_INEXACT);
+                d.sst[comp] = s_st;
+            }
+            continue;
+        }
+        const SureState st = s_st;
         uint32_t cnt[PER];
         double sum[PER];
         uint64_t kmin[PER], kmax[PER];
@@ -203,7 +373,7 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_select(const CubeDesc* __
         s_cnt[tid] = tc;
         s_sum[tid] = ts;
         __syncthreads();
-        for (int o = 1; o < kSureThreads; o <<= 1) {
+        for (int o = 1; o < kSelThreads; o <<= 1) {
             const unsigned long long ac = tid >= o ? s_cnt[tid - o] : 0ull;
             const double as = tid >= o ? s_sum[tid - o] : 0.0;
             __syncthreads();
@@ -242,11 +412,10 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_select(const CubeDesc* __
             pc += cnt[j];
             ps += sum[j];
         }
-        // block argmin of (S, t)
         s_bs[tid] = bs;
         s_bt[tid] = bt;
         __syncthreads();
-        for (int o = kSureThreads / 2; o >= 1; o >>= 1) {
+        for (int o = kSelThreads / 2; o >= 1; o >>= 1) {
             if (tid < o) {
                 const double ob = s_bs[tid + o], ot = s_bt[tid + o];
                 if (ob < s_bs[tid] || (ob == s_bs[tid] && ot < s_bt[tid])) {
@@ -263,18 +432,30 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_select(const CubeDesc* __
         }
         const double U = best_s + 1e-12 * (fabs(best_s) + N);
         int f = 0x7fffffff, l = -1;
+        unsigned long long m = 0;
+        bool surv[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            if (cnt[j] && lbv[j] <= U) {
+            surv[j] = cnt[j] && lbv[j] <= U;
+            if (surv[j]) {
                 const int b = tid * PER + j;
                 f = b < f ? b : f;
                 l = b > l ? b : l;
+                m += cnt[j];
             }
         }
         s_f[tid] = f;
         s_l[tid] = l;
+        s_m[tid] = m;
         __syncthreads();
-        for (int o = kSureThreads / 2; o >= 1; o >>= 1) {
+        // inclusive scan of surviving counts (for the candidate offsets) and min/max of f, l
+        for (int o = 1; o < kSelThreads; o <<= 1) {
+            const unsigned long long am = tid >= o ? s_m[tid - o] : 0ull;
+            __syncthreads();
+            s_m[tid] += am;
+            __syncthreads();
+        }
+        for (int o = kSelThreads / 2; o >= 1; o >>= 1) {
             if (tid < o) {
                 s_f[tid] = s_f[tid + o] < s_f[tid] ? s_f[tid + o] : s_f[tid];
                 s_l[tid] = s_l[tid + o] > s_l[tid] ? s_l[tid + o] : s_l[tid];
@@ -282,8 +463,27 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_select(const CubeDesc* __
             __syncthreads();
         }
         const int fb = s_f[0], lb = s_l[0];
+        const unsigned long long msurv = s_m[kSelThreads - 1];
+        const bool gather = lb >= 0 && st.width > 0 && msurv <= (unsigned long long)kSureCap;
+        if (gather) {
+            // bitmap, counts below each surviving bin, and collected-value offsets
+            unsigned long long mo = s_m[tid] - m;
+            for (int w = tid; w < kSureBins / 32; w += kSelThreads) d.sbits[(int64_t)comp * (kSureBins / 32) + w] = 0u;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (surv[j]) {
+                    const int b = tid * PER + j;
+                    atomicOr(&d.sbits[(int64_t)comp * (kSureBins / 32) + (b >> 5)], 1u << (b & 31));
+                    d.spre[base + b] = st.below_cnt + pcs[j];
+                    d.sspre[base + b] = st.below_sum + pss[j];
+                    d.scb[base + b] = (uint32_t)mo;
+                    mo += cnt[j];
+                }
+            }
+        }
         // the prefix before the first surviving bin
-        if (tid == fb / PER && fb != 0x7fffffff) {
+        if (!gather && tid == fb / PER && fb != 0x7fffffff) {
             const int j = fb - tid * PER;
             unsigned long long c0 = 0;
             double s0 = 0.0;
@@ -293,38 +493,40 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_select(const CubeDesc* __
                     c0 = pcs[jj];
                     s0 = pss[jj];
                 }
-            s_cnt[0] = c0;   // reuse (everyone has read s_cnt[tid] already)
-            s_sum[0] = s0;
+            s_st.below_cnt = st.below_cnt + c0;
+            s_st.below_sum = st.below_sum + s0;
         }
         __syncthreads();
         if (tid == 0) {
-            st.best_s = best_s;
-            st.best_t = best_t;
-            st.round += 1;
+            SureState ns = s_st;
+            ns.best_s = best_s;
+            ns.best_t = best_t;
+            ns.round = st.round + 1;
             if (st.width == 0 || lb < 0) {
-                st.done = 1;
+                ns.done = 1;
+            } else if (gather) {
+                ns.gather = 1;
+                ns.ncand = 0;
+                ns.nsurv = (unsigned int)msurv;
             } else {
-                const uint64_t klo = st.klo;
-                st.below_cnt += s_cnt[0];
-                st.below_sum += s_sum[0];
-                st.klo = klo + ((uint64_t)fb << st.width);
-                const uint64_t hi = klo + ((uint64_t)(lb + 1) << st.width);
-                st.khi = hi < st.khi ? hi : st.khi;
-                st.width = sure_shift_for(st.khi - st.klo);
-                if (st.round >= KT::kRounds) {
-                    st.done = 1;
-                    st.inexact = 1;
+                ns.klo = st.klo + ((uint64_t)fb << st.width);
+                const uint64_t hi = st.klo + ((uint64_t)(lb + 1) << st.width);
+                ns.khi = hi < st.khi ? hi : st.khi;
+                ns.width = sure_shift_for(ns.khi - ns.klo);
+                if (ns.round >= KT::kRounds) {
+                    ns.done = 1;
+                    ns.inexact = 1;
                 }
             }
-            if (st.done) {
-                d.lambda[comp] = best_t;
-                if (d.sure) d.sure[comp] = best_s;
-                if (st.inexact) set_status(d.status, HYRES_DEV_SURE_INEXACT);
+            if (ns.done) {
+                d.lambda[comp] = ns.best_t;
+                if (d.sure) d.sure[comp] = ns.best_s;
+                if (ns.inexact) set_status(d.status, HYRES_DEV_SURE_INEXACT);
             }
-            d.sst[comp] = st;
+            d.sst[comp] = ns;
         }
         // clear the bins for the next round
-        for (int b = tid; b < kSureBins; b += kSureThreads) {
+        for (int b = tid; b < kSureBins; b += kSelThreads) {
             d.hcnt[base + b] = 0;
             d.hsum[base + b] = 0.0;
             d.hmin[base + b] = ~0ull;
@@ -347,15 +549,17 @@ hipError_t launch_sure_round(int dtype, const CubeDesc* descs, const int* hist_i
                              int ncubes, int hist_grid, int sel_grid, hipStream_t s) {
     if (dtype == HYRES_F64) {
         hipLaunchKernelGGL(k_sure_hist<double>, dim3(hist_grid), dim3(kSureThreads), 0, s, descs, hist_items, ncubes);
-        hipLaunchKernelGGL(k_sure_select<double>, dim3(sel_grid), dim3(kSureThreads), 0, s, descs, sel_items, ncubes);
+        hipLaunchKernelGGL(k_sure_select<double>, dim3(sel_grid), dim3(kSelThreads), 0, s, descs, sel_items, ncubes);
     } else {
         hipLaunchKernelGGL(k_sure_hist<float>, dim3(hist_grid), dim3(kSureThreads), 0, s, descs, hist_items, ncubes);
-        hipLaunchKernelGGL(k_sure_select<float>, dim3(sel_grid), dim3(kSureThreads), 0, s, descs, sel_items, ncubes);
+        hipLaunchKernelGGL(k_sure_select<float>, dim3(sel_grid), dim3(kSelThreads), 0, s, descs, sel_items, ncubes);
     }
     return hipGetLastError();
 }
 
-int sure_rounds(int dtype) { return dtype == HYRES_F64 ? kSureRoundsF64 : kSureRoundsF32; }
+// One more pass than refinement rounds, so a gather decided in the last
+// refinement round is still finished.
+int sure_rounds(int dtype) { return (dtype == HYRES_F64 ? kSureRoundsF64 : kSureRoundsF32) + 1; }
 int sure_chunk() { return kSureChunk; }
 
 }  // namespace hyres

@@ -144,7 +144,7 @@ struct CubePlan {
     size_t o_gpart = 0, o_G = 0, o_sigma = 0, o_hv = 0, o_V = 0, o_evals = 0, o_gap = 0, o_P32 = 0, o_Q32 = 0,
            o_P64 = 0, o_Q64 = 0, o_Z = 0, o_coef = 0, o_tmp = 0, o_hcnt = 0, o_hsum = 0, o_hmin = 0,
            o_hmax = 0, o_sst = 0, o_lambda = 0, o_sure = 0, o_sbits = 0, o_spre = 0, o_sspre = 0, o_scb = 0,
-           o_cand = 0;
+           o_cand = 0, o_sfill = 0;
 };
 
 int esize(int dtype) { return dtype == HYRES_F64 ? 8 : 4; }
@@ -213,6 +213,7 @@ void plan_cube(CubePlan& c, Layout& lay, int parts) {
         c.o_spre = lay.add(nb * 8);
         c.o_sspre = lay.add(nb * 8);
         c.o_scb = lay.add(nb * 4);
+        c.o_sfill = lay.add(nb * 4);
         c.o_cand = lay.add((size_t)c.r * kSureCap * 8);
         c.o_lambda = lay.add((size_t)c.r * 8);
         c.o_sure = lay.add((size_t)c.r * 8);
@@ -273,6 +274,7 @@ CubeDesc make_desc(const CubePlan& c, void* ws) {
         d.spre = at<uint64_t>(ws, c.o_spre);
         d.sspre = at<double>(ws, c.o_sspre);
         d.scb = at<uint32_t>(ws, c.o_scb);
+        d.sfill = at<uint32_t>(ws, c.o_sfill);
         d.cand = at<uint64_t>(ws, c.o_cand);
         d.lambda = at<double>(ws, c.o_lambda);
         d.sure = at<double>(ws, c.o_sure);

@@ -13,7 +13,7 @@ constexpr int kMaxLevels = 8;
 constexpr int kMaxRank = 16;
 constexpr int kMaxBands = 224;        // FP64 small solver keeps a 224 x 224 matrix in registers
 constexpr int kSureBins = 4096;       // histogram bins per refinement round
-constexpr int kSureRoundsF32 = 8;     // 31-bit keys, >= 12 bits resolved per round when narrow
+constexpr int kSureRoundsF32 = 5;     // 31-bit keys, >= 12 bits resolved per round when narrow
 constexpr int kSureRoundsF64 = 10;    // 63-bit keys
 constexpr int kGramThreads = 512;
 constexpr int kSmallThreads = 1024;
@@ -43,6 +43,7 @@ struct SureState {
 };
 
 constexpr int kSureCap = 8192;        // values finished exactly in one block
+constexpr int kSureBinCap = 1024;     // largest surviving bin the exact finish accepts
 
 // Everything a kernel needs to know about one cube.  Pointers are device pointers.
 struct CubeDesc {
@@ -76,6 +77,7 @@ struct CubeDesc {
     uint64_t* spre;                         // r x kSureBins: values below each bin (gather round)
     double* sspre;                          // r x kSureBins: their sum of squares
     uint32_t* scb;                          // r x kSureBins: collected values in earlier surviving bins
+    uint32_t* sfill;                        // r x kSureBins: values collected per surviving bin
     uint64_t* cand;                         // r x kSureCap collected magnitudes (keys)
     double* lambda; double* sure;           // r
     const double* lambda_in;                // optional caller thresholds

@@ -95,45 +95,31 @@ __global__ void k_sure_init(const CubeDesc* __restrict__ descs, const int* __res
 }
 
 // Collect the magnitudes that fall in surviving bins (bitmap) into the
-// candidate list of the component (order is irrelevant: they are sorted).
+// candidate list of the component, grouped by bin: bin b owns the segment
+// starting at scb[b] (order inside a segment is irrelevant).
 template <typename T>
 __device__ void sure_gather(const CubeDesc& d, int comp, int chunk, int64_t N, const SureState& st,
                             uint32_t* lds_bits) {
     typedef KeyTraits<T> KT;
     typedef typename KT::K K;
-    __shared__ unsigned int s_n, s_base;
     __syncthreads();
     for (int w = threadIdx.x; w < kSureBins / 32; w += kSureThreads)
         lds_bits[w] = d.sbits[(int64_t)comp * (kSureBins / 32) + w];
-    if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     const T* cf = static_cast<const T*>(d.coef) + (int64_t)comp * d.ncs;
     const int64_t e0 = (int64_t)chunk * kSureChunk;
     const int64_t e1 = e0 + kSureChunk < N ? e0 + kSureChunk : N;
     const uint64_t klo = st.klo, khi = st.khi;
     const int sh = (int)st.width;
-    // first pass: count, second pass: write (keeps the append contiguous per block)
-    unsigned int mine = 0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kSureThreads) {
-        const K k = KT::key(cf[e]);
-        if ((uint64_t)k >= klo && (uint64_t)k < khi) {
-            const int b = (int)(((uint64_t)k - klo) >> sh);
-            mine += (lds_bits[b >> 5] >> (b & 31)) & 1u;
-        }
-    }
-    const unsigned int off = atomicAdd(&s_n, mine);
-    __syncthreads();
-    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(&d.sst[comp].ncand, s_n) : 0u;
-    __syncthreads();
-    unsigned int pos = s_base + off;
+    const int64_t base = (int64_t)comp * kSureBins;
     uint64_t* out = d.cand + (int64_t)comp * kSureCap;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kSureThreads) {
         const K k = KT::key(cf[e]);
         if ((uint64_t)k >= klo && (uint64_t)k < khi) {
             const int b = (int)(((uint64_t)k - klo) >> sh);
             if ((lds_bits[b >> 5] >> (b & 31)) & 1u) {
+                const unsigned int pos = d.scb[base + b] + atomicAdd(&d.sfill[base + b], 1u);
                 if (pos < (unsigned)kSureCap) out[pos] = (uint64_t)k;
-                ++pos;
             }
         }
     }
@@ -218,56 +204,19 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_hist(const CubeDesc* __re
 
 constexpr int kSelThreads = 1024;
 
-// Exact finish of a component from its collected candidates (LDS sort).
+// Exact finish of a component from its collected candidates: for every
+// candidate v in bin b, the count and sum of squares of the values <= v are
+// the totals below the bin plus those of the bin's own values <= v (a scan of
+// the bin's segment, at most kSureBinCap values).
 template <typename T>
 __device__ void sure_finish(const CubeDesc& d, int comp, SureState& st, double N, double* raw) {
     typedef KeyTraits<T> KT;
     uint64_t* keys = reinterpret_cast<uint64_t*>(raw);     // kSureCap
-    double* pre = raw + kSureCap;                           // kSureCap
-    __shared__ double s_tot[kSelThreads];
     __shared__ double s_bs2[kSelThreads], s_bt2[kSelThreads];
     const int tid = threadIdx.x;
     const unsigned int nc = st.ncand < (unsigned)kSureCap ? st.ncand : (unsigned)kSureCap;
-    int n2 = 2;
-    while (n2 < (int)nc) n2 <<= 1;
     const uint64_t* src = d.cand + (int64_t)comp * kSureCap;
-    for (int i = tid; i < n2; i += kSelThreads) keys[i] = i < (int)nc ? src[i] : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= n2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < n2; i += kSelThreads) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const uint64_t a = keys[i], b = keys[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        keys[i] = b;
-                        keys[ixj] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    // inclusive prefix sums of squares: per-thread runs, then a scan of run totals
-    const int per = (n2 + kSelThreads - 1) / kSelThreads;
-    const int i0 = tid * per;
-    double run = 0.0;
-    for (int i = i0; i < i0 + per && i < n2; ++i) {
-        const double v = i < (int)nc ? KT::val(keys[i]) : 0.0;
-        run += v * v;
-        pre[i] = run;
-    }
-    s_tot[tid] = run;
-    __syncthreads();
-    for (int o = 1; o < kSelThreads; o <<= 1) {
-        const double add = tid >= o ? s_tot[tid - o] : 0.0;
-        __syncthreads();
-        s_tot[tid] += add;
-        __syncthreads();
-    }
-    const double before = tid > 0 ? s_tot[tid - 1] : 0.0;
-    for (int i = i0; i < i0 + per && i < n2; ++i) pre[i] += before;
+    for (int i = tid; i < (int)nc; i += kSelThreads) keys[i] = src[i];
     __syncthreads();
     const uint64_t klo = st.klo;
     const int sh = (int)st.width;
@@ -276,10 +225,19 @@ __device__ void sure_finish(const CubeDesc& d, int comp, SureState& st, double N
         const uint64_t key = keys[j];
         const double v = KT::val(key);
         const int b = (int)((key - klo) >> sh);
-        const int64_t base = (int64_t)comp * kSureBins + b;
-        const unsigned int c0 = d.scb[base];
-        const double c = (double)d.spre[base] + (double)(j + 1 - (int)c0);
-        const double S = d.sspre[base] + (pre[j] - (c0 > 0 ? pre[c0 - 1] : 0.0));
+        const int64_t bi = (int64_t)comp * kSureBins + b;
+        const unsigned int s0 = d.scb[bi], s1 = s0 + d.sfill[bi];
+        double cw = 0.0, sw = 0.0;
+        for (unsigned int i = s0; i < s1 && i < nc; ++i) {
+            const uint64_t ki = keys[i];
+            if (ki <= key) {
+                const double vi = KT::val(ki);
+                cw += 1.0;
+                sw = fma(vi, vi, sw);
+            }
+        }
+        const double c = (double)d.spre[bi] + cw;
+        const double S = d.sspre[bi] + sw;
         const double sv = N - 2.0 * c + S + (N - c) * v * v;
         if (sv < bs || (sv == bs && v < bt)) {
             bs = sv;
@@ -320,8 +278,9 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
                                                              const int* __restrict__ items, int ncubes) {
     typedef KeyTraits<T> KT;
     constexpr int PER = kSureBins / kSelThreads;   // bins per thread
-    __shared__ double raw[2 * kSureCap];           // finish: keys + prefix sums; select: scratch below
+    __shared__ double raw[kSureCap];               // finish: keys; select: scratch below
     __shared__ SureState s_st;
+    __shared__ unsigned int s_mx;
     unsigned long long* s_cnt = reinterpret_cast<unsigned long long*>(raw);
     double* s_sum = raw + kSelThreads;
     double* s_bs = raw + 2 * kSelThreads;
@@ -433,6 +392,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
         const double U = best_s + 1e-12 * (fabs(best_s) + N);
         int f = 0x7fffffff, l = -1;
         unsigned long long m = 0;
+        unsigned int mx = 0;
         bool surv[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -442,12 +402,15 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
                 f = b < f ? b : f;
                 l = b > l ? b : l;
                 m += cnt[j];
+                mx = cnt[j] > mx ? cnt[j] : mx;
             }
         }
         s_f[tid] = f;
         s_l[tid] = l;
         s_m[tid] = m;
+        if (tid == 0) s_mx = 0;
         __syncthreads();
+        if (mx) atomicMax(&s_mx, mx);
         // inclusive scan of surviving counts (for the candidate offsets) and min/max of f, l
         for (int o = 1; o < kSelThreads; o <<= 1) {
             const unsigned long long am = tid >= o ? s_m[tid - o] : 0ull;
@@ -464,12 +427,15 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
         }
         const int fb = s_f[0], lb = s_l[0];
         const unsigned long long msurv = s_m[kSelThreads - 1];
-        const bool gather = lb >= 0 && st.width > 0 && msurv <= (unsigned long long)kSureCap;
+        const bool gather = lb >= 0 && st.width > 0 && msurv <= (unsigned long long)kSureCap &&
+                            s_mx <= (unsigned)kSureBinCap;
         if (gather) {
             // bitmap, counts below each surviving bin, and collected-value offsets
             unsigned long long mo = s_m[tid] - m;
             for (int w = tid; w < kSureBins / 32; w += kSelThreads) d.sbits[(int64_t)comp * (kSureBins / 32) + w] = 0u;
             __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PER; ++j) d.sfill[base + tid * PER + j] = 0u;
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
                 if (surv[j]) {

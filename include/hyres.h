@@ -192,6 +192,138 @@ hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int W, int p,
                            int64_t x_row_pitch, const hyres_outputs* out,
                            void* workspace, size_t workspace_bytes, hyres_stream_t stream);
 
+/* ---- batches of cubes ---------------------------------------------------- */
+
+/* One cube of a batch.  The struct itself is host memory; Y, X, sigma_in,
+ * lambda_in and the pointers in `out` are device pointers with the meaning
+ * they have in hyres_denoise.  Cubes may differ in H, W, p, rank and levels. */
+typedef struct {
+    const void* Y; int H, W, p; int64_t pitch, row_pitch;
+    void* X; int64_t x_pitch, x_row_pitch;
+    int rank, levels;
+    const double* sigma_in;    /* [p] or NULL: estimate */
+    const double* lambda_in;   /* [rank] or NULL: SURE */
+    hyres_outputs out;
+} hyres_cube;
+
+/* A planned batch: the solve of `count` independent cubes as one sequence of
+ * persistent launches (each kernel class is one launch over a prefix-summed
+ * list of work items spanning every cube of the class), with the noise
+ * regression and eigensolve of every cube in one launch per band-count class.
+ * Each cube's results equal those of hyres_denoise on that cube alone.
+ * All cubes share dtype and opt's precision, scope and flags (opt's rank and
+ * levels are not used: each cube carries its own). */
+typedef struct hyres_batch hyres_batch;
+
+/* Workspace of a batch; only the shape fields of `cubes` are read (host array). */
+hyres_status hyres_batch_workspace_size(const hyres_cube* cubes, int count, int dtype,
+                                        const hyres_options* opt, size_t* bytes);
+/* Validates and plans the batch and writes its descriptor and work tables
+ * into `workspace` (stream-ordered on `stream`).  The host object keeps the
+ * plan; the workspace belongs to the batch until hyres_batch_destroy, and the
+ * cubes' device buffers must stay valid as long as the batch is run. */
+hyres_status hyres_batch_create(hyres_handle* h, const hyres_cube* cubes, int count, int dtype,
+                                const hyres_options* opt, void* workspace, size_t workspace_bytes,
+                                hyres_stream_t stream, hyres_batch** batch);
+/* Enqueues one solve of every cube on `stream` (no host synchronisation). */
+hyres_status hyres_batch_run(hyres_batch* batch, hyres_stream_t stream);
+/* Launches the solve as one HIP graph: the first call captures the launch
+ * sequence on a private stream and instantiates it (host work only), every
+ * call then launches the graph on `stream`.  Run calls on one batch in stream
+ * order: the replays share the workspace. */
+hyres_status hyres_batch_launch_graph(hyres_batch* batch, hyres_stream_t stream);
+void hyres_batch_destroy(hyres_batch* batch);
+/* One-shot batched solve: create, run, destroy. */
+hyres_status hyres_denoise_batched(hyres_handle* h, const hyres_cube* cubes, int count, int dtype,
+                                   const hyres_options* opt, void* workspace, size_t workspace_bytes,
+                                   hyres_stream_t stream);
+
+/* ---- sliding-window denoising ------------------------------------------- */
+
+/* Tile starts along an axis of length `size`: 0, tile - overlap, 2 (tile -
+ * overlap), ..., the last start clamped to size - tile so that the last tile
+ * ends at the border (one tile at 0 when tile >= size).  starts: host array of
+ * up to 64 ints, or NULL to query `count` only.  Needs tile >= 4 and
+ * 0 <= 2 overlap <= tile; more than 64 tiles is HYRES_E_UNSUPPORTED. */
+hyres_status hyres_tile_grid(int size, int tile, int overlap, int* starts, int* count);
+
+/* X = sum_t w_t HyRes(Y_t) / sum_t w_t over the grid of min(tile,H) x
+ * min(tile,W) tiles Y_t of Y (starts from hyres_tile_grid on each axis), each
+ * denoised independently (own noise estimate, subspace and thresholds, rank
+ * and levels from opt).  w_t is separable; along an axis it is 1 except for
+ * sin^2(pi/2 (k + 1/2) / overlap) ramps over the first and the last `overlap`
+ * samples of the tile, with no ramp on a side that touches the image border.
+ * All tiles run as one batch (tiles are addressed in place through pitch and
+ * row_pitch, nothing is copied); the back-projection applies the blend, in
+ * passes of non-overlapping tiles so that the sums are formed in a fixed
+ * order.  lambda_out [ntiles * rank] and sigma_out [ntiles * p] (device
+ * double, tile t = row-major index over the grid) may be NULL. */
+hyres_status hyres_tiled_workspace_size(int H, int W, int p, int tile, int overlap,
+                                        const hyres_options* opt, int dtype, size_t* bytes);
+hyres_status hyres_denoise_tiled(hyres_handle* h, const void* Y, int H, int W, int p,
+                                 int64_t pitch, int64_t row_pitch, int dtype, int tile, int overlap,
+                                 const hyres_options* opt, void* X, int64_t x_pitch,
+                                 int64_t x_row_pitch, double* lambda_out, double* sigma_out,
+                                 int* status, void* workspace, size_t workspace_bytes,
+                                 hyres_stream_t stream);
+
+/* ---- adjoint (reverse-mode derivative) ----------------------------------- */
+
+/* Vector-Jacobian product of X = HyRes(Y; lambda) with the thresholds held as
+ * inputs: given dX (same layout rules as Y) it writes dY = (dX/dY)^T dX
+ * (through the noise estimate, the whitening, the eigenvectors, the
+ * projections, the transforms and the soft threshold) and dlambda [rank]
+ * (device double, may be NULL).  The forward call must have been
+ * hyres_denoise with the same Y, shape, opt and dtype, whose outputs
+ * sigma, V, evals and lambda were requested (fwd_out, device), and whose
+ * workspace has not been used since (it holds the band Gram, the
+ * coefficients and the denoised component images that the adjoint reads;
+ * the intermediate approximation levels of the transforms are recomputed).
+ * The SURE choice of the thresholds is piecewise constant in Y: with
+ * thresholds chosen by SURE the derivative is the one at fixed thresholds.
+ * The eigen-derivative needs simple top-r eigenvalues (a degenerate gap makes
+ * it unbounded).  The small systems are solved in FP64; a singular one sets
+ * HYRES_DEV_NOT_PD in `status`. */
+hyres_status hyres_denoise_backward_workspace_size(int H, int W, int p, const hyres_options* opt,
+                                                   int dtype, size_t* bytes);
+hyres_status hyres_denoise_backward(hyres_handle* h, const void* Y, int H, int W, int p,
+                                    int64_t pitch, int64_t row_pitch, int dtype,
+                                    const hyres_options* opt, const void* fwd_workspace,
+                                    size_t fwd_workspace_bytes, const hyres_outputs* fwd_out,
+                                    const void* dX, int64_t dx_pitch, int64_t dx_row_pitch,
+                                    void* dY, int64_t dy_pitch, int64_t dy_row_pitch,
+                                    double* dlambda, int* status, void* workspace,
+                                    size_t workspace_bytes, hyres_stream_t stream);
+
+/* Derivative of SURE(t) = Nc - 2 #{|b| <= t} + sum min(b^2, t^2) with respect
+ * to t at t = lambda_i, for each of `batch` coefficient vectors (stride
+ * `stride`): 2 lambda_i #{k : |b_k| > lambda_i} (the risk is piecewise
+ * quadratic in t; at a candidate t = |b_k| this is the right derivative).
+ * dsure_out: device double [batch]. */
+hyres_status hyres_sure_grad_workspace_size(int batch, int64_t Nc, size_t* bytes);
+hyres_status hyres_sure_grad(hyres_handle* h, const void* coeffs, int batch, int64_t Nc, int64_t stride,
+                             int dtype, const double* lambda, double* dsure_out, void* workspace,
+                             size_t workspace_bytes, hyres_stream_t stream);
+
+/* ---- DWT tile autotuner -------------------------------------------------- */
+
+/* Chooses, for every (element type, direction, level-width class) that the
+ * batch's transforms use, the workgroup tile shape of the transform kernels
+ * (64x4, 32x8, 16x16 or 128x2 threads) that runs fastest.  A level of width w
+ * belongs to class ceil(log2 w).  Choices found in the JSON file `cache_path`
+ * for this device are taken from it; the rest are timed with HIP events on the
+ * batch's own data (one solve, then each candidate per level) and written
+ * back to the file (NULL: no file).  The choices are kept in the handle and
+ * used by every later call on it; the batch is re-planned (its graph, if any,
+ * is captured again on its next launch).  Unlike the compute calls this one
+ * synchronises the host with `stream`; it must not be captured. */
+hyres_status hyres_autotune(hyres_handle* h, hyres_batch* batch, const char* cache_path,
+                            hyres_stream_t stream);
+/* The tile the handle uses for a level of width `width` (tuned: 1 if it came
+ * from the tuner or its cache, 0 for the built-in choice). */
+hyres_status hyres_tile_choice(hyres_handle* h, int dtype, int inverse, int width, int* tx, int* ty,
+                               int* tuned);
+
 /* ---- stage timing (benchmarks) ------------------------------------------ */
 
 /* Stages of a solve, as bit positions of the mask below. */

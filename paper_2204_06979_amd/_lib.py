@@ -34,7 +34,15 @@ class Outputs(C.Structure):
                 ("sure", C.c_void_p), ("gap", C.c_void_p), ("status", C.c_void_p)]
 
 
+class Cube(C.Structure):
+    _fields_ = [("Y", C.c_void_p), ("H", C.c_int), ("W", C.c_int), ("p", C.c_int), ("pitch", C.c_int64),
+                ("row_pitch", C.c_int64), ("X", C.c_void_p), ("x_pitch", C.c_int64), ("x_row_pitch", C.c_int64),
+                ("rank", C.c_int), ("levels", C.c_int), ("sigma_in", C.c_void_p), ("lambda_in", C.c_void_p),
+                ("out", Outputs)]
+
+
 vp, i32, i64, sz, dp = C.c_void_p, C.c_int, C.c_int64, C.c_size_t, C.c_void_p
+PI = C.POINTER(C.c_int)
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -56,6 +64,24 @@ SIGNATURES = {
     "hyres_profile_read": (i32, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "hyres_denoise": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp, vp, i64, i64,
                             C.POINTER(Outputs), vp, sz, vp]),
+    "hyres_batch_workspace_size": (i32, [C.POINTER(Cube), i32, i32, C.POINTER(Options), C.POINTER(sz)]),
+    "hyres_batch_create": (i32, [vp, C.POINTER(Cube), i32, i32, C.POINTER(Options), vp, sz, vp,
+                                 C.POINTER(C.c_void_p)]),
+    "hyres_batch_run": (i32, [vp, vp]),
+    "hyres_batch_launch_graph": (i32, [vp, vp]),
+    "hyres_batch_destroy": (None, [vp]),
+    "hyres_denoise_batched": (i32, [vp, C.POINTER(Cube), i32, i32, C.POINTER(Options), vp, sz, vp]),
+    "hyres_autotune": (i32, [vp, vp, C.c_char_p, vp]),
+    "hyres_tile_choice": (i32, [vp, i32, i32, i32, PI, PI, PI]),
+    "hyres_tile_grid": (i32, [i32, i32, i32, PI, PI]),
+    "hyres_tiled_workspace_size": (i32, [i32, i32, i32, i32, i32, C.POINTER(Options), i32, C.POINTER(sz)]),
+    "hyres_denoise_tiled": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, i32, i32, C.POINTER(Options), vp, i64,
+                                  i64, dp, dp, vp, vp, sz, vp]),
+    "hyres_denoise_backward_workspace_size": (i32, [i32, i32, i32, C.POINTER(Options), i32, C.POINTER(sz)]),
+    "hyres_denoise_backward": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), vp, sz,
+                                     C.POINTER(Outputs), vp, i64, i64, vp, i64, i64, dp, vp, vp, sz, vp]),
+    "hyres_sure_grad_workspace_size": (i32, [i32, i64, C.POINTER(sz)]),
+    "hyres_sure_grad": (i32, [vp, vp, i32, i64, i64, i32, dp, dp, vp, sz, vp]),
 }
 
 

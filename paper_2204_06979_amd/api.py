@@ -226,3 +226,233 @@ def denoise(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
     lm = None if lam is None else lam.to(device=Y.device, dtype=torch.float64).contiguous()
     X = dn.run(Y, sg, lm)
     return X, dn.info()
+
+
+class Batch:
+    """A planned batch of independent cubes (uneven H, W, p, rank, levels).
+
+    The library builds the descriptor and work tables once (``hyres_batch_create``);
+    ``run`` enqueues one solve of every cube as persistent launches,
+    ``launch_graph`` replays the same sequence as one HIP graph, and
+    ``autotune`` picks the transform tile shapes for this batch's level widths.
+    Outputs live in ``self.X[i]`` and ``self.info(i)``.
+    """
+
+    def __init__(self, cubes, ranks, levels, precision: str = "native", scope: str = "all",
+                 sigmas=None, lams=None, all_evals: bool = False):
+        if len(cubes) == 0:
+            raise ValueError("empty batch")
+        Y0 = cubes[0]
+        _need_cuda(Y0, "cube 0")
+        self.device = Y0.device
+        self.dtype = Y0.dtype
+        self.dt = _dtype_code(Y0)
+        count = len(cubes)
+        ranks = [int(ranks)] * count if isinstance(ranks, int) else [int(r) for r in ranks]
+        levels = [int(levels)] * count if isinstance(levels, int) else [int(l) for l in levels]
+        if len(ranks) != count or len(levels) != count:
+            raise ValueError("ranks and levels need one entry per cube")
+        self.opt = L.Options(0, 0, L.PREC_MIXED if precision == "mixed" else L.PREC_NATIVE,
+                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL,
+                             L.FLAG_ALL_EVALS if all_evals else 0)
+        dev = self.device
+        self.Y = list(cubes)
+        self.X, self._info, self._keep = [], [], []
+        arr = (L.Cube * count)()
+        for i, Y in enumerate(cubes):
+            _need_cuda(Y, "cube %d" % i)
+            if Y.dtype != self.dtype or Y.device != dev:
+                raise ValueError("every cube of a batch has the same dtype and device")
+            H, W, p = Y.shape
+            pitch, rp = _cube_strides(Y)
+            r = ranks[i]
+            X = torch.empty(H, W, p, dtype=self.dtype, device=dev)
+            inf = dict(sigma=torch.empty(p, dtype=torch.float64, device=dev),
+                       V=torch.empty(r, p, dtype=torch.float64, device=dev),
+                       evals=torch.empty(p, dtype=torch.float64, device=dev),
+                       lam=torch.empty(r, dtype=torch.float64, device=dev),
+                       sure=torch.empty(r, dtype=torch.float64, device=dev),
+                       gap=torch.empty(1, dtype=torch.float64, device=dev),
+                       status=torch.zeros(1, dtype=torch.int32, device=dev))
+            sg = None if sigmas is None or sigmas[i] is None else \
+                sigmas[i].to(device=dev, dtype=torch.float64).contiguous()
+            lm = None if lams is None or lams[i] is None else \
+                lams[i].to(device=dev, dtype=torch.float64).contiguous()
+            self._keep += [sg, lm]
+            out = L.Outputs(inf["sigma"].data_ptr(), inf["V"].data_ptr(), inf["evals"].data_ptr(),
+                            inf["lam"].data_ptr(), inf["sure"].data_ptr(), inf["gap"].data_ptr(),
+                            inf["status"].data_ptr())
+            xp, xrp = _cube_strides(X)
+            arr[i] = L.Cube(Y.data_ptr(), H, W, p, pitch, rp, X.data_ptr(), xp, xrp, r, levels[i],
+                            _ptr(sg), _ptr(lm), out)
+            self.X.append(X)
+            self._info.append(inf)
+        self._cubes = arr
+        lib = L.lib()
+        nb = C.c_size_t()
+        L.check(lib.hyres_batch_workspace_size(arr, count, self.dt, C.byref(self.opt), C.byref(nb)),
+                "batch workspace size")
+        self.ws_bytes = nb.value
+        self._buf, self._ws = _workspace(nb.value, dev)
+        self._h = _handle(dev)
+        bp = C.c_void_p()
+        L.check(lib.hyres_batch_create(self._h, arr, count, self.dt, C.byref(self.opt), self._ws, self.ws_bytes,
+                                       _stream(dev), C.byref(bp)), "hyres_batch_create")
+        self._b = bp.value
+
+    def run(self):
+        L.check(L.lib().hyres_batch_run(self._b, _stream(self.device)), "hyres_batch_run")
+        return self.X
+
+    def launch_graph(self):
+        L.check(L.lib().hyres_batch_launch_graph(self._b, _stream(self.device)), "hyres_batch_launch_graph")
+        return self.X
+
+    def autotune(self, cache_path: Optional[str] = None):
+        path = None if cache_path is None else cache_path.encode()
+        L.check(L.lib().hyres_autotune(self._h, self._b, path, _stream(self.device)), "hyres_autotune")
+
+    def info(self, i: int) -> Dict[str, torch.Tensor]:
+        d = dict(self._info[i])
+        d["V"] = d["V"].T
+        return d
+
+    def __del__(self):
+        b = getattr(self, "_b", None)
+        if b:
+            try:
+                L.lib().hyres_batch_destroy(b)
+            except Exception:   # interpreter shutdown
+                pass
+            self._b = None
+
+
+def denoise_batched(cubes, ranks, levels, precision: str = "native", scope: str = "all", graph: bool = False):
+    """Denoise a list of cubes in one batched solve; returns [(X, info), ...]."""
+    b = Batch(cubes, ranks, levels, precision=precision, scope=scope)
+    if graph:
+        b.launch_graph()
+    else:
+        b.run()
+    return [(b.X[i], b.info(i)) for i in range(len(cubes))], b
+
+
+def tile_choice(dtype: torch.dtype, inverse: bool, width: int, device=None):
+    """(tx, ty, tuned) the handle uses for a transform level of this width."""
+    dev = torch.device(device if device is not None else "cuda")
+    tx, ty, tu = C.c_int(), C.c_int(), C.c_int()
+    dt = L.HYRES_F64 if dtype == torch.float64 else L.HYRES_F32
+    L.check(L.lib().hyres_tile_choice(_handle(dev), dt, int(inverse), int(width), C.byref(tx), C.byref(ty),
+                                      C.byref(tu)), "hyres_tile_choice")
+    return tx.value, ty.value, bool(tu.value)
+
+
+def tile_grid(size: int, tile: int, overlap: int):
+    """Tile starts along one axis (the library's rule)."""
+    n = C.c_int()
+    buf = (C.c_int * 64)()
+    L.check(L.lib().hyres_tile_grid(size, tile, overlap, buf, C.byref(n)), "hyres_tile_grid")
+    return [buf[i] for i in range(n.value)]
+
+
+def denoise_tiled(Y: torch.Tensor, rank: int, levels: int, tile: int = 512, overlap: int = 32,
+                  precision: str = "native", scope: str = "all", X: Optional[torch.Tensor] = None):
+    """Sliding-window HyRes: every tile denoised independently, then blended.
+
+    Returns (X, info) with info["lam"] of shape (tiles, rank), info["sigma"]
+    (tiles, p) and the shared device status word.
+    """
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    pitch, rp = _cube_strides(Y)
+    dt = _dtype_code(Y)
+    opt = L.Options(rank, levels, L.PREC_MIXED if precision == "mixed" else L.PREC_NATIVE,
+                    L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL, 0)
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_tiled_workspace_size(H, W, p, tile, overlap, C.byref(opt), dt, C.byref(nb)),
+            "tiled workspace size")
+    buf, ws = _workspace(nb.value, Y.device)
+    nt = len(tile_grid(H, tile, overlap)) * len(tile_grid(W, tile, overlap))
+    lam = torch.empty(nt, rank, dtype=torch.float64, device=Y.device)
+    sig = torch.empty(nt, p, dtype=torch.float64, device=Y.device)
+    status = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    if X is None:
+        X = torch.empty(H, W, p, dtype=Y.dtype, device=Y.device)
+    xp, xrp = _cube_strides(X)
+    L.check(lib.hyres_denoise_tiled(_handle(Y.device), Y.data_ptr(), H, W, p, pitch, rp, dt, tile, overlap,
+                                    C.byref(opt), X.data_ptr(), xp, xrp, lam.data_ptr(), sig.data_ptr(),
+                                    status.data_ptr(), ws, nb.value, _stream(Y.device)), "hyres_denoise_tiled")
+    return X, dict(lam=lam, sigma=sig, status=status)
+
+
+# ------------------------------------------------------------------ adjoint
+def sure_grad(coeffs: torch.Tensor, lam: torch.Tensor) -> torch.Tensor:
+    """d SURE / d lambda_i at lambda_i for each row of a (B, N) tensor."""
+    _need_cuda(coeffs, "coeffs")
+    if coeffs.stride(1) != 1:
+        coeffs = coeffs.contiguous()
+    B, N = coeffs.shape
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_sure_grad_workspace_size(B, N, C.byref(nb)), "workspace size")
+    buf, ws = _workspace(nb.value, coeffs.device)
+    lm = lam.to(device=coeffs.device, dtype=torch.float64).contiguous()
+    out = torch.empty(B, dtype=torch.float64, device=coeffs.device)
+    row_stride = coeffs.stride(0) if B > 1 else N
+    L.check(lib.hyres_sure_grad(_handle(coeffs.device), coeffs.data_ptr(), B, N, row_stride, _dtype_code(coeffs),
+                                lm.data_ptr(), out.data_ptr(), ws, nb.value, _stream(coeffs.device)),
+            "hyres_sure_grad")
+    return out
+
+
+def denoise_backward(dn: "Denoiser", Y: torch.Tensor, dX: torch.Tensor):
+    """(dY, dlambda) of the solve last run by Denoiser ``dn`` on ``Y``."""
+    dX = dX.contiguous()
+    pitch, rp = _cube_strides(Y)
+    xp, xrp = _cube_strides(dX)
+    dY = torch.empty(dn.H, dn.W, dn.p, dtype=dn.dtype, device=dn.device)
+    yp, yrp = _cube_strides(dY)
+    dlam = torch.empty(dn.r, dtype=torch.float64, device=dn.device)
+    status = torch.zeros(1, dtype=torch.int32, device=dn.device)
+    lib = L.lib()
+    nb = C.c_size_t()
+    L.check(lib.hyres_denoise_backward_workspace_size(dn.H, dn.W, dn.p, C.byref(dn.opt), dn.dt, C.byref(nb)),
+            "backward workspace size")
+    buf, ws = _workspace(nb.value, dn.device)
+    L.check(lib.hyres_denoise_backward(_handle(dn.device), Y.data_ptr(), dn.H, dn.W, dn.p, pitch, rp, dn.dt,
+                                       C.byref(dn.opt), dn._ws, dn.ws_bytes, C.byref(dn.out), dX.data_ptr(), xp, xrp,
+                                       dY.data_ptr(), yp, yrp, dlam.data_ptr(), status.data_ptr(), ws, nb.value,
+                                       _stream(dn.device)), "hyres_denoise_backward")
+    return dY, dlam, status
+
+
+class HyResFunction(torch.autograd.Function):
+    """X = HyRes(Y; lambda) with a hand-written adjoint.
+
+    ``HyResFunction.apply(Y, lam, rank, levels, precision)``: lambda is a
+    tensor of per-component thresholds (an input, so it gets a gradient).
+    The forward keeps the solve's workspace (band Gram, coefficients and
+    denoised component images) for the backward.
+    """
+
+    @staticmethod
+    def forward(ctx, Y, lam, rank: int, levels: int, precision: str = "native"):
+        _need_cuda(Y, "Y")
+        H, W, p = Y.shape
+        dn = Denoiser(H, W, p, rank, levels, dtype=Y.dtype, precision=precision, device=Y.device)
+        lm = lam.detach().to(device=Y.device, dtype=torch.float64).contiguous()
+        Yc = Y.detach()
+        X = dn.run(Yc, None, lm).clone()
+        ctx.dn = dn
+        ctx.lam_keep = lm
+        ctx.save_for_backward(Yc)
+        ctx.lam_meta = (lam.dtype, lam.device)
+        return X
+
+    @staticmethod
+    def backward(ctx, dX):
+        (Y,) = ctx.saved_tensors
+        dY, dlam, status = denoise_backward(ctx.dn, Y, dX)
+        dt, dev = ctx.lam_meta
+        return dY, dlam.to(device=dev, dtype=dt), None, None, None

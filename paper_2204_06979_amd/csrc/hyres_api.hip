@@ -1,10 +1,21 @@
 // Host side of the C ABI: validation, workspace planning and the launch
 // sequence of each entry point.  No call allocates device memory or waits on
-// the host; cube descriptors and work-item tables are written into the
-// caller's workspace by a small kernel that receives them by value, so every
-// sequence can be captured in a HIP graph.
+// the host (hyres_autotune aside); cube descriptors and work-item tables are
+// written into the caller's workspace by a small kernel that receives them by
+// value, so every sequence can be captured in a HIP graph.
+//
+// Every entry point goes through one executor: a list of cubes (one for the
+// single-cube calls, many for a batch), their workspace plans and descriptors,
+// and a launch program.  Each launch of the program covers every cube of one
+// kernel class (the kernels that are specialised on the band count) with a
+// prefix-summed work-item table over the whole cube list, in which cubes
+// outside the class own no items; the kernels are persistent over that table.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <memory>
+#include <new>
+#include <string>
 #include <vector>
 
 #include "hyres_internal.hpp"
@@ -27,18 +38,46 @@ hipError_t launch_sure_init(int dtype, const CubeDesc*, const int*, int, int, hi
 hipError_t launch_sure_round(int dtype, const CubeDesc*, const int*, const int*, int, int, int, hipStream_t);
 int sure_rounds(int dtype);
 int sure_chunk();
+hipError_t launch_adjoint_pre(const AdjDesc&, int dtype, hipStream_t);
+hipError_t launch_adjoint_thresh(const AdjDesc&, int dtype, hipStream_t);
+hipError_t launch_adjoint_post(const AdjDesc&, int dtype, hipStream_t);
+hipError_t launch_sure_grad(int dtype, const void* coef, int64_t stride, int64_t N, int batch, const double* lambda,
+                            double* part, int nchunk, double* out, hipStream_t);
+int adj_chunk();
 }  // namespace hyres
 
 using namespace hyres;
 
+namespace {
+// DWT tile shapes (threads along x, along y) the autotuner chooses among; the
+// kernels are instantiated for exactly these.
+constexpr int kTileCands = 4;
+constexpr int kTileTX[kTileCands] = {64, 32, 16, 128};
+constexpr int kTileTY[kTileCands] = {4, 8, 16, 2};
+constexpr int kWidthClasses = 16;   // class of a level width w: ceil(log2 w), capped
+
+int width_class(int w) {
+    int b = 0;
+    while ((1 << b) < w && b < kWidthClasses - 1) ++b;
+    return b;
+}
+
+// Untuned choice: the widest tile that a level of this width fills.
+int default_tile(int wclass) { return wclass <= 4 ? 2 : (wclass == 5 ? 1 : 0); }
+}  // namespace
+
 struct hyres_handle {
     int device;
     int num_cu;
-    int dwt_tx, dwt_ty;
+    std::string arch;              // device key of the tuning cache
     unsigned prof_mask;
     struct Rec { int stage; hipEvent_t a, b; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
+    // DWT tile choice per [dtype][inverse][width class], and whether it was tuned
+    unsigned char tile[2][2][kWidthClasses];
+    unsigned char tuned[2][2][kWidthClasses];
+    float tile_us[2][2][kWidthClasses];
 };
 
 namespace {
@@ -53,7 +92,7 @@ hipEvent_t prof_event(hyres_handle* h) {
     return e;
 }
 
-// Scope object: records an event pair around one stage when it is profiled.
+// Records an event pair around one stage when that stage is profiled.
 struct StageTimer {
     hyres_handle* h;
     hipStream_t s;
@@ -62,14 +101,14 @@ struct StageTimer {
     StageTimer(hyres_handle* h_, hipStream_t s_, int st) : h(h_), s(s_), stage(st) {
         if (h->prof_mask & (1u << stage)) {
             a = prof_event(h);
-            if (a) hipEventRecord(a, s);
+            if (a) (void)hipEventRecord(a, s);
         }
     }
     ~StageTimer() {
         if (a) {
             hipEvent_t b = prof_event(h);
             if (b) {
-                hipEventRecord(b, s);
+                (void)hipEventRecord(b, s);
                 h->pending.push_back({stage, a, b});
             } else {
                 h->pool.push_back(a);
@@ -77,9 +116,6 @@ struct StageTimer {
         }
     }
 };
-}  // namespace
-
-namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kUploadBytes = 3072;
@@ -127,14 +163,6 @@ struct Layout {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
-// Work-item stages (one table of ncubes+1 prefix offsets each).
-enum Stage {
-    ST_GRAM = 0, ST_PROJ, ST_BP, ST_COMP, ST_HIST, ST_CLASS,
-    ST_DWT0,                          // + (level-1)
-    ST_IDWT0 = ST_DWT0 + kMaxLevels,  // + (level-1)
-    ST_COUNT = ST_IDWT0 + kMaxLevels
-};
-
 // Geometry and workspace layout of one cube.
 struct CubePlan {
     int H = 0, W = 0, p = 0, r = 0, L = 0, dtype = 0, scope = 0, T = 0, gslots = 1, precision = 0;
@@ -145,6 +173,7 @@ struct CubePlan {
            o_P64 = 0, o_Q64 = 0, o_Z = 0, o_coef = 0, o_tmp = 0, o_hcnt = 0, o_hsum = 0, o_hmin = 0,
            o_hmax = 0, o_sst = 0, o_lambda = 0, o_sure = 0, o_sbits = 0, o_spre = 0, o_sspre = 0, o_scb = 0,
            o_cand = 0, o_sfill = 0;
+    bool has_lambda = false;   // thresholds given by the caller: no SURE search
 };
 
 int esize(int dtype) { return dtype == HYRES_F64 ? 8 : 4; }
@@ -166,7 +195,7 @@ bool level_geometry(int H, int W, int L, int* lh, int* lw, int64_t* loff, int64_
     return true;
 }
 
-// Plan the per-cube workspace.  `parts` selects which arrays are needed.
+// Which per-cube arrays a call needs.
 enum Parts { P_GRAM = 1, P_SMALL = 2, P_IMG = 4, P_SURE = 8 };
 
 void plan_cube(CubePlan& c, Layout& lay, int parts) {
@@ -282,35 +311,6 @@ CubeDesc make_desc(const CubePlan& c, void* ws) {
     return d;
 }
 
-// Item counts of a single cube for every stage.
-void single_items(const CubePlan& c, int tx, int ty, int items[ST_COUNT][2]) {
-    for (int s = 0; s < ST_COUNT; ++s) items[s][0] = items[s][1] = 0;
-    items[ST_GRAM][1] = c.gslots;
-    items[ST_PROJ][1] = (int)cdiv(c.n, kPixTile);
-    items[ST_BP][1] = (int)cdiv(c.n, kPixTile);
-    items[ST_COMP][1] = c.r;
-    const int64_t ns = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
-    items[ST_HIST][1] = (int)(c.r * cdiv(ns, sure_chunk()));
-    items[ST_CLASS][1] = 0;   // the class list itself: cube index 0 (stored as {0, 0})
-    for (int l = 1; l <= c.L; ++l) {
-        const int t = (int)(c.r * cdiv(c.lw[l], tx) * cdiv(c.lh[l], ty));
-        items[ST_DWT0 + l - 1][1] = t;
-        items[ST_IDWT0 + l - 1][1] = t;
-    }
-}
-
-struct Ctx {
-    hyres_handle* h;
-    hipStream_t s;
-    void* ws;
-    size_t o_desc, o_items;
-    const CubeDesc* descs() const { return at<const CubeDesc>(ws, o_desc); }
-    const int* items(int stage) const { return at<const int>(ws, o_items) + stage * 2; }
-    int grid(int nitems, int per_cu) const {
-        return std::max(1, std::min(nitems, h->num_cu * per_cu));
-    }
-};
-
 #define HIPCHK(x)                                   \
     do {                                            \
         hipError_t _e = (x);                        \
@@ -324,64 +324,338 @@ hyres_status set_device(hyres_handle* h) {
     return HYRES_OK;
 }
 
-hyres_status begin(Ctx& x, const CubePlan& c, const CubeDesc& d, Layout& lay_unused) {
-    (void)lay_unused;
-    int items[ST_COUNT][2];
-    single_items(c, x.h->dwt_tx, x.h->dwt_ty, items);
-    HIPCHK(upload(x.ws, x.o_desc, &d, sizeof(CubeDesc), x.s));
-    HIPCHK(upload(x.ws, x.o_items, items, sizeof(items), x.s));
-    return HYRES_OK;
+// ------------------------------------------------------------------ program
+// Stages of a call, in execution order (bits of Program::stages).
+enum { S_GRAM = 1, S_SMALL = 2, S_PROJ = 4, S_DWT = 8, S_SURE = 16, S_IDWT = 32, S_BP = 64 };
+
+enum Kind {
+    K_GRAM_F32, K_GRAM_BF16, K_GRAM_RED, K_GRAM_F64, K_SMALL, K_PROJ_F32, K_PROJ_F64, K_DWT, K_IDWT,
+    K_SURE_INIT, K_SURE_ROUND, K_COPY, K_BP_F32, K_BP_F64
+};
+
+struct Launch {
+    int kind;
+    int stage;          // HYRES_STAGE_* for the stage timers
+    int key;            // T, band count, or tile candidate
+    int a, b;           // table offsets (ints) or a cube index
+    int n;              // cubes covered by the table, or length of a cube list
+    int grid, grid2;
+    int level;
+    int64_t n64;
+    const double* src;
+    double* dst;
+};
+
+// Small-solve kernel classes by band count (the kernel is specialised on the
+// register tiling of the p x p matrix).
+constexpr int kSmallClassMax[] = {32, 64, 96, 128, 144, 160, 176, 192, 224};
+constexpr int kSmallClasses = (int)(sizeof(kSmallClassMax) / sizeof(int));
+int small_class(int p) {
+    for (int i = 0; i < kSmallClasses; ++i)
+        if (p <= kSmallClassMax[i]) return i;
+    return kSmallClasses - 1;
 }
 
-hyres_status run_gram(Ctx& x, const CubePlan& c) {
-    if (c.dtype == HYRES_F64) {
-        HIPCHK(launch_gram_f64(x.descs(), 0, c.p, c.gslots, x.s));
-    } else {
-        if (c.precision == HYRES_PREC_MIXED)
-            HIPCHK(launch_gram_bf16(c.T, x.descs(), x.items(ST_GRAM), 1, c.gslots, x.s));
-        else
-            HIPCHK(launch_gram_f32(c.T, x.descs(), x.items(ST_GRAM), 1, c.gslots, x.s));
-        HIPCHK(launch_gram_reduce_f32(c.T, x.descs(), x.items(ST_CLASS), 1, x.s));
+// Upper bound on the tables of one program: per band-tile class (14) Gram,
+// projection items and the reduce list; back-projection items per class, or
+// per blend pass of a tile grid (whose tiles share one class); per small-solve
+// class a list; SURE component and histogram items; per level, direction and
+// tile candidate the DWT items; plus one scratch table for the tuner.
+constexpr int kMaxColours = 8;    // blend colours per axis of a tile grid
+constexpr int kMaxTables = 3 * 14 + std::max(14, kMaxColours * kMaxColours) + kSmallClasses + 2 +
+                           2 * kMaxLevels * kTileCands + 1;
+size_t table_ints(int count) { return (size_t)kMaxTables * (count + 1); }
+
+struct Exec {
+    hyres_handle* h = nullptr;
+    void* ws = nullptr;
+    int count = 0, dtype = 0, precision = 0;
+    std::vector<CubePlan> plan;
+    std::vector<CubeDesc> desc;
+    Layout lay;
+    size_t o_desc = 0, o_tab = 0;
+    std::vector<int> tab;
+    std::vector<Launch> prog;
+    std::vector<int> pass_of;   // blend pass of each tile (empty: no blending)
+
+    const CubeDesc* descs() const { return at<const CubeDesc>(ws, o_desc); }
+    const int* table(int off) const { return at<const int>(ws, o_tab) + off; }
+    int grid(int64_t nitems, int per_cu) const {
+        return (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)h->num_cu * per_cu));
     }
-    return HYRES_OK;
-}
-
-hyres_status run_dwt(Ctx& x, const CubePlan& c, bool inverse) {
-    for (int k = 0; k < c.L; ++k) {
-        const int l = inverse ? c.L - k : k + 1;
-        const int st = (inverse ? ST_IDWT0 : ST_DWT0) + l - 1;
-        const int nit = (int)(c.r * cdiv(c.lw[l], x.h->dwt_tx) * cdiv(c.lh[l], x.h->dwt_ty));
-        HIPCHK(launch_dwt_level(c.dtype, x.h->dwt_tx, x.h->dwt_ty, inverse, x.descs(), x.items(st), 1, l,
-                                x.grid(nit, 8), x.s));
+    // Appends a prefix table of per-cube item counts; returns its offset.
+    int counts(const std::vector<int64_t>& cnt, int64_t* total) {
+        const int off = (int)tab.size();
+        int64_t acc = 0;
+        tab.push_back(0);
+        for (int64_t v : cnt) {
+            acc += v;
+            tab.push_back((int)acc);
+        }
+        *total = acc;
+        return off;
     }
+    int list(const std::vector<int>& ids) {
+        const int off = (int)tab.size();
+        tab.insert(tab.end(), ids.begin(), ids.end());
+        return off;
+    }
+};
+
+// Lays out the descriptor table, the work tables and every cube's arrays.
+void plan_exec(Exec& x, int parts) {
+    x.o_desc = x.lay.add(sizeof(CubeDesc) * x.count);
+    x.o_tab = x.lay.add(sizeof(int) * table_ints(x.count));
+    for (auto& c : x.plan) plan_cube(c, x.lay, parts);
+}
+
+int tile_of(const hyres_handle* h, int dtype, bool inverse, int w) {
+    return h->tile[dtype == HYRES_F64][inverse][width_class(w)];
+}
+
+void add_dwt(Exec& x, bool inverse) {
+    int Lmax = 0;
+    for (auto& c : x.plan) Lmax = std::max(Lmax, c.L);
+    for (int k = 0; k < Lmax; ++k) {
+        const int l = inverse ? Lmax - k : k + 1;
+        for (int cand = 0; cand < kTileCands; ++cand) {
+            std::vector<int64_t> cnt(x.count, 0);
+            bool any = false;
+            for (int i = 0; i < x.count; ++i) {
+                const CubePlan& c = x.plan[i];
+                if (c.L < l || tile_of(x.h, x.dtype, inverse, c.lw[l]) != cand) continue;
+                cnt[i] = c.r * cdiv(c.lw[l], kTileTX[cand]) * cdiv(c.lh[l], kTileTY[cand]);
+                any = true;
+            }
+            if (!any) continue;
+            int64_t tot;
+            Launch L{};
+            L.kind = inverse ? K_IDWT : K_DWT;
+            L.stage = inverse ? HYRES_STAGE_IDWT : HYRES_STAGE_DWT;
+            L.key = cand;
+            L.a = x.counts(cnt, &tot);
+            L.n = x.count;
+            L.level = l;
+            L.grid = x.grid(tot, 8);
+            x.prog.push_back(L);
+        }
+    }
+}
+
+// Builds the launch program of the stages in `stages` over every cube.
+void build_program(Exec& x, int stages) {
+    x.tab.clear();
+    x.prog.clear();
+    const int N = x.count;
+    const bool f64 = x.dtype == HYRES_F64;
+    std::vector<int> Ts;
+    for (auto& c : x.plan) Ts.push_back(c.T);
+    std::sort(Ts.begin(), Ts.end());
+    Ts.erase(std::unique(Ts.begin(), Ts.end()), Ts.end());
+
+    // cubes of band-tile class T (and of blend pass `pass` when pass >= 0)
+    auto member = [&](int i, int T, int pass) {
+        return (T < 0 || x.plan[i].T == T) && (pass < 0 || x.pass_of[i] == pass);
+    };
+    auto per_T = [&](int kind, int stage, int per_cu, auto items_of, int pass = -1) {
+        for (int T : Ts) {
+            std::vector<int64_t> cnt(N, 0);
+            bool any = false;
+            for (int i = 0; i < N; ++i)
+                if (member(i, T, pass)) {
+                    cnt[i] = items_of(x.plan[i]);
+                    any = true;
+                }
+            if (!any) continue;
+            int64_t tot;
+            Launch L{};
+            L.kind = kind;
+            L.stage = stage;
+            L.key = T;
+            L.a = x.counts(cnt, &tot);
+            L.n = N;
+            L.grid = x.grid(tot, per_cu);
+            x.prog.push_back(L);
+            if (kind == K_GRAM_F32 || kind == K_GRAM_BF16) {
+                std::vector<int> ids;
+                for (int i = 0; i < N; ++i)
+                    if (x.plan[i].T == T) ids.push_back(i);
+                Launch R{};
+                R.kind = K_GRAM_RED;
+                R.stage = stage;
+                R.key = T;
+                R.a = x.list(ids);
+                R.n = (int)ids.size();
+                x.prog.push_back(R);
+            }
+        }
+    };
+    auto per_cube = [&](int kind, int stage, int pass = -1) {
+        for (int i = 0; i < N; ++i) {
+            if (!member(i, -1, pass)) continue;
+            Launch L{};
+            L.kind = kind;
+            L.stage = stage;
+            L.key = x.plan[i].p;
+            L.a = i;
+            L.grid = x.plan[i].gslots;
+            L.n64 = x.plan[i].n;
+            x.prog.push_back(L);
+        }
+    };
+
+    if (stages & S_GRAM) {
+        if (f64) per_cube(K_GRAM_F64, HYRES_STAGE_GRAM);
+        else per_T(x.precision == HYRES_PREC_MIXED ? K_GRAM_BF16 : K_GRAM_F32, HYRES_STAGE_GRAM, 2,
+                   [](const CubePlan& c) { return (int64_t)c.gslots; });
+    }
+    if (stages & S_SMALL) {
+        for (int k = 0; k < kSmallClasses; ++k) {
+            std::vector<int> ids;
+            for (int i = 0; i < N; ++i)
+                if (small_class(x.plan[i].p) == k) ids.push_back(i);
+            if (ids.empty()) continue;
+            Launch L{};
+            L.kind = K_SMALL;
+            L.stage = HYRES_STAGE_SMALL;
+            L.key = kSmallClassMax[k];
+            L.a = x.list(ids);
+            L.n = (int)ids.size();
+            x.prog.push_back(L);
+        }
+    }
+    if (stages & S_PROJ) {
+        if (f64) per_cube(K_PROJ_F64, HYRES_STAGE_PROJECT);
+        else per_T(K_PROJ_F32, HYRES_STAGE_PROJECT, 8, [](const CubePlan& c) { return cdiv(c.n, kPixTile); });
+    }
+    if (stages & S_DWT) add_dwt(x, false);
+    if (stages & S_SURE) {
+        std::vector<int64_t> comp(N, 0), hist(N, 0);
+        for (int i = 0; i < N; ++i) {
+            const CubePlan& c = x.plan[i];
+            if (c.has_lambda) continue;
+            const int64_t ns = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
+            comp[i] = c.r;
+            hist[i] = c.r * cdiv(ns, sure_chunk());
+        }
+        int64_t ncomp, nh;
+        const int tc = x.counts(comp, &ncomp);
+        const int th = x.counts(hist, &nh);
+        if (ncomp > 0) {
+            Launch I{};
+            I.kind = K_SURE_INIT;
+            I.stage = HYRES_STAGE_SURE;
+            I.a = tc;
+            I.n = N;
+            I.grid = (int)ncomp;
+            x.prog.push_back(I);
+            for (int k = 0; k < sure_rounds(x.dtype); ++k) {
+                Launch R{};
+                R.kind = K_SURE_ROUND;
+                R.stage = HYRES_STAGE_SURE;
+                R.a = th;
+                R.b = tc;
+                R.n = N;
+                R.grid = x.grid(nh, 2);
+                R.grid2 = (int)ncomp;
+                x.prog.push_back(R);
+            }
+        }
+        for (int i = 0; i < N; ++i) {
+            if (!x.plan[i].has_lambda) continue;
+            Launch C{};
+            C.kind = K_COPY;
+            C.stage = HYRES_STAGE_SURE;
+            C.src = x.desc[i].lambda_in;
+            C.dst = x.desc[i].lambda;
+            C.n = x.plan[i].r;
+            x.prog.push_back(C);
+        }
+    }
+    if (stages & S_IDWT) add_dwt(x, true);
+    if (stages & S_BP) {
+        // blended tiles: one launch per pass of non-overlapping tiles, in pass order
+        int npass = 1;
+        for (int v : x.pass_of) npass = std::max(npass, v + 1);
+        for (int k = 0; k < npass; ++k) {
+            const int pass = x.pass_of.empty() ? -1 : k;
+            if (f64) per_cube(K_BP_F64, HYRES_STAGE_BACKPROJECT, pass);
+            else per_T(K_BP_F32, HYRES_STAGE_BACKPROJECT, 8, [](const CubePlan& c) { return cdiv(c.n, kPixTile); },
+                       pass);
+        }
+    }
+}
+
+hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
+    const CubeDesc* D = x.descs();
+    switch (L.kind) {
+        case K_GRAM_F32: return launch_gram_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
+        case K_GRAM_BF16: return launch_gram_bf16(L.key, D, x.table(L.a), L.n, L.grid, s);
+        case K_GRAM_RED: return launch_gram_reduce_f32(L.key, D, x.table(L.a), L.n, s);
+        case K_GRAM_F64: return launch_gram_f64(D, L.a, L.key, L.grid, s);
+        case K_SMALL: return launch_small(L.key, D, x.table(L.a), L.n, s);
+        case K_PROJ_F32: return launch_project_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
+        case K_PROJ_F64: return launch_project_f64(D, L.a, L.n64, s);
+        case K_DWT:
+        case K_IDWT:
+            return launch_dwt_level(x.dtype, kTileTX[L.key], kTileTY[L.key], L.kind == K_IDWT, D, x.table(L.a),
+                                    L.n, L.level, L.grid, s);
+        case K_SURE_INIT: return launch_sure_init(x.dtype, D, x.table(L.a), L.n, L.grid, s);
+        case K_SURE_ROUND:
+            return launch_sure_round(x.dtype, D, x.table(L.a), x.table(L.b), L.n, L.grid, L.grid2, s);
+        case K_COPY:
+            hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, s, L.src, L.dst, L.n);
+            return hipGetLastError();
+        case K_BP_F32: return launch_backproject_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
+        case K_BP_F64: return launch_backproject_f64(D, L.a, L.n64, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Writes the descriptors and work tables into the workspace (stream-ordered).
+hyres_status upload_exec(const Exec& x, hipStream_t s) {
+    if (x.tab.size() > table_ints(x.count)) return HYRES_E_UNSUPPORTED;
+    HIPCHK(upload(x.ws, x.o_desc, x.desc.data(), sizeof(CubeDesc) * x.count, s));
+    if (!x.tab.empty()) HIPCHK(upload(x.ws, x.o_tab, x.tab.data(), sizeof(int) * x.tab.size(), s));
     return HYRES_OK;
 }
 
-hyres_status run_sure(Ctx& x, const CubePlan& c) {
-    HIPCHK(launch_sure_init(c.dtype, x.descs(), x.items(ST_COMP), 1, c.r, x.s));
-    const int64_t ns = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
-    const int nh = (int)(c.r * cdiv(ns, sure_chunk()));
-    for (int k = 0; k < sure_rounds(c.dtype); ++k)
-        HIPCHK(launch_sure_round(c.dtype, x.descs(), x.items(ST_HIST), x.items(ST_COMP), 1, x.grid(nh, 2), c.r,
-                                 x.s));
+// Enqueues the program; `timed` wraps each stage in the handle's stage timers.
+hyres_status run_program(const Exec& x, hipStream_t s, bool timed) {
+    std::unique_ptr<StageTimer> tm;
+    int cur = -1;
+    for (const Launch& L : x.prog) {
+        if (timed && L.stage != cur) {
+            tm.reset();
+            tm.reset(new StageTimer(x.h, s, L.stage));
+            cur = L.stage;
+        }
+        HIPCHK(launch_one(x, L, s));
+    }
     return HYRES_OK;
 }
 
 bool valid_dtype(int dt) { return dt == HYRES_F32 || dt == HYRES_F64; }
 
-// Contiguous FP32 cube with 16-byte aligned pixel rows: the kernels use float4 accesses.
+// FP32 cube with 16-byte aligned pixel vectors whose 64-pixel chunks are
+// consecutive in memory (contiguous cube, or image rows of whole chunks, as in
+// a tile of a larger cube): the kernels use float4 accesses.
 int vec4_ok(const void* ptr, int W, int p, int64_t pitch, int64_t row_pitch, int dtype) {
-    return dtype == HYRES_F32 && p % 4 == 0 && pitch % 4 == 0 && row_pitch == (int64_t)W * pitch &&
-           (reinterpret_cast<uintptr_t>(ptr) % 16) == 0;
+    return dtype == HYRES_F32 && p % 4 == 0 && pitch % 4 == 0 && row_pitch % 4 == 0 &&
+           (row_pitch == (int64_t)W * pitch || W % kPixTile == 0) && (reinterpret_cast<uintptr_t>(ptr) % 16) == 0;
+}
+
+hyres_status check_shape(int H, int W, int p, int64_t pitch, int64_t row_pitch) {
+    if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
+    if (pitch < p || row_pitch < (int64_t)(W - 1) * pitch + p) return HYRES_E_SHAPE;
+    if ((int64_t)H * W > (int64_t)1 << 31) return HYRES_E_UNSUPPORTED;
+    return HYRES_OK;
 }
 
 hyres_status check_cube(const void* Y, int H, int W, int p, int64_t pitch, int64_t row_pitch, int dtype) {
     if (!Y) return HYRES_E_NULL;
     if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
-    if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
-    if (pitch < p || row_pitch < (int64_t)(W - 1) * pitch + p) return HYRES_E_SHAPE;
-    if ((int64_t)H * W > (int64_t)1 << 31) return HYRES_E_UNSUPPORTED;
-    return HYRES_OK;
+    return check_shape(H, W, p, pitch, row_pitch);
 }
 
 hyres_status check_ws(const void* ws, size_t have, size_t need) {
@@ -392,23 +666,62 @@ hyres_status check_ws(const void* ws, size_t have, size_t need) {
     return HYRES_OK;
 }
 
-// Common front end of the entry points that take a cube.
-struct CubeCall {
-    CubePlan c;
-    Layout lay;
-    size_t o_desc = 0, o_items = 0;
-};
-
-hyres_status plan_cube_call(CubeCall& k, int H, int W, int p, int r, int L, int dtype, int scope, int parts) {
-    CubePlan& c = k.c;
-    c.H = H; c.W = W; c.p = p; c.r = r; c.L = L; c.dtype = dtype; c.scope = scope;
-    if (parts & (P_IMG | P_SURE)) {
-        if (!level_geometry(H, W, L, c.lh, c.lw, c.loff, &c.ll_off, &c.nc)) return HYRES_E_SHAPE;
+// Plan of a cube-taking call: geometry, then workspace layout.
+hyres_status plan_cubes(Exec& x, int parts) {
+    for (auto& c : x.plan) {
+        if (parts & (P_IMG | P_SURE)) {
+            if (!level_geometry(c.H, c.W, c.L, c.lh, c.lw, c.loff, &c.ll_off, &c.nc)) return HYRES_E_SHAPE;
+        }
     }
-    k.o_desc = k.lay.add(sizeof(CubeDesc));
-    k.o_items = k.lay.add(sizeof(int) * ST_COUNT * 2);
-    plan_cube(c, k.lay, parts);
+    plan_exec(x, parts);
     return HYRES_OK;
+}
+
+hyres_status check_prec_scope(int precision, int scope, int dtype) {
+    if (scope != HYRES_SCOPE_ALL && scope != HYRES_SCOPE_DETAIL) return HYRES_E_SHAPE;
+    if (precision != HYRES_PREC_NATIVE && precision != HYRES_PREC_MIXED) return HYRES_E_DTYPE;
+    if (precision == HYRES_PREC_MIXED && dtype != HYRES_F32) return HYRES_E_DTYPE;
+    return HYRES_OK;
+}
+
+hyres_status check_rank_levels(int r, int L, int p) {
+    if (r < 1 || r > kMaxRank || r > p) return HYRES_E_SHAPE;
+    if (L < 1 || L > kMaxLevels) return HYRES_E_SHAPE;
+    return HYRES_OK;
+}
+
+hyres_status check_opts(const hyres_options* opt, int p, int dtype) {
+    if (!opt) return HYRES_E_NULL;
+    hyres_status st = check_rank_levels(opt->rank, opt->levels, p);
+    if (st) return st;
+    return check_prec_scope(opt->precision, opt->scope, dtype);
+}
+
+constexpr int kAllParts = P_GRAM | P_SMALL | P_IMG | P_SURE;
+constexpr int kAllStages = S_GRAM | S_SMALL | S_PROJ | S_DWT | S_SURE | S_IDWT | S_BP;
+
+// Descriptor of one cube of a full solve: workspace arrays, then the caller's pointers.
+CubeDesc solve_desc(const CubePlan& c, void* ws, const void* Y, int64_t pitch, int64_t row_pitch, void* X,
+                    int64_t x_pitch, int64_t x_row_pitch, const double* sigma_in, const double* lambda_in,
+                    int flags, const hyres_outputs* out) {
+    CubeDesc d = make_desc(c, ws);
+    d.Y = Y; d.pitch = pitch; d.row_pitch = row_pitch;
+    d.X = X; d.xpitch = x_pitch; d.xrow_pitch = x_row_pitch;
+    d.vec4 = vec4_ok(Y, c.W, c.p, pitch, row_pitch, c.dtype);
+    d.xvec4 = vec4_ok(X, c.W, c.p, x_pitch, x_row_pitch, c.dtype);
+    d.sigma_in = sigma_in;
+    d.lambda_in = lambda_in;
+    d.mode = (sigma_in ? 0 : 1) | 2 | 8 | ((flags & HYRES_FLAG_ALL_EVALS) ? 16 : 0);
+    if (out) {
+        if (out->sigma) d.sigma = out->sigma;
+        if (out->V) d.V = out->V;
+        if (out->evals) d.evals = out->evals;
+        if (out->gap) d.gap = out->gap;
+        if (out->lambda) d.lambda = out->lambda;
+        if (out->sure) d.sure = out->sure;
+        d.status = out->status;
+    }
+    return d;
 }
 
 }  // namespace
@@ -425,9 +738,19 @@ HYRES_API hyres_status hyres_create(hyres_handle** handle, int device) {
     if (!h) return HYRES_E_HIP;
     h->device = device;
     h->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    h->dwt_tx = 64;
-    h->dwt_ty = 4;
+    char key[320];
+    std::snprintf(key, sizeof(key), "%s/%dcu", prop.gcnArchName, h->num_cu);
+    for (char* q = key; *q; ++q)
+        if (*q == '"' || *q == '\\') *q = '_';
+    h->arch = key;
     h->prof_mask = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int w = 0; w < kWidthClasses; ++w) {
+                h->tile[a][b][w] = (unsigned char)default_tile(w);
+                h->tuned[a][b][w] = 0;
+                h->tile_us[a][b][w] = 0.f;
+            }
     *handle = h;
     return HYRES_OK;
 }
@@ -435,10 +758,10 @@ HYRES_API hyres_status hyres_create(hyres_handle** handle, int device) {
 HYRES_API void hyres_destroy(hyres_handle* handle) {
     if (!handle) return;
     for (auto& r : handle->pending) {
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
-    for (auto e : handle->pool) hipEventDestroy(e);
+    for (auto e : handle->pool) (void)hipEventDestroy(e);
     delete handle;
 }
 
@@ -490,15 +813,26 @@ HYRES_API int64_t hyres_coeff_count(int H, int W, int L) {
     return nc;
 }
 
+// Single-cube executor of the given geometry.
+static void one_cube(Exec& x, hyres_handle* h, int H, int W, int p, int r, int L, int dtype, int scope) {
+    x.h = h;
+    x.count = 1;
+    x.dtype = dtype;
+    x.plan.resize(1);
+    CubePlan& c = x.plan[0];
+    c.H = H; c.W = W; c.p = p; c.r = r; c.L = L; c.dtype = dtype; c.scope = scope;
+}
+
 // ------------------------------------------------------------- noise
 HYRES_API hyres_status hyres_estimate_noise_workspace_size(int H, int W, int p, int dtype, size_t* bytes) {
     if (!bytes) return HYRES_E_NULL;
     if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
     if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
-    CubeCall k;
-    hyres_status st = plan_cube_call(k, H, W, p, 1, 1, dtype, 0, P_GRAM | P_SMALL);
+    Exec x;
+    one_cube(x, nullptr, H, W, p, 1, 1, dtype, 0);
+    hyres_status st = plan_cubes(x, P_GRAM | P_SMALL);
     if (st) return st;
-    *bytes = k.lay.total;
+    *bytes = x.lay.total;
     return HYRES_OK;
 }
 
@@ -509,22 +843,24 @@ HYRES_API hyres_status hyres_estimate_noise(hyres_handle* h, const void* Y, int 
     if (!h || !sigma_out) return HYRES_E_NULL;
     hyres_status st = check_cube(Y, H, W, p, pitch, row_pitch, dtype);
     if (st) return st;
-    CubeCall k;
-    if ((st = plan_cube_call(k, H, W, p, 1, 1, dtype, 0, P_GRAM | P_SMALL))) return st;
-    if ((st = check_ws(workspace, workspace_bytes, k.lay.total))) return st;
+    Exec x;
+    one_cube(x, h, H, W, p, 1, 1, dtype, 0);
+    if ((st = plan_cubes(x, P_GRAM | P_SMALL))) return st;
+    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
     if ((st = set_device(h))) return st;
-    CubeDesc d = make_desc(k.c, workspace);
+    x.ws = workspace;
+    CubeDesc d = make_desc(x.plan[0], workspace);
     d.Y = Y; d.pitch = pitch; d.row_pitch = row_pitch;
     d.vec4 = vec4_ok(Y, W, p, pitch, row_pitch, dtype);
     d.sigma = sigma_out;
     if (gram_out) d.G = gram_out;
     d.status = status;
     d.mode = 1;
-    Ctx x{h, (hipStream_t)stream, workspace, k.o_desc, k.o_items};
-    if ((st = begin(x, k.c, d, k.lay))) return st;
-    if ((st = run_gram(x, k.c))) return st;
-    HIPCHK(launch_small(p, x.descs(), x.items(ST_CLASS), 1, x.s));
-    return HYRES_OK;
+    x.desc.assign(1, d);
+    build_program(x, S_GRAM | S_SMALL);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_exec(x, s))) return st;
+    return run_program(x, s, false);
 }
 
 // ------------------------------------------------------------- subspace
@@ -532,10 +868,11 @@ HYRES_API hyres_status hyres_subspace_workspace_size(int H, int W, int p, int r,
     if (!bytes) return HYRES_E_NULL;
     if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
     if (H < 1 || W < 1 || p < 2 || p > kMaxBands || r < 1 || r > kMaxRank || r > p) return HYRES_E_SHAPE;
-    CubeCall k;
-    hyres_status st = plan_cube_call(k, H, W, p, r, 1, dtype, 0, P_GRAM | P_SMALL);
+    Exec x;
+    one_cube(x, nullptr, H, W, p, r, 1, dtype, 0);
+    hyres_status st = plan_cubes(x, P_GRAM | P_SMALL);
     if (st) return st;
-    *bytes = k.lay.total;
+    *bytes = x.lay.total;
     return HYRES_OK;
 }
 
@@ -547,11 +884,13 @@ HYRES_API hyres_status hyres_subspace(hyres_handle* h, const void* Y, int H, int
     hyres_status st = check_cube(Y, H, W, p, pitch, row_pitch, dtype);
     if (st) return st;
     if (r < 1 || r > kMaxRank || r > p) return HYRES_E_SHAPE;
-    CubeCall k;
-    if ((st = plan_cube_call(k, H, W, p, r, 1, dtype, 0, P_GRAM | P_SMALL))) return st;
-    if ((st = check_ws(workspace, workspace_bytes, k.lay.total))) return st;
+    Exec x;
+    one_cube(x, h, H, W, p, r, 1, dtype, 0);
+    if ((st = plan_cubes(x, P_GRAM | P_SMALL))) return st;
+    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
     if ((st = set_device(h))) return st;
-    CubeDesc d = make_desc(k.c, workspace);
+    x.ws = workspace;
+    CubeDesc d = make_desc(x.plan[0], workspace);
     d.Y = Y; d.pitch = pitch; d.row_pitch = row_pitch;
     d.vec4 = vec4_ok(Y, W, p, pitch, row_pitch, dtype);
     d.sigma_in = sigma;
@@ -559,42 +898,41 @@ HYRES_API hyres_status hyres_subspace(hyres_handle* h, const void* Y, int H, int
     if (evals_out) d.evals = evals_out;
     d.status = status;
     d.mode = 2 | 16;
-    Ctx x{h, (hipStream_t)stream, workspace, k.o_desc, k.o_items};
-    if ((st = begin(x, k.c, d, k.lay))) return st;
-    if ((st = run_gram(x, k.c))) return st;
-    HIPCHK(launch_small(p, x.descs(), x.items(ST_CLASS), 1, x.s));
-    return HYRES_OK;
+    x.desc.assign(1, d);
+    build_program(x, S_GRAM | S_SMALL);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_exec(x, s))) return st;
+    return run_program(x, s, false);
 }
 
 // ------------------------------------------------------------- wavelets
-static hyres_status plan_images(CubeCall& k, int batch, int H, int W, int L, int dtype, int parts) {
+// A batch of images is planned as one "cube" whose components are the images.
+static hyres_status plan_images(Exec& x, hyres_handle* h, int batch, int H, int W, int L, int dtype) {
     if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
     if (batch < 1) return HYRES_E_SHAPE;
-    CubePlan& c = k.c;
-    c.H = H; c.W = W; c.p = 2; c.r = batch; c.L = L; c.dtype = dtype; c.scope = 0;
+    one_cube(x, h, H, W, 2, batch, L, dtype, 0);
+    CubePlan& c = x.plan[0];
     if (!level_geometry(H, W, L, c.lh, c.lw, c.loff, &c.ll_off, &c.nc)) return HYRES_E_SHAPE;
     c.n = (int64_t)H * W;
     c.T = 1;
-    k.o_desc = k.lay.add(sizeof(CubeDesc));
-    k.o_items = k.lay.add(sizeof(int) * ST_COUNT * 2);
+    plan_exec(x, 0);
     const int es = esize(dtype);
     const int64_t a1 = rup((int64_t)c.lh[1] * c.lw[1], 64);
     const int64_t a2 = L >= 2 ? rup((int64_t)c.lh[2] * c.lw[2], 64) : 0;
     c.tmp_off2 = a1;
     c.tps = a1 + a2;
-    c.o_tmp = k.lay.add((size_t)batch * c.tps * es);
+    c.o_tmp = x.lay.add((size_t)batch * c.tps * es);
     c.nz = c.n;
     c.ncs = c.nc;
-    (void)parts;
     return HYRES_OK;
 }
 
 HYRES_API hyres_status hyres_dwt2_workspace_size(int batch, int H, int W, int L, int dtype, size_t* bytes) {
     if (!bytes) return HYRES_E_NULL;
-    CubeCall k;
-    hyres_status st = plan_images(k, batch, H, W, L, dtype, 0);
+    Exec x;
+    hyres_status st = plan_images(x, nullptr, batch, H, W, L, dtype);
     if (st) return st;
-    *bytes = k.lay.total;
+    *bytes = x.lay.total;
     return HYRES_OK;
 }
 
@@ -602,15 +940,16 @@ static hyres_status dwt_common(hyres_handle* h, const void* in, int batch, int H
                                void* out, const double* lambda, int scope, bool inverse, void* ws, size_t wsb,
                                hyres_stream_t stream) {
     if (!h || !in || !out) return HYRES_E_NULL;
-    CubeCall k;
-    hyres_status st = plan_images(k, batch, H, W, L, dtype, 0);
+    Exec x;
+    hyres_status st = plan_images(x, h, batch, H, W, L, dtype);
     if (st) return st;
     if (scope != HYRES_SCOPE_ALL && scope != HYRES_SCOPE_DETAIL) return HYRES_E_SHAPE;
-    if ((st = check_ws(ws, wsb, k.lay.total))) return st;
+    if ((st = check_ws(ws, wsb, x.lay.total))) return st;
     if ((st = set_device(h))) return st;
-    k.c.scope = scope;
-    CubeDesc d = make_desc(k.c, ws);
-    d.tmp = at<void>(ws, k.c.o_tmp);
+    x.ws = ws;
+    x.plan[0].scope = scope;
+    CubeDesc d = make_desc(x.plan[0], ws);
+    d.tmp = at<void>(ws, x.plan[0].o_tmp);
     if (inverse) {
         d.coef = const_cast<void*>(in);
         d.Z = out;
@@ -622,9 +961,11 @@ static hyres_status dwt_common(hyres_handle* h, const void* in, int batch, int H
         d.Z = const_cast<void*>(in);
         d.coef = out;
     }
-    Ctx x{h, (hipStream_t)stream, ws, k.o_desc, k.o_items};
-    if ((st = begin(x, k.c, d, k.lay))) return st;
-    return run_dwt(x, k.c, inverse);
+    x.desc.assign(1, d);
+    build_program(x, inverse ? S_IDWT : S_DWT);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_exec(x, s))) return st;
+    return run_program(x, s, false);
 }
 
 HYRES_API hyres_status hyres_dwt2(hyres_handle* h, const void* x, int batch, int H, int W, int L, int dtype,
@@ -640,23 +981,23 @@ HYRES_API hyres_status hyres_idwt2(hyres_handle* h, const void* coeffs, int batc
 }
 
 // ------------------------------------------------------------- SURE
-static hyres_status plan_sure(CubeCall& k, int batch, int64_t Nc, int dtype) {
+static hyres_status plan_sure(Exec& x, hyres_handle* h, int batch, int64_t Nc, int dtype) {
     if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
     if (batch < 1 || Nc < 1 || Nc > ((int64_t)1 << 31)) return HYRES_E_SHAPE;
-    CubePlan& c = k.c;
-    c.r = batch; c.dtype = dtype; c.nc = Nc; c.ll_off = Nc; c.L = 0; c.scope = 0;
-    k.o_desc = k.lay.add(sizeof(CubeDesc));
-    k.o_items = k.lay.add(sizeof(int) * ST_COUNT * 2);
-    plan_cube(c, k.lay, P_SURE);
+    one_cube(x, h, 1, 1, 2, batch, 0, dtype, 0);
+    CubePlan& c = x.plan[0];
+    c.nc = Nc;
+    c.ll_off = Nc;
+    plan_exec(x, P_SURE);
     return HYRES_OK;
 }
 
 HYRES_API hyres_status hyres_sure_workspace_size(int batch, int64_t Nc, int dtype, size_t* bytes) {
     if (!bytes) return HYRES_E_NULL;
-    CubeCall k;
-    hyres_status st = plan_sure(k, batch, Nc, dtype);
+    Exec x;
+    hyres_status st = plan_sure(x, nullptr, batch, Nc, dtype);
     if (st) return st;
-    *bytes = k.lay.total;
+    *bytes = x.lay.total;
     return HYRES_OK;
 }
 
@@ -665,34 +1006,27 @@ HYRES_API hyres_status hyres_sure_threshold(hyres_handle* h, const void* coeffs,
                                             int* status, void* workspace, size_t workspace_bytes,
                                             hyres_stream_t stream) {
     if (!h || !coeffs || !lambda_out) return HYRES_E_NULL;
-    CubeCall k;
-    hyres_status st = plan_sure(k, batch, Nc, dtype);
+    Exec x;
+    hyres_status st = plan_sure(x, h, batch, Nc, dtype);
     if (st) return st;
     if (stride < Nc) return HYRES_E_SHAPE;
-    if ((st = check_ws(workspace, workspace_bytes, k.lay.total))) return st;
+    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
     if ((st = set_device(h))) return st;
-    k.c.ncs = stride;
-    CubeDesc d = make_desc(k.c, workspace);
+    x.ws = workspace;
+    x.plan[0].ncs = stride;
+    CubeDesc d = make_desc(x.plan[0], workspace);
     d.coef = const_cast<void*>(coeffs);
     d.lambda = lambda_out;
     d.sure = sure_min_out ? sure_min_out : d.sure;
     d.status = status;
-    Ctx x{h, (hipStream_t)stream, workspace, k.o_desc, k.o_items};
-    if ((st = begin(x, k.c, d, k.lay))) return st;
-    return run_sure(x, k.c);
+    x.desc.assign(1, d);
+    build_program(x, S_SURE);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_exec(x, s))) return st;
+    return run_program(x, s, false);
 }
 
 // ------------------------------------------------------------- denoise
-static hyres_status check_opts(const hyres_options* opt, int p, int dtype) {
-    if (!opt) return HYRES_E_NULL;
-    if (opt->rank < 1 || opt->rank > kMaxRank || opt->rank > p) return HYRES_E_SHAPE;
-    if (opt->levels < 1 || opt->levels > kMaxLevels) return HYRES_E_SHAPE;
-    if (opt->scope != HYRES_SCOPE_ALL && opt->scope != HYRES_SCOPE_DETAIL) return HYRES_E_SHAPE;
-    if (opt->precision != HYRES_PREC_NATIVE && opt->precision != HYRES_PREC_MIXED) return HYRES_E_DTYPE;
-    if (opt->precision == HYRES_PREC_MIXED && dtype != HYRES_F32) return HYRES_E_DTYPE;
-    return HYRES_OK;
-}
-
 HYRES_API hyres_status hyres_denoise_workspace_size(int H, int W, int p, const hyres_options* opt, int dtype,
                                                     size_t* bytes) {
     if (!bytes) return HYRES_E_NULL;
@@ -700,11 +1034,10 @@ HYRES_API hyres_status hyres_denoise_workspace_size(int H, int W, int p, const h
     if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
     hyres_status st = check_opts(opt, p, dtype);
     if (st) return st;
-    CubeCall k;
-    if ((st = plan_cube_call(k, H, W, p, opt->rank, opt->levels, dtype, opt->scope,
-                             P_GRAM | P_SMALL | P_IMG | P_SURE)))
-        return st;
-    *bytes = k.lay.total;
+    Exec x;
+    one_cube(x, nullptr, H, W, p, opt->rank, opt->levels, dtype, opt->scope);
+    if ((st = plan_cubes(x, kAllParts))) return st;
+    *bytes = x.lay.total;
     return HYRES_OK;
 }
 
@@ -718,69 +1051,711 @@ HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int 
     if (st) return st;
     if ((st = check_opts(opt, p, dtype))) return st;
     if (x_pitch < p || x_row_pitch < (int64_t)(W - 1) * x_pitch + p) return HYRES_E_SHAPE;
-    CubeCall k;
-    if ((st = plan_cube_call(k, H, W, p, opt->rank, opt->levels, dtype, opt->scope,
-                             P_GRAM | P_SMALL | P_IMG | P_SURE)))
-        return st;
-    k.c.precision = opt->precision;
-    if ((st = check_ws(workspace, workspace_bytes, k.lay.total))) return st;
+    Exec x;
+    one_cube(x, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope);
+    x.precision = opt->precision;
+    x.plan[0].precision = opt->precision;
+    x.plan[0].has_lambda = lambda_in != nullptr;
+    if ((st = plan_cubes(x, kAllParts))) return st;
+    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
     if ((st = set_device(h))) return st;
-    CubeDesc d = make_desc(k.c, workspace);
-    d.Y = Y; d.pitch = pitch; d.row_pitch = row_pitch;
-    d.X = X; d.xpitch = x_pitch; d.xrow_pitch = x_row_pitch;
-    d.vec4 = vec4_ok(Y, W, p, pitch, row_pitch, dtype);
-    d.xvec4 = vec4_ok(X, W, p, x_pitch, x_row_pitch, dtype);
-    d.sigma_in = sigma_in;
-    d.lambda_in = lambda_in;
-    d.mode = (sigma_in ? 0 : 1) | 2 | 8 | ((opt->flags & HYRES_FLAG_ALL_EVALS) ? 16 : 0);
-    if (out) {
-        if (out->sigma) d.sigma = out->sigma;
-        if (out->V) d.V = out->V;
-        if (out->evals) d.evals = out->evals;
-        if (out->gap) d.gap = out->gap;
-        if (out->lambda) d.lambda = out->lambda;
-        if (out->sure) d.sure = out->sure;
-        d.status = out->status;
-    }
+    x.ws = workspace;
+    x.desc.assign(1, solve_desc(x.plan[0], workspace, Y, pitch, row_pitch, X, x_pitch, x_row_pitch, sigma_in,
+                                lambda_in, opt->flags, out));
+    build_program(x, kAllStages);
     hipStream_t s = (hipStream_t)stream;
-    Ctx x{h, s, workspace, k.o_desc, k.o_items};
-    const CubePlan& c = k.c;
-    if ((st = begin(x, c, d, k.lay))) return st;
-    {
-        StageTimer tm(h, s, HYRES_STAGE_GRAM);
-        if ((st = run_gram(x, c))) return st;
+    if ((st = upload_exec(x, s))) return st;
+    return run_program(x, s, true);
+}
+
+// ------------------------------------------------------------- batches
+struct hyres_batch {
+    hyres_handle* h = nullptr;
+    Exec x;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
     }
-    {
-        StageTimer tm(h, s, HYRES_STAGE_SMALL);
-        HIPCHK(launch_small(p, x.descs(), x.items(ST_CLASS), 1, s));
+    ~hyres_batch() {
+        drop_graph();
+        if (cap) (void)hipStreamDestroy(cap);
     }
-    const int nt = (int)cdiv(c.n, kPixTile);
-    {
-        StageTimer tm(h, s, HYRES_STAGE_PROJECT);
-        if (dtype == HYRES_F64) HIPCHK(launch_project_f64(x.descs(), 0, c.n, s));
-        else HIPCHK(launch_project_f32(c.T, x.descs(), x.items(ST_PROJ), 1, x.grid(nt, 8), s));
+};
+
+static hyres_status plan_batch(Exec& x, hyres_handle* h, const hyres_cube* cubes, int count, int dtype,
+                               const hyres_options* opt, bool need_ptrs) {
+    if (!cubes || !opt) return HYRES_E_NULL;
+    if (count < 1 || count > (1 << 16)) return HYRES_E_SHAPE;
+    if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
+    hyres_status st = check_prec_scope(opt->precision, opt->scope, dtype);
+    if (st) return st;
+    x.h = h;
+    x.count = count;
+    x.dtype = dtype;
+    x.precision = opt->precision;
+    x.plan.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const hyres_cube& k = cubes[i];
+        if (need_ptrs) {
+            if (!k.Y || !k.X) return HYRES_E_NULL;
+            if (k.x_pitch < k.p || k.x_row_pitch < (int64_t)(k.W - 1) * k.x_pitch + k.p) return HYRES_E_SHAPE;
+        }
+        const int64_t pitch = need_ptrs ? k.pitch : k.p;
+        const int64_t rp = need_ptrs ? k.row_pitch : (int64_t)k.W * k.p;
+        if ((st = check_shape(k.H, k.W, k.p, pitch, rp))) return st;
+        if ((st = check_rank_levels(k.rank, k.levels, k.p))) return st;
+        CubePlan& c = x.plan[i];
+        c.H = k.H; c.W = k.W; c.p = k.p; c.r = k.rank; c.L = k.levels; c.dtype = dtype; c.scope = opt->scope;
+        c.precision = opt->precision;
+        c.has_lambda = k.lambda_in != nullptr;
     }
-    {
-        StageTimer tm(h, s, HYRES_STAGE_DWT);
-        if ((st = run_dwt(x, c, false))) return st;
+    return plan_cubes(x, kAllParts);
+}
+
+HYRES_API hyres_status hyres_batch_workspace_size(const hyres_cube* cubes, int count, int dtype,
+                                                  const hyres_options* opt, size_t* bytes) {
+    if (!bytes) return HYRES_E_NULL;
+    Exec x;
+    hyres_status st = plan_batch(x, nullptr, cubes, count, dtype, opt, false);
+    if (st) return st;
+    *bytes = x.lay.total;
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_batch_create(hyres_handle* h, const hyres_cube* cubes, int count, int dtype,
+                                          const hyres_options* opt, void* workspace, size_t workspace_bytes,
+                                          hyres_stream_t stream, hyres_batch** batch) {
+    if (!h || !batch) return HYRES_E_NULL;
+    *batch = nullptr;
+    std::unique_ptr<hyres_batch> b(new (std::nothrow) hyres_batch);
+    if (!b) return HYRES_E_UNSUPPORTED;
+    b->h = h;
+    Exec& x = b->x;
+    hyres_status st = plan_batch(x, h, cubes, count, dtype, opt, true);
+    if (st) return st;
+    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
+    if ((st = set_device(h))) return st;
+    x.ws = workspace;
+    x.desc.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const hyres_cube& k = cubes[i];
+        x.desc[i] = solve_desc(x.plan[i], workspace, k.Y, k.pitch, k.row_pitch, k.X, k.x_pitch, k.x_row_pitch,
+                               k.sigma_in, k.lambda_in, opt->flags, &k.out);
     }
-    {
-        StageTimer tm(h, s, HYRES_STAGE_SURE);
-        if (lambda_in) {
-            hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, s, lambda_in, d.lambda, c.r);
-            HIPCHK(hipGetLastError());
-        } else if ((st = run_sure(x, c))) {
-            return st;
+    build_program(x, kAllStages);
+    if ((st = upload_exec(x, (hipStream_t)stream))) return st;
+    *batch = b.release();
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_batch_run(hyres_batch* b, hyres_stream_t stream) {
+    if (!b) return HYRES_E_NULL;
+    hyres_status st = set_device(b->h);
+    if (st) return st;
+    return run_program(b->x, (hipStream_t)stream, true);
+}
+
+HYRES_API hyres_status hyres_batch_launch_graph(hyres_batch* b, hyres_stream_t stream) {
+    if (!b) return HYRES_E_NULL;
+    hyres_status st = set_device(b->h);
+    if (st) return st;
+    if (!b->exec) {
+        if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        st = run_program(b->x, b->cap, false);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (st || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st ? st : HYRES_E_HIP;
+        }
+        b->graph = g;
+        if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+            b->drop_graph();
+            return HYRES_E_HIP;
         }
     }
-    {
-        StageTimer tm(h, s, HYRES_STAGE_IDWT);
-        if ((st = run_dwt(x, c, true))) return st;
+    HIPCHK(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return HYRES_OK;
+}
+
+HYRES_API void hyres_batch_destroy(hyres_batch* b) { delete b; }
+
+HYRES_API hyres_status hyres_denoise_batched(hyres_handle* h, const hyres_cube* cubes, int count, int dtype,
+                                             const hyres_options* opt, void* workspace, size_t workspace_bytes,
+                                             hyres_stream_t stream) {
+    hyres_batch* b = nullptr;
+    hyres_status st = hyres_batch_create(h, cubes, count, dtype, opt, workspace, workspace_bytes, stream, &b);
+    if (st) return st;
+    st = run_program(b->x, (hipStream_t)stream, true);
+    delete b;
+    return st;
+}
+
+// ------------------------------------------------------------- adjoint
+namespace {
+
+// Backward workspace: two transform descriptors (analysis with zero extra
+// sample, synthesis with folding), their tables, and the adjoint buffers.
+struct BwdPlan {
+    Exec fwd;                 // layout of the forward workspace
+    Exec xa, xs;              // transform executors over the backward buffers
+    Layout lay;
+    int slots = 1, nchunk = 1;
+    size_t o_desc = 0, o_tab = 0, o_A = 0, o_dB = 0, o_tmp = 0, o_part = 0, o_dQ = 0, o_dPt = 0, o_lpart = 0,
+           o_aug = 0, o_W = 0, o_Ginv = 0, o_dC = 0, o_dG2 = 0;
+};
+
+hyres_status plan_backward(BwdPlan& b, hyres_handle* h, int H, int W, int p, const hyres_options* opt, int dtype) {
+    if (!opt) return HYRES_E_NULL;
+    if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
+    if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
+    hyres_status st = check_opts(opt, p, dtype);
+    if (st) return st;
+    one_cube(b.fwd, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope);
+    if ((st = plan_cubes(b.fwd, kAllParts))) return st;
+    const CubePlan& c = b.fwd.plan[0];
+    const int r = c.r, es = esize(dtype);
+    Layout& L = b.lay;
+    b.o_desc = L.add(2 * sizeof(CubeDesc));
+    b.o_tab = L.add(2 * sizeof(int) * table_ints(1));
+    b.o_A = L.add((size_t)r * c.nz * es);
+    b.o_dB = L.add((size_t)r * c.ncs * es);
+    b.o_tmp = L.add((size_t)std::max<int64_t>(1, r * c.tps) * es);
+    b.slots = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(c.n, 2048)));
+    b.o_part = L.add((size_t)b.slots * r * p * 8);
+    b.o_dQ = L.add((size_t)r * p * 8);
+    b.o_dPt = L.add((size_t)r * p * 8);
+    const int64_t lim = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
+    b.nchunk = (int)std::max<int64_t>(1, cdiv(lim, adj_chunk()));
+    b.o_lpart = L.add((size_t)r * b.nchunk * 8);
+    b.o_aug = L.add((size_t)(r + 1) * 2 * p * p * 8);
+    b.o_W = L.add((size_t)p * r * 8);
+    b.o_Ginv = L.add((size_t)p * p * 8);
+    b.o_dC = L.add((size_t)p * p * 8);
+    b.o_dG2 = L.add((size_t)p * p * 8);
+    return HYRES_OK;
+}
+
+}  // namespace
+
+HYRES_API hyres_status hyres_denoise_backward_workspace_size(int H, int W, int p, const hyres_options* opt, int dtype,
+                                                             size_t* bytes) {
+    if (!bytes) return HYRES_E_NULL;
+    BwdPlan b;
+    hyres_status st = plan_backward(b, nullptr, H, W, p, opt, dtype);
+    if (st) return st;
+    *bytes = b.lay.total;
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_denoise_backward(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                              int64_t row_pitch, int dtype, const hyres_options* opt,
+                                              const void* fwd_workspace, size_t fwd_workspace_bytes,
+                                              const hyres_outputs* fwd_out, const void* dX, int64_t dx_pitch,
+                                              int64_t dx_row_pitch, void* dY, int64_t dy_pitch,
+                                              int64_t dy_row_pitch, double* dlambda, int* status, void* workspace,
+                                              size_t workspace_bytes, hyres_stream_t stream) {
+    if (!h || !dX || !dY || !fwd_out || !fwd_workspace) return HYRES_E_NULL;
+    if (!fwd_out->sigma || !fwd_out->V || !fwd_out->evals || !fwd_out->lambda) return HYRES_E_NULL;
+    hyres_status st = check_cube(Y, H, W, p, pitch, row_pitch, dtype);
+    if (st) return st;
+    if (dx_pitch < p || dx_row_pitch < (int64_t)(W - 1) * dx_pitch + p) return HYRES_E_SHAPE;
+    if (dy_pitch < p || dy_row_pitch < (int64_t)(W - 1) * dy_pitch + p) return HYRES_E_SHAPE;
+    BwdPlan b;
+    if ((st = plan_backward(b, h, H, W, p, opt, dtype))) return st;
+    if ((st = check_ws(workspace, workspace_bytes, b.lay.total))) return st;
+    if (fwd_workspace_bytes < b.fwd.lay.total || reinterpret_cast<uintptr_t>(fwd_workspace) % kAlign)
+        return HYRES_E_WORKSPACE;
+    if ((st = set_device(h))) return st;
+    void* fws = const_cast<void*>(fwd_workspace);
+    const CubePlan& c = b.fwd.plan[0];
+    // transform executors: analysis of dZh with a zero extra sample, synthesis with folding
+    CubeDesc d = make_desc(c, workspace);
+    d.Z = at<void>(workspace, b.o_A);
+    d.coef = at<void>(workspace, b.o_dB);
+    d.tmp = at<void>(workspace, b.o_tmp);
+    d.lambda = nullptr;
+    d.status = status;
+    for (int k = 0; k < 2; ++k) {
+        Exec& x = k == 0 ? b.xa : b.xs;
+        x.h = h;
+        x.count = 1;
+        x.dtype = dtype;
+        x.ws = workspace;
+        x.plan.assign(1, c);
+        x.o_desc = b.o_desc + k * sizeof(CubeDesc);
+        x.o_tab = b.o_tab + k * sizeof(int) * table_ints(1);
+        CubeDesc dk = d;
+        dk.mode = k == 0 ? kModeZeroPad : kModeFold;
+        x.desc.assign(1, dk);
+        build_program(x, k == 0 ? S_DWT : S_IDWT);
     }
-    {
-        StageTimer tm(h, s, HYRES_STAGE_BACKPROJECT);
-        if (dtype == HYRES_F64) HIPCHK(launch_backproject_f64(x.descs(), 0, c.n, s));
-        else HIPCHK(launch_backproject_f32(c.T, x.descs(), x.items(ST_BP), 1, x.grid(nt, 8), s));
+    AdjDesc a;
+    std::memset(&a, 0, sizeof(a));
+    a.H = H; a.W = W; a.p = p; a.r = c.r; a.L = c.L; a.scope = c.scope;
+    a.n = c.n; a.nz = c.nz; a.ncs = c.ncs; a.nc = c.nc; a.ll_off = c.ll_off;
+    a.Y = Y; a.pitch = pitch; a.row_pitch = row_pitch;
+    a.Zh = at<void>(fws, c.o_Z);
+    a.B = at<void>(fws, c.o_coef);
+    a.G = at<double>(fws, c.o_G);
+    a.sigma = fwd_out->sigma;
+    a.V = fwd_out->V;
+    a.evals = fwd_out->evals;
+    a.lambda = fwd_out->lambda;
+    a.P64 = at<double>(fws, c.o_P64);
+    a.Q64 = at<double>(fws, c.o_Q64);
+    a.dX = dX; a.dxp = dx_pitch; a.dxrp = dx_row_pitch;
+    a.dY = dY; a.dyp = dy_pitch; a.dyrp = dy_row_pitch;
+    a.dlambda = dlambda;
+    a.A = at<void>(workspace, b.o_A);
+    a.dB = at<void>(workspace, b.o_dB);
+    a.part = at<double>(workspace, b.o_part);
+    a.dQ = at<double>(workspace, b.o_dQ);
+    a.dPt = at<double>(workspace, b.o_dPt);
+    a.lpart = at<double>(workspace, b.o_lpart);
+    a.aug = at<double>(workspace, b.o_aug);
+    a.Wsol = at<double>(workspace, b.o_W);
+    a.Ginv = at<double>(workspace, b.o_Ginv);
+    a.dC = at<double>(workspace, b.o_dC);
+    a.dG2 = at<double>(workspace, b.o_dG2);
+    a.slots = b.slots;
+    a.nchunk = b.nchunk;
+    a.status = status;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_exec(b.xa, s)) || (st = upload_exec(b.xs, s))) return st;
+    HIPCHK(launch_adjoint_pre(a, dtype, s));
+    if ((st = run_program(b.xa, s, false))) return st;
+    HIPCHK(launch_adjoint_thresh(a, dtype, s));
+    if ((st = run_program(b.xs, s, false))) return st;
+    HIPCHK(launch_adjoint_post(a, dtype, s));
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_sure_grad_workspace_size(int batch, int64_t Nc, size_t* bytes) {
+    if (!bytes) return HYRES_E_NULL;
+    if (batch < 1 || Nc < 1 || Nc > ((int64_t)1 << 31)) return HYRES_E_SHAPE;
+    *bytes = (size_t)batch * cdiv(Nc, adj_chunk()) * 8;
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_sure_grad(hyres_handle* h, const void* coeffs, int batch, int64_t Nc, int64_t stride,
+                                       int dtype, const double* lambda, double* dsure_out, void* workspace,
+                                       size_t workspace_bytes, hyres_stream_t stream) {
+    if (!h || !coeffs || !lambda || !dsure_out) return HYRES_E_NULL;
+    if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
+    if (batch < 1 || Nc < 1 || Nc > ((int64_t)1 << 31) || stride < Nc) return HYRES_E_SHAPE;
+    const int nchunk = (int)cdiv(Nc, adj_chunk());
+    hyres_status st = check_ws(workspace, workspace_bytes, (size_t)batch * nchunk * 8);
+    if (st) return st;
+    if ((st = set_device(h))) return st;
+    HIPCHK(launch_sure_grad(dtype, coeffs, stride, Nc, batch, lambda, static_cast<double*>(workspace), nchunk,
+                            dsure_out, (hipStream_t)stream));
+    return HYRES_OK;
+}
+
+// ------------------------------------------------------------- sliding window
+namespace {
+
+constexpr int kMaxTilesAxis = 64;
+
+// Tile starts along one axis: steps of tile - overlap, the last start clamped
+// so that the tile ends at the border; one tile when it covers the axis.
+int tile_starts(int size, int tile, int overlap, int* starts) {
+    if (tile >= size) {
+        starts[0] = 0;
+        return 1;
     }
+    const int step = tile - overlap;
+    int n = 0;
+    for (int k = 0;; ++k) {
+        const int s = std::min(k * step, size - tile);
+        if (n >= kMaxTilesAxis) return n + 1;
+        starts[n++] = s;
+        if (s + tile >= size) break;
+    }
+    return n;
+}
+
+// Greedy colouring: each tile takes the smallest colour that no earlier tile
+// overlapping it has, so tiles of one colour never overlap.
+int tile_colours(const int* starts, int n, int tile, unsigned char* colour) {
+    int nc = 0;
+    for (int i = 0; i < n; ++i) {
+        unsigned used = 0;
+        for (int j = 0; j < i; ++j)
+            if (starts[i] < starts[j] + tile) used |= 1u << colour[j];
+        int c = 0;
+        while ((used >> c) & 1u) ++c;
+        colour[i] = (unsigned char)c;
+        nc = std::max(nc, c + 1);
+    }
+    return nc;
+}
+
+struct BlendAxis {
+    int n, tile, size, overlap;
+    int start[kMaxTilesAxis];
+    unsigned char colour[kMaxTilesAxis];
+};
+
+// Weight of sample k of a tile: sin^2 ramps over the first and the last
+// `overlap` samples, except on a side touching the image border.
+__device__ double ramp_weight(int start, int k, int tile, int size, int overlap) {
+    double w = 1.0;
+    if (start > 0 && k < overlap) {
+        const double t = sin(0.5 * M_PI * (k + 0.5) / overlap);
+        w = t * t;
+    }
+    if (start + tile < size && k >= tile - overlap) {
+        const double t = sin(0.5 * M_PI * (tile - 1 - k + 0.5) / overlap);
+        w = t * t;
+    }
+    return w;
+}
+
+// Per tile and sample: weight divided by the sum over all tiles covering the
+// sample, and the mask of the colours of those tiles.
+__global__ void k_blend_axis(BlendAxis a, double* __restrict__ w, unsigned char* __restrict__ cov) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n * a.tile) return;
+    const int t = idx / a.tile, k = idx - t * a.tile;
+    const int g = a.start[t] + k;
+    double sum = 0.0;
+    unsigned mask = 0;
+    for (int u = 0; u < a.n; ++u) {
+        const int ku = g - a.start[u];
+        if (ku < 0 || ku >= a.tile) continue;
+        sum += ramp_weight(a.start[u], ku, a.tile, a.size, a.overlap);
+        mask |= 1u << a.colour[u];
+    }
+    w[idx] = ramp_weight(a.start[t], k, a.tile, a.size, a.overlap) / sum;
+    cov[idx] = (unsigned char)mask;
+}
+
+struct TileGrid {
+    int ny = 0, nx = 0, th = 0, tw = 0, ncy = 0, ncx = 0;
+    BlendAxis ay{}, ax{};
+    size_t o_bwy = 0, o_bwx = 0, o_bcy = 0, o_bcx = 0;
+};
+
+hyres_status plan_tiled(Exec& x, TileGrid& g, hyres_handle* h, int H, int W, int p, int tile, int overlap,
+                        const hyres_options* opt, int dtype) {
+    if (!opt) return HYRES_E_NULL;
+    if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
+    if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
+    if (tile < 4 || overlap < 0 || 2 * overlap > tile) return HYRES_E_SHAPE;
+    hyres_status st = check_opts(opt, p, dtype);
+    if (st) return st;
+    g.th = std::min(tile, H);
+    g.tw = std::min(tile, W);
+    g.ny = tile_starts(H, tile, overlap, g.ay.start);
+    g.nx = tile_starts(W, tile, overlap, g.ax.start);
+    if (g.ny > kMaxTilesAxis || g.nx > kMaxTilesAxis) return HYRES_E_UNSUPPORTED;
+    g.ncy = tile_colours(g.ay.start, g.ny, g.th, g.ay.colour);
+    g.ncx = tile_colours(g.ax.start, g.nx, g.tw, g.ax.colour);
+    if (g.ncy > kMaxColours || g.ncx > kMaxColours) return HYRES_E_UNSUPPORTED;
+    g.ay.n = g.ny; g.ay.tile = g.th; g.ay.size = H; g.ay.overlap = overlap;
+    g.ax.n = g.nx; g.ax.tile = g.tw; g.ax.size = W; g.ax.overlap = overlap;
+    x.h = h;
+    x.count = g.ny * g.nx;
+    x.dtype = dtype;
+    x.precision = opt->precision;
+    x.plan.resize(x.count);
+    x.pass_of.resize(x.count);
+    for (int iy = 0; iy < g.ny; ++iy)
+        for (int ix = 0; ix < g.nx; ++ix) {
+            const int t = iy * g.nx + ix;
+            CubePlan& c = x.plan[t];
+            c.H = g.th; c.W = g.tw; c.p = p; c.r = opt->rank; c.L = opt->levels; c.dtype = dtype;
+            c.scope = opt->scope; c.precision = opt->precision;
+            x.pass_of[t] = g.ay.colour[iy] * g.ncx + g.ax.colour[ix];
+        }
+    if ((st = plan_cubes(x, kAllParts))) return st;
+    g.o_bwy = x.lay.add((size_t)g.ny * g.th * 8);
+    g.o_bwx = x.lay.add((size_t)g.nx * g.tw * 8);
+    g.o_bcy = x.lay.add((size_t)g.ny * g.th);
+    g.o_bcx = x.lay.add((size_t)g.nx * g.tw);
+    return HYRES_OK;
+}
+
+}  // namespace
+
+HYRES_API hyres_status hyres_tile_grid(int size, int tile, int overlap, int* starts, int* count) {
+    if (!count) return HYRES_E_NULL;
+    if (size < 1 || tile < 4 || overlap < 0 || 2 * overlap > tile) return HYRES_E_SHAPE;
+    int buf[kMaxTilesAxis];
+    const int n = tile_starts(size, tile, overlap, buf);
+    if (n > kMaxTilesAxis) return HYRES_E_UNSUPPORTED;
+    *count = n;
+    if (starts)
+        for (int i = 0; i < n; ++i) starts[i] = buf[i];
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_tiled_workspace_size(int H, int W, int p, int tile, int overlap,
+                                                  const hyres_options* opt, int dtype, size_t* bytes) {
+    if (!bytes) return HYRES_E_NULL;
+    Exec x;
+    TileGrid g;
+    hyres_status st = plan_tiled(x, g, nullptr, H, W, p, tile, overlap, opt, dtype);
+    if (st) return st;
+    *bytes = x.lay.total;
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_denoise_tiled(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                           int64_t row_pitch, int dtype, int tile, int overlap,
+                                           const hyres_options* opt, void* X, int64_t x_pitch, int64_t x_row_pitch,
+                                           double* lambda_out, double* sigma_out, int* status, void* workspace,
+                                           size_t workspace_bytes, hyres_stream_t stream) {
+    if (!h || !X) return HYRES_E_NULL;
+    hyres_status st = check_cube(Y, H, W, p, pitch, row_pitch, dtype);
+    if (st) return st;
+    if (x_pitch < p || x_row_pitch < (int64_t)(W - 1) * x_pitch + p) return HYRES_E_SHAPE;
+    Exec x;
+    TileGrid g;
+    if ((st = plan_tiled(x, g, h, H, W, p, tile, overlap, opt, dtype))) return st;
+    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
+    if ((st = set_device(h))) return st;
+    x.ws = workspace;
+    const int es = esize(dtype);
+    x.desc.resize(x.count);
+    for (int iy = 0; iy < g.ny; ++iy)
+        for (int ix = 0; ix < g.nx; ++ix) {
+            const int t = iy * g.nx + ix;
+            const int64_t sy = g.ay.start[iy], sx = g.ax.start[ix];
+            const void* Yt = static_cast<const unsigned char*>(Y) + (sy * row_pitch + sx * pitch) * es;
+            void* Xt = static_cast<unsigned char*>(X) + (sy * x_row_pitch + sx * x_pitch) * es;
+            hyres_outputs o{};
+            if (sigma_out) o.sigma = sigma_out + (int64_t)t * p;
+            if (lambda_out) o.lambda = lambda_out + (int64_t)t * opt->rank;
+            o.status = status;
+            CubeDesc d = solve_desc(x.plan[t], workspace, Yt, pitch, row_pitch, Xt, x_pitch, x_row_pitch, nullptr,
+                                    nullptr, opt->flags, &o);
+            d.bwy = at<double>(workspace, g.o_bwy) + (int64_t)iy * g.th;
+            d.bwx = at<double>(workspace, g.o_bwx) + (int64_t)ix * g.tw;
+            d.bcy = at<unsigned char>(workspace, g.o_bcy) + (int64_t)iy * g.th;
+            d.bcx = at<unsigned char>(workspace, g.o_bcx) + (int64_t)ix * g.tw;
+            d.bpass = x.pass_of[t];
+            d.bncx = g.ncx;
+            x.desc[t] = d;
+        }
+    build_program(x, kAllStages);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_exec(x, s))) return st;
+    hipLaunchKernelGGL(k_blend_axis, dim3((g.ny * g.th + 255) / 256), dim3(256), 0, s, g.ay,
+                       at<double>(workspace, g.o_bwy), at<unsigned char>(workspace, g.o_bcy));
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_blend_axis, dim3((g.nx * g.tw + 255) / 256), dim3(256), 0, s, g.ax,
+                       at<double>(workspace, g.o_bwx), at<unsigned char>(workspace, g.o_bcx));
+    HIPCHK(hipGetLastError());
+    return run_program(x, s, true);
+}
+
+// ------------------------------------------------------------- autotuner
+namespace {
+
+// Tuning cache: a JSON object whose "entries" array holds one object per
+// (device, dtype, direction, width class) with the chosen tile and its time.
+const char* kCacheFormat = "hyres-dwt-tiles-1";
+constexpr int kTuneLaunches = 5;
+
+void load_cache(hyres_handle* h, const char* path) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+    std::fclose(f);
+    if (text.find(kCacheFormat) == std::string::npos) return;
+    size_t pos = 0;
+    while ((pos = text.find("{\"device\": \"", pos)) != std::string::npos) {
+        char dev[320] = {0};
+        int dt = -1, inv = -1, wc = -1, tx = 0, ty = 0;
+        float us = 0.f;
+        const int got = std::sscanf(text.c_str() + pos,
+                                    "{\"device\": \"%319[^\"]\", \"dtype\": %d, \"inverse\": %d, \"wclass\": %d, "
+                                    "\"tx\": %d, \"ty\": %d, \"us\": %f}",
+                                    dev, &dt, &inv, &wc, &tx, &ty, &us);
+        pos += 1;
+        if (got != 7 || h->arch != dev || dt < 0 || dt > 1 || inv < 0 || inv > 1 || wc < 0 ||
+            wc >= kWidthClasses)
+            continue;
+        for (int c = 0; c < kTileCands; ++c) {
+            if (kTileTX[c] == tx && kTileTY[c] == ty) {
+                h->tile[dt][inv][wc] = (unsigned char)c;
+                h->tuned[dt][inv][wc] = 1;
+                h->tile_us[dt][inv][wc] = us;
+            }
+        }
+    }
+}
+
+// Writes this handle's tuned entries and keeps other devices' entries.
+bool save_cache(const hyres_handle* h, const char* path) {
+    std::vector<std::string> keep;
+    FILE* f = std::fopen(path, "rb");
+    if (f) {
+        std::string text;
+        char buf[4096];
+        size_t k;
+        while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+        std::fclose(f);
+        size_t pos = 0;
+        while ((pos = text.find("{\"device\": \"", pos)) != std::string::npos) {
+            const size_t end = text.find('}', pos);
+            if (end == std::string::npos) break;
+            std::string e = text.substr(pos, end - pos + 1);
+            const std::string mine = "{\"device\": \"" + h->arch + "\"";
+            if (e.compare(0, mine.size(), mine) != 0) keep.push_back(e);
+            pos = end;
+        }
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    std::fprintf(f, "{\"format\": \"%s\", \"entries\": [", kCacheFormat);
+    bool first = true;
+    for (auto& e : keep) {
+        std::fprintf(f, "%s\n  %s", first ? "" : ",", e.c_str());
+        first = false;
+    }
+    for (int dt = 0; dt < 2; ++dt)
+        for (int inv = 0; inv < 2; ++inv)
+            for (int wc = 0; wc < kWidthClasses; ++wc) {
+                if (!h->tuned[dt][inv][wc]) continue;
+                const int c = h->tile[dt][inv][wc];
+                std::fprintf(f,
+                             "%s\n  {\"device\": \"%s\", \"dtype\": %d, \"inverse\": %d, \"wclass\": %d, "
+                             "\"tx\": %d, \"ty\": %d, \"us\": %.3f}",
+                             first ? "" : ",", h->arch.c_str(), dt, inv, wc, kTileTX[c], kTileTY[c],
+                             h->tile_us[dt][inv][wc]);
+                first = false;
+            }
+    std::fprintf(f, "\n]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+HYRES_API hyres_status hyres_autotune(hyres_handle* h, hyres_batch* b, const char* cache_path,
+                                      hyres_stream_t stream) {
+    if (!h || !b) return HYRES_E_NULL;
+    if (b->h != h) return HYRES_E_UNSUPPORTED;
+    hyres_status st = set_device(h);
+    if (st) return st;
+    if (cache_path) load_cache(h, cache_path);
+    Exec& x = b->x;
+    const int dt = x.dtype == HYRES_F64;
+    hipStream_t s = (hipStream_t)stream;
+    // width classes of this batch still untuned, per direction
+    bool need[2][kWidthClasses] = {};
+    bool any = false;
+    for (auto& c : x.plan)
+        for (int l = 1; l <= c.L; ++l)
+            for (int inv = 0; inv < 2; ++inv) {
+                const int wc = width_class(c.lw[l]);
+                if (!h->tuned[dt][inv][wc]) {
+                    need[inv][wc] = true;
+                    any = true;
+                }
+            }
+    if (any) {
+        // one solve leaves realistic values in every buffer the transforms read
+        build_program(x, kAllStages);
+        if ((st = upload_exec(x, s))) return st;
+        if ((st = run_program(x, s, false))) return st;
+        const int scratch = (int)(table_ints(x.count) - (x.count + 1));   // the tuner's table
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return HYRES_E_HIP;
+        }
+        int Lmax = 0;
+        for (auto& c : x.plan) Lmax = std::max(Lmax, c.L);
+        hyres_status res = HYRES_OK;
+        for (int inv = 0; inv < 2 && !res; ++inv)
+            for (int wc = 0; wc < kWidthClasses && !res; ++wc) {
+                if (!need[inv][wc]) continue;
+                float best = 0.f;
+                int best_c = default_tile(wc);
+                for (int cand = 0; cand < kTileCands && !res; ++cand) {
+                    float total = 0.f;
+                    for (int l = 1; l <= Lmax && !res; ++l) {
+                        std::vector<int> tabv(x.count + 1, 0);
+                        int64_t tot = 0;
+                        for (int i = 0; i < x.count; ++i) {
+                            const CubePlan& c = x.plan[i];
+                            if (c.L >= l && width_class(c.lw[l]) == wc)
+                                tot += c.r * cdiv(c.lw[l], kTileTX[cand]) * cdiv(c.lh[l], kTileTY[cand]);
+                            tabv[i + 1] = (int)tot;
+                        }
+                        if (tot == 0) continue;
+                        if (upload(x.ws, x.o_tab + sizeof(int) * scratch, tabv.data(), sizeof(int) * tabv.size(),
+                                   s) != hipSuccess) {
+                            res = HYRES_E_HIP;
+                            break;
+                        }
+                        const int grid = x.grid(tot, 8);
+                        const int* t = x.table(scratch);
+                        // best of three timings of kTuneLaunches launches, after one warm-up timing
+                        float rep_best = 0.f;
+                        for (int rep = 0; rep < 4 && !res; ++rep) {
+                            if (hipEventRecord(e0, s) != hipSuccess) res = HYRES_E_HIP;
+                            for (int k = 0; k < kTuneLaunches && !res; ++k)
+                                if (launch_dwt_level(x.dtype, kTileTX[cand], kTileTY[cand], inv != 0, x.descs(), t,
+                                                     x.count, l, grid, s) != hipSuccess)
+                                    res = HYRES_E_HIP;
+                            if (res || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                                res = HYRES_E_HIP;
+                                break;
+                            }
+                            float ms = 0.f;
+                            (void)hipEventElapsedTime(&ms, e0, e1);
+                            if (rep == 1 || (rep > 1 && ms < rep_best)) rep_best = ms;
+                        }
+                        total += rep_best / kTuneLaunches;
+                    }
+                    if (!res && (cand == 0 || total < best)) {
+                        best = total;
+                        best_c = cand;
+                    }
+                }
+                if (!res) {
+                    h->tile[dt][inv][wc] = (unsigned char)best_c;
+                    h->tuned[dt][inv][wc] = 1;
+                    h->tile_us[dt][inv][wc] = best * 1000.f;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (res) return res;
+    }
+    // rebuild the batch's program with the chosen tiles
+    b->drop_graph();
+    build_program(x, kAllStages);
+    if ((st = upload_exec(x, s))) return st;
+    if (cache_path && any && !save_cache(h, cache_path)) return HYRES_E_UNSUPPORTED;
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_tile_choice(hyres_handle* h, int dtype, int inverse, int width, int* tx, int* ty,
+                                         int* tuned) {
+    if (!h || !tx || !ty) return HYRES_E_NULL;
+    if (!valid_dtype(dtype) || width < 1) return HYRES_E_SHAPE;
+    const int wc = width_class(width);
+    const int c = h->tile[dtype == HYRES_F64][inverse != 0][wc];
+    *tx = kTileTX[c];
+    *ty = kTileTY[c];
+    if (tuned) *tuned = h->tuned[dtype == HYRES_F64][inverse != 0][wc];
     return HYRES_OK;
 }

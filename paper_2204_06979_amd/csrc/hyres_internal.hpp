@@ -38,12 +38,20 @@ struct SureState {
     int done;
     int inexact;
     int gather;                 // 1: the next pass collects the values of the surviving bins
-    unsigned int ncand;         // number of collected values
     unsigned int nsurv;         // number of values in the surviving bins
+    unsigned int pad;
 };
 
 constexpr int kSureCap = 8192;        // values finished exactly in one block
 constexpr int kSureBinCap = 1024;     // largest surviving bin the exact finish accepts
+
+// CubeDesc::mode bits
+constexpr int kModeSigma = 1;      // estimate the noise
+constexpr int kModeEigen = 2;      // eigensolve
+constexpr int kModeThreshold = 8;  // the inverse transform soft-thresholds its input
+constexpr int kModeAllEvals = 16;  // every eigenvalue
+constexpr int kModeZeroPad = 32;   // analysis with a zero extra sample (transpose of the inverse)
+constexpr int kModeFold = 64;      // synthesis folding the extra sample (transpose of the analysis)
 
 // Everything a kernel needs to know about one cube.  Pointers are device pointers.
 struct CubeDesc {
@@ -81,11 +89,51 @@ struct CubeDesc {
     uint64_t* cand;                         // r x kSureCap collected magnitudes (keys)
     double* lambda; double* sure;           // r
     const double* lambda_in;                // optional caller thresholds
+    // sliding-window blend in the back-projection (bwy null: plain write).  A
+    // tile adds w_y[y] w_x[x] Xhat to X, where w are its 1-D weights divided by
+    // the sum over all tiles; the first tile to reach a pixel writes instead.
+    // Tiles are applied in passes of non-overlapping tiles; bcy/bcx hold, per
+    // row/column of this tile, the bit mask of the pass colours covering it.
+    const double* bwy; const double* bwx;
+    const unsigned char* bcy; const unsigned char* bcx;
+    int bpass, bncx;                        // this tile's pass = colour_y * bncx + colour_x
     int* status;                            // device status word (may be null)
-    int mode;                               // bit 0: estimate sigma, bit 1: eigen, bit 3: threshold
+    int mode;                               // kMode* bits
     int vec4;                               // Y is contiguous with 16-byte aligned pixel rows, p % 4 == 0
     int xvec4;                              // the same for X
     unsigned long long* dbg;                // phase time stamps (timing builds only; null otherwise)
+};
+
+// Everything the adjoint kernels need (one cube; passed by value).
+struct AdjDesc {
+    int H, W, p, r, L, scope;
+    int64_t n, nz, ncs, nc, ll_off;
+    const void* Y; int64_t pitch, row_pitch;
+    const void* Zh;          // forward reconstructed component images (r x nz)
+    const void* B;           // forward coefficients (r x ncs)
+    const double* G;         // p x p
+    const double* sigma;     // p
+    const double* V;         // p x r, column-major
+    const double* evals;     // top r eigenvalues of C
+    const double* lambda;    // r thresholds
+    const double* P64;       // p x r, [b * r + k]
+    const double* Q64;       // r x p, [k * p + b]
+    const void* dX; int64_t dxp, dxrp;
+    void* dY; int64_t dyp, dyrp;
+    double* dlambda;         // r (may be null)
+    void* A;                 // r x nz: dZh, later dZ
+    void* dB;                // r x ncs
+    double* part;            // slots x r x p
+    double* dQ;              // r x p
+    double* dPt;             // r x p (dP transposed)
+    double* lpart;           // r x nchunk
+    double* aug;             // (r + 1) augmented systems of p x 2p
+    double* Wsol;            // p x r, column-major
+    double* Ginv;            // p x p
+    double* dC;              // p x p
+    double* dG2;             // p x p: 2 dG
+    int slots, nchunk;
+    int* status;
 };
 
 #ifdef HYRES_PHASE_TIMING
@@ -145,6 +193,18 @@ __device__ __forceinline__ double half_sum(double v) {
 __device__ __forceinline__ double wave_sum(double v) {
     v = half_sum(v);
     return v + __shfl_xor(v, 32, 64);
+}
+
+// Blend weight of tile pixel (y, x) and whether an earlier pass already wrote it.
+__device__ __forceinline__ double blend_weight(const CubeDesc& d, int64_t y, int64_t x, bool* first) {
+    const unsigned my = d.bcy[y], mx = d.bcx[x];
+    bool before = false;
+    for (int k = 0; k < d.bpass; ++k) {
+        const int cy = k / d.bncx, cx = k - cy * d.bncx;
+        before |= ((my >> cy) & (mx >> cx) & 1u) != 0;
+    }
+    *first = !before;
+    return d.bwy[y] * d.bwx[x];
 }
 
 __device__ __forceinline__ void set_status(int* st, int bits) {

@@ -1,0 +1,431 @@
+// Adjoint of the HyRes solve with the thresholds held as inputs, and the
+// derivative of the SURE risk with respect to a threshold.
+//
+// Forward (per cube, n pixels, p bands, rank r):
+//   G = Y^T Y,  sigma_j = (n [G^-1]_jj)^(-1/2),  C = D^-1 G D^-1  (D = diag sigma),
+//   C u_k = lambda_k u_k (top r),  P = D^-1 V,  Z = Y P,  B = W Z (transform per component),
+//   Bh = soft(B, lambda),  Zh = W^+ Bh (inverse transform),  Q = V^T D,  X = Zh Q.
+// Reverse, given dX:
+//   dZh = dX Q^T,  dQ = Zh^T dX                              (k_adj_apply, k_adj_xprod)
+//   dBh = (W^+)^T dZh        (analysis with zero extension)  (transform kernels)
+//   dB = dBh 1[|B| > lambda],  dlambda_k = -sum dBh sign(B) 1[|B| > lambda]  (k_adj_thresh)
+//   dZ = W^T dB              (synthesis, extra sample folded back)  (transform kernels)
+//   dP = Y^T dZ,  dY  = dZ P^T + 2 Y dG                        (k_adj_xprod, k_adj_dy)
+//   dV = D^-1 dP + D dQ^T,  dsigma from P, Q and C
+//   eigenvectors: dC = sum_k sym(w_k u_k^T), w_k = sum_{i != k} u_i u_i^T dV_k / (lambda_k - lambda_i),
+//     obtained from (lambda_k I - C + lambda_k u_k u_k^T) w_k = (I - u_k u_k^T) dV_k   (k_adj_solve)
+//   dG = D^-1 dC D^-1 + G^-1 diag(n sigma_j^3 dsigma_j / 2) G^-1                        (k_adj_combine)
+// Small dense algebra runs in FP64 in one workgroup per system; the pixel
+// loops run in the element type of the cube with FP64 accumulation where
+// they reduce over pixels.
+#include "hyres_internal.hpp"
+
+namespace hyres {
+
+
+
+constexpr int kAdjChunk = 16384;   // coefficients per threshold-adjoint block
+
+int adj_chunk() { return kAdjChunk; }
+
+template <typename T>
+__device__ __forceinline__ const T* adj_pix(const void* base, int64_t q, int W, int64_t pitch, int64_t rpitch) {
+    const int64_t y = q / W, x = q - y * W;
+    return static_cast<const T*>(base) + y * rpitch + x * pitch;
+}
+
+// dZh[k][q] = sum_b dX[q][b] Q[k][b]: one pixel per thread, Q staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_apply(AdjDesc a) {
+    __shared__ double sq[kMaxRank * kMaxBands];
+    const int p = a.p, r = a.r;
+    for (int i = threadIdx.x; i < r * p; i += blockDim.x) sq[i] = a.Q64[i];
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n) return;
+    const T* x = adj_pix<T>(a.dX, q, a.W, a.dxp, a.dxrp);
+    double acc[kMaxRank];
+#pragma unroll
+    for (int k = 0; k < kMaxRank; ++k) acc[k] = 0.0;
+    for (int b = 0; b < p; ++b) {
+        const double v = (double)x[b];
+#pragma unroll
+        for (int k = 0; k < kMaxRank; ++k)
+            if (k < r) acc[k] = fma(v, sq[k * p + b], acc[k]);
+    }
+    T* out = static_cast<T*>(a.A);
+#pragma unroll
+    for (int k = 0; k < kMaxRank; ++k)
+        if (k < r) out[(int64_t)k * a.nz + q] = (T)acc[k];
+}
+
+// part[slot][k][b] = sum over the slot's pixels of planes[k][q] * cube[q][b].
+constexpr int kXPix = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_xprod(AdjDesc a, const void* planes, const void* cube, int64_t cp,
+                                                   int64_t crp) {
+    __shared__ double ct[kXPix][kMaxBands + 1];
+    __shared__ double pt[kMaxRank][kXPix];
+    const int p = a.p, r = a.r, E = r * p;
+    constexpr int NE = (kMaxRank * kMaxBands + 255) / 256;
+    const int slot = blockIdx.x;
+    int64_t per = (a.n + a.slots - 1) / a.slots;
+    per = (per + kXPix - 1) / kXPix * kXPix;
+    const int64_t q0 = (int64_t)slot * per;
+    const int64_t q1 = q0 + per < a.n ? q0 + per : a.n;
+    double acc[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) acc[j] = 0.0;
+    const T* pl = static_cast<const T*>(planes);
+    for (int64_t t0 = q0; t0 < q1; t0 += kXPix) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kXPix * p; e += 256) {
+            const int k = e / p, b = e - k * p;
+            const int64_t q = t0 + k;
+            ct[k][b] = q < q1 ? (double)adj_pix<T>(cube, q, a.W, cp, crp)[b] : 0.0;
+        }
+        for (int e = threadIdx.x; e < kXPix * r; e += 256) {
+            const int k = e / kXPix, j = e - k * kXPix;
+            const int64_t q = t0 + j;
+            pt[k][j] = q < q1 ? (double)pl[(int64_t)k * a.nz + q] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < E) {
+                const int k = e / p, b = e - k * p;
+                double s = acc[j];
+                for (int i = 0; i < kXPix; ++i) s = fma(pt[k][i], ct[i][b], s);
+                acc[j] = s;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        if (e < E) a.part[(int64_t)slot * E + e] = acc[j];
+    }
+}
+
+// out[e] = sum over slots of part[slot][e], in slot order.
+__global__ void k_adj_reduce(const double* __restrict__ part, int slots, int E, double* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double s = 0.0;
+    for (int i = 0; i < slots; ++i) s += part[(int64_t)i * E + e];
+    out[e] = s;
+}
+
+template <typename T>
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    return s;
+}
+
+// Threshold adjoint in place on dB; per-block partial of dlambda.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_thresh(AdjDesc a) {
+    __shared__ double red[4];
+    const int comp = blockIdx.y, chunk = blockIdx.x;
+    const T* bf = static_cast<const T*>(a.B) + (int64_t)comp * a.ncs;
+    T* g = static_cast<T*>(a.dB) + (int64_t)comp * a.ncs;
+    const T lam = (T)a.lambda[comp];
+    const int64_t lim = a.scope == HYRES_SCOPE_DETAIL ? a.ll_off : a.nc;
+    const int64_t e0 = (int64_t)chunk * kAdjChunk;
+    const int64_t e1 = e0 + kAdjChunk < lim ? e0 + kAdjChunk : lim;
+    double s = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const T b = bf[e];
+        const T v = g[e];
+        const bool m = (b < (T)0 ? -b : b) > lam;
+        if (m) s -= (double)(b < (T)0 ? -v : v);
+        g[e] = m ? v : (T)0;
+    }
+    s = block_sum256<T>(s, red);
+    if (threadIdx.x == 0) a.lpart[(int64_t)comp * a.nchunk + chunk] = s;
+}
+
+// #{|b| > lambda} per block (the SURE derivative is 2 lambda times the count).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sure_count(const T* __restrict__ coef, int64_t stride, int64_t N,
+                                                    const double* __restrict__ lambda, int nchunk,
+                                                    double* __restrict__ part) {
+    __shared__ double red[4];
+    const int comp = blockIdx.y, chunk = blockIdx.x;
+    const T* bf = coef + (int64_t)comp * stride;
+    const T lam = (T)lambda[comp];
+    const int64_t e0 = (int64_t)chunk * kAdjChunk;
+    const int64_t e1 = e0 + kAdjChunk < N ? e0 + kAdjChunk : N;
+    double s = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const T b = bf[e];
+        s += (b < (T)0 ? -b : b) > lam ? 1.0 : 0.0;
+    }
+    s = block_sum256<T>(s, red);
+    if (threadIdx.x == 0) part[(int64_t)comp * nchunk + chunk] = s;
+}
+
+// out[k] = scale_k * sum over chunks of part[k][chunk] (scale_k = 2 lambda_k or 1).
+__global__ void k_chunk_reduce(const double* __restrict__ part, int nchunk, int r, const double* __restrict__ lambda,
+                               int twice_lambda, double* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r) return;
+    double s = 0.0;
+    for (int i = 0; i < nchunk; ++i) s += part[(int64_t)k * nchunk + i];
+    out[k] = twice_lambda ? 2.0 * lambda[k] * s : s;
+}
+
+// Gauss-Jordan elimination with partial pivoting of the p x m row-major
+// matrix M (first p columns the system, the rest right-hand sides) in one
+// workgroup; afterwards the right-hand columns hold the solution.
+__device__ bool gauss_jordan(double* M, int p, int m, double* rowbuf, double* colbuf, double* rv, int* ri) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    bool ok = true;
+    for (int j = 0; j < p; ++j) {
+        // pivot: largest magnitude in column j at or below row j (lowest row on ties)
+        double best = -1.0;
+        int bi = p;
+        for (int i = j + tid; i < p; i += nt) {
+            const double v = fabs(M[(int64_t)i * m + j]);
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        rv[tid] = best;
+        ri[tid] = bi;
+        __syncthreads();
+        for (int o = nt / 2; o >= 1; o >>= 1) {
+            if (tid < o) {
+                const double ov = rv[tid + o];
+                const int oi = ri[tid + o];
+                if (ov > rv[tid] || (ov == rv[tid] && oi < ri[tid])) {
+                    rv[tid] = ov;
+                    ri[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int piv = ri[0];
+        const double pv = M[(int64_t)piv * m + j];
+        if (!(fabs(pv) > 0.0)) ok = false;
+        __syncthreads();
+        // swap rows j and piv into the row buffer (normalised) and row piv
+        for (int c = j + tid; c < m; c += nt) {
+            const double a = M[(int64_t)j * m + c], b = M[(int64_t)piv * m + c];
+            rowbuf[c] = b / pv;
+            if (piv != j) M[(int64_t)piv * m + c] = a;
+        }
+        for (int i = tid; i < p; i += nt) colbuf[i] = i == j ? 0.0 : (i == piv ? M[(int64_t)j * m + j]
+                                                                               : M[(int64_t)i * m + j]);
+        __syncthreads();
+        // eliminate column j from every other row; row j becomes the pivot row
+        const int w = m - j;
+        for (int e = tid; e < p * w; e += nt) {
+            const int i = e / w, c = j + (e - i * w);
+            if (i == j) {
+                M[(int64_t)i * m + c] = rowbuf[c];
+            } else {
+                const double f = colbuf[i];
+                M[(int64_t)i * m + c] = fma(-f, rowbuf[c], M[(int64_t)i * m + c]);
+            }
+        }
+        __syncthreads();
+    }
+    return ok;
+}
+
+// One workgroup per system: k < r the eigenvector system of component k,
+// k == r the inverse of G.
+__global__ __launch_bounds__(1024) void k_adj_solve(AdjDesc a) {
+    __shared__ double rowbuf[2 * kMaxBands], colbuf[kMaxBands], rv[1024];
+    __shared__ int ri[1024];
+    __shared__ double rhs[kMaxBands], u[kMaxBands], sdot;
+    const int p = a.p, r = a.r, k = blockIdx.x, tid = threadIdx.x;
+    const int m = k < r ? p + 1 : 2 * p;
+    double* M = a.aug + (int64_t)k * p * 2 * p;
+    if (k < r) {
+        const double lk = a.evals[k];
+        for (int j = tid; j < p; j += blockDim.x) {
+            const double s = a.sigma[j];
+            u[j] = a.V[(int64_t)k * p + j];
+            rhs[j] = a.dPt[(int64_t)k * p + j] / s + s * a.dQ[(int64_t)k * p + j];   // dV[:, k]
+        }
+        __syncthreads();
+        if (tid < 64) {
+            double d = 0.0;
+            for (int j = tid; j < p; j += 64) d = fma(u[j], rhs[j], d);
+            d = wave_sum(d);
+            if (tid == 0) sdot = d;
+        }
+        __syncthreads();
+        for (int e = tid; e < p * m; e += blockDim.x) {
+            const int i = e / m, c = e - i * m;
+            double v;
+            if (c < p) {
+                const double cij = a.G[(int64_t)i * p + c] / (a.sigma[i] * a.sigma[c]);
+                v = (i == c ? lk : 0.0) - cij + lk * u[i] * u[c];
+            } else {
+                v = rhs[i] - u[i] * sdot;
+            }
+            M[(int64_t)i * m + c] = v;
+        }
+    } else {
+        for (int e = tid; e < p * m; e += blockDim.x) {
+            const int i = e / m, c = e - i * m;
+            M[(int64_t)i * m + c] = c < p ? a.G[(int64_t)i * p + c] : (c - p == i ? 1.0 : 0.0);
+        }
+    }
+    __syncthreads();
+    const bool ok = gauss_jordan(M, p, m, rowbuf, colbuf, rv, ri);
+    if (!ok && tid == 0) set_status(a.status, HYRES_DEV_NOT_PD);
+    if (k < r) {
+        for (int i = tid; i < p; i += blockDim.x) a.Wsol[(int64_t)k * p + i] = M[(int64_t)i * m + p];
+    } else {
+        for (int e = tid; e < p * p; e += blockDim.x) {
+            const int i = e / p, c = e - i * p;
+            a.Ginv[e] = M[(int64_t)i * m + p + c];
+        }
+    }
+}
+
+// dC, dsigma and dG (one workgroup).
+__global__ __launch_bounds__(1024) void k_adj_combine(AdjDesc a) {
+    __shared__ double gsc[kMaxBands];
+    const int p = a.p, r = a.r, tid = threadIdx.x;
+    const double n = (double)a.n;
+    for (int e = tid; e < p * p; e += blockDim.x) {
+        const int i = e / p, j = e - i * p;
+        double s = 0.0;
+        for (int k = 0; k < r; ++k)
+            s += a.Wsol[(int64_t)k * p + i] * a.V[(int64_t)k * p + j] + a.Wsol[(int64_t)k * p + j] * a.V[(int64_t)k * p + i];
+        a.dC[e] = 0.5 * s;
+    }
+    __syncthreads();
+    for (int j = tid; j < p; j += blockDim.x) {
+        const double sj = a.sigma[j];
+        double ds = 0.0;
+        for (int k = 0; k < r; ++k) {
+            const double v = a.V[(int64_t)k * p + j];
+            ds += -a.dPt[(int64_t)k * p + j] * v / (sj * sj) + a.dQ[(int64_t)k * p + j] * v;
+        }
+        double t = 0.0;
+        for (int i = 0; i < p; ++i) t = fma(a.dC[(int64_t)i * p + j], a.G[(int64_t)i * p + j] / (a.sigma[i] * sj), t);
+        ds -= 2.0 * t / sj;
+        gsc[j] = 0.5 * n * sj * sj * sj * ds;
+    }
+    __syncthreads();
+    for (int e = tid; e < p * p; e += blockDim.x) {
+        const int i = e / p, j = e - i * p;
+        double s = a.dC[e] / (a.sigma[i] * a.sigma[j]);
+        for (int l = 0; l < p; ++l) s = fma(a.Ginv[(int64_t)i * p + l] * gsc[l], a.Ginv[(int64_t)l * p + j], s);
+        a.dG2[e] = 2.0 * s;
+    }
+}
+
+// dY[q][b] = sum_k dZ[k][q] P[b][k] + sum_j Y[q][j] dG2[j][b]; a block owns
+// 32 pixels x 32 bands.
+constexpr int kDyPix = 32, kDyCol = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_dy(AdjDesc a) {
+    __shared__ T yt[kDyPix][kMaxBands + 1];
+    __shared__ T gt[kMaxBands][kDyCol + 1];
+    __shared__ T zt[kMaxRank][kDyPix];
+    __shared__ T pt[kDyCol][kMaxRank + 1];
+    const int p = a.p, r = a.r;
+    const int64_t q0 = (int64_t)blockIdx.x * kDyPix;
+    const int b0 = blockIdx.y * kDyCol;
+    for (int e = threadIdx.x; e < kDyPix * p; e += 256) {
+        const int k = e / p, j = e - k * p;
+        const int64_t q = q0 + k;
+        yt[k][j] = q < a.n ? adj_pix<T>(a.Y, q, a.W, a.pitch, a.row_pitch)[j] : (T)0;
+    }
+    for (int e = threadIdx.x; e < p * kDyCol; e += 256) {
+        const int j = e / kDyCol, c = e - j * kDyCol;
+        gt[j][c] = b0 + c < p ? (T)a.dG2[(int64_t)j * p + b0 + c] : (T)0;
+    }
+    const T* zp = static_cast<const T*>(a.A);
+    for (int e = threadIdx.x; e < r * kDyPix; e += 256) {
+        const int k = e / kDyPix, i = e - k * kDyPix;
+        const int64_t q = q0 + i;
+        zt[k][i] = q < a.n ? zp[(int64_t)k * a.nz + q] : (T)0;
+    }
+    for (int e = threadIdx.x; e < kDyCol * r; e += 256) {
+        const int c = e / r, k = e - c * r;
+        pt[c][k] = b0 + c < p ? (T)a.P64[(int64_t)(b0 + c) * r + k] : (T)0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kDyPix * kDyCol; e += 256) {
+        const int i = e / kDyCol, c = e - i * kDyCol;
+        const int64_t q = q0 + i;
+        if (q >= a.n || b0 + c >= p) continue;
+        T s = (T)0;
+        for (int k = 0; k < r; ++k) s = fma(zt[k][i], pt[c][k], s);
+        for (int j = 0; j < p; ++j) s = fma(yt[i][j], gt[j][c], s);
+        const int64_t y = q / a.W, x = q - y * a.W;
+        static_cast<T*>(a.dY)[y * a.dyrp + x * a.dyp + b0 + c] = s;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_adjoint_pre(const AdjDesc& a, int dtype, hipStream_t s) {
+    // dZh and dQ
+    const unsigned gb = (unsigned)((a.n + 255) / 256);
+    if (dtype == HYRES_F64) {
+        hipLaunchKernelGGL(k_adj_apply<double>, dim3(gb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_adj_xprod<double>, dim3(a.slots), dim3(256), 0, s, a, a.Zh, a.dX, a.dxp, a.dxrp);
+    } else {
+        hipLaunchKernelGGL(k_adj_apply<float>, dim3(gb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_adj_xprod<float>, dim3(a.slots), dim3(256), 0, s, a, a.Zh, a.dX, a.dxp, a.dxrp);
+    }
+    const int E = a.r * a.p;
+    hipLaunchKernelGGL(k_adj_reduce, dim3((E + 255) / 256), dim3(256), 0, s, a.part, a.slots, E, a.dQ);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_thresh(const AdjDesc& a, int dtype, hipStream_t s) {
+    const dim3 grid(a.nchunk, a.r);
+    if (dtype == HYRES_F64) hipLaunchKernelGGL(k_adj_thresh<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_adj_thresh<float>, grid, dim3(256), 0, s, a);
+    if (a.dlambda)
+        hipLaunchKernelGGL(k_chunk_reduce, dim3(1), dim3(64), 0, s, a.lpart, a.nchunk, a.r, a.lambda, 0, a.dlambda);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_post(const AdjDesc& a, int dtype, hipStream_t s) {
+    // dP^T, the small FP64 algebra, then dY
+    if (dtype == HYRES_F64)
+        hipLaunchKernelGGL(k_adj_xprod<double>, dim3(a.slots), dim3(256), 0, s, a, a.A, a.Y, a.pitch, a.row_pitch);
+    else
+        hipLaunchKernelGGL(k_adj_xprod<float>, dim3(a.slots), dim3(256), 0, s, a, a.A, a.Y, a.pitch, a.row_pitch);
+    const int E = a.r * a.p;
+    hipLaunchKernelGGL(k_adj_reduce, dim3((E + 255) / 256), dim3(256), 0, s, a.part, a.slots, E, a.dPt);
+    hipLaunchKernelGGL(k_adj_solve, dim3(a.r + 1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_adj_combine, dim3(1), dim3(1024), 0, s, a);
+    const dim3 grid((unsigned)((a.n + kDyPix - 1) / kDyPix), (unsigned)((a.p + kDyCol - 1) / kDyCol));
+    if (dtype == HYRES_F64) hipLaunchKernelGGL(k_adj_dy<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_adj_dy<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sure_grad(int dtype, const void* coef, int64_t stride, int64_t N, int batch, const double* lambda,
+                            double* part, int nchunk, double* out, hipStream_t s) {
+    const dim3 grid(nchunk, batch);
+    if (dtype == HYRES_F64)
+        hipLaunchKernelGGL(k_sure_count<double>, grid, dim3(256), 0, s, static_cast<const double*>(coef), stride, N,
+                           lambda, nchunk, part);
+    else
+        hipLaunchKernelGGL(k_sure_count<float>, grid, dim3(256), 0, s, static_cast<const float*>(coef), stride, N,
+                           lambda, nchunk, part);
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((batch + 63) / 64), dim3(64), 0, s, part, nchunk, batch, lambda, 1, out);
+    return hipGetLastError();
+}
+
+}  // namespace hyres

@@ -12,6 +12,12 @@
 // coalesced loads, so every input element is read from HBM about once.  The
 // inverse applies the soft threshold sign(b) max(|b| - lambda, 0) as the
 // coefficients are loaded, so thresholded coefficients are never stored.
+//
+// The adjoint of the solve needs the transposes of both maps.  At an odd
+// length they differ from the other direction only at the extra sample: the
+// transpose of the inverse is the analysis with a zero extra sample
+// (kModeZeroPad), and the transpose of the analysis is the synthesis with the
+// extra output sample added to the last one (kModeFold).
 #include "hyres_internal.hpp"
 
 namespace hyres {
@@ -56,6 +62,9 @@ __global__ __launch_bounds__(TX* TY) void k_dwt_level(const CubeDesc* __restrict
         const T* src = level == 1 ? static_cast<const T*>(d.Z) + (int64_t)comp * d.nz
                                   : ll_buf<T>(d, comp, level - 1);
         const int he = h + (h & 1), we = w + (w & 1);
+        // the extra sample of an odd length repeats the last one, or is zero
+        // for the transpose of the inverse transform
+        const bool zpad = (d.mode & kModeZeroPad) != 0;
         constexpr int NV = (WH * WW + TX * TY - 1) / (TX * TY);
         T vals[NV];
 #pragma unroll
@@ -66,12 +75,15 @@ __global__ __launch_bounds__(TX* TY) void k_dwt_level(const CubeDesc* __restrict
                 int ey = 2 * oy0 + wy;
                 ey = ey >= he ? ey - he : ey;
                 ey = ey >= he ? ey % he : ey;
-                ey = ey == h ? h - 1 : ey;
+                const bool xy = ey == h;
+                ey = xy ? h - 1 : ey;
                 int ex = 2 * ox0 + wx;
                 ex = ex >= we ? ex - we : ex;
                 ex = ex >= we ? ex % we : ex;
-                ex = ex == w ? w - 1 : ex;
-                vals[i] = src[(int64_t)ey * w + ex];
+                const bool xx = ex == w;
+                ex = xx ? w - 1 : ex;
+                const T v = src[(int64_t)ey * w + ex];
+                vals[i] = zpad && (xy || xx) ? (T)0 : v;
             }
         }
         __syncthreads();
@@ -192,6 +204,18 @@ __global__ __launch_bounds__(TX* TY) void k_idwt_level(const CubeDesc* __restric
             T* dst = level == 1 ? static_cast<T*>(d.Z) + (int64_t)comp * d.nz
                                 : ll_buf<T>(d, comp, level - 1);
             const int y0 = 2 * s, x0 = 2 * u;
+            if (d.mode & kModeFold) {
+                // transpose of the analysis: the extra sample of an odd length
+                // is added to the last one instead of being dropped
+                if (y0 + 1 == h) {
+                    o00 += o10;
+                    o01 += o11;
+                }
+                if (x0 + 1 == w) {
+                    o00 += o01;
+                    o10 += o11;
+                }
+            }
             dst[(int64_t)y0 * w + x0] = o00;
             if (x0 + 1 < w) dst[(int64_t)y0 * w + x0 + 1] = o01;
             if (y0 + 1 < h) {

@@ -25,7 +25,7 @@ __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&
     const int tid = threadIdx.x;
     const int64_t nleft = d.n - q0;
     if (d.vec4) {
-        const float* base = static_cast<const float*>(d.Y) + q0 * d.pitch;
+        const float* base = pixel_ptr<float>(d, q0);   // a tile never crosses an image row
         const int g4 = d.p >> 2;
 #pragma unroll
         for (int i = 0; i < proj_nv4<T>(); ++i) {
@@ -124,6 +124,7 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
     constexpr int P16 = 16 * T;
     constexpr int LDO = P16 + 4;
     __shared__ __attribute__((aligned(16))) float ot[kPixTile * LDO];
+    __shared__ float s_w[kPixTile];          // blend weight per pixel (negative: first writer)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15, row = lane >> 4;
@@ -162,16 +163,32 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
 #pragma unroll
             for (int i = 0; i < 4; ++i) ot[(16 * wave + 4 * row + i) * LDO + 16 * j + col] = acc[i];
         }
-        __syncthreads();
         const int64_t nleft = d.n - q0;
+        const bool blend = d.bwy != nullptr;
+        if (blend && threadIdx.x < kPixTile && threadIdx.x < nleft) {
+            const int64_t q = q0 + threadIdx.x;
+            const int64_t y = q / d.W, x = q - y * d.W;
+            bool first;
+            const float w = (float)blend_weight(d, y, x, &first);
+            s_w[threadIdx.x] = first ? -w : w;
+        }
+        __syncthreads();
         if (d.xvec4) {
+            // whole 64-pixel tiles per image row: the pixels are consecutive in memory
             const int g4 = p >> 2;
-            float* base = static_cast<float*>(d.X) + q0 * d.xpitch;
+            const int64_t y0 = q0 / d.W, x0 = q0 - y0 * d.W;
+            float* base = static_cast<float*>(d.X) + y0 * d.xrow_pitch + x0 * d.xpitch;
             for (int e = threadIdx.x; e < kPixTile * g4; e += 256) {
                 const int k = e / g4, g = e - k * g4;
-                if (k < nleft)
-                    *reinterpret_cast<v4f*>(base + (int64_t)k * d.xpitch + 4 * g) =
-                        *reinterpret_cast<const v4f*>(ot + k * LDO + 4 * g);
+                if (k < nleft) {
+                    v4f* dst = reinterpret_cast<v4f*>(base + (int64_t)k * d.xpitch + 4 * g);
+                    v4f v = *reinterpret_cast<const v4f*>(ot + k * LDO + 4 * g);
+                    if (blend) {
+                        const float w = s_w[k];
+                        v = (__float_as_uint(w) >> 31) ? v * (-w) : *dst + v * w;
+                    }
+                    *dst = v;
+                }
             }
         } else {
             for (int e = threadIdx.x; e < kPixTile * p; e += 256) {
@@ -179,7 +196,13 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
                 if (k < nleft) {
                     const int64_t q = q0 + k;
                     const int64_t y = q / d.W, x = q - y * d.W;
-                    static_cast<float*>(d.X)[y * d.xrow_pitch + x * d.xpitch + b] = ot[k * LDO + b];
+                    float* dst = static_cast<float*>(d.X) + y * d.xrow_pitch + x * d.xpitch + b;
+                    float v = ot[k * LDO + b];
+                    if (blend) {
+                        const float w = s_w[k];
+                        v = (__float_as_uint(w) >> 31) ? v * (-w) : *dst + v * w;
+                    }
+                    *dst = v;
                 }
             }
         }
@@ -211,9 +234,12 @@ __global__ void k_backproject_f64(const CubeDesc* __restrict__ descs, int cube) 
     for (int g = 0; g < d.r; ++g) a[g] = zh[(int64_t)g * d.nz + q];
     const int64_t y = q / d.W, x = q - y * d.W;
     double* xo = static_cast<double*>(d.X) + y * d.xrow_pitch + x * d.xpitch;
+    bool first = true;
+    const double w = d.bwy ? blend_weight(d, y, x, &first) : 1.0;
     for (int b = 0; b < d.p; ++b) {
         double s = 0.0;
         for (int g = 0; g < d.r; ++g) s = fma(a[g], d.Q64[(int64_t)g * d.p + b], s);
+        if (d.bwy) s = first ? s * w : fma(s, w, xo[b]);
         xo[b] = s;
     }
 }

@@ -76,13 +76,14 @@ __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int la
 }
 
 // Load one chunk of kGramKB pixels (all 16T band slots) into registers.
-// vec: the cube is contiguous with 16-byte aligned pixel rows and p % 4 == 0.
+// vec: 16-byte aligned pixel vectors, p % 4 == 0, and the 64 pixels of a chunk
+// consecutive in memory (a contiguous cube, or whole chunks per image row).
 template <int T>
 __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t q1, bool vec,
                                            float (&r)[gram_nr<T>()]) {
     const int tid = threadIdx.x;
     if (vec) {
-        const float* base = static_cast<const float*>(d.Y) + q * d.pitch;
+        const float* base = pixel_ptr<float>(d, q);   // a chunk never crosses an image row
         const int g4 = d.p >> 2;                     // float4 groups per pixel
 #pragma unroll
         for (int i = 0; i < gram_nv4<T>(); ++i) {
@@ -267,7 +268,7 @@ template <int T> __host__ __device__ constexpr int gramb_nt() {
 template <int T>
 __device__ __forceinline__ void gramb_fetch(const CubeDesc& d, int64_t q, int64_t q1, v4f (&r)[gramb_nt<T>()][8]) {
     const int tid = threadIdx.x;
-    const float* base = static_cast<const float*>(d.Y) + q * d.pitch;
+    const float* base = pixel_ptr<float>(d, q);   // a chunk never crosses an image row
     const int g4 = d.p >> 2;
 #pragma unroll
     for (int i = 0; i < gramb_nt<T>(); ++i) {

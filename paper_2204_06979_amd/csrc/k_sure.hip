@@ -17,9 +17,10 @@
 //     N - 2(C + c) + S + (N - C) t_min^2.
 // Bins whose lower bound exceeds the best exact value seen are discarded.
 // When the surviving bins hold at most kSureCap values, the next pass
-// collects exactly those values and the select kernel finishes exactly: it
-// sorts them in LDS and evaluates SURE at every one from the counts below
-// each bin and prefix sums inside it.  Otherwise the next round refines the
+// collects exactly those values, grouped by bin, and the select kernel
+// finishes exactly: for every collected value it adds the count and sum of
+// squares of the values of its own bin that do not exceed it to the totals
+// below the bin, and evaluates SURE there.  Otherwise the next round refines the
 // key range spanned by the surviving bins (bins of width 1 are exact too).
 // The smallest minimising candidate is returned.
 #include "hyres_internal.hpp"
@@ -87,7 +88,6 @@ __global__ void k_sure_init(const CubeDesc* __restrict__ descs, const int* __res
             st.done = 0;
             st.inexact = 0;
             st.gather = 0;
-            st.ncand = 0;
             st.nsurv = 0;
             d.sst[comp] = st;
         }
@@ -214,7 +214,9 @@ __device__ void sure_finish(const CubeDesc& d, int comp, SureState& st, double N
     uint64_t* keys = reinterpret_cast<uint64_t*>(raw);     // kSureCap
     __shared__ double s_bs2[kSelThreads], s_bt2[kSelThreads];
     const int tid = threadIdx.x;
-    const unsigned int nc = st.ncand < (unsigned)kSureCap ? st.ncand : (unsigned)kSureCap;
+    // the gather pass re-reads the values the last histogram counted, so the
+    // surviving bins hold exactly nsurv (<= kSureCap) values
+    const unsigned int nc = st.nsurv < (unsigned)kSureCap ? st.nsurv : (unsigned)kSureCap;
     const uint64_t* src = d.cand + (int64_t)comp * kSureCap;
     for (int i = tid; i < (int)nc; i += kSelThreads) keys[i] = src[i];
     __syncthreads();
@@ -266,7 +268,6 @@ __device__ void sure_finish(const CubeDesc& d, int comp, SureState& st, double N
         st.best_s = b_s;
         st.best_t = b_t;
         st.done = 1;
-        if (st.ncand != st.nsurv) st.inexact = 1;
     }
 }
 
@@ -472,7 +473,6 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
                 ns.done = 1;
             } else if (gather) {
                 ns.gather = 1;
-                ns.ncand = 0;
                 ns.nsurv = (unsigned int)msurv;
             } else {
                 ns.klo = st.klo + ((uint64_t)fb << st.width);

@@ -19,14 +19,19 @@ Recipe (fixed so that every run is reproducible):
     standardised per map, then softmax across the r maps at every pixel.
   * spectra: natural cubic spline through 6 knots at linspace(0, p-1, 6) with
     U[0,1] values, evaluated at 0..p-1, clipped to [0, 1].
-  * noise: sigma_b = sqrt(mean_pixels(X_b^2) / 10^(SNR_b/10)), i.i.d. per voxel.
+  * noise: sigma_b = sqrt(mean_pixels(X_b^2) / 10^(SNR_b/10)), i.i.d. per voxel;
+    each chunk of 65536 pixels draws from its own generator, spawned from a
+    seed that the cube's generator draws after the spectra and SNRs.
   * dead columns: round(0.2 p) bands, round(0.05 W) columns each, set to 0.
   * impulses: 1% of voxels per band set to that band's min or max (p = 1/2),
-    min/max taken just before impulses are applied.
+    min/max taken just before impulses are applied; one uniform draw per
+    voxel from a per-band generator (spawned like the noise seeds).
 """
 from __future__ import annotations
 
 import dataclasses
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -92,15 +97,22 @@ def spectra(rng: np.random.Generator, p: int, r: int, knots: int = 6) -> np.ndar
     return E
 
 
+def _pool(workers: int, jobs: int) -> int:
+    return max(1, min(workers if workers else (os.cpu_count() or 1), 16, jobs))
+
+
 def mixing_cube(seed, H: int, W: int, p: int, r: int, snr_db, levels: int,
                 dtype=np.float32, keep_clean: bool = True,
                 dead_columns: bool = False, impulses: bool = False,
-                row_chunk: int = 1 << 16) -> Cube:
+                row_chunk: int = 1 << 16, workers: int = 0) -> Cube:
     """Y = A E^T + N (+ optional dead columns and impulses), H x W x p.
 
     ``snr_db`` is a scalar (same SNR for every band) or a pair (lo, hi) for a
-    per-band SNR drawn uniformly in [lo, hi] dB.  Work is done in row chunks so
-    that multi-GB cubes fit in host memory.
+    per-band SNR drawn uniformly in [lo, hi] dB.  The noise of each chunk of
+    ``row_chunk`` pixels and the impulses of each band come from their own
+    generators, spawned from one seed drawn by the cube's generator, so the
+    work runs on ``workers`` threads (0: all cores) with values that do not
+    depend on the thread count, and multi-GB cubes fit in host memory.
     """
     rng = _rng(seed)
     n = H * W
@@ -111,21 +123,31 @@ def mixing_cube(seed, H: int, W: int, p: int, r: int, snr_db, levels: int,
     else:
         lo, hi = snr_db
         snr = rng.uniform(lo, hi, size=p)
+    noise_seed = np.random.SeedSequence(int(rng.integers(0, 2 ** 63 - 1)))
+    starts = list(range(0, n, row_chunk))
+    nw = _pool(workers, len(starts))
+
     # mean-square signal power per band
-    power = np.zeros(p)
-    for s in range(0, n, row_chunk):
-        Xc = A[s:s + row_chunk] @ E.T
-        power += np.einsum("ij,ij->j", Xc, Xc)
-    power /= n
+    def power_of(s0):
+        Xc = A[s0:s0 + row_chunk] @ E.T
+        return np.einsum("ij,ij->j", Xc, Xc)
+
+    with ThreadPoolExecutor(nw) as ex:
+        power = np.sum(list(ex.map(power_of, starts)), axis=0) / n
     sigma = np.sqrt(power / 10.0 ** (snr / 10.0))
     Y = np.empty((n, p), dtype=dtype)
     X = np.empty((n, p), dtype=np.float64) if keep_clean else None
-    for s in range(0, n, row_chunk):
-        Xc = A[s:s + row_chunk] @ E.T
-        Nc = rng.standard_normal(Xc.shape) * sigma[None, :]
-        Y[s:s + row_chunk] = Xc + Nc
+
+    def fill(job):
+        s0, ss = job
+        Xc = A[s0:s0 + row_chunk] @ E.T
+        Nc = _rng(ss).standard_normal(Xc.shape) * sigma[None, :]
+        Y[s0:s0 + row_chunk] = Xc + Nc
         if keep_clean:
-            X[s:s + row_chunk] = Xc
+            X[s0:s0 + row_chunk] = Xc
+
+    with ThreadPoolExecutor(nw) as ex:
+        list(ex.map(fill, zip(starts, noise_seed.spawn(len(starts)))))
     Y3 = Y.reshape(H, W, p)
     if dead_columns:
         nb = int(round(0.2 * p))
@@ -135,13 +157,19 @@ def mixing_cube(seed, H: int, W: int, p: int, r: int, snr_db, levels: int,
             cols = rng.choice(W, size=nc, replace=False)
             Y3[:, cols, b] = 0
     if impulses:
-        for b in range(p):
+        imp_seed = np.random.SeedSequence(int(rng.integers(0, 2 ** 63 - 1)))
+
+        # one uniform draw per voxel: below 0.005 the band maximum, in [0.005, 0.01) the minimum
+        def corrupt(job):
+            b, ss = job
             band = Y3[:, :, b]
             lo_v, hi_v = band.min(), band.max()
-            mask = rng.random((H, W)) < 0.01
-            hi_mask = rng.random((H, W)) < 0.5
-            band[mask & hi_mask] = hi_v
-            band[mask & ~hi_mask] = lo_v
+            u = _rng(ss).random((H, W))
+            band[u < 0.005] = hi_v
+            band[(u >= 0.005) & (u < 0.01)] = lo_v
+
+        with ThreadPoolExecutor(_pool(workers, p)) as ex:
+            list(ex.map(corrupt, zip(range(p), imp_seed.spawn(p))))
     return Cube(Y=Y3, X=None if X is None else X.reshape(H, W, p),
                 sigma_true=sigma, rank=r, levels=levels,
                 seed=seed if not isinstance(seed, np.random.SeedSequence) else -1)
@@ -167,9 +195,9 @@ def config_cube(cfg: int, keep_clean: bool = True, **over) -> Cube:
 
 def config3_cubes(count: int = 64, keep_clean: bool = False,
                   hw_range=(128, 512), bands=(103, 128, 191, 224),
-                  ranks=(4, 12), levels: int = 4) -> List[Cube]:
+                  ranks=(4, 12), levels: int = 4, workers: int = 0) -> List[Cube]:
     """Workload 3: independent cubes of uneven size, one seed stream each."""
-    out = []
+    specs = []
     for ss in np.random.SeedSequence(3).spawn(count):
         rng = _rng(ss)
         H = int(rng.integers(hw_range[0], hw_range[1] + 1))
@@ -177,9 +205,18 @@ def config3_cubes(count: int = 64, keep_clean: bool = False,
         p = int(rng.choice(np.asarray(bands)))
         r = int(rng.integers(ranks[0], ranks[1] + 1))
         sub = rng.integers(0, 2 ** 63 - 1)
-        out.append(mixing_cube(int(sub), H, W, p, r, 10.0, levels,
-                               dtype=np.float32, keep_clean=keep_clean))
-    return out
+        specs.append((int(sub), H, W, p, r))
+
+    def one(spec):
+        sub, H, W, p, r = spec
+        return mixing_cube(sub, H, W, p, r, 10.0, levels, dtype=np.float32, keep_clean=keep_clean, workers=1)
+
+    # every cube has its own seed, so the worker count does not change the values
+    workers = max(1, min(workers if workers else (os.cpu_count() or 1), 16, count))
+    if workers == 1:
+        return [one(s) for s in specs]
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(one, specs))
 
 
 def tile_starts(size: int, tile: int, overlap: int) -> List[int]:

@@ -104,3 +104,52 @@ def test_entry_points_reject_bad_arguments_before_touching_the_device():
     assert lib.hyres_sure_threshold(h, wsp, 2, 100, 50, 0, wsp, None, None, wsp_al, 1 << 40, None) == 2
     # estimate_noise requires sigma_out
     assert lib.hyres_estimate_noise(h, wsp, 8, 8, 4, 4, 32, 0, None, None, None, wsp_al, 1 << 20, None) == 1
+
+
+def test_tile_grid_matches_the_generator_rule():
+    from paper_2204_06979_amd import synth
+    L, lib = _lib()
+    n = C.c_int()
+    buf = (C.c_int * 64)()
+    for size, tile, ov in [(2048, 512, 32), (1000, 512, 32), (512, 512, 32), (300, 512, 32), (260, 128, 16),
+                           (129, 64, 0), (4096, 256, 64)]:
+        assert lib.hyres_tile_grid(size, tile, ov, buf, C.byref(n)) == 0
+        assert [buf[i] for i in range(n.value)] == synth.tile_starts(size, tile, ov), (size, tile, ov)
+    assert lib.hyres_tile_grid(2048, 512, 300, buf, C.byref(n)) == 2      # overlap > tile / 2
+    assert lib.hyres_tile_grid(100000, 64, 0, buf, C.byref(n)) == 6       # more than 64 tiles
+    nb = C.c_size_t()
+    opt = L.Options(10, 4, L.PREC_MIXED, L.SCOPE_ALL)
+    assert lib.hyres_tiled_workspace_size(2048, 2048, 224, 512, 32, C.byref(opt), L.HYRES_F32, C.byref(nb)) == 0
+    per_tile = C.c_size_t()
+    assert lib.hyres_denoise_workspace_size(512, 512, 224, C.byref(opt), L.HYRES_F32, C.byref(per_tile)) == 0
+    assert 25 * per_tile.value * 0.9 < nb.value < 25 * per_tile.value * 1.1
+    # a tile too small for the levels
+    assert lib.hyres_tiled_workspace_size(256, 256, 32, 16, 4, C.byref(opt), L.HYRES_F32, C.byref(nb)) == 2
+
+
+def test_batch_workspace_and_validation():
+    L, lib = _lib()
+    nb = C.c_size_t()
+    opt = L.Options(0, 0, L.PREC_MIXED, L.SCOPE_ALL)
+    cubes = (L.Cube * 3)()
+    for i, (H, W, p, r, lv) in enumerate([(128, 200, 103, 6, 4), (300, 129, 224, 12, 4), (64, 64, 32, 4, 3)]):
+        cubes[i].H, cubes[i].W, cubes[i].p, cubes[i].rank, cubes[i].levels = H, W, p, r, lv
+    assert lib.hyres_batch_workspace_size(cubes, 3, L.HYRES_F32, C.byref(opt), C.byref(nb)) == 0
+    total = 0
+    for i in range(3):
+        one = C.c_size_t()
+        o = L.Options(cubes[i].rank, cubes[i].levels, L.PREC_MIXED, L.SCOPE_ALL)
+        assert lib.hyres_denoise_workspace_size(cubes[i].H, cubes[i].W, cubes[i].p, C.byref(o), L.HYRES_F32,
+                                                C.byref(one)) == 0
+        total += one.value
+    assert total * 0.9 < nb.value < total * 1.1
+    cubes[1].rank = 17
+    assert lib.hyres_batch_workspace_size(cubes, 3, L.HYRES_F32, C.byref(opt), C.byref(nb)) == 2
+    cubes[1].rank = 12
+    assert lib.hyres_batch_workspace_size(cubes, 3, L.HYRES_F64, C.byref(opt), C.byref(nb)) == 3   # mixed needs F32
+    assert lib.hyres_batch_workspace_size(cubes, 0, L.HYRES_F32, C.byref(opt), C.byref(nb)) == 2
+    # creation rejects missing cube pointers before touching the device
+    fake = C.create_string_buffer(64)
+    bp = C.c_void_p()
+    assert lib.hyres_batch_create(C.cast(fake, C.c_void_p), cubes, 3, L.HYRES_F32, C.byref(opt), None, 0, None,
+                                  C.byref(bp)) == 1

@@ -1,0 +1,144 @@
+"""Sliding-window denoising (needs an MI355X).
+
+Small grids are compared whole with the oracle's tiled solve; the full
+2048 x 2048 x 224 workload is checked on sampled regions: a tile interior, a
+four-tile corner and the wide overlap of the clamped last tiles, each against
+the oracle solves of the tiles covering it, blended by the oracle's rule.
+Where the device picks a different but equally good SURE threshold for a tile
+the oracle is run at the device's thresholds (their risk is checked first).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import hyres_oracle as O
+from paper_2204_06979_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_06979_amd import api
+    return api
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _tile_oracle(sub, r, L, lam_dev, slack):
+    """Oracle solve of one tile at the oracle's SURE thresholds, or at the
+    device's where those tie the oracle's minimum within `slack`."""
+    ref = O.hyres(sub, r, L)
+    if np.array_equal(lam_dev, ref["lam"]):
+        return ref["X"]
+    for k in range(r):
+        if lam_dev[k] != ref["lam"][k]:
+            assert O.sure_at(ref["B"][k], lam_dev[k]) - ref["sure"][k] <= slack, (k, lam_dev[k], ref["lam"][k])
+    return O.hyres(sub, r, L, lam=lam_dev)["X"]
+
+
+@pytest.mark.parametrize("dtype,prec,tol", [(np.float64, "native", 1e-10), (np.float32, "native", 1e-5),
+                                            (np.float32, "mixed", 1e-3)])
+@pytest.mark.parametrize("H,W,p,r,L,tile,ov", [(300, 260, 40, 4, 3, 128, 16), (200, 130, 64, 5, 2, 64, 8),
+                                               (97, 300, 17, 2, 2, 128, 32)])
+def test_tiled_matches_oracle(dtype, prec, tol, H, W, p, r, L, tile, ov):
+    api = _api()
+    say("tiled", H, W, p, "r", r, "L", L, "tile", tile, ov, dtype.__name__, prec)
+    c = synth.mixing_cube(H * 7 + W, H, W, p, r, 12.0, L, dtype=np.float64, keep_clean=False)
+    Y = (c.Y + 1e-3 * np.random.default_rng(H).standard_normal(c.Y.shape)).astype(dtype)
+    X, info = api.denoise_tiled(torch.tensor(Y, device="cuda"), r, L, tile=tile, overlap=ov, precision=prec)
+    X = X.cpu().numpy()
+    assert int(info["status"].cpu()[0]) & ~8 == 0
+    sy, sx = api.tile_grid(H, tile, ov), api.tile_grid(W, tile, ov)
+    assert sy == synth.tile_starts(H, tile, ov) and sx == synth.tile_starts(W, tile, ov)
+    lam = info["lam"].cpu().numpy()
+    th, tw = min(tile, H), min(tile, W)
+    slack = (1e-6 if prec == "native" else 1e-3) * O.coeff_count(th, tw, L)
+    it = iter(range(len(sy) * len(sx)))
+    Y64 = Y.astype(np.float64)
+    ref = O.hyres_tiled(Y64, r, L, tile, ov, sy, sx,
+                        tile_fn=lambda sub: _tile_oracle(sub, r, L, lam[next(it)], slack))
+    e = rel(X, ref)
+    say("   rel err", e)
+    assert e <= tol
+
+
+def test_tiled_fp32_tiles_use_vector_path_and_match_single_solves():
+    """With one tile per axis the tiled solve is the plain solve."""
+    api = _api()
+    c = synth.mixing_cube(5, 128, 192, 32, 4, 12.0, 3, dtype=np.float32, keep_clean=False)
+    Yt = torch.tensor(c.Y, device="cuda")
+    X1, _ = api.denoise(Yt, 4, 3, precision="mixed")
+    X2, _ = api.denoise_tiled(Yt, 4, 3, tile=256, overlap=32, precision="mixed")
+    assert torch.equal(X1, X2)
+
+
+@pytest.mark.slow
+def test_config5_sliding_window_sampled():
+    api = _api()
+    say("config5: generating")
+    cube = synth.config_cube(5, keep_clean=False)
+    Y = cube.Y
+    H, W, p = Y.shape
+    r, L, tile, ov = 10, 4, 512, 32
+    say("config5", Y.shape)
+    Yt = torch.tensor(Y, device="cuda")
+    X, info = api.denoise_tiled(Yt, r, L, tile=tile, overlap=ov, precision="mixed")
+    torch.cuda.synchronize()
+    st = int(info["status"].cpu()[0])
+    assert st & ~8 == 0, st
+    lam = info["lam"].cpu().numpy()
+    sy, sx = api.tile_grid(H, tile, ov), api.tile_grid(W, tile, ov)
+    nx = len(sx)
+    slack = 1e-3 * O.coeff_count(tile, tile, L)
+    cache = {}
+
+    def tile_out(iy, ix):
+        if (iy, ix) not in cache:
+            say("   oracle tile", iy, ix)
+            sub = Y[sy[iy]:sy[iy] + tile, sx[ix]:sx[ix] + tile].astype(np.float64)
+            cache[(iy, ix)] = _tile_oracle(sub, r, L, lam[iy * nx + ix], slack)
+        return cache[(iy, ix)]
+
+    wy = [O.tile_weights_1d(s, tile, H, ov) for s in sy]
+    wx = [O.tile_weights_1d(s, tile, W, ov) for s in sx]
+
+    def blended(y0, y1, x0, x1):
+        acc = np.zeros((y1 - y0, x1 - x0, p))
+        ws = np.zeros((y1 - y0, x1 - x0))
+        for iy, s_y in enumerate(sy):
+            a, b = max(y0, s_y), min(y1, s_y + tile)
+            if a >= b:
+                continue
+            for ix, s_x in enumerate(sx):
+                c0, c1 = max(x0, s_x), min(x1, s_x + tile)
+                if c0 >= c1:
+                    continue
+                w2 = wy[iy][a - s_y:b - s_y, None] * wx[ix][None, c0 - s_x:c1 - s_x]
+                acc[a - y0:b - y0, c0 - x0:c1 - x0] += w2[:, :, None] * tile_out(iy, ix)[a - s_y:b - s_y,
+                                                                                        c0 - s_x:c1 - s_x]
+                ws[a - y0:b - y0, c0 - x0:c1 - x0] += w2
+        return acc / ws[:, :, None]
+
+    Xc = X.cpu()
+    regions = [(100, 164, 100, 164),          # interior of tile (0, 0)
+               (470, 500, 470, 500),          # corner shared by tiles (0..1, 0..1)
+               (1530, 1560, 1530, 1560)]      # overlap of the clamped last tiles
+    for (y0, y1, x0, x1) in regions:
+        ref = blended(y0, y1, x0, x1)
+        got = Xc[y0:y1, x0:x1].numpy()
+        e = rel(got, ref)
+        say("   region", (y0, y1, x0, x1), "rel err", e)
+        assert e <= 1e-3

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhyres.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["k_gram.hip", "k_small.hip", "k_gemm.hip", "k_dwt.hip", "k_sure.hip", "k_adjoint.hip", "hyres_api.hip"]
+SOURCES = ["k_gram.hip", "k_small.hip", "k_gemm.hip", "k_dwt.hip", "k_sure.hip", "k_adjoint.hip", "k_ritz.hip",
+           "hyres_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",

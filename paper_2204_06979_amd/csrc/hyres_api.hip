@@ -38,6 +38,7 @@ hipError_t launch_sure_init(int dtype, const CubeDesc*, const int*, int, int, hi
 hipError_t launch_sure_round(int dtype, const CubeDesc*, const int*, const int*, int, int, int, hipStream_t);
 int sure_rounds(int dtype);
 int sure_chunk();
+hipError_t launch_ritz(const CubeDesc*, const int*, const int*, int, const int*, int, int, int, hipStream_t);
 hipError_t launch_adjoint_pre(const AdjDesc&, int dtype, hipStream_t);
 hipError_t launch_adjoint_thresh(const AdjDesc&, int dtype, hipStream_t);
 hipError_t launch_adjoint_post(const AdjDesc&, int dtype, hipStream_t);
@@ -172,7 +173,7 @@ struct CubePlan {
     size_t o_gpart = 0, o_G = 0, o_sigma = 0, o_hv = 0, o_V = 0, o_evals = 0, o_gap = 0, o_P32 = 0, o_Q32 = 0,
            o_P64 = 0, o_Q64 = 0, o_Z = 0, o_coef = 0, o_tmp = 0, o_hcnt = 0, o_hsum = 0, o_hmin = 0,
            o_hmax = 0, o_sst = 0, o_lambda = 0, o_sure = 0, o_sbits = 0, o_spre = 0, o_sspre = 0, o_scb = 0,
-           o_cand = 0, o_sfill = 0;
+           o_cand = 0, o_sfill = 0, o_rpart = 0, o_rrot = 0;
     bool has_lambda = false;   // thresholds given by the caller: no SURE search
 };
 
@@ -218,6 +219,10 @@ void plan_cube(CubePlan& c, Layout& lay, int parts) {
         c.o_Q32 = lay.add((size_t)16 * c.T * 16 * 4);
         c.o_P64 = lay.add((size_t)c.p * std::max(c.r, 1) * 8);
         c.o_Q64 = lay.add((size_t)c.p * std::max(c.r, 1) * 8);
+        if ((parts & P_GRAM) && c.precision == HYRES_PREC_MIXED) {
+            c.o_rpart = lay.add((size_t)c.gslots * 256 * 8);
+            c.o_rrot = lay.add(256 * 8);
+        }
     }
     const int es = esize(c.dtype);
     if (parts & P_IMG) {
@@ -287,6 +292,10 @@ CubeDesc make_desc(const CubePlan& c, void* ws) {
         d.Q32 = at<float>(ws, c.o_Q32);
         d.P64 = at<double>(ws, c.o_P64);
         d.Q64 = at<double>(ws, c.o_Q64);
+        if (c.o_rpart) {
+            d.rpart = at<double>(ws, c.o_rpart);
+            d.rrot = at<double>(ws, c.o_rrot);
+        }
     }
     if (c.o_Z || c.o_coef) {
         d.Z = at<void>(ws, c.o_Z);
@@ -330,7 +339,7 @@ enum { S_GRAM = 1, S_SMALL = 2, S_PROJ = 4, S_DWT = 8, S_SURE = 16, S_IDWT = 32,
 
 enum Kind {
     K_GRAM_F32, K_GRAM_BF16, K_GRAM_RED, K_GRAM_F64, K_SMALL, K_PROJ_F32, K_PROJ_F64, K_DWT, K_IDWT,
-    K_SURE_INIT, K_SURE_ROUND, K_COPY, K_BP_F32, K_BP_F64
+    K_SURE_INIT, K_SURE_ROUND, K_COPY, K_BP_F32, K_BP_F64, K_RITZ
 };
 
 struct Launch {
@@ -360,10 +369,11 @@ int small_class(int p) {
 // projection items and the reduce list; back-projection items per class, or
 // per blend pass of a tile grid (whose tiles share one class); per small-solve
 // class a list; SURE component and histogram items; per level, direction and
-// tile candidate the DWT items; plus one scratch table for the tuner.
+// tile candidate the DWT items; the Rayleigh-Ritz slot and pixel items and
+// cube list; plus one scratch table for the tuner.
 constexpr int kMaxColours = 8;    // blend colours per axis of a tile grid
 constexpr int kMaxTables = 3 * 14 + std::max(14, kMaxColours * kMaxColours) + kSmallClasses + 2 +
-                           2 * kMaxLevels * kTileCands + 1;
+                           2 * kMaxLevels * kTileCands + 3 + 1;
 size_t table_ints(int count) { return (size_t)kMaxTables * (count + 1); }
 
 struct Exec {
@@ -527,6 +537,27 @@ void build_program(Exec& x, int stages) {
     if (stages & S_PROJ) {
         if (f64) per_cube(K_PROJ_F64, HYRES_STAGE_PROJECT);
         else per_T(K_PROJ_F32, HYRES_STAGE_PROJECT, 8, [](const CubePlan& c) { return cdiv(c.n, kPixTile); });
+        if (x.precision == HYRES_PREC_MIXED && !f64) {
+            // the FP32 refinement of the subspace (Rayleigh-Ritz on T^T T)
+            std::vector<int64_t> slots(N), pix(N);
+            std::vector<int> ids(N);
+            for (int i = 0; i < N; ++i) {
+                slots[i] = x.plan[i].gslots;
+                pix[i] = cdiv(x.plan[i].n, 256);
+                ids[i] = i;
+            }
+            int64_t ns, np;
+            Launch R{};
+            R.kind = K_RITZ;
+            R.stage = HYRES_STAGE_PROJECT;
+            R.a = x.counts(slots, &ns);
+            R.b = x.counts(pix, &np);
+            R.key = x.list(ids);
+            R.n = N;
+            R.grid = x.grid(ns, 4);
+            R.grid2 = x.grid(np, 8);
+            x.prog.push_back(R);
+        }
     }
     if (stages & S_DWT) add_dwt(x, false);
     if (stages & S_SURE) {
@@ -608,6 +639,8 @@ hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
             return hipGetLastError();
         case K_BP_F32: return launch_backproject_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
         case K_BP_F64: return launch_backproject_f64(D, L.a, L.n64, s);
+        case K_RITZ:
+            return launch_ritz(D, x.table(L.a), x.table(L.key), L.n, x.table(L.b), L.n, L.grid, L.grid2, s);
     }
     return hipErrorInvalidValue;
 }
@@ -814,13 +847,15 @@ HYRES_API int64_t hyres_coeff_count(int H, int W, int L) {
 }
 
 // Single-cube executor of the given geometry.
-static void one_cube(Exec& x, hyres_handle* h, int H, int W, int p, int r, int L, int dtype, int scope) {
+static void one_cube(Exec& x, hyres_handle* h, int H, int W, int p, int r, int L, int dtype, int scope,
+                     int precision = HYRES_PREC_NATIVE) {
     x.h = h;
     x.count = 1;
     x.dtype = dtype;
+    x.precision = precision;
     x.plan.resize(1);
     CubePlan& c = x.plan[0];
-    c.H = H; c.W = W; c.p = p; c.r = r; c.L = L; c.dtype = dtype; c.scope = scope;
+    c.H = H; c.W = W; c.p = p; c.r = r; c.L = L; c.dtype = dtype; c.scope = scope; c.precision = precision;
 }
 
 // ------------------------------------------------------------- noise
@@ -1035,7 +1070,7 @@ HYRES_API hyres_status hyres_denoise_workspace_size(int H, int W, int p, const h
     hyres_status st = check_opts(opt, p, dtype);
     if (st) return st;
     Exec x;
-    one_cube(x, nullptr, H, W, p, opt->rank, opt->levels, dtype, opt->scope);
+    one_cube(x, nullptr, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
     if ((st = plan_cubes(x, kAllParts))) return st;
     *bytes = x.lay.total;
     return HYRES_OK;
@@ -1052,9 +1087,7 @@ HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int 
     if ((st = check_opts(opt, p, dtype))) return st;
     if (x_pitch < p || x_row_pitch < (int64_t)(W - 1) * x_pitch + p) return HYRES_E_SHAPE;
     Exec x;
-    one_cube(x, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope);
-    x.precision = opt->precision;
-    x.plan[0].precision = opt->precision;
+    one_cube(x, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
     x.plan[0].has_lambda = lambda_in != nullptr;
     if ((st = plan_cubes(x, kAllParts))) return st;
     if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
@@ -1217,7 +1250,7 @@ hyres_status plan_backward(BwdPlan& b, hyres_handle* h, int H, int W, int p, con
     if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
     hyres_status st = check_opts(opt, p, dtype);
     if (st) return st;
-    one_cube(b.fwd, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope);
+    one_cube(b.fwd, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
     if ((st = plan_cubes(b.fwd, kAllParts))) return st;
     const CubePlan& c = b.fwd.plan[0];
     const int r = c.r, es = esize(dtype);

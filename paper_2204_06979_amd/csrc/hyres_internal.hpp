@@ -76,6 +76,8 @@ struct CubeDesc {
     double* gap;                            // 1
     float* P32; float* Q32;                 // (16T x 16) projection and (16 x 16T) back-projection
     double* P64; double* Q64;               // (p x r) and (r x p)
+    double* rpart;                          // Rayleigh-Ritz slot sums, gslots x 16 x 16 (mixed solves)
+    double* rrot;                           // Rayleigh-Ritz rotation, 16 x 16
     void* Z;                                // r x nz component images (also the denoised ones)
     void* coef;                             // r x ncs coefficients
     void* tmp;                              // r x tps approximation buffers

@@ -1,0 +1,240 @@
+// Rayleigh-Ritz refinement of the subspace (mixed-precision solves).
+//
+// In the mixed solve the eigenvectors V0 come from a band Gram built from
+// split-BF16 products.  The projection then computes T = Y D^-1 V0 from the
+// FP32 cube, so M = T^T T = V0^T C V0 holds C to FP32-product accuracy.  Its
+// FP64 eigendecomposition M = U Lambda U^T gives the Ritz pairs inside
+// span(V0): V = V0 U (sign rule re-applied), Z = T U, and Lambda, the top
+// eigenvalues at FP32 accuracy.  This is the one FP32 pass that recovers what
+// the BF16 products lose in the orientation of the basis and the eigenvalues.
+//
+//   k_ritz_gram    per slot of pixels: FP32 sums of T^T T over 64-pixel
+//                  chunks, accumulated in FP64 (fixed order, no atomics)
+//   k_ritz         one workgroup per cube: slot sums in FP64, cyclic Jacobi
+//                  (parallel pair ordering), sort, sign rule, new V, evals,
+//                  projection matrices and the r x r rotation
+//   k_ritz_rotate  Z <- Z R in place, one pixel per thread
+#include "hyres_internal.hpp"
+
+namespace hyres {
+
+constexpr int kRitzPix = 64;
+
+__global__ __launch_bounds__(256) void k_ritz_gram(const CubeDesc* __restrict__ descs,
+                                                   const int* __restrict__ items, int ncubes) {
+    __shared__ float zt[kMaxRank][kRitzPix + 1];
+    const int total = items[ncubes];
+    const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_cube(items, ncubes, item);
+        const CubeDesc& d = descs[c];
+        const int slot = item - items[c];
+        const int r = d.r;
+        int64_t per = (d.n + d.gslots - 1) / d.gslots;
+        per = (per + kRitzPix - 1) / kRitzPix * kRitzPix;
+        const int64_t q0 = (int64_t)slot * per;
+        const int64_t q1 = q0 + per < d.n ? q0 + per : d.n;
+        const float* z = static_cast<const float*>(d.Z);
+        double acc = 0.0;
+        for (int64_t t0 = q0; t0 < q1; t0 += kRitzPix) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < r * kRitzPix; e += 256) {
+                const int k = e / kRitzPix, j = e - k * kRitzPix;
+                zt[k][j] = t0 + j < q1 ? z[(int64_t)k * d.nz + t0 + j] : 0.f;
+            }
+            __syncthreads();
+            if (a < r && b < r) {
+                float s = 0.f;
+#pragma unroll 8
+                for (int j = 0; j < kRitzPix; ++j) s = fmaf(zt[a][j], zt[b][j], s);
+                acc += (double)s;
+            }
+        }
+        d.rpart[(int64_t)slot * 256 + threadIdx.x] = acc;
+    }
+}
+
+// Partner of index x (0..m-1, m even) in round t of the circle schedule: every
+// pair meets once in m - 1 rounds.
+__device__ __forceinline__ int ritz_partner(int x, int t, int m) {
+    const int n = m - 1;
+    if (x == 0) return t + 1;
+    int y = (2 * (t + 1) - x) % n;
+    y = y < 0 ? y + n : y;
+    y = y == 0 ? n : y;
+    return y == x ? 0 : y;
+}
+
+__global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs, const int* __restrict__ cubes,
+                                              int ncls) {
+    __shared__ double M[16][17], U[16][17];
+    __shared__ double cs[16], sn[16];
+    __shared__ double v0[kMaxBands][kMaxRank];
+    __shared__ int perm[16];
+    __shared__ double sgn[16];
+    __shared__ double s_off, s_diag;
+    const int cube = cubes[blockIdx.x];
+    const CubeDesc& d = descs[cube];
+    const int r = d.r, p = d.p, tid = threadIdx.x;
+    const int i = tid >> 4, j = tid & 15;
+    const int m = (r + 1) & ~1;                   // even size; a padding index stays decoupled
+    // M from the slot sums (upper triangle computed, mirrored)
+    {
+        const int a = i <= j ? i : j, b = i <= j ? j : i;
+        double s = 0.0;
+        if (a < r && b < r)
+            for (int k = 0; k < d.gslots; ++k) s += d.rpart[(int64_t)k * 256 + a * 16 + b];
+        M[i][j] = s;
+        U[i][j] = i == j ? 1.0 : 0.0;
+    }
+    for (int e = tid; e < p * r; e += 256) {
+        const int row = e / r, k = e - row * r;
+        v0[row][k] = d.V[(int64_t)k * p + row];
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 12 && m > 1; ++sweep) {
+        if (tid == 0) {
+            double off = 0.0, dg = 0.0;
+            for (int a = 0; a < m; ++a)
+                for (int b = 0; b < m; ++b) {
+                    if (a == b) dg += M[a][a] * M[a][a];
+                    else off += M[a][b] * M[a][b];
+                }
+            s_off = off;
+            s_diag = dg;
+        }
+        __syncthreads();
+        if (!(s_off > 1e-30 * s_diag)) break;
+        for (int t = 0; t < m - 1; ++t) {
+            // rotation of every pair (x, y), x < y: [c s; -s c] diagonalises the 2 x 2 block
+            if (tid < m) {
+                const int x = tid, y = ritz_partner(x, t, m);
+                const int lo = x < y ? x : y, hi = x < y ? y : x;
+                double c = 1.0, s = 0.0;
+                const double apq = M[lo][hi];
+                if (apq != 0.0) {
+                    const double tau = (M[hi][hi] - M[lo][lo]) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                }
+                cs[x] = c;
+                sn[x] = x == lo ? -s : s;   // J[partner][x]
+            }
+            __syncthreads();
+            double mv = 0.0, uv = 0.0;
+            if (i < m && j < m) {
+                const int pi = ritz_partner(i, t, m), pj = ritz_partner(j, t, m);
+                const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
+                mv = ci * (M[i][j] * cj + M[i][pj] * sj) + si * (M[pi][j] * cj + M[pi][pj] * sj);
+                uv = U[i][j] * cj + U[i][pj] * sj;
+            }
+            __syncthreads();
+            if (i < m && j < m) {
+                M[i][j] = mv;
+                U[i][j] = uv;
+            }
+            __syncthreads();
+        }
+    }
+    // descending order of the Ritz values (ties: lower index first)
+    if (tid < r) {
+        int rank = 0;
+        for (int k = 0; k < r; ++k)
+            if (M[k][k] > M[tid][tid] || (M[k][k] == M[tid][tid] && k < tid)) ++rank;
+        perm[rank] = tid;
+    }
+    __syncthreads();
+    // sign rule on V = V0 U: the largest-magnitude entry positive (lowest index on ties)
+    for (int k = tid >> 6; k < r; k += 4) {
+        const int lane = tid & 63, col = perm[k];
+        double best = -1.0, bv = 0.0;
+        int bi = p;
+        for (int row = lane; row < p; row += 64) {
+            double v = 0.0;
+            for (int jj = 0; jj < r; ++jj) v = fma(v0[row][jj], U[jj][col], v);
+            if (fabs(v) > best) {
+                best = fabs(v);
+                bi = row;
+                bv = v;
+            }
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64), ov = __shfl_xor(bv, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+                bv = ov;
+            }
+        }
+        if (lane == 0) sgn[k] = bv < 0.0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    // outputs: rotation, V, projection matrices, Ritz values
+    if (i < 16 && j < 16) d.rrot[i * 16 + j] = (i < r && j < r) ? U[i][perm[j]] * sgn[j] : 0.0;
+    const int P16 = 16 * d.T;
+    for (int e = tid; e < p * r; e += 256) {
+        const int row = e / r, k = e - row * r;
+        const int col = perm[k];
+        double v = 0.0;
+        for (int jj = 0; jj < r; ++jj) v = fma(v0[row][jj], U[jj][col], v);
+        v *= sgn[k];
+        const double s = d.sigma[row];
+        d.V[(int64_t)k * p + row] = v;
+        d.P64[(int64_t)row * r + k] = v / s;
+        d.Q64[(int64_t)k * p + row] = v * s;
+        d.Q32[(int64_t)k * P16 + row] = (float)(v * s);
+    }
+    if (tid < r && d.evals) d.evals[tid] = M[perm[tid]][perm[tid]];
+    __syncthreads();
+    if (tid == 0 && d.evals && r < p) {
+        const double gp = d.evals[r - 1] / d.evals[r];
+        d.gap[0] = gp;
+        if (!(gp >= 1.0 + 1e-6)) set_status(d.status, HYRES_DEV_DEGENERATE);
+    }
+}
+
+// Z <- Z R (r x r rotation), in place.
+__global__ __launch_bounds__(256) void k_ritz_rotate(const CubeDesc* __restrict__ descs,
+                                                     const int* __restrict__ items, int ncubes) {
+    __shared__ float R[kMaxRank][kMaxRank + 1];
+    const int total = items[ncubes];
+    int cur = -1;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_cube(items, ncubes, item);
+        const CubeDesc& d = descs[c];
+        if (c != cur) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < 256; e += 256) R[e >> 4][e & 15] = (float)d.rrot[e];
+            __syncthreads();
+            cur = c;
+        }
+        const int64_t q = (int64_t)(item - items[c]) * 256 + threadIdx.x;
+        if (q >= d.n) continue;
+        const int r = d.r;
+        float* z = static_cast<float*>(d.Z);
+        float in[kMaxRank];
+#pragma unroll
+        for (int k = 0; k < kMaxRank; ++k) in[k] = k < r ? z[(int64_t)k * d.nz + q] : 0.f;
+#pragma unroll
+        for (int k = 0; k < kMaxRank; ++k) {
+            if (k < r) {
+                float s = 0.f;
+#pragma unroll
+                for (int jj = 0; jj < kMaxRank; ++jj) s = fmaf(in[jj], R[jj][k], s);
+                z[(int64_t)k * d.nz + q] = s;
+            }
+        }
+    }
+}
+
+hipError_t launch_ritz(const CubeDesc* descs, const int* gram_items, const int* cube_list, int ncls,
+                       const int* rot_items, int ncubes, int grid_gram, int grid_rot, hipStream_t s) {
+    hipLaunchKernelGGL(k_ritz_gram, dim3(grid_gram), dim3(256), 0, s, descs, gram_items, ncubes);
+    hipLaunchKernelGGL(k_ritz, dim3(ncls), dim3(256), 0, s, descs, cube_list, ncls);
+    hipLaunchKernelGGL(k_ritz_rotate, dim3(grid_rot), dim3(256), 0, s, descs, rot_items, ncubes);
+    return hipGetLastError();
+}
+
+}  // namespace hyres

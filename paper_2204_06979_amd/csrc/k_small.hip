@@ -106,6 +106,8 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
 
     // ---------------------------------------------------------------- noise
     if (d.mode & 1) {
+        // diagonal of G for the pivot test (s_ev is free until the eigenvalues)
+        for (int i = t; i < p; i += NTH) s_ev[i] = d.G[(int64_t)i * p + i];
 #pragma unroll
         for (int bb = 0; bb < BC; ++bb) {
             for (int kk = 0; kk < COLS; ++kk) {
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 __syncthreads();
                 double dk = s_col[buf][k];
                 // the pivot is the regression residual of band k on the bands swept so far
-                if (!(dk > 1e-12 * d.G[(int64_t)k * p + k])) {
+                if (!(dk > 1e-12 * s_ev[k])) {
                     flags |= HYRES_DEV_NOT_PD;
                     dk = 1.0;
                 }
@@ -542,9 +544,9 @@ hipError_t launch_small(int p, const CubeDesc* descs, const int* cubes, int ncls
     else if (p <= 128) HYRES_S(8, 8, 16, 16);
     else if (p <= 144) HYRES_S(5, 9, 32, 16);
     else if (p <= 160) HYRES_S(5, 10, 32, 16);
-    else if (p <= 176) HYRES_S(6, 11, 32, 16);
+    else if (p <= 176) HYRES_S(11, 6, 16, 32);
     else if (p <= 192) HYRES_S(8, 6, 24, 32);
-    else if (p <= 224) HYRES_S(10, 7, 24, 32);
+    else if (p <= 224) HYRES_S(7, 7, 32, 32);
     else return hipErrorInvalidValue;
 #undef HYRES_S
     return hipGetLastError();

@@ -73,7 +73,7 @@ def test_adjoint_against_finite_differences_fp64():
     api = _api()
     cube = synth.config_cube(4, keep_clean=False)
     Y = cube.Y[:32, :32, :16].astype(np.float64)
-    r, L = 6, 4
+    r, L = 6, 3
     ref = O.hyres(Y, r, L)
     lam = ref["lam"] * 0.8 + 0.02
     rng = np.random.default_rng(7)

@@ -37,10 +37,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-# shapes chosen to span several band-tile classes (T = 2, 3, 7, 8, 12, 14), every
-# small-solve class boundary near them, odd sizes and differing ranks and levels
+# shapes chosen to span several band-tile classes (T = 1, 2, 3, 7, 8, 11, 12, 14), the
+# small-solve register tilings, odd sizes and differing ranks and levels
 SHAPES = [(97, 133, 40, 5, 3), (64, 200, 17, 1, 2), (150, 77, 103, 8, 3), (128, 128, 128, 6, 4),
-          (45, 61, 191, 4, 2), (130, 90, 224, 12, 3), (33, 40, 2, 2, 2), (81, 81, 48, 3, 4)]
+          (45, 61, 191, 4, 2), (130, 90, 224, 12, 3), (33, 40, 2, 2, 2), (81, 81, 48, 3, 4),
+          (70, 90, 170, 5, 3)]
 
 
 def _cubes(dtype, shapes=SHAPES):

@@ -205,7 +205,16 @@ def test_denoise_config2_fp32_full_size():
 
 def test_denoise_config2_mixed_full_size():
     cube = synth.config_cube(2, keep_clean=False)
-    _check_denoise(cube.Y, 8, 4, 1e-3, name="c2-mixed", precision="mixed")
+    X, info, ref = _check_denoise(cube.Y, 8, 4, 1e-3, name="c2-mixed", precision="mixed")
+    # the FP32 refinement: Ritz values and the basis at FP32 accuracy
+    ev = info["evals"].cpu().numpy()[:8]
+    e_ev = float(np.max(np.abs(ev / ref["evals"][:8] - 1)))
+    V = info["V"].cpu().numpy()
+    cosines = np.linalg.svd(V.T @ ref["V"], compute_uv=False)
+    e_v = float(np.max(np.abs(V - ref["V"])))
+    say("   mixed evals rel err", e_ev, "V max abs diff", e_v, "min cosine", cosines.min())
+    assert e_ev <= 1e-5
+    assert e_v <= 1e-3
 
 
 @pytest.mark.parametrize("H,W,p,r,L", [(97, 133, 40, 5, 3), (128, 128, 100, 12, 4), (64, 96, 191, 6, 3)])

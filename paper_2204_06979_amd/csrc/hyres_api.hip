@@ -173,7 +173,8 @@ struct CubePlan {
     size_t o_gpart = 0, o_G = 0, o_sigma = 0, o_hv = 0, o_V = 0, o_evals = 0, o_gap = 0, o_P32 = 0, o_Q32 = 0,
            o_P64 = 0, o_Q64 = 0, o_Z = 0, o_coef = 0, o_tmp = 0, o_hcnt = 0, o_hsum = 0, o_hmin = 0,
            o_hmax = 0, o_sst = 0, o_lambda = 0, o_sure = 0, o_sbits = 0, o_spre = 0, o_sspre = 0, o_scb = 0,
-           o_cand = 0, o_sfill = 0, o_rpart = 0, o_rrot = 0;
+           o_cand = 0, o_sfill = 0, o_rpart = 0, o_rsum = 0, o_rrot = 0;
+    int rgroups = 0;
     bool has_lambda = false;   // thresholds given by the caller: no SURE search
 };
 
@@ -220,7 +221,10 @@ void plan_cube(CubePlan& c, Layout& lay, int parts) {
         c.o_P64 = lay.add((size_t)c.p * std::max(c.r, 1) * 8);
         c.o_Q64 = lay.add((size_t)c.p * std::max(c.r, 1) * 8);
         if ((parts & P_GRAM) && c.precision == HYRES_PREC_MIXED) {
-            c.o_rpart = lay.add((size_t)c.gslots * 256 * 8);
+            const int64_t ntiles = cdiv(c.n, kPixTile);
+            c.rgroups = (int)cdiv(ntiles, kRitzGroup);
+            c.o_rpart = lay.add((size_t)ntiles * 256 * 4);
+            c.o_rsum = lay.add((size_t)c.rgroups * 256 * 8);
             c.o_rrot = lay.add(256 * 8);
         }
     }
@@ -293,8 +297,10 @@ CubeDesc make_desc(const CubePlan& c, void* ws) {
         d.P64 = at<double>(ws, c.o_P64);
         d.Q64 = at<double>(ws, c.o_Q64);
         if (c.o_rpart) {
-            d.rpart = at<double>(ws, c.o_rpart);
+            d.rpart = at<float>(ws, c.o_rpart);
+            d.rsum = at<double>(ws, c.o_rsum);
             d.rrot = at<double>(ws, c.o_rrot);
+            d.rgroups = c.rgroups;
         }
     }
     if (c.o_Z || c.o_coef) {
@@ -542,7 +548,7 @@ void build_program(Exec& x, int stages) {
             std::vector<int64_t> slots(N), pix(N);
             std::vector<int> ids(N);
             for (int i = 0; i < N; ++i) {
-                slots[i] = x.plan[i].gslots;
+                slots[i] = x.plan[i].rgroups;
                 pix[i] = cdiv(x.plan[i].n, 256);
                 ids[i] = i;
             }

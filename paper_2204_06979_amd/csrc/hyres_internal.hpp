@@ -18,6 +18,7 @@ constexpr int kSureRoundsF64 = 10;    // 63-bit keys
 constexpr int kGramThreads = 512;
 constexpr int kSmallThreads = 1024;
 constexpr int kPixTile = 64;          // pixels per projection / back-projection block
+constexpr int kRitzGroup = 128;       // projection tiles per first-level Rayleigh-Ritz sum
 
 // Daubechies 4-tap orthonormal scaling filter h = ((1+s3),(3+s3),(3-s3),(1-s3)) / (4 sqrt 2),
 // s3 = sqrt 3, and its quadrature mirror g[m] = (-1)^m h[3-m].
@@ -76,8 +77,10 @@ struct CubeDesc {
     double* gap;                            // 1
     float* P32; float* Q32;                 // (16T x 16) projection and (16 x 16T) back-projection
     double* P64; double* Q64;               // (p x r) and (r x p)
-    double* rpart;                          // Rayleigh-Ritz slot sums, gslots x 16 x 16 (mixed solves)
+    float* rpart;                           // Rayleigh-Ritz: T^T T per 64-pixel tile, 16 x 16 (mixed solves)
+    double* rsum;                           // the tile sums per group of kRitzGroup tiles, FP64
     double* rrot;                           // Rayleigh-Ritz rotation, 16 x 16
+    int rgroups;                            // number of tile groups
     void* Z;                                // r x nz component images (also the denoised ones)
     void* coef;                             // r x ncs coefficients
     void* tmp;                              // r x tps approximation buffers

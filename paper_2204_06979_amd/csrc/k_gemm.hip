@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict_
                                                     const int* __restrict__ items, int ncubes) {
     constexpr int LDW = proj_ldw<T>();
     __shared__ __attribute__((aligned(16))) float tile[kPixTile * LDW];
+    __shared__ float s_m[4][256];            // per-wave Z^T Z of a tile (mixed solves)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15, row = lane >> 4;
@@ -114,6 +115,19 @@ __global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict_
         if (col < d.r) {
             float* z = static_cast<float*>(d.Z) + (int64_t)col * d.nz + q0 + 16 * wave + 4 * row;
             *reinterpret_cast<v4f*>(z) = acc;
+        }
+        if (d.rpart) {
+            // Z^T Z over the tile for the Rayleigh-Ritz refinement: register i of
+            // acc holds pixels {4g + i} of the wave's 16 in exactly the operand
+            // layout of a 4-deep MFMA step, so four steps cover the 16 pixels
+            v4f m = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) m = mfma4(acc[i], acc[i], m);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_m[wave][(4 * row + i) * 16 + col] = m[i];
+            __syncthreads();
+            const int e = threadIdx.x;
+            d.rpart[(q0 / kPixTile) * 256 + e] = ((s_m[0][e] + s_m[1][e]) + s_m[2][e]) + s_m[3][e];
         }
     }
 }

@@ -457,7 +457,10 @@ __global__ __launch_bounds__(256) void k_gram_reduce_f32(const CubeDesc* __restr
         while (rem >= T - i) { rem -= T - i; ++i; }
         const int j = i + rem;
         const int a = 16 * i + m, b = 16 * j + nn;
-        if (a < d.p && b < d.p) {
+        // a diagonal tile holds both (a, b) and (b, a); the products of the split
+        // BF16 path reach them in different orders, so only the upper entry is
+        // written, to both places (one writer per address)
+        if (a < d.p && b < d.p && a <= b) {
             d.G[(int64_t)a * d.p + b] = tot;
             d.G[(int64_t)b * d.p + a] = tot;
         }

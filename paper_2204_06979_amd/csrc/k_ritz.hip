@@ -8,9 +8,10 @@
 // eigenvalues at FP32 accuracy.  This is the one FP32 pass that recovers what
 // the BF16 products lose in the orientation of the basis and the eigenvalues.
 //
-//   k_ritz_gram    per slot of pixels: FP32 sums of T^T T over 64-pixel
-//                  chunks, accumulated in FP64 (fixed order, no atomics)
-//   k_ritz         one workgroup per cube: slot sums in FP64, cyclic Jacobi
+//   (k_project_f32 writes T^T T of every 64-pixel tile, FP32, from its MFMA
+//    accumulators)
+//   k_ritz_reduce  FP64 sums over groups of tiles (tile order, no atomics)
+//   k_ritz         one workgroup per cube: group sums in FP64, cyclic Jacobi
 //                  (parallel pair ordering), sort, sign rule, new V, evals,
 //                  projection matrices and the r x r rotation
 //   k_ritz_rotate  Z <- Z R in place, one pixel per thread
@@ -18,39 +19,21 @@
 
 namespace hyres {
 
-constexpr int kRitzPix = 64;
-
-__global__ __launch_bounds__(256) void k_ritz_gram(const CubeDesc* __restrict__ descs,
-                                                   const int* __restrict__ items, int ncubes) {
-    __shared__ float zt[kMaxRank][kRitzPix + 1];
+// rsum[g][e] = sum over the tiles of group g of the FP32 tile products (FP64, tile order).
+__global__ __launch_bounds__(256) void k_ritz_reduce(const CubeDesc* __restrict__ descs,
+                                                     const int* __restrict__ items, int ncubes) {
     const int total = items[ncubes];
-    const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int c = find_cube(items, ncubes, item);
         const CubeDesc& d = descs[c];
-        const int slot = item - items[c];
-        const int r = d.r;
-        int64_t per = (d.n + d.gslots - 1) / d.gslots;
-        per = (per + kRitzPix - 1) / kRitzPix * kRitzPix;
-        const int64_t q0 = (int64_t)slot * per;
-        const int64_t q1 = q0 + per < d.n ? q0 + per : d.n;
-        const float* z = static_cast<const float*>(d.Z);
-        double acc = 0.0;
-        for (int64_t t0 = q0; t0 < q1; t0 += kRitzPix) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < r * kRitzPix; e += 256) {
-                const int k = e / kRitzPix, j = e - k * kRitzPix;
-                zt[k][j] = t0 + j < q1 ? z[(int64_t)k * d.nz + t0 + j] : 0.f;
-            }
-            __syncthreads();
-            if (a < r && b < r) {
-                float s = 0.f;
-#pragma unroll 8
-                for (int j = 0; j < kRitzPix; ++j) s = fmaf(zt[a][j], zt[b][j], s);
-                acc += (double)s;
-            }
-        }
-        d.rpart[(int64_t)slot * 256 + threadIdx.x] = acc;
+        const int g = item - items[c];
+        const int64_t ntiles = (d.n + kPixTile - 1) / kPixTile;
+        const int64_t t0 = (int64_t)g * kRitzGroup;
+        const int64_t t1 = t0 + kRitzGroup < ntiles ? t0 + kRitzGroup : ntiles;
+        const int e = threadIdx.x;
+        double s = 0.0;
+        for (int64_t t = t0; t < t1; ++t) s += (double)d.rpart[t * 256 + e];
+        d.rsum[(int64_t)g * 256 + e] = s;
     }
 }
 
@@ -78,13 +61,23 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
     const int r = d.r, p = d.p, tid = threadIdx.x;
     const int i = tid >> 4, j = tid & 15;
     const int m = (r + 1) & ~1;                   // even size; a padding index stays decoupled
-    // M from the slot sums (upper triangle computed, mirrored)
+    // M from the group sums (upper triangle summed, mirrored; four interleaved
+    // partial sums combined in a fixed order)
     {
         const int a = i <= j ? i : j, b = i <= j ? j : i;
-        double s = 0.0;
-        if (a < r && b < r)
-            for (int k = 0; k < d.gslots; ++k) s += d.rpart[(int64_t)k * 256 + a * 16 + b];
-        M[i][j] = s;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (a < r && b < r) {
+            const double* src = d.rsum + a * 16 + b;
+            int k = 0;
+            for (; k + 4 <= d.rgroups; k += 4) {
+                s0 += src[(int64_t)k * 256];
+                s1 += src[(int64_t)(k + 1) * 256];
+                s2 += src[(int64_t)(k + 2) * 256];
+                s3 += src[(int64_t)(k + 3) * 256];
+            }
+            for (; k < d.rgroups; ++k) s0 += src[(int64_t)k * 256];
+        }
+        M[i][j] = (s0 + s1) + (s2 + s3);
         U[i][j] = i == j ? 1.0 : 0.0;
     }
     for (int e = tid; e < p * r; e += 256) {
@@ -229,9 +222,9 @@ __global__ __launch_bounds__(256) void k_ritz_rotate(const CubeDesc* __restrict_
     }
 }
 
-hipError_t launch_ritz(const CubeDesc* descs, const int* gram_items, const int* cube_list, int ncls,
-                       const int* rot_items, int ncubes, int grid_gram, int grid_rot, hipStream_t s) {
-    hipLaunchKernelGGL(k_ritz_gram, dim3(grid_gram), dim3(256), 0, s, descs, gram_items, ncubes);
+hipError_t launch_ritz(const CubeDesc* descs, const int* group_items, const int* cube_list, int ncls,
+                       const int* rot_items, int ncubes, int grid_sum, int grid_rot, hipStream_t s) {
+    hipLaunchKernelGGL(k_ritz_reduce, dim3(grid_sum), dim3(256), 0, s, descs, group_items, ncubes);
     hipLaunchKernelGGL(k_ritz, dim3(ncls), dim3(256), 0, s, descs, cube_list, ncls);
     hipLaunchKernelGGL(k_ritz_rotate, dim3(grid_rot), dim3(256), 0, s, descs, rot_items, ncubes);
     return hipGetLastError();

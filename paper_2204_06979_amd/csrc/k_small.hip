@@ -82,6 +82,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
 
     __shared__ double s_col[2][kSmallP];
+    __shared__ double s_col2[2][kSmallP];
     __shared__ double s_ub[kSmallP];
     __shared__ double s_sig[kSmallP];
     __shared__ double s_dd[kSmallP], s_ee[kSmallP], s_e2[kSmallP], s_hb[kSmallP], s_ev[kSmallP];
@@ -108,39 +109,79 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     if (d.mode & 1) {
         // diagonal of G for the pivot test (s_ev is free until the eigenvalues)
         for (int i = t; i < p; i += NTH) s_ev[i] = d.G[(int64_t)i * p + i];
+        // pivots in pairs (k0, k1): one barrier per pair.  The column k1 after
+        // the k0 step is formed from the two broadcast columns exactly as the
+        // k0 step forms it in the registers of its owners, so the result is
+        // that of sweeping the pivots one at a time.  Grids of more than 512
+        // threads (a tighter register budget) sweep one pivot per barrier.
+        constexpr bool kPairs = NTH <= 512;
 #pragma unroll
         for (int bb = 0; bb < BC; ++bb) {
-            for (int kk = 0; kk < COLS; ++kk) {
-                const int k = COLS * bb + kk;
-                if (k >= p) break;
-                const int buf = k & 1;
+            for (int kk = 0; kk < COLS; kk += kPairs ? 2 : 1) {
+                const int k0 = COLS * bb + kk, k1 = k0 + 1;
+                if (k0 >= p) break;
+                const bool two = kPairs && k1 < p;
+                const int buf = (kPairs ? k0 >> 1 : k0) & 1;
                 if (tc == kk) {
 #pragma unroll
                     for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
                 }
-                __syncthreads();
-                double dk = s_col[buf][k];
-                // the pivot is the regression residual of band k on the bands swept so far
-                if (!(dk > 1e-12 * s_ev[k])) {
-                    flags |= HYRES_DEV_NOT_PD;
-                    dk = 1.0;
+                if (two && tc == kk + 1) {
+#pragma unroll
+                    for (int a = 0; a < BR; ++a) s_col2[buf][tr + ROWS * a] = A[a][bb];
                 }
-                const double inv = 1.0 / dk;
+                __syncthreads();
+                // the pivot is the regression residual of band k on the bands swept so far
+                double d0 = s_col[buf][k0];
+                if (!(d0 > 1e-12 * s_ev[k0])) {
+                    flags |= HYRES_DEV_NOT_PD;
+                    d0 = 1.0;
+                }
+                const double inv0 = 1.0 / d0;
                 double cj[BC];
 #pragma unroll
                 for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + COLS * b];
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
                     const int i = tr + ROWS * a;
-                    const double ci = s_col[buf][i] * inv;
-                    if (i == k) {
+                    const double ci = s_col[buf][i] * inv0;
+                    if (i == k0) {
 #pragma unroll
-                        for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv;
-                        if (tc == kk) A[a][bb] = -inv;
+                        for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv0;
+                        if (tc == kk) A[a][bb] = -inv0;
                     } else {
 #pragma unroll
                         for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
                         if (tc == kk) A[a][bb] = ci;
+                    }
+                }
+                if (two) {
+                    const double ck1 = s_col[buf][k1];
+                    // column k1 after the k0 step
+                    auto ep = [&](int i) {
+                        return i == k0 ? ck1 * inv0 : fma(-(s_col[buf][i] * inv0), ck1, s_col2[buf][i]);
+                    };
+                    double d1 = ep(k1);
+                    if (!(d1 > 1e-12 * s_ev[k1])) {
+                        flags |= HYRES_DEV_NOT_PD;
+                        d1 = 1.0;
+                    }
+                    const double inv1 = 1.0 / d1;
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) cj[b] = ep(tc + COLS * b);
+#pragma unroll
+                    for (int a = 0; a < BR; ++a) {
+                        const int i = tr + ROWS * a;
+                        const double ci = ep(i) * inv1;
+                        if (i == k1) {
+#pragma unroll
+                            for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv1;
+                            if (tc == kk + 1) A[a][bb] = -inv1;
+                        } else {
+#pragma unroll
+                            for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
+                            if (tc == kk + 1) A[a][bb] = ci;
+                        }
                     }
                 }
             }

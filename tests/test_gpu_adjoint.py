@@ -88,22 +88,28 @@ def test_adjoint_against_finite_differences_fp64():
 
     def f(Yv, lv):
         Xv, _ = api.denoise(torch.tensor(Yv, device="cuda"), r, L, lam=torch.tensor(lv))
-        return float((Xv.cpu().numpy() * R).sum())
+        Xv = Xv.cpu().numpy()
+        return float((Xv * R).sum()), float(np.abs(Xv * R).sum())
 
+    # a central difference carries the truncation error O(h^2) and the
+    # rounding of the two evaluations, about 1e-15 sum|R X| / h; the
+    # comparison allows that plus 1e-5 relative
     h = 1e-6
     for k in range(6):
         E = rng.standard_normal(Y.shape)
         E /= np.linalg.norm(E)
-        fd = (f(Y + h * E, lam) - f(Y - h * E, lam)) / (2 * h)
+        (fp, mag), (fm, _) = f(Y + h * E, lam), f(Y - h * E, lam)
+        fd = (fp - fm) / (2 * h)
         an = float((gY * E).sum())
         say("  dir", k, "fd", fd, "adjoint", an)
-        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * np.linalg.norm(gY))
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-15 * mag / h
     for i in range(r):
         e = np.zeros(r)
         e[i] = h
-        fd = (f(Y, lam + e) - f(Y, lam - e)) / (2 * h)
+        (fp, mag), (fm, _) = f(Y, lam + e), f(Y, lam - e)
+        fd = (fp - fm) / (2 * h)
         say("  lambda", i, "fd", fd, "adjoint", gl[i])
-        assert abs(fd - gl[i]) <= 1e-5 * max(abs(gl[i]), 1e-3 * np.abs(gl).max())
+        assert abs(fd - gl[i]) <= 1e-5 * abs(gl[i]) + 1e-15 * mag / h
 
 
 @pytest.mark.parametrize("H,W,p,r,L", [(64, 64, 32, 4, 3), (37, 53, 20, 3, 2)])
@@ -130,17 +136,37 @@ def test_adjoint_config4_fp32_against_oracle_gradient():
     H, W, p = Y.shape
     r, L = 6, 4
     Yt = torch.tensor(Y, device="cuda", requires_grad=True)
-    # thresholds from the device's own SURE solve, then held fixed
+    # The soft threshold has a kink where |b| = lambda, and a SURE threshold is
+    # one of the coefficients, sitting exactly on it.  The gradient is checked
+    # at thresholds away from every kink: near each oracle SURE threshold, the
+    # middle of the widest gap between the 32 nearest coefficient magnitudes.
     _, info = api.denoise(Yt.detach(), r, L)
-    lam = info["lam"].clone()
+    ref = O.hyres(Y.astype(np.float64), r, L)
+    lam_np = np.empty(r)
+    for k in range(r):
+        a = np.sort(np.abs(ref["B"][k]))
+        i0 = int(np.searchsorted(a, ref["lam"][k]))
+        w = a[max(0, i0 - 16):i0 + 16]
+        g = int(np.argmax(np.diff(w)))
+        lam_np[k] = 0.5 * (w[g] + w[g + 1])
+    lam = torch.tensor(lam_np, device="cuda")
     lt = lam.clone().requires_grad_(True)
     R = np.random.default_rng(2).standard_normal(Y.shape).astype(np.float32)
     X = api.HyResFunction.apply(Yt, lt, r, L, "native")
     (X * torch.tensor(R, device="cuda")).sum().backward()
     V = info["V"].cpu().numpy()
     say("config4 oracle gradient", Y.shape)
-    gY, gl = _oracle_grad(Y.astype(np.float64), lam.cpu().numpy(), r, L, V, R.astype(np.float64))
+    Y64 = Y.astype(np.float64)
+    gY, gl = _oracle_grad(Y64, lam.cpu().numpy(), r, L, V, R.astype(np.float64))
+    # the tolerance is the oracle gradient's own sensitivity to FP32-level
+    # perturbations of its input (relative 6e-8 per voxel): thresholded
+    # coefficients that sit that close to lambda switch between kept and
+    # zeroed, which moves the gradient far more than the FP32 rounding of
+    # the adjoint's own arithmetic
+    Yp = Y64 * (1.0 + 6e-8 * np.random.default_rng(9).standard_normal(Y.shape))
+    gYp, glp = _oracle_grad(Yp, lam.cpu().numpy(), r, L, V, R.astype(np.float64))
+    s_y, s_l = rel(gYp, gY), rel(glp, gl)
     e = rel(Yt.grad.cpu().numpy(), gY)
     el = rel(lt.grad.cpu().numpy(), gl)
-    say("  dY rel err", e, "dlambda rel err", el)
-    assert e <= 1e-3 and el <= 1e-3
+    say("  dY rel err", e, "dlambda rel err", el, "oracle spread", s_y, s_l)
+    assert e <= max(1e-4, 2.0 * s_y) and el <= max(1e-4, 2.0 * s_l)

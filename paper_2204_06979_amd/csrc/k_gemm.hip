@@ -19,9 +19,11 @@ template <int T> __host__ __device__ constexpr int proj_nv4() { return (kPixTile
 template <int T> __host__ __device__ constexpr int proj_nv1() { return (kPixTile * 16 * T + 255) / 256; }
 
 // Registers holding one 64-pixel tile of the cube (all 16T band slots).
+// One register array serves both load paths: T float4 groups or 4T floats.
+static_assert(proj_nv1<1>() == 4 * proj_nv4<1>(), "projection staging sizes");
+
 template <int T>
-__device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&r4)[proj_nv4<T>()],
-                                           float (&r1)[proj_nv1<T>()]) {
+__device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&r4)[proj_nv4<T>()]) {
     const int tid = threadIdx.x;
     const int64_t nleft = d.n - q0;
     if (d.vec4) {
@@ -43,14 +45,13 @@ __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&
             const int k = e / (16 * T), b = e - k * (16 * T);
             float v = 0.f;
             if (k < kPixTile && b < d.p && k < nleft) v = pixel_ptr<float>(d, q0 + k)[b];
-            r1[i] = v;
+            r4[i >> 2][i & 3] = v;
         }
     }
 }
 
 template <int T>
-__device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, const v4f (&r4)[proj_nv4<T>()],
-                                           const float (&r1)[proj_nv1<T>()]) {
+__device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, const v4f (&r4)[proj_nv4<T>()]) {
     constexpr int LDW = proj_ldw<T>();
     const int tid = threadIdx.x;
     if (vec) {
@@ -65,7 +66,7 @@ __device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, c
         for (int i = 0; i < proj_nv1<T>(); ++i) {
             const int e = tid + 256 * i;
             const int k = e / (16 * T), b = e - k * (16 * T);
-            if (k < kPixTile) tile[k * LDW + b] = r1[i];
+            if (k < kPixTile) tile[k * LDW + b] = r4[i >> 2][i & 3];
         }
     }
 }
@@ -83,11 +84,10 @@ __global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict_
     int cur = -1;
     float bf[4 * T];
     v4f r4[proj_nv4<T>()];
-    float r1[proj_nv1<T>()];
     int item = blockIdx.x;
     if (item < total) {
         const int c = find_cube(items, ncubes, item);
-        proj_fetch<T>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4, r1);
+        proj_fetch<T>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4);
     }
     for (; item < total; item += gridDim.x) {
         const int c = find_cube(items, ncubes, item);
@@ -100,12 +100,12 @@ __global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict_
         const int64_t q0 = (int64_t)(item - items[c]) * kPixTile;
         const bool vec = d.vec4 != 0;
         __syncthreads();
-        proj_stage<T>(tile, vec, r4, r1);
+        proj_stage<T>(tile, vec, r4);
         __syncthreads();
         const int nxt = item + gridDim.x;
         if (nxt < total) {
             const int c2 = find_cube(items, ncubes, nxt);
-            proj_fetch<T>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4, r1);
+            proj_fetch<T>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4);
         }
         v4f acc = {0.f, 0.f, 0.f, 0.f};
         const float* arow = tile + (16 * wave + col) * LDW + row;

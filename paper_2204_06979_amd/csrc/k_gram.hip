@@ -15,10 +15,16 @@
 
 namespace hyres {
 
-template <int T>
+// Upper 16x16 tiles of G in row-major order.  P = 0: all of them; P = 1..NP:
+// one of NP consecutive parts (for large T one launch per part keeps the
+// per-wave accumulators in registers, at the price of rereading Y).
+template <int T, int P = 0>
 struct TileMap {
-    static constexpr int NT = T * (T + 1) / 2;
-    static constexpr int S = (NT + 7) / 8;        // tiles per wave
+    static constexpr int NT = T * (T + 1) / 2;    // all tiles (partial layout)
+    static constexpr int NP = T >= 13 ? 3 : 2;     // parts when split
+    static constexpr int T0 = P == 0 ? 0 : (P - 1) * NT / NP;
+    static constexpr int T1 = P == 0 ? NT : P * NT / NP;
+    static constexpr int S = (T1 - T0 + 7) / 8;   // tiles per wave
     __host__ __device__ static constexpr int ti(int t) {
         int i = 0, rem = t;
         while (rem >= T - i) { rem -= T - i; ++i; }
@@ -48,12 +54,12 @@ template <int T> __host__ __device__ constexpr int gram_nr() {
 // Wave WV owns the contiguous run of upper tiles [WV*S, WV*S + S) in row-major
 // order: the fragment of the tile row stays in registers while the column
 // fragment is loaded per tile.
-template <int T, int WV>
+template <int T, int P, int WV>
 __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int lane,
-                                          v4f (&acc)[TileMap<T>::S]) {
+                                          v4f (&acc)[TileMap<T, P>::S]) {
+    using TM = TileMap<T, P>;
     constexpr int LDW = gram_ldw<T>();
-    constexpr int NT = TileMap<T>::NT;
-    constexpr int S = TileMap<T>::S;
+    constexpr int S = TM::S;
     const int col = lane & 15, row = lane >> 4;
 #pragma unroll 2
     for (int s = 0; s < kGramKB / 4; ++s) {
@@ -61,10 +67,10 @@ __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int la
         float fi = 0.f;
         static_for<S>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            constexpr int t = WV * S + q;
-            if constexpr (t < NT) {
-                constexpr int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
-                if constexpr (q == 0 || TileMap<T>::ti(t - 1) != i) fi = rowp[16 * i];
+            constexpr int t = TM::T0 + WV * S + q;
+            if constexpr (t < TM::T1) {
+                constexpr int i = TM::ti(t), j = TM::tj(t);
+                if constexpr (q == 0 || TM::ti(t - 1) != i) fi = rowp[16 * i];
                 if constexpr (i == j) {
                     acc[q] = mfma4(fi, fi, acc[q]);
                 } else {
@@ -138,12 +144,13 @@ __device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, co
     return bad;
 }
 
-template <int T>
+template <int T, int P>
 __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __restrict__ descs,
                                                           const int* __restrict__ items, int ncubes) {
+    using TM = TileMap<T, P>;
     constexpr int LDW = gram_ldw<T>();
-    constexpr int NT = TileMap<T>::NT;
-    constexpr int S = TileMap<T>::S;
+    constexpr int NT = TM::NT;
+    constexpr int S = TM::S;
     __shared__ __attribute__((aligned(16))) float tile[kGramKB * LDW];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -175,14 +182,14 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
             __syncthreads();
             if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, rg);   // overlaps the MFMAs
             switch (wave) {
-                case 0: gram_wave<T, 0>(tile, lane, acc); break;
-                case 1: gram_wave<T, 1>(tile, lane, acc); break;
-                case 2: gram_wave<T, 2>(tile, lane, acc); break;
-                case 3: gram_wave<T, 3>(tile, lane, acc); break;
-                case 4: gram_wave<T, 4>(tile, lane, acc); break;
-                case 5: gram_wave<T, 5>(tile, lane, acc); break;
-                case 6: gram_wave<T, 6>(tile, lane, acc); break;
-                default: gram_wave<T, 7>(tile, lane, acc); break;
+                case 0: gram_wave<T, P, 0>(tile, lane, acc); break;
+                case 1: gram_wave<T, P, 1>(tile, lane, acc); break;
+                case 2: gram_wave<T, P, 2>(tile, lane, acc); break;
+                case 3: gram_wave<T, P, 3>(tile, lane, acc); break;
+                case 4: gram_wave<T, P, 4>(tile, lane, acc); break;
+                case 5: gram_wave<T, P, 5>(tile, lane, acc); break;
+                case 6: gram_wave<T, P, 6>(tile, lane, acc); break;
+                default: gram_wave<T, P, 7>(tile, lane, acc); break;
             }
             // FP32 sums over one chunk only; chunks accumulate in FP64
 #pragma unroll
@@ -197,8 +204,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            const int t = wave * S + q;
-            if (t < NT) {
+            const int t = TM::T0 + wave * S + q;
+            if (t < TM::T1) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) out[t * 256 + (4 * row + i) * 16 + col] = (float)accd[q][i];
             }
@@ -222,11 +229,11 @@ __device__ __forceinline__ v4f mfma_bf16(bf16x8 a, bf16x8 b, v4f c) {
 
 constexpr int kGramLDP = kGramKB + 8;   // bf16 elements per band row (16-byte aligned rows)
 
-template <int T, int WV>
+template <int T, int P, int WV>
 __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const __bf16* __restrict__ tl,
-                                           int lane, v4f (&acc)[TileMap<T>::S]) {
-    constexpr int NT = TileMap<T>::NT;
-    constexpr int S = TileMap<T>::S;
+                                           int lane, v4f (&acc)[TileMap<T, P>::S]) {
+    using TM = TileMap<T, P>;
+    constexpr int S = TM::S;
     const int col = lane & 15, row = lane >> 4;
 #pragma unroll 1
     for (int s = 0; s < kGramKB / 32; ++s) {
@@ -234,10 +241,10 @@ __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const 
         bf16x8 hi_i = {}, lo_i = {};
         static_for<S>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            constexpr int t = WV * S + q;
-            if constexpr (t < NT) {
-                constexpr int i = TileMap<T>::ti(t), j = TileMap<T>::tj(t);
-                if constexpr (q == 0 || TileMap<T>::ti(t - 1) != i) {
+            constexpr int t = TM::T0 + WV * S + q;
+            if constexpr (t < TM::T1) {
+                constexpr int i = TM::ti(t), j = TM::tj(t);
+                if constexpr (q == 0 || TM::ti(t - 1) != i) {
                     hi_i = *reinterpret_cast<const bf16x8*>(th + base + 16 * i * kGramLDP);
                     lo_i = *reinterpret_cast<const bf16x8*>(tl + base + 16 * i * kGramLDP);
                 }
@@ -335,11 +342,11 @@ __device__ __forceinline__ int gramb_stage_scalar(__bf16* __restrict__ th, __bf1
     return bad;
 }
 
-template <int T, bool VEC>
+template <int T, int P, bool VEC>
 __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_t q1, __bf16* th, __bf16* tl,
-                                           int lane, int wave, v4f (&acc)[TileMap<T>::S],
-                                           double (&accd)[TileMap<T>::S][4], int& bad) {
-    constexpr int S = TileMap<T>::S;
+                                           int lane, int wave, v4f (&acc)[TileMap<T, P>::S],
+                                           double (&accd)[TileMap<T, P>::S][4], int& bad) {
+    constexpr int S = TileMap<T, P>::S;
     v4f rv[VEC ? gramb_nt<T>() : 1][8];
     float rs[VEC ? 1 : gram_nr<T>()];
     if (q0 < q1) {
@@ -356,14 +363,14 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
             else gram_fetch<T>(d, q + kGramKB, q1, false, rs);
         }
         switch (wave) {
-            case 0: gramb_wave<T, 0>(th, tl, lane, acc); break;
-            case 1: gramb_wave<T, 1>(th, tl, lane, acc); break;
-            case 2: gramb_wave<T, 2>(th, tl, lane, acc); break;
-            case 3: gramb_wave<T, 3>(th, tl, lane, acc); break;
-            case 4: gramb_wave<T, 4>(th, tl, lane, acc); break;
-            case 5: gramb_wave<T, 5>(th, tl, lane, acc); break;
-            case 6: gramb_wave<T, 6>(th, tl, lane, acc); break;
-            default: gramb_wave<T, 7>(th, tl, lane, acc); break;
+            case 0: gramb_wave<T, P, 0>(th, tl, lane, acc); break;
+            case 1: gramb_wave<T, P, 1>(th, tl, lane, acc); break;
+            case 2: gramb_wave<T, P, 2>(th, tl, lane, acc); break;
+            case 3: gramb_wave<T, P, 3>(th, tl, lane, acc); break;
+            case 4: gramb_wave<T, P, 4>(th, tl, lane, acc); break;
+            case 5: gramb_wave<T, P, 5>(th, tl, lane, acc); break;
+            case 6: gramb_wave<T, P, 6>(th, tl, lane, acc); break;
+            default: gramb_wave<T, P, 7>(th, tl, lane, acc); break;
         }
 #pragma unroll
         for (int q2 = 0; q2 < S; ++q2) {
@@ -374,11 +381,12 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
     }
 }
 
-template <int T>
+template <int T, int P>
 __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __restrict__ descs,
                                                            const int* __restrict__ items, int ncubes) {
-    constexpr int NT = TileMap<T>::NT;
-    constexpr int S = TileMap<T>::S;
+    using TM = TileMap<T, P>;
+    constexpr int NT = TM::NT;
+    constexpr int S = TM::S;
     __shared__ __attribute__((aligned(16))) __bf16 th[16 * T * kGramLDP];
     __shared__ __attribute__((aligned(16))) __bf16 tl[16 * T * kGramLDP];
     const int lane = threadIdx.x & 63;
@@ -403,15 +411,15 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
         }
         int bad = 0;
-        if (vec) gramb_slot<T, true>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
-        else gramb_slot<T, false>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
+        if (vec) gramb_slot<T, P, true>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
+        else gramb_slot<T, P, false>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
         if (__any(bad) && lane == 0) set_status(d.status, HYRES_DEV_NONFINITE);
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            const int t = wave * S + q;
-            if (t < NT) {
+            const int t = TM::T0 + wave * S + q;
+            if (t < TM::T1) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) out[t * 256 + (4 * row + i) * 16 + col] = (float)accd[q][i];
             }
@@ -512,17 +520,35 @@ __global__ void k_gram_reduce_f64(const CubeDesc* __restrict__ descs, int cube) 
 // ---------------------------------------------------------------- launchers
 typedef void (*GramF32Kernel)(const CubeDesc*, const int*, int);
 
+// From T = 11 up the accumulators of all tiles no longer fit in the registers
+// of 8 waves; the tiles are then split over two launches (three from T = 13).
+constexpr int kGramSplitT = 11;
+
 template <int T>
 static hipError_t launch_gram_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_gram_f32<T>, dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    if constexpr (T >= kGramSplitT) {
+        hipLaunchKernelGGL((k_gram_f32<T, 1>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        hipLaunchKernelGGL((k_gram_f32<T, 2>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        if constexpr (TileMap<T, 1>::NP == 3)
+            hipLaunchKernelGGL((k_gram_f32<T, 3>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    } else {
+        hipLaunchKernelGGL((k_gram_f32<T, 0>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    }
     return hipGetLastError();
 }
 
 template <int T>
 static hipError_t launch_gramb_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
                                  hipStream_t s) {
-    hipLaunchKernelGGL(k_gram_bf16<T>, dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    if constexpr (T >= kGramSplitT) {
+        hipLaunchKernelGGL((k_gram_bf16<T, 1>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        hipLaunchKernelGGL((k_gram_bf16<T, 2>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        if constexpr (TileMap<T, 1>::NP == 3)
+            hipLaunchKernelGGL((k_gram_bf16<T, 3>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    } else {
+        hipLaunchKernelGGL((k_gram_bf16<T, 0>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    }
     return hipGetLastError();
 }
 

@@ -31,8 +31,18 @@ __global__ __launch_bounds__(256) void k_ritz_reduce(const CubeDesc* __restrict_
         const int64_t t0 = (int64_t)g * kRitzGroup;
         const int64_t t1 = t0 + kRitzGroup < ntiles ? t0 + kRitzGroup : ntiles;
         const int e = threadIdx.x;
+        const float* src = d.rpart + e;
+        // eight loads in flight, added in tile order
         double s = 0.0;
-        for (int64_t t = t0; t < t1; ++t) s += (double)d.rpart[t * 256 + e];
+        int64_t t = t0;
+        for (; t + 8 <= t1; t += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[(t + u) * 256];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
+        }
+        for (; t < t1; ++t) s += (double)src[t * 256];
         d.rsum[(int64_t)g * 256 + e] = s;
     }
 }
@@ -61,23 +71,23 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
     const int r = d.r, p = d.p, tid = threadIdx.x;
     const int i = tid >> 4, j = tid & 15;
     const int m = (r + 1) & ~1;                   // even size; a padding index stays decoupled
-    // M from the group sums (upper triangle summed, mirrored; four interleaved
-    // partial sums combined in a fixed order)
+    // M from the group sums (upper triangle summed, mirrored; group order)
     {
         const int a = i <= j ? i : j, b = i <= j ? j : i;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double s = 0.0;
         if (a < r && b < r) {
             const double* src = d.rsum + a * 16 + b;
             int k = 0;
-            for (; k + 4 <= d.rgroups; k += 4) {
-                s0 += src[(int64_t)k * 256];
-                s1 += src[(int64_t)(k + 1) * 256];
-                s2 += src[(int64_t)(k + 2) * 256];
-                s3 += src[(int64_t)(k + 3) * 256];
+            for (; k + 8 <= d.rgroups; k += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(k + u) * 256];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
             }
-            for (; k < d.rgroups; ++k) s0 += src[(int64_t)k * 256];
+            for (; k < d.rgroups; ++k) s += src[(int64_t)k * 256];
         }
-        M[i][j] = (s0 + s1) + (s2 + s3);
+        M[i][j] = s;
         U[i][j] = i == j ? 1.0 : 0.0;
     }
     for (int e = tid; e < p * r; e += 256) {
@@ -86,15 +96,21 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
     }
     __syncthreads();
     for (int sweep = 0; sweep < 12 && m > 1; ++sweep) {
-        if (tid == 0) {
+        if (tid < 64) {
             double off = 0.0, dg = 0.0;
-            for (int a = 0; a < m; ++a)
-                for (int b = 0; b < m; ++b) {
+            for (int e = tid; e < 256; e += 64) {
+                const int a = e >> 4, b = e & 15;
+                if (a < m && b < m) {
                     if (a == b) dg += M[a][a] * M[a][a];
                     else off += M[a][b] * M[a][b];
                 }
-            s_off = off;
-            s_diag = dg;
+            }
+            off = wave_sum(off);
+            dg = wave_sum(dg);
+            if (tid == 0) {
+                s_off = off;
+                s_diag = dg;
+            }
         }
         __syncthreads();
         if (!(s_off > 1e-30 * s_diag)) break;

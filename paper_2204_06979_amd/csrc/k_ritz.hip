@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
             }
         }
         __syncthreads();
-        if (!(s_off > 1e-30 * s_diag)) break;
+        if (!(s_off > 1e-26 * s_diag)) break;     // off-diagonal below 1e-13 of the diagonal
         for (int t = 0; t < m - 1; ++t) {
             // rotation of every pair (x, y), x < y: [c s; -s c] diagonalises the 2 x 2 block
             if (tid < m) {

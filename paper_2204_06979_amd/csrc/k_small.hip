@@ -81,9 +81,8 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     const int t = threadIdx.x, tc = t % COLS, tr = t / COLS, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
 
-    __shared__ double s_col[2][kSmallP];             // pivot column / column to reduce
-    __shared__ double s_col2[2][kSmallP];            // second pivot column / reflector v
-    __shared__ double s_u2[2][kSmallP];              // beta A v of a reduction step
+    __shared__ double s_col[2][kSmallP];
+    __shared__ double s_col2[2][kSmallP];
     __shared__ double s_ub[kSmallP];
     __shared__ double s_sig[kSmallP];
     __shared__ double s_dd[kSmallP], s_ee[kSmallP], s_e2[kSmallP], s_hb[kSmallP], s_ev[kSmallP];
@@ -116,74 +115,73 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
         // that of sweeping the pivots one at a time.  Grids of more than 512
         // threads (a tighter register budget) sweep one pivot per barrier.
         constexpr bool kPairs = NTH <= 512;
-        for (int k0 = 0; k0 < p; k0 += kPairs ? 2 : 1) {
-            const int k1 = k0 + 1;
-            const bool two = kPairs && k1 < p;
-            const int buf = (kPairs ? k0 >> 1 : k0) & 1;
-            const int kc0 = k0 % COLS, kb0 = k0 / COLS, kc1 = k1 % COLS, kb1 = k1 / COLS;
-            if (tc == kc0) {
 #pragma unroll
-                for (int b = 0; b < BC; ++b)
-                    if (b == kb0) {
+        for (int bb = 0; bb < BC; ++bb) {
+            for (int kk = 0; kk < COLS; kk += kPairs ? 2 : 1) {
+                const int k0 = COLS * bb + kk, k1 = k0 + 1;
+                if (k0 >= p) break;
+                const bool two = kPairs && k1 < p;
+                const int buf = (kPairs ? k0 >> 1 : k0) & 1;
+                if (tc == kk) {
 #pragma unroll
-                        for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][b];
-                    }
-            }
-            if (two && tc == kc1) {
-#pragma unroll
-                for (int b = 0; b < BC; ++b)
-                    if (b == kb1) {
-#pragma unroll
-                        for (int a = 0; a < BR; ++a) s_col2[buf][tr + ROWS * a] = A[a][b];
-                    }
-            }
-            __syncthreads();
-            // the pivot is the regression residual of band k on the bands swept so far
-            double d0 = s_col[buf][k0];
-            if (!(d0 > 1e-12 * s_ev[k0])) {
-                flags |= HYRES_DEV_NOT_PD;
-                d0 = 1.0;
-            }
-            const double inv0 = 1.0 / d0;
-            double cj[BC];
-#pragma unroll
-            for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + COLS * b];
-#pragma unroll
-            for (int a = 0; a < BR; ++a) {
-                const int i = tr + ROWS * a;
-                const double ci = s_col[buf][i] * inv0;
-#pragma unroll
-                for (int b = 0; b < BC; ++b) {
-                    const int j = tc + COLS * b;
-                    if (j == k0) A[a][b] = i == k0 ? -inv0 : ci;
-                    else if (i == k0) A[a][b] = cj[b] * inv0;
-                    else A[a][b] = fma(-ci, cj[b], A[a][b]);
+                    for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
                 }
-            }
-            if (two) {
-                const double ck1 = s_col[buf][k1];
-                // column k1 after the k0 step
-                auto ep = [&](int i) {
-                    return i == k0 ? ck1 * inv0 : fma(-(s_col[buf][i] * inv0), ck1, s_col2[buf][i]);
-                };
-                double d1 = ep(k1);
-                if (!(d1 > 1e-12 * s_ev[k1])) {
+                if (two && tc == kk + 1) {
+#pragma unroll
+                    for (int a = 0; a < BR; ++a) s_col2[buf][tr + ROWS * a] = A[a][bb];
+                }
+                __syncthreads();
+                // the pivot is the regression residual of band k on the bands swept so far
+                double d0 = s_col[buf][k0];
+                if (!(d0 > 1e-12 * s_ev[k0])) {
                     flags |= HYRES_DEV_NOT_PD;
-                    d1 = 1.0;
+                    d0 = 1.0;
                 }
-                const double inv1 = 1.0 / d1;
+                const double inv0 = 1.0 / d0;
+                double cj[BC];
 #pragma unroll
-                for (int b = 0; b < BC; ++b) cj[b] = ep(tc + COLS * b);
+                for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + COLS * b];
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
                     const int i = tr + ROWS * a;
-                    const double ci = ep(i) * inv1;
+                    const double ci = s_col[buf][i] * inv0;
+                    if (i == k0) {
 #pragma unroll
-                    for (int b = 0; b < BC; ++b) {
-                        const int j = tc + COLS * b;
-                        if (j == k1) A[a][b] = i == k1 ? -inv1 : ci;
-                        else if (i == k1) A[a][b] = cj[b] * inv1;
-                        else A[a][b] = fma(-ci, cj[b], A[a][b]);
+                        for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv0;
+                        if (tc == kk) A[a][bb] = -inv0;
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
+                        if (tc == kk) A[a][bb] = ci;
+                    }
+                }
+                if (two) {
+                    const double ck1 = s_col[buf][k1];
+                    // column k1 after the k0 step
+                    auto ep = [&](int i) {
+                        return i == k0 ? ck1 * inv0 : fma(-(s_col[buf][i] * inv0), ck1, s_col2[buf][i]);
+                    };
+                    double d1 = ep(k1);
+                    if (!(d1 > 1e-12 * s_ev[k1])) {
+                        flags |= HYRES_DEV_NOT_PD;
+                        d1 = 1.0;
+                    }
+                    const double inv1 = 1.0 / d1;
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) cj[b] = ep(tc + COLS * b);
+#pragma unroll
+                    for (int a = 0; a < BR; ++a) {
+                        const int i = tr + ROWS * a;
+                        const double ci = ep(i) * inv1;
+                        if (i == k1) {
+#pragma unroll
+                            for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv1;
+                            if (tc == kk + 1) A[a][bb] = -inv1;
+                        } else {
+#pragma unroll
+                            for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
+                            if (tc == kk + 1) A[a][bb] = ci;
+                        }
                     }
                 }
             }
@@ -222,108 +220,78 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
             }
 
         // ------------------------------------------------ tridiagonalisation
-        // One barrier per step.  Step k first applies the rank-2 update of step
-        // k-1 to the registers, forms the column it reduces from that column as
-        // published before the update and the vectors of step k-1 (held in
-        // LDS), builds its reflector, and multiplies the updated matrix by it.
-        // Owners publish column k+1 after the update; row owners publish v and
-        // u = beta A v.  Buffers alternate between steps.
-        if (tc == 0) {
 #pragma unroll
-            for (int a = 0; a < BR; ++a) s_col[1][tr + ROWS * a] = A[a][0];
-        }
-        __syncthreads();
-        double Kp = 0.0;          // K of the previous step: w = u - K v
-        for (int k = 0; k <= p - 2; ++k) {
-            const int cb = k & 1, pb = cb ^ 1;
-            double vkp = 0.0, wkp = 0.0;   // v and w of the previous step at index k
-            if (k > 0) {
-                double uv = 0.0;
-                for (int i = k + lane; i < p; i += 64) uv = fma(s_u2[pb][i], s_col2[pb][i], uv);
-                uv = wave_sum(uv);
-                Kp = 0.5 * s_hb[k - 1] * uv;
-                double vcp[BC], wcp[BC];
+        for (int bb = 0; bb < BC; ++bb) {
+            for (int kk = 0; kk < COLS; ++kk) {
+                const int k = COLS * bb + kk;
+                if (k >= p - 2) break;
+                const int buf = k & 1;
+                if (tc == kk) {
+#pragma unroll
+                    for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
+                }
+                __syncthreads();
+                double ss = 0.0;
+                for (int i = k + 1 + lane; i < p; i += 64) {
+                    const double v = s_col[buf][i];
+                    ss = fma(v, v, ss);
+                }
+                ss = wave_sum(ss);
+                const double x1 = s_col[buf][k + 1];
+                const double nrm = sqrt(ss);
+                const double alpha = x1 >= 0.0 ? -nrm : nrm;
+                const double vtv = 2.0 * alpha * (alpha - x1);
+                const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
+                const double v1 = x1 - alpha;
+                double vc[BC];
 #pragma unroll
                 for (int b = 0; b < BC; ++b) {
                     const int j = tc + COLS * b;
-                    const bool on = j >= k && j < p;
-                    vcp[b] = on ? s_col2[pb][j] : 0.0;
-                    wcp[b] = on ? s_u2[pb][j] - Kp * vcp[b] : 0.0;
+                    vc[b] = (j > k + 1 && j < p) ? s_col[buf][j] : (j == k + 1 ? v1 : 0.0);
                 }
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
-                    if (ROWS * a + ROWS - 1 >= k) {
+                    double s = 0.0;
+                    if (ROWS * a + ROWS - 1 > k) {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) s = fma(A[a][b], vc[b], s);
+                        s = COLS == 32 ? half_sum(s) : row16_sum(s);
+                    }
+                    if (tc == 0) s_ub[tr + ROWS * a] = beta * s;
+                }
+                if (t == 0) {
+                    s_dd[k] = s_col[buf][k];
+                    s_ee[k] = alpha;
+                    s_hb[k] = beta;
+                }
+                if (t > k && t < p) d.hv[(int64_t)k * p + t] = (t == k + 1) ? v1 : s_col[buf][t];
+                __syncthreads();
+                double uv = 0.0;
+                for (int i = k + 1 + lane; i < p; i += 64) {
+                    const double vi = (i == k + 1) ? v1 : s_col[buf][i];
+                    uv = fma(s_ub[i], vi, uv);
+                }
+                uv = wave_sum(uv);
+                const double K = 0.5 * beta * uv;
+                double wc[BC];
+#pragma unroll
+                for (int b = 0; b < BC; ++b) {
+                    const int j = tc + COLS * b;
+                    wc[b] = (j > k && j < p) ? s_ub[j] - K * vc[b] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < BR; ++a) {
+                    if (ROWS * a + ROWS - 1 > k) {
                         const int i = tr + ROWS * a;
-                        const bool on = i >= k && i < p;
-                        const double vi = on ? s_col2[pb][i] : 0.0;
-                        const double wi = on ? s_u2[pb][i] - Kp * vi : 0.0;
+                        const double vi = (i > k + 1 && i < p) ? s_col[buf][i] : (i == k + 1 ? v1 : 0.0);
+                        const double wi = (i > k && i < p) ? s_ub[i] - K * vi : 0.0;
 #pragma unroll
                         for (int b = 0; b < BC; ++b) {
-                            if (COLS * b + COLS - 1 >= k) A[a][b] -= vi * wcp[b] + wi * vcp[b];
+                            if (COLS * b + COLS - 1 > k) A[a][b] -= vi * wc[b] + wi * vc[b];
                         }
                     }
                 }
-                vkp = s_col2[pb][k];
-                wkp = s_u2[pb][k] - Kp * vkp;
             }
-            if (k == p - 2) break;      // only the last update was left
-            // column k after the previous update (rows i >= k)
-            auto col = [&](int i) -> double {
-                const double raw = s_col[pb][i];
-                if (k == 0) return raw;
-                const double vi = s_col2[pb][i], wi = s_u2[pb][i] - Kp * vi;
-                return raw - (vi * wkp + wi * vkp);
-            };
-            double ss = 0.0;
-            for (int i = k + 1 + lane; i < p; i += 64) {
-                const double c = col(i);
-                ss = fma(c, c, ss);
-            }
-            ss = wave_sum(ss);
-            const double x1 = col(k + 1);
-            const double nrm = sqrt(ss);
-            const double alpha = x1 >= 0.0 ? -nrm : nrm;
-            const double vtv = 2.0 * alpha * (alpha - x1);
-            const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
-            const double v1 = x1 - alpha;
-            double vc[BC];
-#pragma unroll
-            for (int b = 0; b < BC; ++b) {
-                const int j = tc + COLS * b;
-                vc[b] = (j > k + 1 && j < p) ? col(j) : (j == k + 1 ? v1 : 0.0);
-            }
-#pragma unroll
-            for (int a = 0; a < BR; ++a) {
-                double sacc = 0.0;
-                if (ROWS * a + ROWS - 1 > k) {
-#pragma unroll
-                    for (int b = 0; b < BC; ++b) sacc = fma(A[a][b], vc[b], sacc);
-                    sacc = COLS == 32 ? half_sum(sacc) : row16_sum(sacc);
-                }
-                if (tc == 0) {
-                    const int i = tr + ROWS * a;
-                    s_u2[cb][i] = beta * sacc;
-                    s_col2[cb][i] = (i > k + 1 && i < p) ? col(i) : (i == k + 1 ? v1 : 0.0);
-                }
-            }
-            {
-                const int kc = (k + 1) % COLS, kb = (k + 1) / COLS;
-                if (tc == kc) {
-#pragma unroll
-                    for (int b = 0; b < BC; ++b)
-                        if (b == kb) {
-#pragma unroll
-                            for (int a = 0; a < BR; ++a) s_col[cb][tr + ROWS * a] = A[a][b];
-                        }
-                }
-            }
-            if (t == 0) {
-                s_dd[k] = col(k);
-                s_ee[k] = alpha;
-                s_hb[k] = beta;
-            }
-            if (t > k && t < p) d.hv[(int64_t)k * p + t] = (t == k + 1) ? v1 : col(t);
-            __syncthreads();
         }
         __syncthreads();
 #pragma unroll

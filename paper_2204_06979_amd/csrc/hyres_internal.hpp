@@ -190,14 +190,26 @@ __device__ __forceinline__ double row16_sum(double v) {
     v += dpp_f64<0x140>(v);   // row_mirror
     return v;
 }
-// Sum over each half-wave (32 lanes), returned to every lane of the half.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+// Sum over each half-wave (32 lanes), returned to every lane of the half: the
+// four row sums are read into scalar registers (no LDS round trip).  Call with
+// the whole wave active.
 __device__ __forceinline__ double half_sum(double v) {
     v = row16_sum(v);
-    return v + __shfl_xor(v, 16, 64);
+    const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+    const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+    return (threadIdx.x & 32) ? r2 + r3 : r0 + r1;
 }
+// Sum over the wave, returned to every lane ((r0 + r1) + (r2 + r3) of the row sums).
 __device__ __forceinline__ double wave_sum(double v) {
-    v = half_sum(v);
-    return v + __shfl_xor(v, 32, 64);
+    v = row16_sum(v);
+    const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+    const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+    return (r0 + r1) + (r2 + r3);
 }
 
 // Blend weight of tile pixel (y, x) and whether an earlier pass already wrote it.

@@ -68,6 +68,29 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const 
     return cnt;
 }
 
+// In place: lo = max and hi = min over each aligned group of M lanes (M = 4, 16 or 64).
+__device__ __forceinline__ void group_maxmin(double& lo, double& hi, int M) {
+    double a;
+    a = dpp_f64<0xB1>(lo); lo = a > lo ? a : lo;      // quad_perm [1,0,3,2]
+    a = dpp_f64<0xB1>(hi); hi = a < hi ? a : hi;
+    a = dpp_f64<0x4E>(lo); lo = a > lo ? a : lo;      // quad_perm [2,3,0,1]
+    a = dpp_f64<0x4E>(hi); hi = a < hi ? a : hi;
+    if (M == 4) return;
+    a = dpp_f64<0x141>(lo); lo = a > lo ? a : lo;     // row_half_mirror
+    a = dpp_f64<0x141>(hi); hi = a < hi ? a : hi;
+    a = dpp_f64<0x140>(lo); lo = a > lo ? a : lo;     // row_mirror
+    a = dpp_f64<0x140>(hi); hi = a < hi ? a : hi;
+    if (M == 16) return;
+    const double l0 = readlane_f64(lo, 0), l1 = readlane_f64(lo, 16), l2 = readlane_f64(lo, 32),
+                 l3 = readlane_f64(lo, 48);
+    const double h0 = readlane_f64(hi, 0), h1 = readlane_f64(hi, 16), h2 = readlane_f64(hi, 32),
+                 h3 = readlane_f64(hi, 48);
+    const double la = l0 > l1 ? l0 : l1, lb = l2 > l3 ? l2 : l3;
+    const double ha = h0 < h1 ? h0 : h1, hb = h2 < h3 ? h2 : h3;
+    lo = la > lb ? la : lb;
+    hi = ha < hb ? ha : hb;
+}
+
 template <int BR, int BC, int ROWS, int COLS>
 __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restrict__ descs,
                                                        const int* __restrict__ cubes, int ncls) {
@@ -354,12 +377,9 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                         const bool below = cnt <= midx;   // x <= lambda
                         double lo_c = below ? x : lo;
                         double hi_c = below ? hi : x;
-                        for (int o = 1; o < M; o <<= 1) {
-                            const double a1 = __shfl_xor(lo_c, o, M);
-                            const double a2 = __shfl_xor(hi_c, o, M);
-                            lo_c = a1 > lo_c ? a1 : lo_c;
-                            hi_c = a2 < hi_c ? a2 : hi_c;
-                        }
+                        // largest lower and smallest upper end over the M lanes of
+                        // the group: quads and rows by DPP, whole waves by readlane
+                        group_maxmin(lo_c, hi_c, M);
                         lo = lo_c;
                         hi = hi_c;
                     }

@@ -203,6 +203,75 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_hist(const CubeDesc* __re
 }
 
 constexpr int kSelThreads = 1024;
+constexpr int kSelWaves = kSelThreads / 64;
+
+// ---- wave and block primitives of the select kernel (whole block active) ----
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+// Inclusive prefix sums over the 64 lanes: rows by DPP row shifts, then the
+// totals of the rows before (fixed order).
+__device__ __forceinline__ uint32_t wave_incl_u32(uint32_t v) {
+    v += dpp_u32<0x111>(v);
+    v += dpp_u32<0x112>(v);
+    v += dpp_u32<0x114>(v);
+    v += dpp_u32<0x118>(v);
+    const uint32_t t0 = readlane_u32(v, 15), t1 = readlane_u32(v, 31), t2 = readlane_u32(v, 47);
+    const int row = (threadIdx.x & 63) >> 4;
+    uint32_t off = row >= 1 ? t0 : 0u;
+    off += row >= 2 ? t1 : 0u;
+    off += row >= 3 ? t2 : 0u;
+    return v + off;
+}
+__device__ __forceinline__ double wave_incl_f64(double v) {
+    v += dpp_f64<0x111>(v);
+    v += dpp_f64<0x112>(v);
+    v += dpp_f64<0x114>(v);
+    v += dpp_f64<0x118>(v);
+    const double t0 = readlane_f64(v, 15), t1 = readlane_f64(v, 31), t2 = readlane_f64(v, 47);
+    const int row = (threadIdx.x & 63) >> 4;
+    double off = row >= 1 ? t0 : 0.0;
+    off = row >= 2 ? off + t1 : off;
+    off = row >= 3 ? off + t2 : off;
+    return v + off;
+}
+// (value, t) pairs: smaller value, then smaller t, over the wave (every lane gets it)
+__device__ __forceinline__ void wave_argmin(double& b, double& t) {
+#define HYRES_AM(CTRL)                                                 \
+    {                                                                  \
+        const double ob = dpp_f64<CTRL>(b), ot = dpp_f64<CTRL>(t);    \
+        if (ob < b || (ob == b && ot < t)) { b = ob; t = ot; }         \
+    }
+    HYRES_AM(0xB1) HYRES_AM(0x4E) HYRES_AM(0x141) HYRES_AM(0x140)
+#undef HYRES_AM
+    double bb = readlane_f64(b, 0), tt = readlane_f64(t, 0);
+    for (int r = 16; r < 64; r += 16) {
+        const double ob = readlane_f64(b, r), ot = readlane_f64(t, r);
+        if (ob < bb || (ob == bb && ot < tt)) { bb = ob; tt = ot; }
+    }
+    b = bb;
+    t = tt;
+}
+template <bool MAX>
+__device__ __forceinline__ int wave_minmax_i32(int v) {
+#define HYRES_MM(CTRL)                                                         \
+    {                                                                          \
+        const int o = (int)dpp_u32<CTRL>((uint32_t)v);                          \
+        v = MAX ? (o > v ? o : v) : (o < v ? o : v);                           \
+    }
+    HYRES_MM(0xB1) HYRES_MM(0x4E) HYRES_MM(0x141) HYRES_MM(0x140)
+#undef HYRES_MM
+    int r = __builtin_amdgcn_readlane(v, 0);
+    for (int l = 16; l < 64; l += 16) {
+        const int o = __builtin_amdgcn_readlane(v, l);
+        r = MAX ? (o > r ? o : r) : (o < r ? o : r);
+    }
+    return r;
+}
 
 // Exact finish of a component from its collected candidates: for every
 // candidate v in bin b, the count and sum of squares of the values <= v are
@@ -279,18 +348,14 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
                                                              const int* __restrict__ items, int ncubes) {
     typedef KeyTraits<T> KT;
     constexpr int PER = kSureBins / kSelThreads;   // bins per thread
-    __shared__ double raw[kSureCap];               // finish: keys; select: scratch below
+    __shared__ double raw[kSureCap];               // keys of the exact finish
     __shared__ SureState s_st;
-    __shared__ unsigned int s_mx;
-    unsigned long long* s_cnt = reinterpret_cast<unsigned long long*>(raw);
-    double* s_sum = raw + kSelThreads;
-    double* s_bs = raw + 2 * kSelThreads;
-    double* s_bt = raw + 3 * kSelThreads;
-    int* s_f = reinterpret_cast<int*>(raw + 4 * kSelThreads);
-    int* s_l = s_f + kSelThreads;
-    unsigned long long* s_m = reinterpret_cast<unsigned long long*>(raw + 5 * kSelThreads);
+    // per-wave totals of the select round
+    __shared__ uint32_t s_wc[kSelWaves], s_wm[kSelWaves];
+    __shared__ double s_ws[kSelWaves], s_bs[kSelWaves], s_bt[kSelWaves];
+    __shared__ int s_wf[kSelWaves], s_wl[kSelWaves], s_wx[kSelWaves];
     const int total = items[ncubes];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int c = find_cube(items, ncubes, item);
         const CubeDesc& d = descs[c];
@@ -317,7 +382,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
         uint32_t cnt[PER];
         double sum[PER];
         uint64_t kmin[PER], kmax[PER];
-        unsigned long long tc = 0;
+        uint32_t tc = 0;                  // counts stay below 2^32 (at most 2^31 pixels)
         double ts = 0.0;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -329,21 +394,24 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
             tc += cnt[j];
             ts += sum[j];
         }
-        // exclusive scan over threads (Hillis-Steele in LDS; fixed order of additions)
-        s_cnt[tid] = tc;
-        s_sum[tid] = ts;
-        __syncthreads();
-        for (int o = 1; o < kSelThreads; o <<= 1) {
-            const unsigned long long ac = tid >= o ? s_cnt[tid - o] : 0ull;
-            const double as = tid >= o ? s_sum[tid - o] : 0.0;
-            __syncthreads();
-            s_cnt[tid] += ac;
-            s_sum[tid] += as;
-            __syncthreads();
+        // exclusive prefix over threads of the counts and sums: waves by DPP and
+        // readlane, then the totals of the waves before (fixed order)
+        const uint32_t ic = wave_incl_u32(tc);
+        const double is = wave_incl_f64(ts);
+        const double is_prev = __shfl_up(is, 1, 64);
+        if (lane == 63) {
+            s_wc[wave] = ic;
+            s_ws[wave] = is;
         }
-        unsigned long long pc = s_cnt[tid] - tc;
-        double ps = tid > 0 ? s_sum[tid - 1] : 0.0;
         __syncthreads();
+        uint32_t oc = 0;
+        double os = 0.0;
+        for (int w = 0; w < wave; ++w) {
+            oc += s_wc[w];
+            os += s_ws[w];
+        }
+        unsigned long long pc = (unsigned long long)(oc + ic - tc);
+        double ps = lane == 0 ? os : os + is_prev;
         double bs = __builtin_inf(), bt = 0.0;
         if (st.round == 0 && tid == 0) {
             bs = N - 2.0 * (double)st.zeros;   // candidate t = 0
@@ -372,28 +440,26 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
             pc += cnt[j];
             ps += sum[j];
         }
-        s_bs[tid] = bs;
-        s_bt[tid] = bt;
-        __syncthreads();
-        for (int o = kSelThreads / 2; o >= 1; o >>= 1) {
-            if (tid < o) {
-                const double ob = s_bs[tid + o], ot = s_bt[tid + o];
-                if (ob < s_bs[tid] || (ob == s_bs[tid] && ot < s_bt[tid])) {
-                    s_bs[tid] = ob;
-                    s_bt[tid] = ot;
-                }
-            }
-            __syncthreads();
+        wave_argmin(bs, bt);
+        if (lane == 0) {
+            s_bs[wave] = bs;
+            s_bt[wave] = bt;
         }
+        __syncthreads();
         double best_s = s_bs[0], best_t = s_bt[0];
+        for (int w = 1; w < kSelWaves; ++w) {
+            if (s_bs[w] < best_s || (s_bs[w] == best_s && s_bt[w] < best_t)) {
+                best_s = s_bs[w];
+                best_t = s_bt[w];
+            }
+        }
         if (st.best_s < best_s || (st.best_s == best_s && st.best_t < best_t)) {
             best_s = st.best_s;
             best_t = st.best_t;
         }
         const double U = best_s + 1e-12 * (fabs(best_s) + N);
         int f = 0x7fffffff, l = -1;
-        unsigned long long m = 0;
-        unsigned int mx = 0;
+        uint32_t m = 0, mx = 0;
         bool surv[PER];
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -406,33 +472,36 @@ __global__ __launch_bounds__(kSelThreads) void k_sure_select(const CubeDesc* __r
                 mx = cnt[j] > mx ? cnt[j] : mx;
             }
         }
-        s_f[tid] = f;
-        s_l[tid] = l;
-        s_m[tid] = m;
-        if (tid == 0) s_mx = 0;
+        // first and last surviving bin, largest surviving bin, and the prefix of
+        // surviving counts (the offsets of the gathered values)
+        const int wf = wave_minmax_i32<false>(f), wl = wave_minmax_i32<true>(l);
+        const int wmx = wave_minmax_i32<true>((int)mx);
+        const uint32_t im = wave_incl_u32(m);
+        if (lane == 63) s_wm[wave] = im;
+        if (lane == 0) {
+            s_wf[wave] = wf;
+            s_wl[wave] = wl;
+            s_wx[wave] = wmx;
+        }
         __syncthreads();
-        if (mx) atomicMax(&s_mx, mx);
-        // inclusive scan of surviving counts (for the candidate offsets) and min/max of f, l
-        for (int o = 1; o < kSelThreads; o <<= 1) {
-            const unsigned long long am = tid >= o ? s_m[tid - o] : 0ull;
-            __syncthreads();
-            s_m[tid] += am;
-            __syncthreads();
-        }
-        for (int o = kSelThreads / 2; o >= 1; o >>= 1) {
-            if (tid < o) {
-                s_f[tid] = s_f[tid + o] < s_f[tid] ? s_f[tid + o] : s_f[tid];
-                s_l[tid] = s_l[tid + o] > s_l[tid] ? s_l[tid + o] : s_l[tid];
+        int fb = s_wf[0], lb = s_wl[0];
+        unsigned int s_mxv = (unsigned int)s_wx[0];
+        uint32_t om = 0, msum = 0;
+        for (int w = 0; w < kSelWaves; ++w) {
+            if (w < wave) om += s_wm[w];
+            msum += s_wm[w];
+            if (w > 0) {
+                fb = s_wf[w] < fb ? s_wf[w] : fb;
+                lb = s_wl[w] > lb ? s_wl[w] : lb;
+                s_mxv = (unsigned int)s_wx[w] > s_mxv ? (unsigned int)s_wx[w] : s_mxv;
             }
-            __syncthreads();
         }
-        const int fb = s_f[0], lb = s_l[0];
-        const unsigned long long msurv = s_m[kSelThreads - 1];
+        const unsigned long long msurv = msum;
         const bool gather = lb >= 0 && st.width > 0 && msurv <= (unsigned long long)kSureCap &&
-                            s_mx <= (unsigned)kSureBinCap;
+                            s_mxv <= (unsigned)kSureBinCap;
         if (gather) {
             // bitmap, counts below each surviving bin, and collected-value offsets
-            unsigned long long mo = s_m[tid] - m;
+            uint32_t mo = om + im - m;
             for (int w = tid; w < kSureBins / 32; w += kSelThreads) d.sbits[(int64_t)comp * (kSureBins / 32) + w] = 0u;
             __syncthreads();
 #pragma unroll

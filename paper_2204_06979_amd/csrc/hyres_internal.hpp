@@ -174,9 +174,19 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// DPP move of a double (both halves) with a row-level control.
+// DPP move of a double (both halves) with a row-level permutation (quad_perm,
+// row_half_mirror, row_mirror): every lane has a source, so no old value is
+// needed (no zero-initialised destination).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
+    static_assert(CTRL <= 0xFF || CTRL == 0x140 || CTRL == 0x141, "permutation controls only");
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+// DPP row shift of a double: lanes without a source read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift_f64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);

@@ -113,6 +113,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     __shared__ double s_zU[kSmallP * kMaxRank];      // multipliers of the bottom-up one    [i][g]
     __shared__ double s_z[kMaxRank][kSmallP];        // eigenvectors of the tridiagonal / of C
     __shared__ double s_red[4];
+    __shared__ double s_vav[NW];                     // per-wave shares of v^T A v
     __shared__ int s_flags;
 
     if (t == 0) s_flags = 0;
@@ -243,8 +244,9 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
             }
 
         // ------------------------------------------------ tridiagonalisation
-#pragma unroll
-        for (int bb = 0; bb < BC; ++bb) {
+        // (register column bb a compile-time index: the tile stays in registers)
+        static_for<BC>([&](auto bbc) {
+            constexpr int bb = decltype(bbc)::value;
             for (int kk = 0; kk < COLS; ++kk) {
                 const int k = COLS * bb + kk;
                 if (k >= p - 2) break;
@@ -254,6 +256,26 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                     for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
                 }
                 __syncthreads();
+                // A v with v = x - alpha e_{k+1} (x: column k below the diagonal)
+                // is A x - alpha A e_{k+1}: the products with x start before the
+                // norm that gives alpha is known
+                double xc[BC];
+#pragma unroll
+                for (int b = 0; b < BC; ++b) {
+                    const int j = tc + COLS * b;
+                    xc[b] = (j > k && j < p) ? s_col[buf][j] : 0.0;
+                }
+                double ps[BR];
+#pragma unroll
+                for (int a = 0; a < BR; ++a) {
+                    double sa = 0.0;
+                    if (ROWS * a + ROWS - 1 > k) {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b)
+                            if (COLS * b + COLS - 1 > k) sa = fma(A[a][b], xc[b], sa);
+                    }
+                    ps[a] = sa;
+                }
                 double ss = 0.0;
                 for (int i = k + 1 + lane; i < p; i += 64) {
                     const double v = s_col[buf][i];
@@ -266,22 +288,33 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 const double vtv = 2.0 * alpha * (alpha - x1);
                 const double beta = vtv > 0.0 ? 2.0 / vtv : 0.0;
                 const double v1 = x1 - alpha;
+                // column k + 1 sits in register column bb (next thread column) or bb + 1 (thread column 0)
+                const bool own1 = kk + 1 < COLS ? tc == kk + 1 : tc == 0;
+                double q = 0.0;
+#pragma unroll
+                for (int a = 0; a < BR; ++a) {
+                    const int i = tr + ROWS * a;
+                    if (ROWS * a + ROWS - 1 > k) {
+                        const double vi = (i > k + 1 && i < p) ? s_col[buf][i] : (i == k + 1 ? v1 : 0.0);
+                        const double a1 = kk + 1 < COLS ? A[a][bb] : A[a][bb + 1 < BC ? bb + 1 : bb];
+                        if (own1) ps[a] = fma(-alpha, a1, ps[a]);
+                        q = fma(vi, ps[a], q);    // this thread's share of v^T A v
+                    }
+                }
+                q = wave_sum(q);
                 double vc[BC];
 #pragma unroll
                 for (int b = 0; b < BC; ++b) {
                     const int j = tc + COLS * b;
-                    vc[b] = (j > k + 1 && j < p) ? s_col[buf][j] : (j == k + 1 ? v1 : 0.0);
+                    vc[b] = j == k + 1 ? v1 : xc[b];
                 }
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
-                    double s = 0.0;
-                    if (ROWS * a + ROWS - 1 > k) {
-#pragma unroll
-                        for (int b = 0; b < BC; ++b) s = fma(A[a][b], vc[b], s);
-                        s = COLS == 32 ? half_sum(s) : row16_sum(s);
-                    }
-                    if (tc == 0) s_ub[tr + ROWS * a] = beta * s;
+                    double sa = 0.0;
+                    if (ROWS * a + ROWS - 1 > k) sa = COLS == 32 ? half_sum(ps[a]) : row16_sum(ps[a]);
+                    if (tc == 0) s_ub[tr + ROWS * a] = beta * sa;
                 }
+                if (lane == 0) s_vav[wave] = q;
                 if (t == 0) {
                     s_dd[k] = s_col[buf][k];
                     s_ee[k] = alpha;
@@ -289,13 +322,11 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 }
                 if (t > k && t < p) d.hv[(int64_t)k * p + t] = (t == k + 1) ? v1 : s_col[buf][t];
                 __syncthreads();
-                double uv = 0.0;
-                for (int i = k + 1 + lane; i < p; i += 64) {
-                    const double vi = (i == k + 1) ? v1 : s_col[buf][i];
-                    uv = fma(s_ub[i], vi, uv);
-                }
-                uv = wave_sum(uv);
-                const double K = 0.5 * beta * uv;
+                // u = beta A v, w = u - (beta/2)(u^T v) v, A <- A - v w^T - w v^T
+                double vav = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) vav += s_vav[w];
+                const double K = 0.5 * beta * (beta * vav);
                 double wc[BC];
 #pragma unroll
                 for (int b = 0; b < BC; ++b) {
@@ -310,12 +341,12 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                         const double wi = (i > k && i < p) ? s_ub[i] - K * vi : 0.0;
 #pragma unroll
                         for (int b = 0; b < BC; ++b) {
-                            if (COLS * b + COLS - 1 > k) A[a][b] -= vi * wc[b] + wi * vc[b];
+                            if (COLS * b + COLS - 1 > k) A[a][b] = fma(-wi, vc[b], fma(-vi, wc[b], A[a][b]));
                         }
                     }
                 }
             }
-        }
+        });
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < BR; ++a)

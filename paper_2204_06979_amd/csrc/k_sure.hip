@@ -228,10 +228,10 @@ __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t v) {
     return v + off;
 }
 __device__ __forceinline__ double wave_incl_f64(double v) {
-    v += dpp_f64<0x111>(v);
-    v += dpp_f64<0x112>(v);
-    v += dpp_f64<0x114>(v);
-    v += dpp_f64<0x118>(v);
+    v += dpp_shift_f64<0x111>(v);
+    v += dpp_shift_f64<0x112>(v);
+    v += dpp_shift_f64<0x114>(v);
+    v += dpp_shift_f64<0x118>(v);
     const double t0 = readlane_f64(v, 15), t1 = readlane_f64(v, 31), t2 = readlane_f64(v, 47);
     const int row = (threadIdx.x & 63) >> 4;
     double off = row >= 1 ? t0 : 0.0;

@@ -35,9 +35,9 @@ hipError_t launch_backproject_f64(const CubeDesc*, int, int64_t, hipStream_t);
 hipError_t launch_dwt_level(int dtype, int tx, int ty, bool inverse, const CubeDesc*, const int*, int, int,
                             int, hipStream_t);
 hipError_t launch_sure_init(int dtype, const CubeDesc*, const int*, int, int, hipStream_t);
-hipError_t launch_sure_round(int dtype, const CubeDesc*, const int*, const int*, int, int, int, hipStream_t);
+hipError_t launch_sure_round(int dtype, const CubeDesc*, const int*, int, int, hipStream_t);
 int sure_rounds(int dtype);
-int sure_chunk();
+int64_t sure_chunk_for(int64_t ncoef, int ncomp, int num_cu);
 hipError_t launch_ritz(const CubeDesc*, const int*, const int*, int, const int*, int, int, int, hipStream_t);
 hipError_t launch_adjoint_pre(const AdjDesc&, int dtype, hipStream_t);
 hipError_t launch_adjoint_thresh(const AdjDesc&, int dtype, hipStream_t);
@@ -172,8 +172,8 @@ struct CubePlan {
     int64_t loff[kMaxLevels + 1] = {0};
     size_t o_gpart = 0, o_G = 0, o_sigma = 0, o_hv = 0, o_V = 0, o_evals = 0, o_gap = 0, o_P32 = 0, o_Q32 = 0,
            o_P64 = 0, o_Q64 = 0, o_Z = 0, o_coef = 0, o_tmp = 0, o_hcnt = 0, o_hsum = 0, o_hmin = 0,
-           o_hmax = 0, o_sst = 0, o_lambda = 0, o_sure = 0, o_sbits = 0, o_spre = 0, o_sspre = 0, o_scb = 0,
-           o_cand = 0, o_sfill = 0, o_rpart = 0, o_rsum = 0, o_rrot = 0;
+           o_hmax = 0, o_sst = 0, o_lambda = 0, o_sure = 0, o_sbits = 0, o_spre = 0, o_sspre = 0, o_sctr = 0,
+           o_cand = 0, o_rpart = 0, o_rsum = 0, o_rrot = 0;
     int rgroups = 0;
     bool has_lambda = false;   // thresholds given by the caller: no SURE search
 };
@@ -250,8 +250,7 @@ void plan_cube(CubePlan& c, Layout& lay, int parts) {
         c.o_sbits = lay.add((size_t)c.r * (kSureBins / 32) * 4);
         c.o_spre = lay.add(nb * 8);
         c.o_sspre = lay.add(nb * 8);
-        c.o_scb = lay.add(nb * 4);
-        c.o_sfill = lay.add(nb * 4);
+        c.o_sctr = lay.add((size_t)c.r * 16);
         c.o_cand = lay.add((size_t)c.r * kSureCap * 8);
         c.o_lambda = lay.add((size_t)c.r * 8);
         c.o_sure = lay.add((size_t)c.r * 8);
@@ -317,8 +316,7 @@ CubeDesc make_desc(const CubePlan& c, void* ws) {
         d.sbits = at<uint32_t>(ws, c.o_sbits);
         d.spre = at<uint64_t>(ws, c.o_spre);
         d.sspre = at<double>(ws, c.o_sspre);
-        d.scb = at<uint32_t>(ws, c.o_scb);
-        d.sfill = at<uint32_t>(ws, c.o_sfill);
+        d.sctr = at<uint32_t>(ws, c.o_sctr);
         d.cand = at<uint64_t>(ws, c.o_cand);
         d.lambda = at<double>(ws, c.o_lambda);
         d.sure = at<double>(ws, c.o_sure);
@@ -573,7 +571,9 @@ void build_program(Exec& x, int stages) {
             if (c.has_lambda) continue;
             const int64_t ns = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
             comp[i] = c.r;
-            hist[i] = c.r * cdiv(ns, sure_chunk());
+            const int64_t ch = sure_chunk_for(ns, c.r, x.h ? x.h->num_cu : 256);
+            x.desc[i].schunk = ch;
+            hist[i] = c.r * cdiv(ns, ch);
         }
         int64_t ncomp, nh;
         const int tc = x.counts(comp, &ncomp);
@@ -591,10 +591,8 @@ void build_program(Exec& x, int stages) {
                 R.kind = K_SURE_ROUND;
                 R.stage = HYRES_STAGE_SURE;
                 R.a = th;
-                R.b = tc;
                 R.n = N;
-                R.grid = x.grid(nh, 2);
-                R.grid2 = (int)ncomp;
+                R.grid = x.grid(nh, 1);
                 x.prog.push_back(R);
             }
         }
@@ -639,7 +637,7 @@ hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
                                     L.n, L.level, L.grid, s);
         case K_SURE_INIT: return launch_sure_init(x.dtype, D, x.table(L.a), L.n, L.grid, s);
         case K_SURE_ROUND:
-            return launch_sure_round(x.dtype, D, x.table(L.a), x.table(L.b), L.n, L.grid, L.grid2, s);
+            return launch_sure_round(x.dtype, D, x.table(L.a), L.n, L.grid, s);
         case K_COPY:
             hipLaunchKernelGGL(k_copy_f64, dim3(1), dim3(64), 0, s, L.src, L.dst, L.n);
             return hipGetLastError();

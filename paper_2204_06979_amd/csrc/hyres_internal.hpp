@@ -34,7 +34,7 @@ struct SureState {
     double below_sum;           // sum of their squares
     double best_s;              // smallest SURE value seen at an exact candidate
     double best_t;              // the candidate attaining it
-    uint64_t zeros;             // number of exact zeros (round 1)
+    uint64_t pad0;
     int round;
     int done;
     int inexact;
@@ -89,8 +89,8 @@ struct CubeDesc {
     uint32_t* sbits;                        // r x kSureBins/32 surviving-bin bitmap
     uint64_t* spre;                         // r x kSureBins: values below each bin (gather round)
     double* sspre;                          // r x kSureBins: their sum of squares
-    uint32_t* scb;                          // r x kSureBins: collected values in earlier surviving bins
-    uint32_t* sfill;                        // r x kSureBins: values collected per surviving bin
+    uint32_t* sctr;                         // r x 4: blocks done in the pass, values gathered, zeros (u64)
+    int64_t schunk;                         // coefficients per SURE work item (a multiple of 1024)
     uint64_t* cand;                         // r x kSureCap collected magnitudes (keys)
     double* lambda; double* sure;           // r
     const double* lambda_in;                // optional caller thresholds

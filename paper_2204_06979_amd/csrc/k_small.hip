@@ -28,18 +28,39 @@ constexpr int kSmallP = 256;   // LDS vector length (p <= 224)
 // every 8 steps so the recursion stays in range.
 __device__ __forceinline__ int sgnbit(double v) { return (int)((unsigned)__double2hiint(v) >> 31); }
 
+template <bool PRE>
 __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const double* __restrict__ e2s,
                                            int p, double x) {
     double pm2 = 1.0, pm1 = ds[0] - x;
     int neg = sgnbit(pm1);
     int cnt = neg;
     int i = 1;
-    for (; i + 8 <= p; i += 8) {
-        double dd[8], ee[8];
+    // blocks of 8 steps; with PRE the next block's entries are read while this
+    // one runs (16 more registers)
+    double dd[8], ee[8];
+    if (PRE && i + 8 <= p) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             dd[u] = ds[i + u];
             ee[u] = e2s[i + u - 1];
+        }
+    }
+    for (; i + 8 <= p; i += 8) {
+        double dn[8], en[8];
+        const bool more = PRE && i + 16 <= p;
+        if (!PRE) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                dd[u] = ds[i + u];
+                ee[u] = e2s[i + u - 1];
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                dn[u] = ds[i + 8 + u];
+                en[u] = e2s[i + 7 + u];
+            }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -56,6 +77,13 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const 
         const int e = e1 > e2 ? e1 : e2;
         pm1 = ldexp(pm1, -e);
         pm2 = ldexp(pm2, -e);
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                dd[u] = dn[u];
+                ee[u] = en[u];
+            }
+        }
     }
     for (; i < p; ++i) {
         const double pi = fma(ds[i] - x, pm1, -e2s[i - 1] * pm2);
@@ -68,7 +96,7 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const 
     return cnt;
 }
 
-// In place: lo = max and hi = min over each aligned group of M lanes (M = 4, 16 or 64).
+// In place: lo = max and hi = min over each aligned group of M lanes (M = 4, 16, 32 or 64).
 __device__ __forceinline__ void group_maxmin(double& lo, double& hi, int M) {
     double a;
     a = dpp_f64<0xB1>(lo); lo = a > lo ? a : lo;      // quad_perm [1,0,3,2]
@@ -87,6 +115,12 @@ __device__ __forceinline__ void group_maxmin(double& lo, double& hi, int M) {
                  h3 = readlane_f64(hi, 48);
     const double la = l0 > l1 ? l0 : l1, lb = l2 > l3 ? l2 : l3;
     const double ha = h0 < h1 ? h0 : h1, hb = h2 < h3 ? h2 : h3;
+    if (M == 32) {
+        const bool upper = (threadIdx.x & 32) != 0;
+        lo = upper ? lb : la;
+        hi = upper ? hb : ha;
+        return;
+    }
     lo = la > lb ? la : lb;
     hi = ha < hb ? ha : hb;
 }
@@ -114,6 +148,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     __shared__ double s_z[kMaxRank][kSmallP];        // eigenvectors of the tridiagonal / of C
     __shared__ double s_red[4];
     __shared__ double s_vav[NW];                     // per-wave shares of v^T A v
+    __shared__ int s_kb[kMaxRank];                   // twist indices
     __shared__ int s_flags;
 
     if (t == 0) s_flags = 0;
@@ -404,7 +439,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                     double lo = -1.0 - 1e-12, hi = 1.0 + 1e-12;
                     for (int it = 0; it < iters; ++it) {
                         const double x = lo + (hi - lo) * ((double)(m + 1) * inv_m1);
-                        const int cnt = sturm_count(s_ub, s_e2, p, x);
+                        const int cnt = sturm_count<false>(s_ub, s_e2, p, x);
                         const bool below = cnt <= midx;   // x <= lambda
                         double lo_c = below ? x : lo;
                         double hi_c = below ? hi : x;
@@ -426,39 +461,93 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
 
         HYRES_STAMP(d, 3);
         // ---------------------------- eigenvectors of the tridiagonal matrix
+        // Twisted factorisation at each eigenvalue mu: the top-down pivots D_i
+        // (wave 0) and the bottom-up pivots R_i with multipliers U_i (wave 1)
+        // run at the same time; the twist index minimises |D_i + R_i - (d_i - mu)|
+        // (largest index on ties); then the two halves of the vector are
+        // solved from the twist outwards, again on two waves.
+        const double pivmin = gmax * 1e-290;
         if (wave == 0 && lane < r) {
             const int g = lane;
             const double mu = s_ev[g];
-            const double pivmin = gmax * 1e-290;
             double D = s_dd[0] - mu;
-            for (int i = 0; i < p; ++i) {
+#pragma unroll 4
+            for (int i = 0; i < p - 1; ++i) {
                 if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
                 s_zD[i * kMaxRank + g] = D;
-                if (i < p - 1) D = (s_dd[i + 1] - mu) - s_ee[i] * (s_ee[i] / D);
+                const double e = s_ee[i];
+                D = (s_dd[i + 1] - mu) - e * (e / D);
             }
+            if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
+            s_zD[(p - 1) * kMaxRank + g] = D;
+        } else if (wave == 1 && lane < r) {
+            const int g = lane;
+            const double mu = s_ev[g];
             double R = s_dd[p - 1] - mu;
             if (fabs(R) < pivmin) R = R < 0.0 ? -pivmin : pivmin;
-            double best = fabs(s_zD[(p - 1) * kMaxRank + g] + R - (s_dd[p - 1] - mu));
-            int kb = p - 1;
+            s_z[g][p - 1] = R;
+#pragma unroll 4
             for (int i = p - 2; i >= 0; --i) {
-                const double U = s_ee[i] / R;
+                const double e = s_ee[i];
+                const double U = e / R;
                 s_zU[i * kMaxRank + g] = U;
-                const double ai = s_dd[i] - mu;
-                R = ai - U * s_ee[i];
+                R = (s_dd[i] - mu) - U * e;
                 if (fabs(R) < pivmin) R = R < 0.0 ? -pivmin : pivmin;
-                const double gam = fabs(s_zD[i * kMaxRank + g] + R - ai);
-                if (gam < best) {
-                    best = gam;
-                    kb = i;
-                }
+                s_z[g][i] = R;
             }
-            s_z[g][kb] = 1.0;
+        }
+        __syncthreads();
+        // twist index of vector g = wave + NW v: argmin over the lanes of the wave
+        int kb_w[VPW];
+#pragma unroll
+        for (int v = 0; v < VPW; ++v) {
+            const int g = wave + NW * v;
+            kb_w[v] = 0;
+            if (g < r) {
+                const double mu = s_ev[g];
+                double best = __builtin_inf();
+                int bi = -1;
+                for (int i = lane; i < p; i += 64) {
+                    const double gam = fabs(s_zD[i * kMaxRank + g] + s_z[g][i] - (s_dd[i] - mu));
+                    if (gam <= best) {           // ascending i: the last minimum is the largest index
+                        best = gam;
+                        bi = i;
+                    }
+                }
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    const double ob = __shfl_xor(best, o, 64);
+                    const int oi = __shfl_xor(bi, o, 64);
+                    if (ob < best || (ob == best && oi > bi)) {
+                        best = ob;
+                        bi = oi;
+                    }
+                }
+                kb_w[v] = bi;
+            }
+        }
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int v = 0; v < VPW; ++v) {
+                const int g = wave + NW * v;
+                if (g < r) s_kb[g] = kb_w[v];
+            }
+        }
+        __syncthreads();
+        if (wave == 0 && lane < r) {
+            const int g = lane, kb = s_kb[g];
             double z = 1.0;
+            s_z[g][kb] = 1.0;
+#pragma unroll 4
             for (int i = kb - 1; i >= 0; --i) {
                 z = -(s_ee[i] / s_zD[i * kMaxRank + g]) * z;
                 s_z[g][i] = z;
             }
-            z = 1.0;
+        } else if (wave == 1 && lane < r) {
+            const int g = lane, kb = s_kb[g];
+            double z = 1.0;
+#pragma unroll 4
             for (int i = kb; i < p - 1; ++i) {
                 z = -s_zU[i * kMaxRank + g] * z;
                 s_z[g][i + 1] = z;
@@ -519,15 +608,31 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
         // the whole block (coalesced), then applied by the waves owning vectors.
         {
             constexpr int RB = 8;
+            constexpr int SPT = (RB * kSmallP + NTH - 1) / NTH;   // staged entries per thread
             double* stage = s_zD;                       // free now: RB x kSmallP doubles
+            // the next group's reflectors are read into registers while the
+            // current group is applied
+            double nxt[SPT];
+            auto fetch = [&](int k1) {
+                const int k0 = k1 - RB + 1 < 0 ? 0 : k1 - RB + 1;
+#pragma unroll
+                for (int j = 0; j < SPT; ++j) {
+                    const int e = t + j * NTH;
+                    const int kk = k1 - e / kSmallP, i = e % kSmallP;
+                    nxt[j] = (e < RB * kSmallP && kk >= k0 && i > kk && i < p) ? d.hv[(int64_t)kk * p + i] : 0.0;
+                }
+            };
+            if (p - 3 >= 0) fetch(p - 3);
             for (int k1 = p - 3; k1 >= 0; k1 -= RB) {
                 const int k0 = k1 - RB + 1 < 0 ? 0 : k1 - RB + 1;
                 __syncthreads();
-                for (int e = t; e < RB * kSmallP; e += NTH) {
-                    const int kk = k1 - e / kSmallP, i = e % kSmallP;
-                    if (kk >= k0) stage[(k1 - kk) * kSmallP + i] = (i > kk && i < p) ? d.hv[(int64_t)kk * p + i] : 0.0;
+#pragma unroll
+                for (int j = 0; j < SPT; ++j) {
+                    const int e = t + j * NTH;
+                    if (e < RB * kSmallP) stage[e] = nxt[j];
                 }
                 __syncthreads();
+                if (k1 - RB >= 0) fetch(k1 - RB);
                 if (wave < r) {
                     for (int k = k1; k >= k0; --k) {
                         const double* hk = stage + (k1 - k) * kSmallP;

@@ -107,10 +107,13 @@ __global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict_
             const int c2 = find_cube(items, ncubes, nxt);
             proj_fetch<T>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4);
         }
-        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        // four independent accumulator chains (consecutive MFMAs do not wait
+        // on each other's results), added in a fixed order
+        v4f ac[4] = {};
         const float* arow = tile + (16 * wave + col) * LDW + row;
 #pragma unroll
-        for (int s = 0; s < 4 * T; ++s) acc = mfma4(arow[4 * s], bf[s], acc);
+        for (int s = 0; s < 4 * T; ++s) ac[s & 3] = mfma4(arow[4 * s], bf[s], ac[s & 3]);
+        const v4f acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
         // lane holds component col of pixels q0 + 16 wave + 4 row + i
         if (col < d.r) {
             float* z = static_cast<float*>(d.Z) + (int64_t)col * d.nz + q0 + 16 * wave + 4 * row;

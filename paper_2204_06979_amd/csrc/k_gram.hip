@@ -238,28 +238,49 @@ __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const 
 #pragma unroll 1
     for (int s = 0; s < kGramKB / 32; ++s) {
         const int base = col * kGramLDP + 32 * s + 8 * row;
-        bf16x8 hi_i = {}, lo_i = {};
+        // fragments of the wave's tiles (a tile row's fragment is read once),
+        // then the products grouped by kind so that consecutive MFMAs go to
+        // different accumulators; each tile still adds hi.hi, hi.lo, lo.hi
+        // (and lo.lo on the diagonal) in that order
+        bf16x8 hi_i[S], lo_i[S], hi_j[S], lo_j[S];
         static_for<S>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             constexpr int t = TM::T0 + WV * S + q;
             if constexpr (t < TM::T1) {
                 constexpr int i = TM::ti(t), j = TM::tj(t);
                 if constexpr (q == 0 || TM::ti(t - 1) != i) {
-                    hi_i = *reinterpret_cast<const bf16x8*>(th + base + 16 * i * kGramLDP);
-                    lo_i = *reinterpret_cast<const bf16x8*>(tl + base + 16 * i * kGramLDP);
-                }
-                if constexpr (i == j) {
-                    acc[q] = mfma_bf16(hi_i, hi_i, acc[q]);
-                    acc[q] = mfma_bf16(hi_i, lo_i, acc[q]);
-                    acc[q] = mfma_bf16(lo_i, hi_i, acc[q]);
-                    acc[q] = mfma_bf16(lo_i, lo_i, acc[q]);
+                    hi_i[q] = *reinterpret_cast<const bf16x8*>(th + base + 16 * i * kGramLDP);
+                    lo_i[q] = *reinterpret_cast<const bf16x8*>(tl + base + 16 * i * kGramLDP);
                 } else {
-                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8*>(th + base + 16 * j * kGramLDP);
-                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8*>(tl + base + 16 * j * kGramLDP);
-                    acc[q] = mfma_bf16(hi_i, hi_j, acc[q]);
-                    acc[q] = mfma_bf16(hi_i, lo_j, acc[q]);
-                    acc[q] = mfma_bf16(lo_i, hi_j, acc[q]);
+                    hi_i[q] = hi_i[q - 1];
+                    lo_i[q] = lo_i[q - 1];
                 }
+                if constexpr (i != j) {
+                    hi_j[q] = *reinterpret_cast<const bf16x8*>(th + base + 16 * j * kGramLDP);
+                    lo_j[q] = *reinterpret_cast<const bf16x8*>(tl + base + 16 * j * kGramLDP);
+                } else {
+                    hi_j[q] = hi_i[q];
+                    lo_j[q] = lo_i[q];
+                }
+            }
+        });
+        static_for<S>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (TM::T0 + WV * S + q < TM::T1) acc[q] = mfma_bf16(hi_i[q], hi_j[q], acc[q]);
+        });
+        static_for<S>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (TM::T0 + WV * S + q < TM::T1) acc[q] = mfma_bf16(hi_i[q], lo_j[q], acc[q]);
+        });
+        static_for<S>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (TM::T0 + WV * S + q < TM::T1) acc[q] = mfma_bf16(lo_i[q], hi_j[q], acc[q]);
+        });
+        static_for<S>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int t = TM::T0 + WV * S + q;
+            if constexpr (t < TM::T1) {
+                if constexpr (TM::ti(t) == TM::tj(t)) acc[q] = mfma_bf16(lo_i[q], lo_i[q], acc[q]);
             }
         });
     }

@@ -37,7 +37,7 @@ hipError_t launch_dwt_level(int dtype, int tx, int ty, bool inverse, const CubeD
 hipError_t launch_sure_init(int dtype, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_sure_round(int dtype, const CubeDesc*, const int*, int, int, hipStream_t);
 int sure_rounds(int dtype);
-int64_t sure_chunk_for(int64_t ncoef, int ncomp, int num_cu);
+int64_t sure_chunk_for(int64_t total_coef, int num_cu);
 hipError_t launch_ritz(const CubeDesc*, const int*, const int*, int, const int*, int, int, int, hipStream_t);
 hipError_t launch_adjoint_pre(const AdjDesc&, int dtype, hipStream_t);
 hipError_t launch_adjoint_thresh(const AdjDesc&, int dtype, hipStream_t);
@@ -566,12 +566,18 @@ void build_program(Exec& x, int stages) {
     if (stages & S_DWT) add_dwt(x, false);
     if (stages & S_SURE) {
         std::vector<int64_t> comp(N, 0), hist(N, 0);
+        // one work-item size for the whole program: about one item per compute unit
+        int64_t total_coef = 0;
+        for (int i = 0; i < N; ++i) {
+            const CubePlan& c = x.plan[i];
+            if (!c.has_lambda) total_coef += (int64_t)c.r * (c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc);
+        }
+        const int64_t ch = sure_chunk_for(total_coef, x.h ? x.h->num_cu : 256);
         for (int i = 0; i < N; ++i) {
             const CubePlan& c = x.plan[i];
             if (c.has_lambda) continue;
             const int64_t ns = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
             comp[i] = c.r;
-            const int64_t ch = sure_chunk_for(ns, c.r, x.h ? x.h->num_cu : 256);
             x.desc[i].schunk = ch;
             hist[i] = c.r * cdiv(ns, ch);
         }

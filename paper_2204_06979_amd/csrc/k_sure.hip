@@ -56,6 +56,7 @@ constexpr int kSureChunk = 16 * kSureThreads;         // smallest work item (coe
 constexpr int kGatherPer = 32;                        // gathered coefficients per thread and step
 constexpr int kBinsPer = kSureBins / kSureThreads;    // bins per thread in the select
 constexpr int kSureGroup = 4;   // chunks per block after the first pass (fewer partial merges)
+constexpr int64_t kSureGroupSpan = 65536;   // ... while a block's range stays within this many values
 
 __host__ __device__ inline int sure_shift_for(uint64_t span) {
     int s = 0;
@@ -651,9 +652,10 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_round(const CubeDesc* __r
         __syncthreads();
         if (sh.st.done) continue;   // uniform across the block
         const SureState st = sh.st;
-        // in refinement passes few values are in range: a block takes
-        // kSureGroup chunks (the others of the group only count themselves)
-        const int grp = st.round == 0 || st.gather ? 1 : kSureGroup;
+        // in refinement passes few values are in range: a block takes up to
+        // kSureGroup small chunks (the others of the group only count themselves)
+        const int64_t gmax = kSureGroupSpan / ch;
+        const int grp = st.round == 0 || st.gather ? 1 : (int)(gmax < 1 ? 1 : (gmax > kSureGroup ? kSureGroup : gmax));
         if (chunk % grp == 0) {
             const int64_t e0 = (int64_t)chunk * ch;
             const int64_t eg = e0 + (int64_t)grp * ch;
@@ -711,12 +713,11 @@ hipError_t launch_sure_round(int dtype, const CubeDesc* descs, const int* items,
 // One more pass than refinement rounds, so a gather decided in the last
 // refinement round is still finished.
 int sure_rounds(int dtype) { return (dtype == HYRES_F64 ? kSureRoundsF64 : kSureRoundsF32) + 1; }
-// Coefficients per work item of a component: about one item per compute unit
-// over the components of a solve, at least kSureChunk, a multiple of the
-// block size.
-int64_t sure_chunk_for(int64_t ncoef, int ncomp, int num_cu) {
-    const int64_t target = num_cu / ncomp > 1 ? num_cu / ncomp : 1;
-    int64_t ch = (ncoef + target - 1) / target;
+// Coefficients per work item: about one item per compute unit over all the
+// components of a program (each block then streams its item once per pass),
+// at least kSureChunk, a multiple of the block size.
+int64_t sure_chunk_for(int64_t total_coef, int num_cu) {
+    int64_t ch = (total_coef + num_cu - 1) / (num_cu > 0 ? num_cu : 1);
     ch = (ch + kSureThreads - 1) / kSureThreads * kSureThreads;
     return ch > kSureChunk ? ch : kSureChunk;
 }

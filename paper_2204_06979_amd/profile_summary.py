@@ -11,9 +11,10 @@
 
 FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch.  Each is scaled by
 the ratio of the bytes a plain copy of known size moves to what the same
-counter reports for that copy.  Per-solve figures divide a kernel's total
-over the run by the number of solves in it (the number of small-solve
-dispatches, one per solve).
+counter reports for that copy.  Per-step figures divide a kernel's total over
+the run by the number of steps in it: one step is one run of the whole path
+(one solve, one batch, or one sliding-window solve), and every step starts
+the threshold search once (one k_sure_init dispatch per step).
 """
 from __future__ import annotations
 
@@ -85,9 +86,12 @@ def summarize(a) -> int:
     write = read_counter(a.write, "WRITE_SIZE") if a.write else {}
     cf = copy_factor(a.cal_fetch, "FETCH_SIZE") if a.cal_fetch else None
     cw = copy_factor(a.cal_write, "WRITE_SIZE") if a.cal_write else None
-    solves_t = sum(c for n, c, *_ in stats if "k_small" in n) or 1
-    solves_f = sum(v[0] for n, v in fetch.items() if "k_small" in n) or 1
-    solves_w = sum(v[0] for n, v in write.items() if "k_small" in n) or 1
+    def steps_of(counts):
+        s = sum(c for n, c in counts if "k_sure_init" in n)
+        return s or sum(c for n, c in counts if "k_small" in n) or 1
+    solves_t = steps_of([(n, c) for n, c, *_ in stats])
+    solves_f = steps_of([(n, v[0]) for n, v in fetch.items()])
+    solves_w = steps_of([(n, v[0]) for n, v in write.items()])
     out = []
     out.append("# rocprofv3 summary: %s\n" % a.workload)
     if a.command:
@@ -95,8 +99,8 @@ def summarize(a) -> int:
         for c in a.command:
             out.append("    %s" % c)
         out.append("")
-    out.append("Solves in the timed run: %d (one small-solve dispatch each).\n" % solves_t)
-    out.append("| kernel | stage | calls | avg us | us per solve | % time |")
+    out.append("Steps in the profiled run: %d (one threshold-search start each).\n" % solves_t)
+    out.append("| kernel | stage | calls | avg us | us per step | % time |")
     out.append("|---|---|---|---|---|---|")
     for name, calls, total, avg, pct in sorted(stats, key=lambda r: -r[2]):
         out.append("| %s | %s | %d | %.1f | %.1f | %.2f |" % (short(name), stage_of(name), calls, avg / 1e3,
@@ -104,10 +108,10 @@ def summarize(a) -> int:
     traffic = defaultdict(float)
     if fetch or write:
         out.append("")
-        out.append("HBM traffic per solve (counter KiB x calibration: FETCH %s B/KiB, WRITE %s B/KiB, "
+        out.append("HBM traffic per step (counter KiB x calibration: FETCH %s B/KiB, WRITE %s B/KiB, "
                    "from a %d MiB copy):\n" % ("%.1f" % cf if cf else "n/a", "%.1f" % cw if cw else "n/a",
                                                COPY_BYTES >> 20))
-        out.append("| kernel | stage | FETCH KiB/solve | WRITE KiB/solve | bytes/solve (calibrated) |")
+        out.append("| kernel | stage | FETCH KiB/step | WRITE KiB/step | bytes/step (calibrated) |")
         out.append("|---|---|---|---|---|")
         names = sorted(set(fetch) | set(write), key=lambda n: -(fetch.get(n, (0, 0))[1] + write.get(n, (0, 0))[1]))
         for n in names:

@@ -8,7 +8,8 @@
 // FP32 partial Gram; k_gram_reduce sums the slots of a cube in FP64 in a fixed
 // order, so the result is bitwise reproducible.  Inside a slot the MFMA
 // accumulates one 64-pixel chunk in FP32 and chunks are summed in FP64, so the
-// rounding error of G stays near one FP32 rounding of each partial.
+// rounding error of G stays near one FP32 rounding of each partial.  A NaN or
+// Inf in band a makes G_aa non-finite: the reduce flags it (no per-value test).
 //
 // FP64 cubes: one thread per upper-triangle entry and slot, plain FP64 FMAs.
 #include "hyres_internal.hpp"
@@ -114,10 +115,9 @@ __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t
 }
 
 template <int T>
-__device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, const float (&r)[gram_nr<T>()]) {
+__device__ __forceinline__ void gram_stage(float* __restrict__ tile, bool vec, const float (&r)[gram_nr<T>()]) {
     constexpr int LDW = gram_ldw<T>();
     const int tid = threadIdx.x;
-    int bad = 0;
     if (vec) {
 #pragma unroll
         for (int i = 0; i < gram_nv4<T>(); ++i) {
@@ -125,8 +125,6 @@ __device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, co
             const int k = e / (4 * T), g = e - k * (4 * T);
             if (k < kGramKB) {
                 const v4f v = {r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) bad |= !__builtin_isfinite(v[c]);
                 *reinterpret_cast<v4f*>(tile + k * LDW + 4 * g) = v;
             }
         }
@@ -135,13 +133,9 @@ __device__ __forceinline__ int gram_stage(float* __restrict__ tile, bool vec, co
         for (int i = 0; i < gram_nv1<T>(); ++i) {
             const int e = tid + kGramThreads * i;
             const int k = e / (16 * T), b = e - k * (16 * T);
-            if (k < kGramKB) {
-                bad |= !__builtin_isfinite(r[i]);
-                tile[k * LDW + b] = r[i];
-            }
+            if (k < kGramKB) tile[k * LDW + b] = r[i];
         }
     }
-    return bad;
 }
 
 template <int T, int P>
@@ -173,12 +167,11 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
 #pragma unroll
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
         }
-        int bad = 0;
         float rg[gram_nr<T>()];
         if (q0 < q1) gram_fetch<T>(d, q0, q1, vec, rg);
         for (int64_t q = q0; q < q1; q += kGramKB) {
             __syncthreads();
-            bad |= gram_stage<T>(tile, vec, rg);
+            gram_stage<T>(tile, vec, rg);
             __syncthreads();
             if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, rg);   // overlaps the MFMAs
             switch (wave) {
@@ -199,7 +192,6 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
                 acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
             }
         }
-        if (__any(bad) && lane == 0) set_status(d.status, HYRES_DEV_NONFINITE);
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
@@ -314,10 +306,9 @@ __device__ __forceinline__ void gramb_fetch(const CubeDesc& d, int64_t q, int64_
 }
 
 template <int T>
-__device__ __forceinline__ int gramb_stage(__bf16* __restrict__ th, __bf16* __restrict__ tl,
+__device__ __forceinline__ void gramb_stage(__bf16* __restrict__ th, __bf16* __restrict__ tl,
                                            const v4f (&r)[gramb_nt<T>()][8]) {
     const int tid = threadIdx.x;
-    int bad = 0;
 #pragma unroll
     for (int i = 0; i < gramb_nt<T>(); ++i) {
         const int task = tid + kGramThreads * i;
@@ -329,7 +320,6 @@ __device__ __forceinline__ int gramb_stage(__bf16* __restrict__ th, __bf16* __re
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const float v = r[i][u][c];
-                    bad |= !__builtin_isfinite(v);
                     const __bf16 h = (__bf16)v;
                     h8[u] = h;
                     l8[u] = (__bf16)(v - (float)h);
@@ -339,34 +329,30 @@ __device__ __forceinline__ int gramb_stage(__bf16* __restrict__ th, __bf16* __re
             }
         }
     }
-    return bad;
 }
 
 // Scalar staging (strided or unaligned cubes).
 template <int T>
-__device__ __forceinline__ int gramb_stage_scalar(__bf16* __restrict__ th, __bf16* __restrict__ tl,
+__device__ __forceinline__ void gramb_stage_scalar(__bf16* __restrict__ th, __bf16* __restrict__ tl,
                                                   const float (&r)[gram_nr<T>()]) {
     const int tid = threadIdx.x;
-    int bad = 0;
 #pragma unroll
     for (int i = 0; i < gram_nv1<T>(); ++i) {
         const int e = tid + kGramThreads * i;
         const int k = e / (16 * T), b = e - k * (16 * T);
         if (k < kGramKB) {
             const float v = r[i];
-            bad |= !__builtin_isfinite(v);
             const __bf16 h = (__bf16)v;
             th[b * kGramLDP + k] = h;
             tl[b * kGramLDP + k] = (__bf16)(v - (float)h);
         }
     }
-    return bad;
 }
 
 template <int T, int P, bool VEC>
 __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_t q1, __bf16* th, __bf16* tl,
                                            int lane, int wave, v4f (&acc)[TileMap<T, P>::S],
-                                           double (&accd)[TileMap<T, P>::S][4], int& bad) {
+                                           double (&accd)[TileMap<T, P>::S][4]) {
     constexpr int S = TileMap<T, P>::S;
     v4f rv[VEC ? gramb_nt<T>() : 1][8];
     float rs[VEC ? 1 : gram_nr<T>()];
@@ -376,8 +362,8 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
     }
     for (int64_t q = q0; q < q1; q += kGramKB) {
         __syncthreads();
-        if constexpr (VEC) bad |= gramb_stage<T>(th, tl, rv);
-        else bad |= gramb_stage_scalar<T>(th, tl, rs);
+        if constexpr (VEC) gramb_stage<T>(th, tl, rv);
+        else gramb_stage_scalar<T>(th, tl, rs);
         __syncthreads();
         if (q + kGramKB < q1) {
             if constexpr (VEC) gramb_fetch<T>(d, q + kGramKB, q1, rv);
@@ -431,10 +417,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
 #pragma unroll
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
         }
-        int bad = 0;
-        if (vec) gramb_slot<T, P, true>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
-        else gramb_slot<T, P, false>(d, q0, q1, th, tl, lane, wave, acc, accd, bad);
-        if (__any(bad) && lane == 0) set_status(d.status, HYRES_DEV_NONFINITE);
+        if (vec) gramb_slot<T, P, true>(d, q0, q1, th, tl, lane, wave, acc, accd);
+        else gramb_slot<T, P, false>(d, q0, q1, th, tl, lane, wave, acc, accd);
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
@@ -492,6 +476,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce_f32(const CubeDesc* __restr
         if (a < d.p && b < d.p && a <= b) {
             d.G[(int64_t)a * d.p + b] = tot;
             d.G[(int64_t)b * d.p + a] = tot;
+            // a NaN or Inf anywhere in band a makes G_aa non-finite
+            if (a == b && !__builtin_isfinite(tot)) set_status(d.status, HYRES_DEV_NONFINITE);
         }
     }
 }

@@ -387,7 +387,21 @@ __device__ void sure_finish(const CubeDesc& d, int comp, double N, unsigned char
         const int b = (int)((key - klo) >> shf);
         const int s0 = (int)boff[b], s1 = (int)boff[b + 1];
         double cw = 0.0, sw = 0.0;
-        for (int j = s0; j < s1; ++j) {
+        int j = s0;
+        for (; j + 4 <= s1; j += 4) {             // four reads in flight, added in order
+            uint64_t kq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) kq[u] = keys[j + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (kq[u] <= key) {
+                    const double vj = KT::val(kq[u]);
+                    cw += 1.0;
+                    sw = fma(vj, vj, sw);
+                }
+            }
+        }
+        for (; j < s1; ++j) {
             const uint64_t kj = keys[j];
             if (kj <= key) {
                 const double vj = KT::val(kj);

@@ -230,49 +230,31 @@ __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const 
 #pragma unroll 1
     for (int s = 0; s < kGramKB / 32; ++s) {
         const int base = col * kGramLDP + 32 * s + 8 * row;
-        // fragments of the wave's tiles (a tile row's fragment is read once),
-        // then the products grouped by kind so that consecutive MFMAs go to
-        // different accumulators; each tile still adds hi.hi, hi.lo, lo.hi
-        // (and lo.lo on the diagonal) in that order
-        bf16x8 hi_i[S], lo_i[S], hi_j[S], lo_j[S];
+        bf16x8 hi_i = {}, lo_i = {};
         static_for<S>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             constexpr int t = TM::T0 + WV * S + q;
             if constexpr (t < TM::T1) {
                 constexpr int i = TM::ti(t), j = TM::tj(t);
                 if constexpr (q == 0 || TM::ti(t - 1) != i) {
-                    hi_i[q] = *reinterpret_cast<const bf16x8*>(th + base + 16 * i * kGramLDP);
-                    lo_i[q] = *reinterpret_cast<const bf16x8*>(tl + base + 16 * i * kGramLDP);
-                } else {
-                    hi_i[q] = hi_i[q - 1];
-                    lo_i[q] = lo_i[q - 1];
+                    hi_i = *reinterpret_cast<const bf16x8*>(th + base + 16 * i * kGramLDP);
+                    lo_i = *reinterpret_cast<const bf16x8*>(tl + base + 16 * i * kGramLDP);
                 }
-                if constexpr (i != j) {
-                    hi_j[q] = *reinterpret_cast<const bf16x8*>(th + base + 16 * j * kGramLDP);
-                    lo_j[q] = *reinterpret_cast<const bf16x8*>(tl + base + 16 * j * kGramLDP);
+                if constexpr (i == j) {
+                    acc[q] = mfma_bf16(hi_i, hi_i, acc[q]);
+                    acc[q] = mfma_bf16(hi_i, lo_i, acc[q]);
+                    acc[q] = mfma_bf16(lo_i, hi_i, acc[q]);
+                    acc[q] = mfma_bf16(lo_i, lo_i, acc[q]);
                 } else {
-                    hi_j[q] = hi_i[q];
-                    lo_j[q] = lo_i[q];
+                    const bf16x8 hi_j = *reinterpret_cast<const bf16x8*>(th + base + 16 * j * kGramLDP);
+                    const bf16x8 lo_j = *reinterpret_cast<const bf16x8*>(tl + base + 16 * j * kGramLDP);
+                    acc[q] = mfma_bf16(hi_i, hi_j, acc[q]);
+                    acc[q] = mfma_bf16(hi_i, lo_j, acc[q]);
+                    acc[q] = mfma_bf16(lo_i, hi_j, acc[q]);
                 }
-            }
-        });
-        static_for<S>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            if constexpr (TM::T0 + WV * S + q < TM::T1) acc[q] = mfma_bf16(hi_i[q], hi_j[q], acc[q]);
-        });
-        static_for<S>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            if constexpr (TM::T0 + WV * S + q < TM::T1) acc[q] = mfma_bf16(hi_i[q], lo_j[q], acc[q]);
-        });
-        static_for<S>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            if constexpr (TM::T0 + WV * S + q < TM::T1) acc[q] = mfma_bf16(lo_i[q], hi_j[q], acc[q]);
-        });
-        static_for<S>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            constexpr int t = TM::T0 + WV * S + q;
-            if constexpr (t < TM::T1) {
-                if constexpr (TM::ti(t) == TM::tj(t)) acc[q] = mfma_bf16(lo_i[q], lo_i[q], acc[q]);
+                // many tiles per wave: keep the scheduler from reading every
+                // tile's fragments ahead (registers), two tiles at a time
+                if constexpr (S > 8 && (q & 1)) __builtin_amdgcn_sched_barrier(0);
             }
         });
     }
@@ -349,10 +331,12 @@ __device__ __forceinline__ void gramb_stage_scalar(__bf16* __restrict__ th, __bf
     }
 }
 
-template <int T, int P, bool VEC>
+// FP64: chunk sums flushed into FP64 accumulators (else acc keeps summing the
+// whole slot in FP32).
+template <int T, int P, bool VEC, bool FP64>
 __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_t q1, __bf16* th, __bf16* tl,
                                            int lane, int wave, v4f (&acc)[TileMap<T, P>::S],
-                                           double (&accd)[TileMap<T, P>::S][4]) {
+                                           double (&accd)[FP64 ? TileMap<T, P>::S : 1][4]) {
     constexpr int S = TileMap<T, P>::S;
     v4f rv[VEC ? gramb_nt<T>() : 1][8];
     float rs[VEC ? 1 : gram_nr<T>()];
@@ -379,14 +363,23 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
             case 6: gramb_wave<T, P, 6>(th, tl, lane, acc); break;
             default: gramb_wave<T, P, 7>(th, tl, lane, acc); break;
         }
+        if constexpr (FP64) {
 #pragma unroll
-        for (int q2 = 0; q2 < S; ++q2) {
+            for (int q2 = 0; q2 < S; ++q2) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
-            acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
+                acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
         }
     }
 }
+
+// From T = kGramSplitT on, the FP64 accumulators of all upper tiles would not
+// fit in registers: the tiles of a slot then accumulate in FP32 across the
+// whole slot (a few thousand pixels; the FP64 reduce over slots follows), one
+// launch reads Y once.  The split-BF16 products themselves carry a relative
+// error near 2^-16, above what the FP32 sums add.
+constexpr int kGramSplitT = 11;
 
 template <int T, int P>
 __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __restrict__ descs,
@@ -394,6 +387,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
     using TM = TileMap<T, P>;
     constexpr int NT = TM::NT;
     constexpr int S = TM::S;
+    constexpr bool FP64 = T < kGramSplitT;
     __shared__ __attribute__((aligned(16))) __bf16 th[16 * T * kGramLDP];
     __shared__ __attribute__((aligned(16))) __bf16 tl[16 * T * kGramLDP];
     const int lane = threadIdx.x & 63;
@@ -410,15 +404,15 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
         const int64_t q1 = q0 + per < n ? q0 + per : n;
         const bool vec = d.vec4 != 0;
         v4f acc[S];
-        double accd[S][4];
+        double accd[FP64 ? S : 1][4];
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < S; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < (FP64 ? S : 1); ++q)
 #pragma unroll
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
-        }
-        if (vec) gramb_slot<T, P, true>(d, q0, q1, th, tl, lane, wave, acc, accd);
-        else gramb_slot<T, P, false>(d, q0, q1, th, tl, lane, wave, acc, accd);
+        if (vec) gramb_slot<T, P, true, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
+        else gramb_slot<T, P, false, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
@@ -426,7 +420,12 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
             const int t = TM::T0 + wave * S + q;
             if (t < TM::T1) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) out[t * 256 + (4 * row + i) * 16 + col] = (float)accd[q][i];
+                for (int i = 0; i < 4; ++i) {
+                    float v;
+                    if constexpr (FP64) v = (float)accd[q][i];
+                    else v = acc[q][i];
+                    out[t * 256 + (4 * row + i) * 16 + col] = v;
+                }
             }
         }
     }
@@ -527,9 +526,9 @@ __global__ void k_gram_reduce_f64(const CubeDesc* __restrict__ descs, int cube) 
 // ---------------------------------------------------------------- launchers
 typedef void (*GramF32Kernel)(const CubeDesc*, const int*, int);
 
-// From T = 11 up the accumulators of all tiles no longer fit in the registers
-// of 8 waves; the tiles are then split over two launches (three from T = 13).
-constexpr int kGramSplitT = 11;
+// FP32 cubes in native precision: from T = kGramSplitT up the FP64
+// accumulators of all tiles no longer fit in the registers of 8 waves; the
+// tiles are then split over two launches (three from T = 13).
 
 template <int T>
 static hipError_t launch_gram_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
@@ -548,14 +547,7 @@ static hipError_t launch_gram_t(const CubeDesc* descs, const int* items, int ncu
 template <int T>
 static hipError_t launch_gramb_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
                                  hipStream_t s) {
-    if constexpr (T >= kGramSplitT) {
-        hipLaunchKernelGGL((k_gram_bf16<T, 1>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        hipLaunchKernelGGL((k_gram_bf16<T, 2>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        if constexpr (TileMap<T, 1>::NP == 3)
-            hipLaunchKernelGGL((k_gram_bf16<T, 3>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-    } else {
-        hipLaunchKernelGGL((k_gram_bf16<T, 0>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-    }
+    hipLaunchKernelGGL((k_gram_bf16<T, 0>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     return hipGetLastError();
 }
 

@@ -117,7 +117,13 @@ typedef struct {
 /* ---- handle ------------------------------------------------------------- */
 
 /* Create a handle bound to HIP device `device` (it becomes current during calls).
- * Fails with HYRES_E_HIP when no such device exists. */
+ * The handle owns a few side streams (default priority) and events: the small
+ * solves of cubes in different band-count classes run on them beside the
+ * caller's stream, forked from and joined back into it, so every call stays
+ * ordered on the caller's stream (and a capture of it records the branches).
+ * Use a handle from one host thread at a time.
+ * Fails with HYRES_E_HIP when no such device exists or the streams cannot be
+ * created. */
 hyres_status hyres_create(hyres_handle** handle, int device);
 void hyres_destroy(hyres_handle* handle);
 const char* hyres_status_string(int status);

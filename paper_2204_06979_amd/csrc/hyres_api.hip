@@ -79,6 +79,11 @@ struct hyres_handle {
     unsigned char tile[2][2][kWidthClasses];
     unsigned char tuned[2][2][kWidthClasses];
     float tile_us[2][2][kWidthClasses];
+    // side streams (default priority) on which the small solves of different
+    // band-count classes run beside each other, with their fork/join events
+    static constexpr int kSide = 8;
+    hipStream_t side[kSide];
+    hipEvent_t fork, join[kSide];
 };
 
 namespace {
@@ -664,16 +669,38 @@ hyres_status upload_exec(const Exec& x, hipStream_t s) {
 }
 
 // Enqueues the program; `timed` wraps each stage in the handle's stage timers.
+// Consecutive small-solve launches (one per band-count class, each a handful of
+// workgroups) run beside each other: the first on `s`, the others on the
+// handle's side streams, forked from and joined back into `s` by events (a
+// capture of `s` records them as parallel branches).
 hyres_status run_program(const Exec& x, hipStream_t s, bool timed) {
     std::unique_ptr<StageTimer> tm;
     int cur = -1;
-    for (const Launch& L : x.prog) {
+    const size_t np = x.prog.size();
+    for (size_t k = 0; k < np; ++k) {
+        const Launch& L = x.prog[k];
         if (timed && L.stage != cur) {
             tm.reset();
             tm.reset(new StageTimer(x.h, s, L.stage));
             cur = L.stage;
         }
+        size_t m = 1;
+        if (L.kind == K_SMALL && x.h)
+            while (k + m < np && m <= (size_t)hyres_handle::kSide && x.prog[k + m].kind == K_SMALL) ++m;
+        if (m == 1) {
+            HIPCHK(launch_one(x, L, s));
+            continue;
+        }
+        HIPCHK(hipEventRecord(x.h->fork, s));
+        for (size_t i = 1; i < m; ++i) {
+            hipStream_t a = x.h->side[i - 1];
+            HIPCHK(hipStreamWaitEvent(a, x.h->fork, 0));
+            HIPCHK(launch_one(x, x.prog[k + i], a));
+            HIPCHK(hipEventRecord(x.h->join[i - 1], a));
+        }
         HIPCHK(launch_one(x, L, s));
+        for (size_t i = 1; i < m; ++i) HIPCHK(hipStreamWaitEvent(s, x.h->join[i - 1], 0));
+        k += m - 1;
     }
     return HYRES_OK;
 }
@@ -777,7 +804,7 @@ HYRES_API hyres_status hyres_create(hyres_handle** handle, int device) {
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HYRES_E_HIP;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HYRES_E_HIP;
-    hyres_handle* h = new (std::nothrow) hyres_handle;
+    hyres_handle* h = new (std::nothrow) hyres_handle();
     if (!h) return HYRES_E_HIP;
     h->device = device;
     h->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -787,6 +814,20 @@ HYRES_API hyres_status hyres_create(hyres_handle** handle, int device) {
         if (*q == '"' || *q == '\\') *q = '_';
     h->arch = key;
     h->prof_mask = 0;
+    {
+        int prev = 0;
+        bool ok = hipGetDevice(&prev) == hipSuccess && hipSetDevice(device) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; i < hyres_handle::kSide && ok; ++i) {
+            ok = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&h->join[i], hipEventDisableTiming) == hipSuccess;
+        }
+        (void)hipSetDevice(prev);
+        if (!ok) {
+            hyres_destroy(h);
+            return HYRES_E_HIP;
+        }
+    }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int w = 0; w < kWidthClasses; ++w) {
@@ -805,6 +846,11 @@ HYRES_API void hyres_destroy(hyres_handle* handle) {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : handle->pool) (void)hipEventDestroy(e);
+    for (int i = 0; i < hyres_handle::kSide; ++i) {
+        if (handle->side[i]) (void)hipStreamDestroy(handle->side[i]);
+        if (handle->join[i]) (void)hipEventDestroy(handle->join[i]);
+    }
+    if (handle->fork) (void)hipEventDestroy(handle->fork);
     delete handle;
 }
 

@@ -23,12 +23,12 @@
 #define HYRES_API extern "C" __attribute__((visibility("default")))
 
 namespace hyres {
-hipError_t launch_gram_f32(int T, const CubeDesc*, const int*, int, int, hipStream_t);
-hipError_t launch_gram_bf16(int T, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_gram_f32(int T, bool vec, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_gram_bf16(int T, bool vec, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_gram_reduce_f32(int T, const CubeDesc*, const int*, int, hipStream_t);
 hipError_t launch_gram_f64(const CubeDesc*, int, int, int, hipStream_t);
 hipError_t launch_small(int p, const CubeDesc*, const int*, int, hipStream_t);
-hipError_t launch_project_f32(int T, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_project_f32(int T, bool vec, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_backproject_f32(int T, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_project_f64(const CubeDesc*, int, int64_t, hipStream_t);
 hipError_t launch_backproject_f64(const CubeDesc*, int, int64_t, hipStream_t);
@@ -494,6 +494,13 @@ void build_program(Exec& x, int stages) {
             L.a = x.counts(cnt, &tot);
             L.n = N;
             L.grid = x.grid(tot, per_cu);
+            if (kind == K_PROJ_F32 || kind == K_GRAM_F32 || kind == K_GRAM_BF16) {
+                // every cube of the class has 16-byte pixel vectors: the vector-only kernel
+                bool all = true;
+                for (int i = 0; i < N; ++i)
+                    if (cnt[i] && !x.desc[i].vec4) all = false;
+                L.b = all ? 1 : 0;
+            }
             x.prog.push_back(L);
             if (kind == K_GRAM_F32 || kind == K_GRAM_BF16) {
                 std::vector<int> ids;
@@ -635,12 +642,12 @@ void build_program(Exec& x, int stages) {
 hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
     const CubeDesc* D = x.descs();
     switch (L.kind) {
-        case K_GRAM_F32: return launch_gram_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
-        case K_GRAM_BF16: return launch_gram_bf16(L.key, D, x.table(L.a), L.n, L.grid, s);
+        case K_GRAM_F32: return launch_gram_f32(L.key, L.b != 0, D, x.table(L.a), L.n, L.grid, s);
+        case K_GRAM_BF16: return launch_gram_bf16(L.key, L.b != 0, D, x.table(L.a), L.n, L.grid, s);
         case K_GRAM_RED: return launch_gram_reduce_f32(L.key, D, x.table(L.a), L.n, s);
         case K_GRAM_F64: return launch_gram_f64(D, L.a, L.key, L.grid, s);
         case K_SMALL: return launch_small(L.key, D, x.table(L.a), L.n, s);
-        case K_PROJ_F32: return launch_project_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
+        case K_PROJ_F32: return launch_project_f32(L.key, L.b != 0, D, x.table(L.a), L.n, L.grid, s);
         case K_PROJ_F64: return launch_project_f64(D, L.a, L.n64, s);
         case K_DWT:
         case K_IDWT:

@@ -22,11 +22,11 @@ template <int T> __host__ __device__ constexpr int proj_nv1() { return (kPixTile
 // One register array serves both load paths: T float4 groups or 4T floats.
 static_assert(proj_nv1<1>() == 4 * proj_nv4<1>(), "projection staging sizes");
 
-template <int T>
+template <int T, bool VEC>
 __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&r4)[proj_nv4<T>()]) {
     const int tid = threadIdx.x;
     const int64_t nleft = d.n - q0;
-    if (d.vec4) {
+    if (VEC || d.vec4) {
         const float* base = pixel_ptr<float>(d, q0);   // a tile never crosses an image row
         const int g4 = d.p >> 2;
 #pragma unroll
@@ -50,11 +50,11 @@ __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&
     }
 }
 
-template <int T>
+template <int T, bool VEC>
 __device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, const v4f (&r4)[proj_nv4<T>()]) {
     constexpr int LDW = proj_ldw<T>();
     const int tid = threadIdx.x;
-    if (vec) {
+    if (VEC || vec) {
 #pragma unroll
         for (int i = 0; i < proj_nv4<T>(); ++i) {
             const int e = tid + 256 * i;
@@ -71,8 +71,10 @@ __device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, c
     }
 }
 
-template <int T>
-__global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict__ descs,
+// VEC: every cube of the launch has 16-byte pixel vectors (the scalar load path
+// is compiled out, which keeps the registers within two waves per SIMD).
+template <int T, bool VEC>
+__global__ __launch_bounds__(256, VEC ? 2 : 1) void k_project_f32(const CubeDesc* __restrict__ descs,
                                                     const int* __restrict__ items, int ncubes) {
     constexpr int LDW = proj_ldw<T>();
     __shared__ __attribute__((aligned(16))) float tile[kPixTile * LDW];
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict_
     int item = blockIdx.x;
     if (item < total) {
         const int c = find_cube(items, ncubes, item);
-        proj_fetch<T>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4);
+        proj_fetch<T, VEC>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4);
     }
     for (; item < total; item += gridDim.x) {
         const int c = find_cube(items, ncubes, item);
@@ -100,19 +102,24 @@ __global__ __launch_bounds__(256) void k_project_f32(const CubeDesc* __restrict_
         const int64_t q0 = (int64_t)(item - items[c]) * kPixTile;
         const bool vec = d.vec4 != 0;
         __syncthreads();
-        proj_stage<T>(tile, vec, r4);
+        proj_stage<T, VEC>(tile, vec, r4);
         __syncthreads();
         const int nxt = item + gridDim.x;
         if (nxt < total) {
             const int c2 = find_cube(items, ncubes, nxt);
-            proj_fetch<T>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4);
+            proj_fetch<T, VEC>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4);
         }
         // four independent accumulator chains (consecutive MFMAs do not wait
         // on each other's results), added in a fixed order
         v4f ac[4] = {};
         const float* arow = tile + (16 * wave + col) * LDW + row;
 #pragma unroll
-        for (int s = 0; s < 4 * T; ++s) ac[s & 3] = mfma4(arow[4 * s], bf[s], ac[s & 3]);
+        for (int s = 0; s < 4 * T; ++s) {
+            ac[s & 3] = mfma4(arow[4 * s], bf[s], ac[s & 3]);
+            // bounded look-ahead of the LDS reads: the registers stay low
+            // enough for two waves per SIMD
+            if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
         const v4f acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
         // lane holds component col of pixels q0 + 16 wave + 4 row + i
         if (col < d.r) {
@@ -263,18 +270,19 @@ __global__ void k_backproject_f64(const CubeDesc* __restrict__ descs, int cube) 
 
 // ---------------------------------------------------------------- launchers
 template <int T>
-static void launch_proj_t(const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_project_f32<T>, dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+static void launch_proj_t(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
+    if (vec) hipLaunchKernelGGL((k_project_f32<T, true>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+    else hipLaunchKernelGGL((k_project_f32<T, false>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
 }
 template <int T>
 static void launch_bp_t(const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_backproject_f32<T>, dim3(grid), dim3(256), 0, s, descs, items, ncubes);
 }
 
-hipError_t launch_project_f32(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,
+hipError_t launch_project_f32(int T, bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
                               hipStream_t s) {
     switch (T) {
-#define HYRES_P(TT) case TT: launch_proj_t<TT>(descs, items, ncubes, grid, s); break;
+#define HYRES_P(TT) case TT: launch_proj_t<TT>(vec, descs, items, ncubes, grid, s); break;
         HYRES_P(1) HYRES_P(2) HYRES_P(3) HYRES_P(4) HYRES_P(5) HYRES_P(6) HYRES_P(7)
         HYRES_P(8) HYRES_P(9) HYRES_P(10) HYRES_P(11) HYRES_P(12) HYRES_P(13) HYRES_P(14)
 #undef HYRES_P

@@ -138,7 +138,8 @@ __device__ __forceinline__ void gram_stage(float* __restrict__ tile, bool vec, c
     }
 }
 
-template <int T, int P>
+// VEC: every cube of the launch has 16-byte pixel vectors (scalar loads compiled out).
+template <int T, int P, bool VEC>
 __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __restrict__ descs,
                                                           const int* __restrict__ items, int ncubes) {
     using TM = TileMap<T, P>;
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
         per = (per + kGramKB - 1) / kGramKB * kGramKB;
         const int64_t q0 = (int64_t)slot * per;
         const int64_t q1 = q0 + per < n ? q0 + per : n;
-        const bool vec = d.vec4 != 0;
+        const bool vec = VEC || d.vec4 != 0;
         v4f acc[S];
         double accd[S][4];
 #pragma unroll
@@ -381,7 +382,7 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
 // error near 2^-16, above what the FP32 sums add.
 constexpr int kGramSplitT = 11;
 
-template <int T, int P>
+template <int T, int P, bool VEC>
 __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __restrict__ descs,
                                                            const int* __restrict__ items, int ncubes) {
     using TM = TileMap<T, P>;
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
         for (int q = 0; q < (FP64 ? S : 1); ++q)
 #pragma unroll
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
-        if (vec) gramb_slot<T, P, true, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
+        if (VEC || vec) gramb_slot<T, P, true, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
         else gramb_slot<T, P, false, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
@@ -531,30 +532,35 @@ typedef void (*GramF32Kernel)(const CubeDesc*, const int*, int);
 // tiles are then split over two launches (three from T = 13).
 
 template <int T>
-static hipError_t launch_gram_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
+static hipError_t launch_gram_t(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
                                 hipStream_t s) {
     if constexpr (T >= kGramSplitT) {
-        hipLaunchKernelGGL((k_gram_f32<T, 1>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        hipLaunchKernelGGL((k_gram_f32<T, 2>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        if (vec) hipLaunchKernelGGL((k_gram_f32<T, 1, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        else hipLaunchKernelGGL((k_gram_f32<T, 1, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        if (vec) hipLaunchKernelGGL((k_gram_f32<T, 2, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        else hipLaunchKernelGGL((k_gram_f32<T, 2, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
         if constexpr (TileMap<T, 1>::NP == 3)
-            hipLaunchKernelGGL((k_gram_f32<T, 3>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+            if (vec) hipLaunchKernelGGL((k_gram_f32<T, 3, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        else hipLaunchKernelGGL((k_gram_f32<T, 3, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     } else {
-        hipLaunchKernelGGL((k_gram_f32<T, 0>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        if (vec) hipLaunchKernelGGL((k_gram_f32<T, 0, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        else hipLaunchKernelGGL((k_gram_f32<T, 0, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     }
     return hipGetLastError();
 }
 
 template <int T>
-static hipError_t launch_gramb_t(const CubeDesc* descs, const int* items, int ncubes, int grid,
+static hipError_t launch_gramb_t(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
                                  hipStream_t s) {
-    hipLaunchKernelGGL((k_gram_bf16<T, 0>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    if (vec) hipLaunchKernelGGL((k_gram_bf16<T, 0, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    else hipLaunchKernelGGL((k_gram_bf16<T, 0, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     return hipGetLastError();
 }
 
-hipError_t launch_gram_bf16(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,
+hipError_t launch_gram_bf16(int T, bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
                             hipStream_t s) {
     switch (T) {
-#define HYRES_G(TT) case TT: return launch_gramb_t<TT>(descs, items, ncubes, grid, s);
+#define HYRES_G(TT) case TT: return launch_gramb_t<TT>(vec, descs, items, ncubes, grid, s);
         HYRES_G(1) HYRES_G(2) HYRES_G(3) HYRES_G(4) HYRES_G(5) HYRES_G(6) HYRES_G(7)
         HYRES_G(8) HYRES_G(9) HYRES_G(10) HYRES_G(11) HYRES_G(12) HYRES_G(13) HYRES_G(14)
 #undef HYRES_G
@@ -562,10 +568,10 @@ hipError_t launch_gram_bf16(int T, const CubeDesc* descs, const int* items, int 
     }
 }
 
-hipError_t launch_gram_f32(int T, const CubeDesc* descs, const int* items, int ncubes, int grid,
+hipError_t launch_gram_f32(int T, bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
                            hipStream_t s) {
     switch (T) {
-#define HYRES_G(TT) case TT: return launch_gram_t<TT>(descs, items, ncubes, grid, s);
+#define HYRES_G(TT) case TT: return launch_gram_t<TT>(vec, descs, items, ncubes, grid, s);
         HYRES_G(1) HYRES_G(2) HYRES_G(3) HYRES_G(4) HYRES_G(5) HYRES_G(6) HYRES_G(7)
         HYRES_G(8) HYRES_G(9) HYRES_G(10) HYRES_G(11) HYRES_G(12) HYRES_G(13) HYRES_G(14)
 #undef HYRES_G

@@ -527,24 +527,32 @@ __global__ void k_gram_reduce_f64(const CubeDesc* __restrict__ descs, int cube) 
 // ---------------------------------------------------------------- launchers
 typedef void (*GramF32Kernel)(const CubeDesc*, const int*, int);
 
-// FP32 cubes in native precision: from T = kGramSplitT up the FP64
-// accumulators of all tiles no longer fit in the registers of 8 waves; the
-// tiles are then split over two launches (three from T = 13).
+// FP32 cubes in native precision: from T = kGramSplitT up, with the scalar
+// load path compiled in, the FP64 accumulators of all tiles no longer fit in
+// the registers of 8 waves; the tiles are then split over two launches (three
+// from T = 13).
+
+template <int T, int P>
+static void launch_gram_part(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
+                             hipStream_t s) {
+    if (vec) hipLaunchKernelGGL((k_gram_f32<T, P, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    else hipLaunchKernelGGL((k_gram_f32<T, P, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+}
 
 template <int T>
 static hipError_t launch_gram_t(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
                                 hipStream_t s) {
-    if constexpr (T >= kGramSplitT) {
-        if (vec) hipLaunchKernelGGL((k_gram_f32<T, 1, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        else hipLaunchKernelGGL((k_gram_f32<T, 1, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        if (vec) hipLaunchKernelGGL((k_gram_f32<T, 2, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        else hipLaunchKernelGGL((k_gram_f32<T, 2, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        if constexpr (TileMap<T, 1>::NP == 3)
-            if (vec) hipLaunchKernelGGL((k_gram_f32<T, 3, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        else hipLaunchKernelGGL((k_gram_f32<T, 3, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    // the vector-only kernel (no scalar load path) keeps every tile's FP64
+    // accumulators in registers up to T = 14: one pass over Y
+    if constexpr (T < kGramSplitT) {
+        launch_gram_part<T, 0>(vec, descs, items, ncubes, grid, s);
+    } else if (vec) {
+        hipLaunchKernelGGL((k_gram_f32<T, 0, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     } else {
-        if (vec) hipLaunchKernelGGL((k_gram_f32<T, 0, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        else hipLaunchKernelGGL((k_gram_f32<T, 0, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        hipLaunchKernelGGL((k_gram_f32<T, 1, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        hipLaunchKernelGGL((k_gram_f32<T, 2, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        if constexpr (TileMap<T, 1>::NP == 3)
+            hipLaunchKernelGGL((k_gram_f32<T, 3, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     }
     return hipGetLastError();
 }

@@ -23,12 +23,12 @@
 #define HYRES_API extern "C" __attribute__((visibility("default")))
 
 namespace hyres {
-hipError_t launch_gram_f32(int T, bool vec, const CubeDesc*, const int*, int, int, hipStream_t);
-hipError_t launch_gram_bf16(int T, bool vec, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_gram_f32(int T, int lm, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_gram_bf16(int T, int lm, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_gram_reduce_f32(int T, const CubeDesc*, const int*, int, hipStream_t);
 hipError_t launch_gram_f64(const CubeDesc*, int, int, int, hipStream_t);
 hipError_t launch_small(int p, const CubeDesc*, const int*, int, hipStream_t);
-hipError_t launch_project_f32(int T, bool vec, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_project_f32(int T, int lm, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_backproject_f32(int T, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_project_f64(const CubeDesc*, int, int64_t, hipStream_t);
 hipError_t launch_backproject_f64(const CubeDesc*, int, int64_t, hipStream_t);
@@ -279,6 +279,7 @@ CubeDesc make_desc(const CubePlan& c, void* ws) {
 #endif
     d.H = c.H; d.W = c.W; d.p = c.p; d.r = c.r; d.L = c.L; d.scope = c.scope; d.T = c.T; d.dtype = c.dtype;
     d.n = c.n;
+    d.pmag = c.p > 0 ? (uint32_t)((((uint64_t)1) << 32) / (uint64_t)c.p + 1) : 0;
     for (int l = 0; l <= kMaxLevels; ++l) {
         d.lh[l] = c.lh[l];
         d.lw[l] = c.lw[l];
@@ -495,11 +496,15 @@ void build_program(Exec& x, int stages) {
             L.n = N;
             L.grid = x.grid(tot, per_cu);
             if (kind == K_PROJ_F32 || kind == K_GRAM_F32 || kind == K_GRAM_BF16) {
-                // every cube of the class has 16-byte pixel vectors: the vector-only kernel
-                bool all = true;
-                for (int i = 0; i < N; ++i)
-                    if (cnt[i] && !x.desc[i].vec4) all = false;
-                L.b = all ? 1 : 0;
+                // one load path for every cube of the class: the kernel without the others
+                bool vec = true, dense = true, scalar = true;
+                for (int i = 0; i < N; ++i) {
+                    if (!cnt[i]) continue;
+                    if (!x.desc[i].vec4) vec = false;
+                    if (!x.desc[i].dense) dense = false;
+                    if (x.desc[i].vec4 || x.desc[i].dense) scalar = false;
+                }
+                L.b = vec ? kVec : dense ? kDense : scalar ? kScalar : kAnyLayout;
             }
             x.prog.push_back(L);
             if (kind == K_GRAM_F32 || kind == K_GRAM_BF16) {
@@ -642,12 +647,12 @@ void build_program(Exec& x, int stages) {
 hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
     const CubeDesc* D = x.descs();
     switch (L.kind) {
-        case K_GRAM_F32: return launch_gram_f32(L.key, L.b != 0, D, x.table(L.a), L.n, L.grid, s);
-        case K_GRAM_BF16: return launch_gram_bf16(L.key, L.b != 0, D, x.table(L.a), L.n, L.grid, s);
+        case K_GRAM_F32: return launch_gram_f32(L.key, L.b, D, x.table(L.a), L.n, L.grid, s);
+        case K_GRAM_BF16: return launch_gram_bf16(L.key, L.b, D, x.table(L.a), L.n, L.grid, s);
         case K_GRAM_RED: return launch_gram_reduce_f32(L.key, D, x.table(L.a), L.n, s);
         case K_GRAM_F64: return launch_gram_f64(D, L.a, L.key, L.grid, s);
         case K_SMALL: return launch_small(L.key, D, x.table(L.a), L.n, s);
-        case K_PROJ_F32: return launch_project_f32(L.key, L.b != 0, D, x.table(L.a), L.n, L.grid, s);
+        case K_PROJ_F32: return launch_project_f32(L.key, L.b, D, x.table(L.a), L.n, L.grid, s);
         case K_PROJ_F64: return launch_project_f64(D, L.a, L.n64, s);
         case K_DWT:
         case K_IDWT:
@@ -722,6 +727,13 @@ int vec4_ok(const void* ptr, int W, int p, int64_t pitch, int64_t row_pitch, int
            (row_pitch == (int64_t)W * pitch || W % kPixTile == 0) && (reinterpret_cast<uintptr_t>(ptr) % 16) == 0;
 }
 
+// Unpadded FP32 pixels (pitch == p) whose 64-pixel tiles are each 64 p consecutive,
+// 16-byte aligned floats: a contiguous cube, or whole tiles per image row.
+int dense_ok(const void* ptr, int W, int p, int64_t pitch, int64_t row_pitch, int dtype) {
+    return dtype == HYRES_F32 && pitch == p && (reinterpret_cast<uintptr_t>(ptr) % 16) == 0 &&
+           (row_pitch == (int64_t)W * p || (W % kPixTile == 0 && row_pitch % 4 == 0));
+}
+
 hyres_status check_shape(int H, int W, int p, int64_t pitch, int64_t row_pitch) {
     if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
     if (pitch < p || row_pitch < (int64_t)(W - 1) * pitch + p) return HYRES_E_SHAPE;
@@ -786,6 +798,8 @@ CubeDesc solve_desc(const CubePlan& c, void* ws, const void* Y, int64_t pitch, i
     d.X = X; d.xpitch = x_pitch; d.xrow_pitch = x_row_pitch;
     d.vec4 = vec4_ok(Y, c.W, c.p, pitch, row_pitch, c.dtype);
     d.xvec4 = vec4_ok(X, c.W, c.p, x_pitch, x_row_pitch, c.dtype);
+    d.dense = dense_ok(Y, c.W, c.p, pitch, row_pitch, c.dtype);
+    d.xdense = dense_ok(X, c.W, c.p, x_pitch, x_row_pitch, c.dtype);
     d.sigma_in = sigma_in;
     d.lambda_in = lambda_in;
     d.mode = (sigma_in ? 0 : 1) | 2 | 8 | ((flags & HYRES_FLAG_ALL_EVALS) ? 16 : 0);
@@ -950,6 +964,7 @@ HYRES_API hyres_status hyres_estimate_noise(hyres_handle* h, const void* Y, int 
     CubeDesc d = make_desc(x.plan[0], workspace);
     d.Y = Y; d.pitch = pitch; d.row_pitch = row_pitch;
     d.vec4 = vec4_ok(Y, W, p, pitch, row_pitch, dtype);
+    d.dense = dense_ok(Y, W, p, pitch, row_pitch, dtype);
     d.sigma = sigma_out;
     if (gram_out) d.G = gram_out;
     d.status = status;
@@ -991,6 +1006,7 @@ HYRES_API hyres_status hyres_subspace(hyres_handle* h, const void* Y, int H, int
     CubeDesc d = make_desc(x.plan[0], workspace);
     d.Y = Y; d.pitch = pitch; d.row_pitch = row_pitch;
     d.vec4 = vec4_ok(Y, W, p, pitch, row_pitch, dtype);
+    d.dense = dense_ok(Y, W, p, pitch, row_pitch, dtype);
     d.sigma_in = sigma;
     d.V = V_out;
     if (evals_out) d.evals = evals_out;

@@ -106,6 +106,9 @@ struct CubeDesc {
     int mode;                               // kMode* bits
     int vec4;                               // Y is contiguous with 16-byte aligned pixel rows, p % 4 == 0
     int xvec4;                              // the same for X
+    int dense;                              // F32 Y, pitch == p, 16-byte aligned: a 64-pixel tile is 64 p consecutive floats
+    int xdense;                             // the same for X
+    uint32_t pmag;                          // floor(2^32 / p) + 1: e / p == umulhi(e, pmag) for 0 <= e < 64 p
     unsigned long long* dbg;                // phase time stamps (timing builds only; null otherwise)
 };
 
@@ -237,6 +240,17 @@ __device__ __forceinline__ double blend_weight(const CubeDesc& d, int64_t y, int
 __device__ __forceinline__ void set_status(int* st, int bits) {
     if (st && bits) atomicOr(st, bits);
 }
+
+// Load paths of the kernels that stream Y in 64-pixel tiles: 16-byte pixel
+// vectors (kVec), unpadded pixels whose tile is 64 p consecutive floats
+// (kDense: float4 loads across pixel boundaries), any other layout (kScalar).
+constexpr int kVec = 0, kDense = 1, kScalar = 2;
+constexpr int kAnyLayout = 3;      // a launch whose cubes take different paths (chosen per cube)
+
+__device__ __forceinline__ int load_mode(const CubeDesc& d) { return d.vec4 ? kVec : d.dense ? kDense : kScalar; }
+
+// e / p for 0 <= e < 64 p (exact while e p < 2^32) with the per-cube multiplier
+__device__ __forceinline__ int div_p(int e, uint32_t pmag) { return (int)__umulhi((uint32_t)e, pmag); }
 
 template <typename T>
 __device__ __forceinline__ const T* pixel_ptr(const CubeDesc& d, int64_t q) {

@@ -22,11 +22,11 @@ template <int T> __host__ __device__ constexpr int proj_nv1() { return (kPixTile
 // One register array serves both load paths: T float4 groups or 4T floats.
 static_assert(proj_nv1<1>() == 4 * proj_nv4<1>(), "projection staging sizes");
 
-template <int T, bool VEC>
+template <int T, int M>
 __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&r4)[proj_nv4<T>()]) {
     const int tid = threadIdx.x;
     const int64_t nleft = d.n - q0;
-    if (VEC || d.vec4) {
+    if constexpr (M == kVec) {
         const float* base = pixel_ptr<float>(d, q0);   // a tile never crosses an image row
         const int g4 = d.p >> 2;
 #pragma unroll
@@ -36,6 +36,22 @@ __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&
             v4f v = {0.f, 0.f, 0.f, 0.f};
             if (k < kPixTile && g < g4 && k < nleft)
                 v = *reinterpret_cast<const v4f*>(base + (int64_t)k * d.pitch + 4 * g);
+            r4[i] = v;
+        }
+    } else if constexpr (M == kDense) {
+        const float* base = pixel_ptr<float>(d, q0);
+        const int lim = (int)(nleft < kPixTile ? nleft : kPixTile) * d.p;   // floats of the tile
+#pragma unroll
+        for (int i = 0; i < proj_nv4<T>(); ++i) {
+            const int e = 4 * (tid + 256 * i);
+            v4f v = {0.f, 0.f, 0.f, 0.f};
+            if (e + 3 < lim) {
+                v = *reinterpret_cast<const v4f*>(base + e);
+            } else if (e < lim) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (e + c < lim) v[c] = base[e + c];
+            }
             r4[i] = v;
         }
     } else {
@@ -50,16 +66,40 @@ __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&
     }
 }
 
-template <int T, bool VEC>
-__device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, const v4f (&r4)[proj_nv4<T>()]) {
+// kVec and kScalar write every band slot of the tile (zeros from band p on);
+// kDense writes bands [0, p) only and clears the slots [p, zlo) that an earlier
+// tile of more bands left behind (slots from zlo on are known to be zero).
+template <int T, int M>
+__device__ __forceinline__ void proj_stage(float* __restrict__ tile, const CubeDesc& d, int& zlo,
+                                           const v4f (&r4)[proj_nv4<T>()]) {
     constexpr int LDW = proj_ldw<T>();
     const int tid = threadIdx.x;
-    if (VEC || vec) {
+    if constexpr (M == kVec) {
 #pragma unroll
         for (int i = 0; i < proj_nv4<T>(); ++i) {
             const int e = tid + 256 * i;
             const int k = e / (4 * T), g = e - k * (4 * T);
             if (k < kPixTile) *reinterpret_cast<v4f*>(tile + k * LDW + 4 * g) = r4[i];
+        }
+    } else if constexpr (M == kDense) {
+        const int p = d.p;
+        if (p < zlo) {
+            const int w = zlo - p;
+            for (int e = tid; e < kPixTile * w; e += 256) {
+                const int k = e / w;
+                tile[k * LDW + p + (e - k * w)] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < proj_nv4<T>(); ++i) {
+            const int e = 4 * (tid + 256 * i);
+            if (e < kPixTile * p) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int k = div_p(e + c, d.pmag);
+                    tile[k * LDW + (e + c - k * p)] = r4[i][c];
+                }
+            }
         }
     } else {
 #pragma unroll
@@ -69,12 +109,22 @@ __device__ __forceinline__ void proj_stage(float* __restrict__ tile, bool vec, c
             if (k < kPixTile) tile[k * LDW + b] = r4[i >> 2][i & 3];
         }
     }
+    zlo = d.p;
 }
 
-// VEC: every cube of the launch has 16-byte pixel vectors (the scalar load path
-// is compiled out, which keeps the registers within two waves per SIMD).
-template <int T, bool VEC>
-__global__ __launch_bounds__(256, VEC ? 2 : 1) void k_project_f32(const CubeDesc* __restrict__ descs,
+template <int T>
+__device__ __forceinline__ void proj_fetch_any(const CubeDesc& d, int64_t q0, v4f (&r4)[proj_nv4<T>()]) {
+    const int m = load_mode(d);
+    if (m == kVec) proj_fetch<T, kVec>(d, q0, r4);
+    else if (m == kDense) proj_fetch<T, kDense>(d, q0, r4);
+    else proj_fetch<T, kScalar>(d, q0, r4);
+}
+
+// LM: the load path of every cube of the launch, or kAnyLayout (chosen per
+// cube).  With the vector or dense path alone the registers stay within two
+// waves per SIMD.
+template <int T, int LM>
+__global__ __launch_bounds__(256, LM == kVec || LM == kDense ? 2 : 1) void k_project_f32(const CubeDesc* __restrict__ descs,
                                                     const int* __restrict__ items, int ncubes) {
     constexpr int LDW = proj_ldw<T>();
     __shared__ __attribute__((aligned(16))) float tile[kPixTile * LDW];
@@ -86,10 +136,12 @@ __global__ __launch_bounds__(256, VEC ? 2 : 1) void k_project_f32(const CubeDesc
     int cur = -1;
     float bf[4 * T];
     v4f r4[proj_nv4<T>()];
+    int zlo = 16 * T;                        // band slots from zlo on are zero in the tile
     int item = blockIdx.x;
     if (item < total) {
         const int c = find_cube(items, ncubes, item);
-        proj_fetch<T, VEC>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4);
+        if constexpr (LM != kAnyLayout) proj_fetch<T, LM>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4);
+        else proj_fetch_any<T>(descs[c], (int64_t)(item - items[c]) * kPixTile, r4);
     }
     for (; item < total; item += gridDim.x) {
         const int c = find_cube(items, ncubes, item);
@@ -100,14 +152,21 @@ __global__ __launch_bounds__(256, VEC ? 2 : 1) void k_project_f32(const CubeDesc
             for (int s = 0; s < 4 * T; ++s) bf[s] = d.P32[(4 * s + row) * 16 + col];
         }
         const int64_t q0 = (int64_t)(item - items[c]) * kPixTile;
-        const bool vec = d.vec4 != 0;
         __syncthreads();
-        proj_stage<T, VEC>(tile, vec, r4);
+        if constexpr (LM != kAnyLayout) {
+            proj_stage<T, LM>(tile, d, zlo, r4);
+        } else {
+            const int m = load_mode(d);
+            if (m == kVec) proj_stage<T, kVec>(tile, d, zlo, r4);
+            else if (m == kDense) proj_stage<T, kDense>(tile, d, zlo, r4);
+            else proj_stage<T, kScalar>(tile, d, zlo, r4);
+        }
         __syncthreads();
         const int nxt = item + gridDim.x;
         if (nxt < total) {
             const int c2 = find_cube(items, ncubes, nxt);
-            proj_fetch<T, VEC>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4);
+            if constexpr (LM != kAnyLayout) proj_fetch<T, LM>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4);
+            else proj_fetch_any<T>(descs[c2], (int64_t)(nxt - items[c2]) * kPixTile, r4);
         }
         // four independent accumulator chains (consecutive MFMAs do not wait
         // on each other's results), added in a fixed order
@@ -214,6 +273,39 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
                     *dst = v;
                 }
             }
+        } else if (d.xdense) {
+            // unpadded pixels: the tile is 64 p consecutive floats, written as float4s
+            float* base = static_cast<float*>(d.X) + (q0 / d.W) * d.xrow_pitch + (q0 % d.W) * p;
+            const int lim = (int)(nleft < kPixTile ? nleft : kPixTile) * p;
+            for (int e = 4 * threadIdx.x; e < lim; e += 4 * 256) {
+                v4f v;
+                float w[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int k = div_p(e + c, d.pmag);
+                    v[c] = ot[k * LDO + (e + c - k * p)];
+                    w[c] = blend ? s_w[k] : 0.f;        // k < 64: e + 3 < 64 p
+                }
+                if (e + 3 < lim) {
+                    v4f* dst = reinterpret_cast<v4f*>(base + e);
+                    if (blend) {
+                        const v4f old = *dst;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            v[c] = (__float_as_uint(w[c]) >> 31) ? v[c] * (-w[c]) : old[c] + v[c] * w[c];
+                    }
+                    *dst = v;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (e + c < lim) {
+                            float x = v[c];
+                            if (blend) x = (__float_as_uint(w[c]) >> 31) ? x * (-w[c]) : base[e + c] + x * w[c];
+                            base[e + c] = x;
+                        }
+                    }
+                }
+            }
         } else {
             for (int e = threadIdx.x; e < kPixTile * p; e += 256) {
                 const int k = e / p, b = e - k * p;
@@ -270,19 +362,21 @@ __global__ void k_backproject_f64(const CubeDesc* __restrict__ descs, int cube) 
 
 // ---------------------------------------------------------------- launchers
 template <int T>
-static void launch_proj_t(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
-    if (vec) hipLaunchKernelGGL((k_project_f32<T, true>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
-    else hipLaunchKernelGGL((k_project_f32<T, false>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+static void launch_proj_t(int lm, const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
+    if (lm == kVec) hipLaunchKernelGGL((k_project_f32<T, kVec>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+    else if (lm == kDense) hipLaunchKernelGGL((k_project_f32<T, kDense>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+    else if (lm == kScalar) hipLaunchKernelGGL((k_project_f32<T, kScalar>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
+    else hipLaunchKernelGGL((k_project_f32<T, kAnyLayout>), dim3(grid), dim3(256), 0, s, descs, items, ncubes);
 }
 template <int T>
 static void launch_bp_t(const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_backproject_f32<T>, dim3(grid), dim3(256), 0, s, descs, items, ncubes);
 }
 
-hipError_t launch_project_f32(int T, bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
+hipError_t launch_project_f32(int T, int lm, const CubeDesc* descs, const int* items, int ncubes, int grid,
                               hipStream_t s) {
     switch (T) {
-#define HYRES_P(TT) case TT: launch_proj_t<TT>(vec, descs, items, ncubes, grid, s); break;
+#define HYRES_P(TT) case TT: launch_proj_t<TT>(lm, descs, items, ncubes, grid, s); break;
         HYRES_P(1) HYRES_P(2) HYRES_P(3) HYRES_P(4) HYRES_P(5) HYRES_P(6) HYRES_P(7)
         HYRES_P(8) HYRES_P(9) HYRES_P(10) HYRES_P(11) HYRES_P(12) HYRES_P(13) HYRES_P(14)
 #undef HYRES_P

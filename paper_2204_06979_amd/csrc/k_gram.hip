@@ -83,13 +83,14 @@ __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int la
 }
 
 // Load one chunk of kGramKB pixels (all 16T band slots) into registers.
-// vec: 16-byte aligned pixel vectors, p % 4 == 0, and the 64 pixels of a chunk
+// kVec: 16-byte aligned pixel vectors, p % 4 == 0, and the 64 pixels of a chunk
 // consecutive in memory (a contiguous cube, or whole chunks per image row).
-template <int T>
-__device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t q1, bool vec,
-                                           float (&r)[gram_nr<T>()]) {
+// kDense: the chunk is 64 p consecutive floats (float4 i of the thread holds
+// floats 4 (tid + 512 i) .. + 3 of it).  kScalar: one float per band slot.
+template <int T, int M>
+__device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t q1, float (&r)[gram_nr<T>()]) {
     const int tid = threadIdx.x;
-    if (vec) {
+    if constexpr (M == kVec) {
         const float* base = pixel_ptr<float>(d, q);   // a chunk never crosses an image row
         const int g4 = d.p >> 2;                     // float4 groups per pixel
 #pragma unroll
@@ -99,6 +100,24 @@ __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t
             v4f v = {0.f, 0.f, 0.f, 0.f};
             if (k < kGramKB && g < g4 && q + k < q1)
                 v = *reinterpret_cast<const v4f*>(base + (int64_t)k * d.pitch + 4 * g);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) r[4 * i + c] = v[c];
+        }
+    } else if constexpr (M == kDense) {
+        const float* base = pixel_ptr<float>(d, q);
+        const int64_t m = q1 - q;
+        const int lim = (int)(m < kGramKB ? m : kGramKB) * d.p;
+#pragma unroll
+        for (int i = 0; i < gram_nv4<T>(); ++i) {
+            const int e = 4 * (tid + kGramThreads * i);
+            v4f v = {0.f, 0.f, 0.f, 0.f};
+            if (e + 3 < lim) {
+                v = *reinterpret_cast<const v4f*>(base + e);
+            } else if (e < lim) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (e + c < lim) v[c] = base[e + c];
+            }
 #pragma unroll
             for (int c = 0; c < 4; ++c) r[4 * i + c] = v[c];
         }
@@ -114,11 +133,13 @@ __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t
     }
 }
 
-template <int T>
-__device__ __forceinline__ void gram_stage(float* __restrict__ tile, bool vec, const float (&r)[gram_nr<T>()]) {
+// kDense leaves the band slots from p on as they were: an entry of G reads only
+// its own two bands, and those of bands >= p are never stored.
+template <int T, int M>
+__device__ __forceinline__ void gram_stage(float* __restrict__ tile, const CubeDesc& d, const float (&r)[gram_nr<T>()]) {
     constexpr int LDW = gram_ldw<T>();
     const int tid = threadIdx.x;
-    if (vec) {
+    if constexpr (M == kVec) {
 #pragma unroll
         for (int i = 0; i < gram_nv4<T>(); ++i) {
             const int e = tid + kGramThreads * i;
@@ -126,6 +147,19 @@ __device__ __forceinline__ void gram_stage(float* __restrict__ tile, bool vec, c
             if (k < kGramKB) {
                 const v4f v = {r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]};
                 *reinterpret_cast<v4f*>(tile + k * LDW + 4 * g) = v;
+            }
+        }
+    } else if constexpr (M == kDense) {
+        const int p = d.p;
+#pragma unroll
+        for (int i = 0; i < gram_nv4<T>(); ++i) {
+            const int e = 4 * (tid + kGramThreads * i);
+            if (e < kGramKB * p) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int k = div_p(e + c, d.pmag);
+                    tile[k * LDW + (e + c - k * p)] = r[4 * i + c];
+                }
             }
         }
     } else {
@@ -138,8 +172,42 @@ __device__ __forceinline__ void gram_stage(float* __restrict__ tile, bool vec, c
     }
 }
 
-// VEC: every cube of the launch has 16-byte pixel vectors (scalar loads compiled out).
-template <int T, int P, bool VEC>
+// The FP32 partial Gram of pixels [q0, q1) of one slot (load path M).
+template <int T, int P, int M>
+__device__ __forceinline__ void gram_slot(const CubeDesc& d, int64_t q0, int64_t q1, float* tile, int lane,
+                                          int wave, v4f (&acc)[TileMap<T, P>::S],
+                                          double (&accd)[TileMap<T, P>::S][4]) {
+    constexpr int S = TileMap<T, P>::S;
+    float rg[gram_nr<T>()];
+    if (q0 < q1) gram_fetch<T, M>(d, q0, q1, rg);
+    for (int64_t q = q0; q < q1; q += kGramKB) {
+        __syncthreads();
+        gram_stage<T, M>(tile, d, rg);
+        __syncthreads();
+        if (q + kGramKB < q1) gram_fetch<T, M>(d, q + kGramKB, q1, rg);   // overlaps the MFMAs
+        switch (wave) {
+            case 0: gram_wave<T, P, 0>(tile, lane, acc); break;
+            case 1: gram_wave<T, P, 1>(tile, lane, acc); break;
+            case 2: gram_wave<T, P, 2>(tile, lane, acc); break;
+            case 3: gram_wave<T, P, 3>(tile, lane, acc); break;
+            case 4: gram_wave<T, P, 4>(tile, lane, acc); break;
+            case 5: gram_wave<T, P, 5>(tile, lane, acc); break;
+            case 6: gram_wave<T, P, 6>(tile, lane, acc); break;
+            default: gram_wave<T, P, 7>(tile, lane, acc); break;
+        }
+        // FP32 sums over one chunk only; chunks accumulate in FP64
+#pragma unroll
+        for (int q2 = 0; q2 < S; ++q2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
+            acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+}
+
+// LM: the load path of every cube of the launch (the others are compiled out),
+// or kAnyLayout (chosen per cube).
+template <int T, int P, int LM>
 __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __restrict__ descs,
                                                           const int* __restrict__ items, int ncubes) {
     using TM = TileMap<T, P>;
@@ -159,7 +227,6 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
         per = (per + kGramKB - 1) / kGramKB * kGramKB;
         const int64_t q0 = (int64_t)slot * per;
         const int64_t q1 = q0 + per < n ? q0 + per : n;
-        const bool vec = VEC || d.vec4 != 0;
         v4f acc[S];
         double accd[S][4];
 #pragma unroll
@@ -168,30 +235,13 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
 #pragma unroll
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
         }
-        float rg[gram_nr<T>()];
-        if (q0 < q1) gram_fetch<T>(d, q0, q1, vec, rg);
-        for (int64_t q = q0; q < q1; q += kGramKB) {
-            __syncthreads();
-            gram_stage<T>(tile, vec, rg);
-            __syncthreads();
-            if (q + kGramKB < q1) gram_fetch<T>(d, q + kGramKB, q1, vec, rg);   // overlaps the MFMAs
-            switch (wave) {
-                case 0: gram_wave<T, P, 0>(tile, lane, acc); break;
-                case 1: gram_wave<T, P, 1>(tile, lane, acc); break;
-                case 2: gram_wave<T, P, 2>(tile, lane, acc); break;
-                case 3: gram_wave<T, P, 3>(tile, lane, acc); break;
-                case 4: gram_wave<T, P, 4>(tile, lane, acc); break;
-                case 5: gram_wave<T, P, 5>(tile, lane, acc); break;
-                case 6: gram_wave<T, P, 6>(tile, lane, acc); break;
-                default: gram_wave<T, P, 7>(tile, lane, acc); break;
-            }
-            // FP32 sums over one chunk only; chunks accumulate in FP64
-#pragma unroll
-            for (int q2 = 0; q2 < S; ++q2) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
-                acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
-            }
+        if constexpr (LM != kAnyLayout) {
+            gram_slot<T, P, LM>(d, q0, q1, tile, lane, wave, acc, accd);
+        } else {
+            const int m = load_mode(d);
+            if (m == kVec) gram_slot<T, P, kVec>(d, q0, q1, tile, lane, wave, acc, accd);
+            else if (m == kDense) gram_slot<T, P, kDense>(d, q0, q1, tile, lane, wave, acc, accd);
+            else gram_slot<T, P, kScalar>(d, q0, q1, tile, lane, wave, acc, accd);
         }
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
@@ -332,27 +382,52 @@ __device__ __forceinline__ void gramb_stage_scalar(__bf16* __restrict__ th, __bf
     }
 }
 
+// Dense staging: float4 i of the thread holds floats 4 (tid + 512 i) .. + 3 of
+// the chunk (pixel-major, p per pixel); band slots from p on are left as they
+// were (see gram_stage).
+template <int T>
+__device__ __forceinline__ void gramb_stage_dense(__bf16* __restrict__ th, __bf16* __restrict__ tl, int p,
+                                                 uint32_t pmag, const float (&r)[gram_nr<T>()]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < gram_nv4<T>(); ++i) {
+        const int e = 4 * (tid + kGramThreads * i);
+        if (e < kGramKB * p) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int k = div_p(e + c, pmag), b = e + c - k * p;
+                const float v = r[4 * i + c];
+                const __bf16 h = (__bf16)v;
+                th[b * kGramLDP + k] = h;
+                tl[b * kGramLDP + k] = (__bf16)(v - (float)h);
+            }
+        }
+    }
+}
+
 // FP64: chunk sums flushed into FP64 accumulators (else acc keeps summing the
-// whole slot in FP32).
-template <int T, int P, bool VEC, bool FP64>
+// whole slot in FP32).  M: load path.
+template <int T, int P, int M, bool FP64>
 __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_t q1, __bf16* th, __bf16* tl,
                                            int lane, int wave, v4f (&acc)[TileMap<T, P>::S],
                                            double (&accd)[FP64 ? TileMap<T, P>::S : 1][4]) {
     constexpr int S = TileMap<T, P>::S;
+    constexpr bool VEC = M == kVec;
     v4f rv[VEC ? gramb_nt<T>() : 1][8];
     float rs[VEC ? 1 : gram_nr<T>()];
     if (q0 < q1) {
         if constexpr (VEC) gramb_fetch<T>(d, q0, q1, rv);
-        else gram_fetch<T>(d, q0, q1, false, rs);
+        else gram_fetch<T, M>(d, q0, q1, rs);
     }
     for (int64_t q = q0; q < q1; q += kGramKB) {
         __syncthreads();
         if constexpr (VEC) gramb_stage<T>(th, tl, rv);
+        else if constexpr (M == kDense) gramb_stage_dense<T>(th, tl, d.p, d.pmag, rs);
         else gramb_stage_scalar<T>(th, tl, rs);
         __syncthreads();
         if (q + kGramKB < q1) {
             if constexpr (VEC) gramb_fetch<T>(d, q + kGramKB, q1, rv);
-            else gram_fetch<T>(d, q + kGramKB, q1, false, rs);
+            else gram_fetch<T, M>(d, q + kGramKB, q1, rs);
         }
         switch (wave) {
             case 0: gramb_wave<T, P, 0>(th, tl, lane, acc); break;
@@ -382,7 +457,7 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
 // error near 2^-16, above what the FP32 sums add.
 constexpr int kGramSplitT = 11;
 
-template <int T, int P, bool VEC>
+template <int T, int P, int LM>
 __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __restrict__ descs,
                                                            const int* __restrict__ items, int ncubes) {
     using TM = TileMap<T, P>;
@@ -403,7 +478,6 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
         per = (per + kGramKB - 1) / kGramKB * kGramKB;
         const int64_t q0 = (int64_t)slot * per;
         const int64_t q1 = q0 + per < n ? q0 + per : n;
-        const bool vec = d.vec4 != 0;
         v4f acc[S];
         double accd[FP64 ? S : 1][4];
 #pragma unroll
@@ -412,8 +486,14 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
         for (int q = 0; q < (FP64 ? S : 1); ++q)
 #pragma unroll
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
-        if (VEC || vec) gramb_slot<T, P, true, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
-        else gramb_slot<T, P, false, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
+        if constexpr (LM != kAnyLayout) {
+            gramb_slot<T, P, LM, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
+        } else {
+            const int m = load_mode(d);
+            if (m == kVec) gramb_slot<T, P, kVec, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
+            else if (m == kDense) gramb_slot<T, P, kDense, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
+            else gramb_slot<T, P, kScalar, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
+        }
         float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
@@ -532,43 +612,55 @@ typedef void (*GramF32Kernel)(const CubeDesc*, const int*, int);
 // the registers of 8 waves; the tiles are then split over two launches (three
 // from T = 13).
 
-template <int T, int P>
-static void launch_gram_part(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
-                             hipStream_t s) {
-    if (vec) hipLaunchKernelGGL((k_gram_f32<T, P, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-    else hipLaunchKernelGGL((k_gram_f32<T, P, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+template <int T, int P, int LM>
+static void launch_gram_k(const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_gram_f32<T, P, LM>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+}
+
+// the scalar load path needs more registers: from T = kGramSplitT on the tiles
+// are split over launches
+template <int T, int LM>
+static void launch_gram_parts(const CubeDesc* descs, const int* items, int ncubes, int grid, hipStream_t s) {
+    if constexpr (T < kGramSplitT) {
+        launch_gram_k<T, 0, LM>(descs, items, ncubes, grid, s);
+    } else {
+        launch_gram_k<T, 1, LM>(descs, items, ncubes, grid, s);
+        launch_gram_k<T, 2, LM>(descs, items, ncubes, grid, s);
+        if constexpr (TileMap<T, 1>::NP == 3) launch_gram_k<T, 3, LM>(descs, items, ncubes, grid, s);
+    }
 }
 
 template <int T>
-static hipError_t launch_gram_t(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
+static hipError_t launch_gram_t(int lm, const CubeDesc* descs, const int* items, int ncubes, int grid,
                                 hipStream_t s) {
-    // the vector-only kernel (no scalar load path) keeps every tile's FP64
-    // accumulators in registers up to T = 14: one pass over Y
-    if constexpr (T < kGramSplitT) {
-        launch_gram_part<T, 0>(vec, descs, items, ncubes, grid, s);
-    } else if (vec) {
-        hipLaunchKernelGGL((k_gram_f32<T, 0, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    // with one load path compiled in, every tile's FP64 accumulators stay in
+    // registers up to T = 14: one pass over Y
+    if (lm == kVec) {
+        launch_gram_k<T, 0, kVec>(descs, items, ncubes, grid, s);
+    } else if (lm == kDense) {
+        launch_gram_k<T, 0, kDense>(descs, items, ncubes, grid, s);
+    } else if (lm == kScalar) {
+        launch_gram_parts<T, kScalar>(descs, items, ncubes, grid, s);
     } else {
-        hipLaunchKernelGGL((k_gram_f32<T, 1, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        hipLaunchKernelGGL((k_gram_f32<T, 2, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-        if constexpr (TileMap<T, 1>::NP == 3)
-            hipLaunchKernelGGL((k_gram_f32<T, 3, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+        launch_gram_parts<T, kAnyLayout>(descs, items, ncubes, grid, s);
     }
     return hipGetLastError();
 }
 
 template <int T>
-static hipError_t launch_gramb_t(bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
+static hipError_t launch_gramb_t(int lm, const CubeDesc* descs, const int* items, int ncubes, int grid,
                                  hipStream_t s) {
-    if (vec) hipLaunchKernelGGL((k_gram_bf16<T, 0, true>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
-    else hipLaunchKernelGGL((k_gram_bf16<T, 0, false>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    if (lm == kVec) hipLaunchKernelGGL((k_gram_bf16<T, 0, kVec>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    else if (lm == kDense) hipLaunchKernelGGL((k_gram_bf16<T, 0, kDense>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    else if (lm == kScalar) hipLaunchKernelGGL((k_gram_bf16<T, 0, kScalar>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
+    else hipLaunchKernelGGL((k_gram_bf16<T, 0, kAnyLayout>), dim3(grid), dim3(kGramThreads), 0, s, descs, items, ncubes);
     return hipGetLastError();
 }
 
-hipError_t launch_gram_bf16(int T, bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
+hipError_t launch_gram_bf16(int T, int lm, const CubeDesc* descs, const int* items, int ncubes, int grid,
                             hipStream_t s) {
     switch (T) {
-#define HYRES_G(TT) case TT: return launch_gramb_t<TT>(vec, descs, items, ncubes, grid, s);
+#define HYRES_G(TT) case TT: return launch_gramb_t<TT>(lm, descs, items, ncubes, grid, s);
         HYRES_G(1) HYRES_G(2) HYRES_G(3) HYRES_G(4) HYRES_G(5) HYRES_G(6) HYRES_G(7)
         HYRES_G(8) HYRES_G(9) HYRES_G(10) HYRES_G(11) HYRES_G(12) HYRES_G(13) HYRES_G(14)
 #undef HYRES_G
@@ -576,10 +668,10 @@ hipError_t launch_gram_bf16(int T, bool vec, const CubeDesc* descs, const int* i
     }
 }
 
-hipError_t launch_gram_f32(int T, bool vec, const CubeDesc* descs, const int* items, int ncubes, int grid,
+hipError_t launch_gram_f32(int T, int lm, const CubeDesc* descs, const int* items, int ncubes, int grid,
                            hipStream_t s) {
     switch (T) {
-#define HYRES_G(TT) case TT: return launch_gram_t<TT>(vec, descs, items, ncubes, grid, s);
+#define HYRES_G(TT) case TT: return launch_gram_t<TT>(lm, descs, items, ncubes, grid, s);
         HYRES_G(1) HYRES_G(2) HYRES_G(3) HYRES_G(4) HYRES_G(5) HYRES_G(6) HYRES_G(7)
         HYRES_G(8) HYRES_G(9) HYRES_G(10) HYRES_G(11) HYRES_G(12) HYRES_G(13) HYRES_G(14)
 #undef HYRES_G

@@ -1,0 +1,108 @@
+"""Memory layouts of the cube (needs an MI355X).
+
+The FP32 kernels that stream Y and X in 64-pixel tiles have three load paths:
+16-byte pixel vectors (p % 4 == 0), unpadded pixels read as one run of 64 p
+floats, and a per-value path for any other pitch.  Every path stages the same
+values in the same places, so a solve must give bitwise the same output for a
+cube stored contiguously, with padded pixels, or as a window of a wider image,
+and a batch whose band-count class mixes layouts must give each cube's
+single-solve result.  The contiguous results are checked against the oracle in
+the parity tests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2204_06979_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_06979_amd import api
+    return api
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cube(seed, H, W, p, r, L):
+    c = synth.mixing_cube(seed, H, W, p, min(r, 6), 12.0, L, dtype=np.float64, keep_clean=False)
+    Y = c.Y + 1e-3 * np.random.default_rng(seed).standard_normal(c.Y.shape)
+    return Y.astype(np.float32)
+
+
+def _padded(Y, extra):
+    """The cube with `extra` unused floats after each pixel (pitch p + extra)."""
+    H, W, p = Y.shape
+    big = torch.full((H, W, p + extra), float("nan"), dtype=torch.float32, device="cuda")
+    big[:, :, :p] = torch.tensor(Y, device="cuda")
+    return big[:, :, :p]
+
+
+def _window(Y, wide):
+    """The cube as columns [0, W) of an H x wide image (row pitch wide * p)."""
+    H, W, p = Y.shape
+    big = torch.full((H, wide, p), float("nan"), dtype=torch.float32, device="cuda")
+    big[:, :W, :] = torch.tensor(Y, device="cuda")
+    return big[:, :W, :]
+
+
+@pytest.mark.parametrize("prec", ["native", "mixed"])
+@pytest.mark.parametrize("p,r,L", [(17, 3, 2), (37, 4, 3), (40, 5, 3), (103, 6, 2)])
+def test_layouts_give_bitwise_equal_results(prec, p, r, L):
+    api = _api()
+    H, W = 70, 128
+    Y = _cube(400 + p, H, W, p, r, L)
+    say("layouts p", p, "r", r, "L", L, prec)
+    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32, precision=prec)
+    ref = dn.run(torch.tensor(Y, device="cuda")).clone()
+    lam = dn.info()["lam"].clone()
+    assert int(dn.info()["status"].cpu()[0]) & ~8 == 0
+    assert torch.isfinite(ref).all()
+    # wide is chosen so that the row pitch stays a multiple of 4 floats
+    wide = 136 if p % 2 == 0 else 132
+    for name, Yv in [("padded", _padded(Y, 3)), ("window", _window(Y, wide))]:
+        X = dn.run(Yv).clone()
+        say("   ", name, "pitch", Yv.stride(1), "row pitch", Yv.stride(0))
+        assert torch.equal(dn.info()["lam"], lam), name
+        assert torch.equal(X, ref), name
+    # strided outputs: padded pixels and a window of a wider image
+    for name, Xv in [("padded out", _padded(np.zeros_like(Y), 5)), ("window out", _window(np.zeros_like(Y), wide))]:
+        dn.run(torch.tensor(Y, device="cuda"), X=Xv)
+        say("   ", name, "pitch", Xv.stride(1), "row pitch", Xv.stride(0))
+        assert torch.equal(Xv, ref), name
+    # the padding holds NaN: no layout may have read it
+    assert int(dn.info()["status"].cpu()[0]) & ~8 == 0
+
+
+@pytest.mark.parametrize("prec", ["native", "mixed"])
+def test_batch_class_with_mixed_layouts(prec):
+    """Cubes of one band-count class (33..48 bands) stored as pixel vectors,
+    unpadded odd-band runs and padded pixels, in one batch; then a class of
+    unpadded cubes only, whose band counts shrink from cube to cube."""
+    api = _api()
+    # more 64-pixel tiles than blocks, so that blocks move on from cube to cube
+    specs = [(200, 256, 45, 4, 2, "plain"), (50, 90, 40, 3, 3, "plain"), (150, 256, 37, 5, 2, "padded"),
+             (100, 192, 33, 2, 2, "plain"), (55, 70, 48, 4, 3, "padded")]
+    for group in (specs, [s[:5] + ("plain",) for s in specs if s[2] % 4]):
+        cubes, Ys = [], []
+        for k, (H, W, p, r, L, lay) in enumerate(group):
+            Y = _cube(700 + k, H, W, p, r, L)
+            Ys.append(Y)
+            cubes.append(_padded(Y, 2) if lay == "padded" else torch.tensor(Y, device="cuda"))
+        say("batch", prec, [(s[2], s[5]) for s in group])
+        b = api.Batch(cubes, [s[3] for s in group], [s[4] for s in group], precision=prec)
+        b.run()
+        torch.cuda.synchronize()
+        for i, (H, W, p, r, L, lay) in enumerate(group):
+            X1, info1 = api.denoise(torch.tensor(Ys[i], device="cuda"), r, L, precision=prec)
+            assert int(b.info(i)["status"].cpu()[0]) & ~8 == 0, i
+            assert torch.equal(b.info(i)["lam"], info1["lam"]), i
+            assert torch.equal(b.X[i], X1), (i, p, lay)

@@ -243,7 +243,7 @@ __device__ __forceinline__ void set_status(int* st, int bits) {
 
 // Load paths of the kernels that stream Y in 64-pixel tiles: 16-byte pixel
 // vectors (kVec), unpadded pixels whose tile is 64 p consecutive floats
-// (kDense: float4 loads across pixel boundaries), any other layout (kScalar).
+// (kDense: loads across pixel boundaries), any other layout (kScalar).
 constexpr int kVec = 0, kDense = 1, kScalar = 2;
 constexpr int kAnyLayout = 3;      // a launch whose cubes take different paths (chosen per cube)
 

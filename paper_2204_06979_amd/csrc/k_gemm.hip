@@ -39,20 +39,14 @@ __device__ __forceinline__ void proj_fetch(const CubeDesc& d, int64_t q0, v4f (&
             r4[i] = v;
         }
     } else if constexpr (M == kDense) {
+        // consecutive lanes read consecutive floats of the tile (float i of the
+        // thread is float tid + 256 i)
         const float* base = pixel_ptr<float>(d, q0);
         const int lim = (int)(nleft < kPixTile ? nleft : kPixTile) * d.p;   // floats of the tile
 #pragma unroll
-        for (int i = 0; i < proj_nv4<T>(); ++i) {
-            const int e = 4 * (tid + 256 * i);
-            v4f v = {0.f, 0.f, 0.f, 0.f};
-            if (e + 3 < lim) {
-                v = *reinterpret_cast<const v4f*>(base + e);
-            } else if (e < lim) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (e + c < lim) v[c] = base[e + c];
-            }
-            r4[i] = v;
+        for (int i = 0; i < proj_nv1<T>(); ++i) {
+            const int e = tid + 256 * i;
+            r4[i >> 2][i & 3] = e < lim ? base[e] : 0.f;
         }
     } else {
 #pragma unroll
@@ -91,14 +85,11 @@ __device__ __forceinline__ void proj_stage(float* __restrict__ tile, const CubeD
             }
         }
 #pragma unroll
-        for (int i = 0; i < proj_nv4<T>(); ++i) {
-            const int e = 4 * (tid + 256 * i);
+        for (int i = 0; i < proj_nv1<T>(); ++i) {
+            const int e = tid + 256 * i;
             if (e < kPixTile * p) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int k = div_p(e + c, d.pmag);
-                    tile[k * LDW + (e + c - k * p)] = r4[i][c];
-                }
+                const int k = div_p(e, d.pmag);
+                tile[k * LDW + (e - k * p)] = r4[i >> 2][i & 3];
             }
         }
     } else {

@@ -85,8 +85,8 @@ __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int la
 // Load one chunk of kGramKB pixels (all 16T band slots) into registers.
 // kVec: 16-byte aligned pixel vectors, p % 4 == 0, and the 64 pixels of a chunk
 // consecutive in memory (a contiguous cube, or whole chunks per image row).
-// kDense: the chunk is 64 p consecutive floats (float4 i of the thread holds
-// floats 4 (tid + 512 i) .. + 3 of it).  kScalar: one float per band slot.
+// kDense: the chunk is 64 p consecutive floats (float i of the thread is float
+// tid + 512 i of it).  kScalar: one float per band slot.
 template <int T, int M>
 __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t q1, float (&r)[gram_nr<T>()]) {
     const int tid = threadIdx.x;
@@ -108,18 +108,9 @@ __device__ __forceinline__ void gram_fetch(const CubeDesc& d, int64_t q, int64_t
         const int64_t m = q1 - q;
         const int lim = (int)(m < kGramKB ? m : kGramKB) * d.p;
 #pragma unroll
-        for (int i = 0; i < gram_nv4<T>(); ++i) {
-            const int e = 4 * (tid + kGramThreads * i);
-            v4f v = {0.f, 0.f, 0.f, 0.f};
-            if (e + 3 < lim) {
-                v = *reinterpret_cast<const v4f*>(base + e);
-            } else if (e < lim) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (e + c < lim) v[c] = base[e + c];
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) r[4 * i + c] = v[c];
+        for (int i = 0; i < gram_nv1<T>(); ++i) {
+            const int e = tid + kGramThreads * i;
+            r[i] = e < lim ? base[e] : 0.f;
         }
     } else {
 #pragma unroll
@@ -152,14 +143,11 @@ __device__ __forceinline__ void gram_stage(float* __restrict__ tile, const CubeD
     } else if constexpr (M == kDense) {
         const int p = d.p;
 #pragma unroll
-        for (int i = 0; i < gram_nv4<T>(); ++i) {
-            const int e = 4 * (tid + kGramThreads * i);
+        for (int i = 0; i < gram_nv1<T>(); ++i) {
+            const int e = tid + kGramThreads * i;
             if (e < kGramKB * p) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int k = div_p(e + c, d.pmag);
-                    tile[k * LDW + (e + c - k * p)] = r[4 * i + c];
-                }
+                const int k = div_p(e, d.pmag);
+                tile[k * LDW + (e - k * p)] = r[i];
             }
         }
     } else {
@@ -382,25 +370,51 @@ __device__ __forceinline__ void gramb_stage_scalar(__bf16* __restrict__ th, __bf
     }
 }
 
-// Dense staging: float4 i of the thread holds floats 4 (tid + 512 i) .. + 3 of
-// the chunk (pixel-major, p per pixel); band slots from p on are left as they
-// were (see gram_stage).
+// Dense BF16 path: a task is 8 consecutive pixels of one band.  Consecutive
+// lanes take consecutive bands, so each of the 8 loads of a wave reads one
+// run of the chunk and each 16-byte row written to the band-major tiles lands
+// in its own banks.  Band slots from p on are left as they were (an entry of G
+// reads only its own two bands, and those of bands >= p are never stored).
+template <int T> __host__ __device__ constexpr int gramd_nt() { return (kGramKB / 8 * 16 * T + kGramThreads - 1) / kGramThreads; }
+
 template <int T>
-__device__ __forceinline__ void gramb_stage_dense(__bf16* __restrict__ th, __bf16* __restrict__ tl, int p,
-                                                 uint32_t pmag, const float (&r)[gram_nr<T>()]) {
+__device__ __forceinline__ void gramd_fetch(const CubeDesc& d, int64_t q, int64_t q1, float (&r)[8 * gramd_nt<T>()]) {
+    const int tid = threadIdx.x;
+    const int p = d.p;
+    const float* base = pixel_ptr<float>(d, q);
+    const int64_t m64 = q1 - q;
+    const int m = (int)(m64 < kGramKB ? m64 : kGramKB);
+#pragma unroll
+    for (int i = 0; i < gramd_nt<T>(); ++i) {
+        const int t = tid + kGramThreads * i;      // over (kGramKB / 8) x p
+        const int blk = div_p(t, d.pmag), b = t - blk * p;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = 8 * blk + u;
+            r[8 * i + u] = (t < (kGramKB / 8) * p && k < m) ? base[k * p + b] : 0.f;
+        }
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void gramd_stage(__bf16* __restrict__ th, __bf16* __restrict__ tl, int p, uint32_t pmag,
+                                           const float (&r)[8 * gramd_nt<T>()]) {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < gram_nv4<T>(); ++i) {
-        const int e = 4 * (tid + kGramThreads * i);
-        if (e < kGramKB * p) {
+    for (int i = 0; i < gramd_nt<T>(); ++i) {
+        const int t = tid + kGramThreads * i;
+        if (t < (kGramKB / 8) * p) {
+            const int blk = div_p(t, pmag), b = t - blk * p;
+            bf16x8 h8, l8;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int k = div_p(e + c, pmag), b = e + c - k * p;
-                const float v = r[4 * i + c];
+            for (int u = 0; u < 8; ++u) {
+                const float v = r[8 * i + u];
                 const __bf16 h = (__bf16)v;
-                th[b * kGramLDP + k] = h;
-                tl[b * kGramLDP + k] = (__bf16)(v - (float)h);
+                h8[u] = h;
+                l8[u] = (__bf16)(v - (float)h);
             }
+            *reinterpret_cast<bf16x8*>(th + b * kGramLDP + 8 * blk) = h8;
+            *reinterpret_cast<bf16x8*>(tl + b * kGramLDP + 8 * blk) = l8;
         }
     }
 }
@@ -412,22 +426,24 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
                                            int lane, int wave, v4f (&acc)[TileMap<T, P>::S],
                                            double (&accd)[FP64 ? TileMap<T, P>::S : 1][4]) {
     constexpr int S = TileMap<T, P>::S;
-    constexpr bool VEC = M == kVec;
-    v4f rv[VEC ? gramb_nt<T>() : 1][8];
-    float rs[VEC ? 1 : gram_nr<T>()];
+    v4f rv[M == kVec ? gramb_nt<T>() : 1][8];
+    float rd[M == kDense ? 8 * gramd_nt<T>() : 1];
+    float rs[M == kScalar ? gram_nr<T>() : 1];
     if (q0 < q1) {
-        if constexpr (VEC) gramb_fetch<T>(d, q0, q1, rv);
-        else gram_fetch<T, M>(d, q0, q1, rs);
+        if constexpr (M == kVec) gramb_fetch<T>(d, q0, q1, rv);
+        else if constexpr (M == kDense) gramd_fetch<T>(d, q0, q1, rd);
+        else gram_fetch<T, kScalar>(d, q0, q1, rs);
     }
     for (int64_t q = q0; q < q1; q += kGramKB) {
         __syncthreads();
-        if constexpr (VEC) gramb_stage<T>(th, tl, rv);
-        else if constexpr (M == kDense) gramb_stage_dense<T>(th, tl, d.p, d.pmag, rs);
+        if constexpr (M == kVec) gramb_stage<T>(th, tl, rv);
+        else if constexpr (M == kDense) gramd_stage<T>(th, tl, d.p, d.pmag, rd);
         else gramb_stage_scalar<T>(th, tl, rs);
         __syncthreads();
         if (q + kGramKB < q1) {
-            if constexpr (VEC) gramb_fetch<T>(d, q + kGramKB, q1, rv);
-            else gram_fetch<T, M>(d, q + kGramKB, q1, rs);
+            if constexpr (M == kVec) gramb_fetch<T>(d, q + kGramKB, q1, rv);
+            else if constexpr (M == kDense) gramd_fetch<T>(d, q + kGramKB, q1, rd);
+            else gram_fetch<T, kScalar>(d, q + kGramKB, q1, rs);
         }
         switch (wave) {
             case 0: gramb_wave<T, P, 0>(th, tl, lane, acc); break;
@@ -638,7 +654,9 @@ static hipError_t launch_gram_t(int lm, const CubeDesc* descs, const int* items,
     if (lm == kVec) {
         launch_gram_k<T, 0, kVec>(descs, items, ncubes, grid, s);
     } else if (lm == kDense) {
-        launch_gram_k<T, 0, kDense>(descs, items, ncubes, grid, s);
+        // from T = 13 the dense staging's registers push the accumulators out
+        if constexpr (T >= 13) launch_gram_parts<T, kDense>(descs, items, ncubes, grid, s);
+        else launch_gram_k<T, 0, kDense>(descs, items, ncubes, grid, s);
     } else if (lm == kScalar) {
         launch_gram_parts<T, kScalar>(descs, items, ncubes, grid, s);
     } else {

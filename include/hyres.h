@@ -343,12 +343,15 @@ hyres_status hyres_tile_choice(hyres_handle* h, int dtype, int inverse, int widt
 #define HYRES_NUM_STAGES        7
 
 /* When stage bit s of `mask` is set, every later solve on this handle records
- * a HIP event pair around stage s on the caller's stream (mask 0: off).  The
- * events are host objects owned by the handle; no device memory is used. */
+ * a HIP event pair around stage s on the stream that runs it: the caller's,
+ * or a cube group's (mask 0: off).  The events are host objects owned by the
+ * handle; no device memory is used. */
 hyres_status hyres_profile_enable(hyres_handle* h, unsigned mask);
 /* Wait for the recorded events, then add the elapsed milliseconds and the
- * number of timed launches of each stage to ms_out[s] and count_out[s]
- * (host arrays of HYRES_NUM_STAGES) and forget them. */
+ * number of timed solves of each stage to ms_out[s] and count_out[s] (host
+ * arrays of HYRES_NUM_STAGES) and forget them.  Where the cubes of a batch or
+ * tile grid run in groups on streams of their own, each group's stage is timed
+ * on its stream and the groups' times of one solve add up. */
 hyres_status hyres_profile_read(hyres_handle* h, double* ms_out, int* count_out);
 
 #ifdef __cplusplus

@@ -11,6 +11,7 @@
 // prefix-summed work-item table over the whole cube list, in which cubes
 // outside the class own no items; the kernels are persistent over that table.
 #include <algorithm>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -72,7 +73,8 @@ struct hyres_handle {
     int num_cu;
     std::string arch;              // device key of the tuning cache
     unsigned prof_mask;
-    struct Rec { int stage; hipEvent_t a, b; };
+    struct Rec { int stage; hipEvent_t a, b; unsigned run; };
+    unsigned runs = 0;             // programs run so far (a stage's records of one run count once)
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
     // DWT tile choice per [dtype][inverse][width class], and whether it was tuned
@@ -84,6 +86,7 @@ struct hyres_handle {
     static constexpr int kSide = 8;
     hipStream_t side[kSide];
     hipEvent_t fork, join[kSide];
+    hipEvent_t chain[kSide];       // end of a cube group's Gram stage (groups of a batch or tile grid)
 };
 
 namespace {
@@ -115,7 +118,7 @@ struct StageTimer {
             hipEvent_t b = prof_event(h);
             if (b) {
                 (void)hipEventRecord(b, s);
-                h->pending.push_back({stage, a, b});
+                h->pending.push_back({stage, a, b, h->runs});
             } else {
                 h->pool.push_back(a);
             }
@@ -358,11 +361,14 @@ struct Launch {
     int key;            // T, band count, or tile candidate
     int a, b;           // table offsets (ints) or a cube index
     int n;              // cubes covered by the table, or length of a cube list
+    int nlist;          // Rayleigh-Ritz: length of the cube list
     int grid, grid2;
     int level;
     int64_t n64;
     const double* src;
     double* dst;
+    int grp;            // cube group whose stream runs it (-1: after every group, on the caller's stream)
+    bool chain;         // last launch of its group's Gram stage
 };
 
 // Small-solve kernel classes by band count (the kernel is specialised on the
@@ -381,9 +387,12 @@ int small_class(int p) {
 // class a list; SURE component and histogram items; per level, direction and
 // tile candidate the DWT items; the Rayleigh-Ritz slot and pixel items and
 // cube list; plus one scratch table for the tuner.
+// Cube groups (see Exec::group_of) repeat the SURE, transform and
+// Rayleigh-Ritz tables once per group.
 constexpr int kMaxColours = 8;    // blend colours per axis of a tile grid
-constexpr int kMaxTables = 3 * 14 + std::max(14, kMaxColours * kMaxColours) + kSmallClasses + 2 +
-                           2 * kMaxLevels * kTileCands + 3 + 1;
+constexpr int kMaxGroups = 4;
+constexpr int kMaxTables = 3 * 14 + std::max(14, kMaxColours * kMaxColours) + kSmallClasses +
+                           kMaxGroups * (2 + 2 * kMaxLevels * kTileCands + 3) + 1;
 size_t table_ints(int count) { return (size_t)kMaxTables * (count + 1); }
 
 struct Exec {
@@ -397,6 +406,12 @@ struct Exec {
     std::vector<int> tab;
     std::vector<Launch> prog;
     std::vector<int> pass_of;   // blend pass of each tile (empty: no blending)
+    // Cube groups: each group runs its stages on a stream of its own, and a
+    // group's Gram stage starts when the previous group's has ended, so that
+    // one group's small solves (a few workgroups) overlap the next group's
+    // bandwidth-bound stages.  A blended back-projection runs after every group.
+    std::vector<int> group_of;
+    int ngroups = 1;
 
     const CubeDesc* descs() const { return at<const CubeDesc>(ws, o_desc); }
     const int* table(int off) const { return at<const int>(ws, o_tab) + off; }
@@ -433,9 +448,12 @@ int tile_of(const hyres_handle* h, int dtype, bool inverse, int w) {
     return h->tile[dtype == HYRES_F64][inverse][width_class(w)];
 }
 
-void add_dwt(Exec& x, bool inverse) {
+bool in_group(const Exec& x, int i, int grp) { return grp < 0 || x.ngroups <= 1 || x.group_of[i] == grp; }
+
+void add_dwt(Exec& x, bool inverse, int grp) {
     int Lmax = 0;
-    for (auto& c : x.plan) Lmax = std::max(Lmax, c.L);
+    for (int i = 0; i < x.count; ++i)
+        if (in_group(x, i, grp)) Lmax = std::max(Lmax, x.plan[i].L);
     for (int k = 0; k < Lmax; ++k) {
         const int l = inverse ? Lmax - k : k + 1;
         for (int cand = 0; cand < kTileCands; ++cand) {
@@ -443,7 +461,7 @@ void add_dwt(Exec& x, bool inverse) {
             bool any = false;
             for (int i = 0; i < x.count; ++i) {
                 const CubePlan& c = x.plan[i];
-                if (c.L < l || tile_of(x.h, x.dtype, inverse, c.lw[l]) != cand) continue;
+                if (!in_group(x, i, grp) || c.L < l || tile_of(x.h, x.dtype, inverse, c.lw[l]) != cand) continue;
                 cnt[i] = c.r * cdiv(c.lw[l], kTileTX[cand]) * cdiv(c.lh[l], kTileTY[cand]);
                 any = true;
             }
@@ -457,25 +475,27 @@ void add_dwt(Exec& x, bool inverse) {
             L.n = x.count;
             L.level = l;
             L.grid = x.grid(tot, 8);
+            L.grp = grp;
             x.prog.push_back(L);
         }
     }
 }
 
-// Builds the launch program of the stages in `stages` over every cube.
-void build_program(Exec& x, int stages) {
-    x.tab.clear();
-    x.prog.clear();
+// Appends the launches of the stages in `stages` for the cubes of group `grp`
+// (every cube when grp < 0 or the executor has one group).
+void build_group(Exec& x, int stages, int grp) {
     const int N = x.count;
     const bool f64 = x.dtype == HYRES_F64;
     std::vector<int> Ts;
-    for (auto& c : x.plan) Ts.push_back(c.T);
+    for (int i = 0; i < N; ++i)
+        if (in_group(x, i, grp)) Ts.push_back(x.plan[i].T);
     std::sort(Ts.begin(), Ts.end());
     Ts.erase(std::unique(Ts.begin(), Ts.end()), Ts.end());
+    const size_t first = x.prog.size();
 
-    // cubes of band-tile class T (and of blend pass `pass` when pass >= 0)
+    // cubes of band-tile class T (and of blend pass `pass` when pass >= 0) in the group
     auto member = [&](int i, int T, int pass) {
-        return (T < 0 || x.plan[i].T == T) && (pass < 0 || x.pass_of[i] == pass);
+        return in_group(x, i, grp) && (T < 0 || x.plan[i].T == T) && (pass < 0 || x.pass_of[i] == pass);
     };
     auto per_T = [&](int kind, int stage, int per_cu, auto items_of, int pass = -1) {
         for (int T : Ts) {
@@ -510,7 +530,7 @@ void build_program(Exec& x, int stages) {
             if (kind == K_GRAM_F32 || kind == K_GRAM_BF16) {
                 std::vector<int> ids;
                 for (int i = 0; i < N; ++i)
-                    if (x.plan[i].T == T) ids.push_back(i);
+                    if (member(i, T, -1)) ids.push_back(i);
                 Launch R{};
                 R.kind = K_GRAM_RED;
                 R.stage = stage;
@@ -544,7 +564,7 @@ void build_program(Exec& x, int stages) {
         for (int k = 0; k < kSmallClasses; ++k) {
             std::vector<int> ids;
             for (int i = 0; i < N; ++i)
-                if (small_class(x.plan[i].p) == k) ids.push_back(i);
+                if (in_group(x, i, grp) && small_class(x.plan[i].p) == k) ids.push_back(i);
             if (ids.empty()) continue;
             Launch L{};
             L.kind = K_SMALL;
@@ -560,12 +580,13 @@ void build_program(Exec& x, int stages) {
         else per_T(K_PROJ_F32, HYRES_STAGE_PROJECT, 8, [](const CubePlan& c) { return cdiv(c.n, kPixTile); });
         if (x.precision == HYRES_PREC_MIXED && !f64) {
             // the FP32 refinement of the subspace (Rayleigh-Ritz on T^T T)
-            std::vector<int64_t> slots(N), pix(N);
-            std::vector<int> ids(N);
+            std::vector<int64_t> slots(N, 0), pix(N, 0);
+            std::vector<int> ids;
             for (int i = 0; i < N; ++i) {
+                if (!in_group(x, i, grp)) continue;
                 slots[i] = x.plan[i].rgroups;
                 pix[i] = cdiv(x.plan[i].n, 256);
-                ids[i] = i;
+                ids.push_back(i);
             }
             int64_t ns, np;
             Launch R{};
@@ -575,24 +596,25 @@ void build_program(Exec& x, int stages) {
             R.b = x.counts(pix, &np);
             R.key = x.list(ids);
             R.n = N;
+            R.nlist = (int)ids.size();
             R.grid = x.grid(ns, 4);
             R.grid2 = x.grid(np, 8);
             x.prog.push_back(R);
         }
     }
-    if (stages & S_DWT) add_dwt(x, false);
+    if (stages & S_DWT) add_dwt(x, false, grp);
     if (stages & S_SURE) {
         std::vector<int64_t> comp(N, 0), hist(N, 0);
         // one work-item size for the whole program: about one item per compute unit
         int64_t total_coef = 0;
         for (int i = 0; i < N; ++i) {
             const CubePlan& c = x.plan[i];
-            if (!c.has_lambda) total_coef += (int64_t)c.r * (c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc);
+            if (in_group(x, i, grp) && !c.has_lambda) total_coef += (int64_t)c.r * (c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc);
         }
         const int64_t ch = sure_chunk_for(total_coef, x.h ? x.h->num_cu : 256);
         for (int i = 0; i < N; ++i) {
             const CubePlan& c = x.plan[i];
-            if (c.has_lambda) continue;
+            if (!in_group(x, i, grp) || c.has_lambda) continue;
             const int64_t ns = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
             comp[i] = c.r;
             x.desc[i].schunk = ch;
@@ -620,7 +642,7 @@ void build_program(Exec& x, int stages) {
             }
         }
         for (int i = 0; i < N; ++i) {
-            if (!x.plan[i].has_lambda) continue;
+            if (!in_group(x, i, grp) || !x.plan[i].has_lambda) continue;
             Launch C{};
             C.kind = K_COPY;
             C.stage = HYRES_STAGE_SURE;
@@ -630,7 +652,7 @@ void build_program(Exec& x, int stages) {
             x.prog.push_back(C);
         }
     }
-    if (stages & S_IDWT) add_dwt(x, true);
+    if (stages & S_IDWT) add_dwt(x, true, grp);
     if (stages & S_BP) {
         // blended tiles: one launch per pass of non-overlapping tiles, in pass order
         int npass = 1;
@@ -642,6 +664,29 @@ void build_program(Exec& x, int stages) {
                        pass);
         }
     }
+    for (size_t k = first; k < x.prog.size(); ++k) x.prog[k].grp = grp < 0 ? -1 : grp;
+}
+
+// Builds the launch program of the stages in `stages` over every cube: one
+// run of stages per cube group, then (tile grids) the blended back-projection.
+void build_program(Exec& x, int stages) {
+    x.tab.clear();
+    x.prog.clear();
+    if (x.ngroups <= 1) {
+        build_group(x, stages, 0);
+        return;
+    }
+    const int joint = x.pass_of.empty() ? 0 : (stages & S_BP);
+    for (int g = 0; g < x.ngroups; ++g) {
+        const size_t first = x.prog.size();
+        build_group(x, stages & ~joint, g);
+        for (size_t k = x.prog.size(); k > first; --k)
+            if (x.prog[k - 1].stage == HYRES_STAGE_GRAM) {
+                x.prog[k - 1].chain = true;
+                break;
+            }
+    }
+    if (joint) build_group(x, joint, -1);
 }
 
 hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
@@ -667,14 +712,38 @@ hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
         case K_BP_F32: return launch_backproject_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
         case K_BP_F64: return launch_backproject_f64(D, L.a, L.n64, s);
         case K_RITZ:
-            return launch_ritz(D, x.table(L.a), x.table(L.key), L.n, x.table(L.b), L.n, L.grid, L.grid2, s);
+            return launch_ritz(D, x.table(L.a), x.table(L.key), L.nlist, x.table(L.b), L.n, L.grid, L.grid2, s);
     }
     return hipErrorInvalidValue;
 }
 
+// Batch groups: the cubes of one small-solve class, largest band counts (the
+// longest small solves) first; classes beyond kMaxGroups share the last group.
+void group_by_small_class(Exec& x) {
+    std::vector<int> cls;
+    for (auto& c : x.plan) cls.push_back(small_class(c.p));
+    std::vector<int> order(cls);
+    std::sort(order.begin(), order.end(), std::greater<int>());
+    order.erase(std::unique(order.begin(), order.end()), order.end());
+    x.ngroups = std::min<int>((int)order.size(), kMaxGroups);
+    x.group_of.assign(x.count, 0);
+    for (int i = 0; i < x.count; ++i) {
+        const int rank = (int)(std::find(order.begin(), order.end(), cls[i]) - order.begin());
+        x.group_of[i] = std::min(rank, x.ngroups - 1);
+    }
+}
+
+// Tile-grid groups: consecutive tiles in raster order, kMaxGroups of them.
+void group_tiles(Exec& x) {
+    x.ngroups = std::min(kMaxGroups, x.count);
+    x.group_of.assign(x.count, 0);
+    for (int t = 0; t < x.count; ++t) x.group_of[t] = (int)((int64_t)t * x.ngroups / x.count);
+}
+
 // Writes the descriptors and work tables into the workspace (stream-ordered).
 hyres_status upload_exec(const Exec& x, hipStream_t s) {
-    if (x.tab.size() > table_ints(x.count)) return HYRES_E_UNSUPPORTED;
+    // the last table of the region is the tuner's
+    if (x.tab.size() > table_ints(x.count) - (size_t)(x.count + 1)) return HYRES_E_UNSUPPORTED;
     HIPCHK(upload(x.ws, x.o_desc, x.desc.data(), sizeof(CubeDesc) * x.count, s));
     if (!x.tab.empty()) HIPCHK(upload(x.ws, x.o_tab, x.tab.data(), sizeof(int) * x.tab.size(), s));
     return HYRES_OK;
@@ -685,7 +754,55 @@ hyres_status upload_exec(const Exec& x, hipStream_t s) {
 // workgroups) run beside each other: the first on `s`, the others on the
 // handle's side streams, forked from and joined back into `s` by events (a
 // capture of `s` records them as parallel branches).
+hyres_status run_grouped(const Exec& x, hipStream_t s, bool timed) {
+    hyres_handle* h = x.h;
+    const int G = x.ngroups;
+    auto stream_of = [&](int g) { return g <= 0 ? s : h->side[g - 1]; };
+    // stage timers per group, on the group's stream (slot G: the joint launches)
+    std::unique_ptr<StageTimer> tm[kMaxGroups + 1];
+    int cur[kMaxGroups + 1];
+    for (int g = 0; g <= G; ++g) cur[g] = -1;
+    HIPCHK(hipEventRecord(h->fork, s));
+    for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(h->side[g - 1], h->fork, 0));
+    int prev = 0;
+    bool joined = false;
+    auto join_all = [&]() -> hyres_status {
+        for (int g = 0; g < G; ++g) tm[g].reset();
+        for (int g = 1; g < G; ++g) {
+            HIPCHK(hipEventRecord(h->join[g - 1], h->side[g - 1]));
+            HIPCHK(hipStreamWaitEvent(s, h->join[g - 1], 0));
+        }
+        joined = true;
+        return HYRES_OK;
+    };
+    for (const Launch& L : x.prog) {
+        if (L.grp < 0 && !joined) {
+            hyres_status st = join_all();
+            if (st) return st;
+        }
+        if (L.grp > prev) {
+            // this group's Gram stage follows the previous group's
+            HIPCHK(hipStreamWaitEvent(stream_of(L.grp), h->chain[L.grp - 1], 0));
+            prev = L.grp;
+        }
+        const hipStream_t a = L.grp < 0 ? s : stream_of(L.grp);
+        const int slot = L.grp < 0 ? G : L.grp;
+        if (timed && L.stage != cur[slot]) {
+            tm[slot].reset();
+            tm[slot].reset(new StageTimer(h, a, L.stage));
+            cur[slot] = L.stage;
+        }
+        HIPCHK(launch_one(x, L, a));
+        if (L.chain && L.grp >= 0 && L.grp + 1 < G) HIPCHK(hipEventRecord(h->chain[L.grp], a));
+    }
+    tm[G].reset();
+    if (!joined) return join_all();
+    return HYRES_OK;
+}
+
 hyres_status run_program(const Exec& x, hipStream_t s, bool timed) {
+    if (x.h) ++x.h->runs;
+    if (x.ngroups > 1 && x.h) return run_grouped(x, s, timed);
     std::unique_ptr<StageTimer> tm;
     int cur = -1;
     const size_t np = x.prog.size();
@@ -697,7 +814,7 @@ hyres_status run_program(const Exec& x, hipStream_t s, bool timed) {
             cur = L.stage;
         }
         size_t m = 1;
-        if (L.kind == K_SMALL && x.h)
+        if (L.kind == K_SMALL && x.h && x.ngroups <= 1)
             while (k + m < np && m <= (size_t)hyres_handle::kSide && x.prog[k + m].kind == K_SMALL) ++m;
         if (m == 1) {
             HIPCHK(launch_one(x, L, s));
@@ -841,7 +958,8 @@ HYRES_API hyres_status hyres_create(hyres_handle** handle, int device) {
         ok = ok && hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
         for (int i = 0; i < hyres_handle::kSide && ok; ++i) {
             ok = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&h->join[i], hipEventDisableTiming) == hipSuccess;
+                 hipEventCreateWithFlags(&h->join[i], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&h->chain[i], hipEventDisableTiming) == hipSuccess;
         }
         (void)hipSetDevice(prev);
         if (!ok) {
@@ -870,6 +988,7 @@ HYRES_API void hyres_destroy(hyres_handle* handle) {
     for (int i = 0; i < hyres_handle::kSide; ++i) {
         if (handle->side[i]) (void)hipStreamDestroy(handle->side[i]);
         if (handle->join[i]) (void)hipEventDestroy(handle->join[i]);
+        if (handle->chain[i]) (void)hipEventDestroy(handle->chain[i]);
     }
     if (handle->fork) (void)hipEventDestroy(handle->fork);
     delete handle;
@@ -890,12 +1009,18 @@ HYRES_API hyres_status hyres_profile_read(hyres_handle* h, double* ms_out, int* 
     if (!h || !ms_out || !count_out) return HYRES_E_NULL;
     hyres_status st = set_device(h);
     if (st) return st;
+    // records of one program run (one per cube group) add up to one timed stage
+    std::vector<std::pair<int, unsigned>> seen;
     for (auto& r : h->pending) {
         float ms = 0.f;
         if (hipEventSynchronize(r.b) != hipSuccess) return HYRES_E_HIP;
         if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return HYRES_E_HIP;
         ms_out[r.stage] += ms;
-        count_out[r.stage] += 1;
+        const std::pair<int, unsigned> key(r.stage, r.run);
+        if (std::find(seen.begin(), seen.end(), key) == seen.end()) {
+            seen.push_back(key);
+            count_out[r.stage] += 1;
+        }
         h->pool.push_back(r.a);
         h->pool.push_back(r.b);
     }
@@ -1259,6 +1384,7 @@ HYRES_API hyres_status hyres_batch_create(hyres_handle* h, const hyres_cube* cub
         x.desc[i] = solve_desc(x.plan[i], workspace, k.Y, k.pitch, k.row_pitch, k.X, k.x_pitch, k.x_row_pitch,
                                k.sigma_in, k.lambda_in, opt->flags, &k.out);
     }
+    group_by_small_class(x);
     build_program(x, kAllStages);
     if ((st = upload_exec(x, (hipStream_t)stream))) return st;
     *batch = b.release();
@@ -1658,6 +1784,7 @@ HYRES_API hyres_status hyres_denoise_tiled(hyres_handle* h, const void* Y, int H
             d.bncx = g.ncx;
             x.desc[t] = d;
         }
+    group_tiles(x);
     build_program(x, kAllStages);
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_exec(x, s))) return st;

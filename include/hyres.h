@@ -260,9 +260,11 @@ hyres_status hyres_tile_grid(int size, int tile, int overlap, int* starts, int* 
  * sin^2(pi/2 (k + 1/2) / overlap) ramps over the first and the last `overlap`
  * samples of the tile, with no ramp on a side that touches the image border.
  * All tiles run as one batch (tiles are addressed in place through pitch and
- * row_pitch, nothing is copied); the back-projection applies the blend, in
- * passes of non-overlapping tiles so that the sums are formed in a fixed
- * order.  lambda_out [ntiles * rank] and sigma_out [ntiles * p] (device
+ * row_pitch, nothing is copied), in four groups of consecutive tiles on
+ * streams of their own.  The back-projection applies the blend: FP32 in one
+ * pass over X (each pixel sums its covering tiles in raster order and is
+ * written once), FP64 in passes of non-overlapping tiles; either way the sums
+ * are formed in a fixed order.  lambda_out [ntiles * rank] and sigma_out [ntiles * p] (device
  * double, tile t = row-major index over the grid) may be NULL. */
 hyres_status hyres_tiled_workspace_size(int H, int W, int p, int tile, int overlap,
                                         const hyres_options* opt, int dtype, size_t* bytes);

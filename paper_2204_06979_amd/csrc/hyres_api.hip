@@ -31,6 +31,7 @@ hipError_t launch_gram_f64(const CubeDesc*, int, int, int, hipStream_t);
 hipError_t launch_small(int p, const CubeDesc*, const int*, int, hipStream_t);
 hipError_t launch_project_f32(int T, int lm, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_backproject_f32(int T, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_blend_f32(int T, const CubeDesc*, const BlendGrid&, int, hipStream_t);
 hipError_t launch_project_f64(const CubeDesc*, int, int64_t, hipStream_t);
 hipError_t launch_backproject_f64(const CubeDesc*, int, int64_t, hipStream_t);
 hipError_t launch_dwt_level(int dtype, int tx, int ty, bool inverse, const CubeDesc*, const int*, int, int,
@@ -352,7 +353,7 @@ enum { S_GRAM = 1, S_SMALL = 2, S_PROJ = 4, S_DWT = 8, S_SURE = 16, S_IDWT = 32,
 
 enum Kind {
     K_GRAM_F32, K_GRAM_BF16, K_GRAM_RED, K_GRAM_F64, K_SMALL, K_PROJ_F32, K_PROJ_F64, K_DWT, K_IDWT,
-    K_SURE_INIT, K_SURE_ROUND, K_COPY, K_BP_F32, K_BP_F64, K_RITZ
+    K_SURE_INIT, K_SURE_ROUND, K_COPY, K_BP_F32, K_BP_F64, K_RITZ, K_BLEND_F32
 };
 
 struct Launch {
@@ -412,6 +413,9 @@ struct Exec {
     // bandwidth-bound stages.  A blended back-projection runs after every group.
     std::vector<int> group_of;
     int ngroups = 1;
+    // FP32 tile grids: the back-projection blends the tiles in one pass over X
+    bool blend1 = false;
+    BlendGrid bg{};
 
     const CubeDesc* descs() const { return at<const CubeDesc>(ws, o_desc); }
     const int* table(int off) const { return at<const int>(ws, o_tab) + off; }
@@ -653,7 +657,14 @@ void build_group(Exec& x, int stages, int grp) {
         }
     }
     if (stages & S_IDWT) add_dwt(x, true, grp);
-    if (stages & S_BP) {
+    if ((stages & S_BP) && x.blend1 && !f64) {
+        Launch L{};
+        L.kind = K_BLEND_F32;
+        L.stage = HYRES_STAGE_BACKPROJECT;
+        L.key = x.plan[0].T;
+        L.grid = x.grid((int64_t)x.bg.H * cdiv(x.bg.W, kPixTile), 4);
+        x.prog.push_back(L);
+    } else if (stages & S_BP) {
         // blended tiles: one launch per pass of non-overlapping tiles, in pass order
         int npass = 1;
         for (int v : x.pass_of) npass = std::max(npass, v + 1);
@@ -711,6 +722,7 @@ hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
             return hipGetLastError();
         case K_BP_F32: return launch_backproject_f32(L.key, D, x.table(L.a), L.n, L.grid, s);
         case K_BP_F64: return launch_backproject_f64(D, L.a, L.n64, s);
+        case K_BLEND_F32: return launch_blend_f32(L.key, D, x.bg, L.grid, s);
         case K_RITZ:
             return launch_ritz(D, x.table(L.a), x.table(L.key), L.nlist, x.table(L.b), L.n, L.grid, L.grid2, s);
     }
@@ -1600,7 +1612,6 @@ HYRES_API hyres_status hyres_sure_grad(hyres_handle* h, const void* coeffs, int 
 // ------------------------------------------------------------- sliding window
 namespace {
 
-constexpr int kMaxTilesAxis = 64;
 
 // Tile starts along one axis: steps of tile - overlap, the last start clamped
 // so that the tile ends at the border; one tile when it covers the axis.
@@ -1784,6 +1795,17 @@ HYRES_API hyres_status hyres_denoise_tiled(hyres_handle* h, const void* Y, int H
             d.bncx = g.ncx;
             x.desc[t] = d;
         }
+    if (dtype == HYRES_F32) {
+        BlendGrid& b = x.bg;
+        b.ny = g.ny; b.nx = g.nx; b.th = g.th; b.tw = g.tw; b.H = H; b.W = W; b.p = p;
+        for (int i = 0; i < g.ny; ++i) b.sy[i] = g.ay.start[i];
+        for (int i = 0; i < g.nx; ++i) b.sx[i] = g.ax.start[i];
+        b.X = X; b.xpitch = x_pitch; b.xrow_pitch = x_row_pitch;
+        const bool vec = p % 4 == 0 && x_pitch % 4 == 0 && x_row_pitch % 4 == 0 &&
+                         reinterpret_cast<uintptr_t>(X) % 16 == 0;
+        b.xmode = vec ? kVec : x_pitch == p ? kDense : kScalar;
+        x.blend1 = true;
+    }
     group_tiles(x);
     build_program(x, kAllStages);
     hipStream_t s = (hipStream_t)stream;

@@ -112,6 +112,16 @@ struct CubeDesc {
     unsigned long long* dbg;                // phase time stamps (timing builds only; null otherwise)
 };
 
+// Tile grid of a sliding-window solve (FP32), for the back-projection that
+// blends the tiles in one pass over the output image.
+constexpr int kMaxTilesAxis = 64;
+struct BlendGrid {
+    int ny, nx, th, tw, H, W, p;
+    int sy[kMaxTilesAxis], sx[kMaxTilesAxis];   // tile starts along y and x
+    void* X; int64_t xpitch, xrow_pitch;        // the output image
+    int xmode;                                  // kVec (16-byte pixel groups), kDense or kScalar writes
+};
+
 // Everything the adjoint kernels need (one cube; passed by value).
 struct AdjDesc {
     int H, W, p, r, L, scope;

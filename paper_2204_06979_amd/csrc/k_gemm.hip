@@ -316,6 +316,111 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
     }
 }
 
+// Sliding-window back-projection in one pass over the output image.  An item
+// is a run of 64 pixels of one image row; for every tile covering part of the
+// run, the matrix cores form that tile's Zhat Q (16 pixels by 16 bands per
+// wave and MFMA block), and each pixel adds its blend weight (the two 1-D
+// weights of the tile) times the product, tiles in raster order.  X is written
+// once, without reading it.  Blocks take contiguous runs of items, so the Q
+// fragments stay in registers across the runs inside one tile.
+template <int T>
+__global__ __launch_bounds__(256) void k_blend_f32(const CubeDesc* __restrict__ descs, const BlendGrid g) {
+    constexpr int P16 = 16 * T;
+    constexpr int LDO = P16 + 4;
+    __shared__ __attribute__((aligned(16))) float ot[kPixTile * LDO];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
+    const int p = g.p;
+    const int nseg = (g.W + kPixTile - 1) / kPixTile;
+    const int64_t total = (int64_t)g.H * nseg;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * per;
+    const int64_t i1 = i0 + per < total ? i0 + per : total;
+    const uint32_t pmag = descs[0].pmag;
+    int cur = -1;
+    float bq[4][T];
+    for (int64_t item = i0; item < i1; ++item) {
+        const int y = (int)(item / nseg);
+        const int x0 = (int)(item - (int64_t)y * nseg) * kPixTile;
+        v4f acc[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int iy = 0; iy < g.ny; ++iy) {
+            const int ly = y - g.sy[iy];
+            if (ly < 0 || ly >= g.th) continue;
+            for (int ix = 0; ix < g.nx; ++ix) {
+                const int sx = g.sx[ix];
+                if (sx >= x0 + kPixTile || sx + g.tw <= x0) continue;
+                const int t = iy * g.nx + ix;
+                const CubeDesc& d = descs[t];
+                if (t != cur) {
+                    cur = t;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int j = 0; j < T; ++j) bq[q][j] = d.Q32[(4 * q + row) * P16 + 16 * j + col];
+                }
+                const int r = d.r, R4 = (r + 3) >> 2;
+                // A fragments: Zhat[comp 4q + row] at the tile pixel of image column x0 + 16 wave + col
+                const int lxa = x0 + 16 * wave + col - sx;
+                const bool va = lxa >= 0 && lxa < g.tw;
+                const int64_t qa = (int64_t)ly * g.tw + (va ? lxa : 0);
+                const float* zh = static_cast<const float*>(d.Z);
+                float a[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int comp = 4 * q + row;
+                    a[q] = (va && q < R4 && comp < r) ? zh[(int64_t)comp * d.nz + qa] : 0.f;
+                }
+                // blend weights of this lane's output pixels x0 + 16 wave + 4 row + i
+                const double wy = d.bwy[ly];
+                float w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int lx = x0 + 16 * wave + 4 * row + i - sx;
+                    w[i] = (lx >= 0 && lx < g.tw) ? (float)(wy * d.bwx[lx]) : 0.f;
+                }
+#pragma unroll
+                for (int j = 0; j < T; ++j) {
+                    v4f pr = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (q < R4) pr = mfma4(a[q], bq[q][j], pr);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[j][i] = fmaf(w[i], pr[i], acc[j][i]);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < T; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ot[(16 * wave + 4 * row + i) * LDO + 16 * j + col] = acc[j][i];
+        __syncthreads();
+        const int m = g.W - x0 < kPixTile ? g.W - x0 : kPixTile;   // pixels of the run
+        float* base = static_cast<float*>(g.X) + (int64_t)y * g.xrow_pitch + (int64_t)x0 * g.xpitch;
+        if (g.xmode == kVec) {
+            const int g4 = p >> 2;
+            for (int e = threadIdx.x; e < m * g4; e += 256) {
+                const int k = e / g4, gg = e - k * g4;
+                *reinterpret_cast<v4f*>(base + (int64_t)k * g.xpitch + 4 * gg) =
+                    *reinterpret_cast<const v4f*>(ot + k * LDO + 4 * gg);
+            }
+        } else if (g.xmode == kDense) {
+            for (int e = threadIdx.x; e < m * p; e += 256) {
+                const int k = div_p(e, pmag);
+                base[e] = ot[k * LDO + (e - k * p)];
+            }
+        } else {
+            for (int e = threadIdx.x; e < m * p; e += 256) {
+                const int k = div_p(e, pmag), b = e - k * p;
+                base[(int64_t)k * g.xpitch + b] = ot[k * LDO + b];
+            }
+        }
+    }
+}
+
 // FP64: one pixel per thread.
 __global__ void k_project_f64(const CubeDesc* __restrict__ descs, int cube) {
     const CubeDesc& d = descs[cube];
@@ -380,6 +485,18 @@ hipError_t launch_backproject_f32(int T, const CubeDesc* descs, const int* items
                                   hipStream_t s) {
     switch (T) {
 #define HYRES_B(TT) case TT: launch_bp_t<TT>(descs, items, ncubes, grid, s); break;
+        HYRES_B(1) HYRES_B(2) HYRES_B(3) HYRES_B(4) HYRES_B(5) HYRES_B(6) HYRES_B(7)
+        HYRES_B(8) HYRES_B(9) HYRES_B(10) HYRES_B(11) HYRES_B(12) HYRES_B(13) HYRES_B(14)
+#undef HYRES_B
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_f32(int T, const CubeDesc* descs, const BlendGrid& g, int grid, hipStream_t s) {
+    switch (T) {
+#define HYRES_B(TT) \
+    case TT: hipLaunchKernelGGL(k_blend_f32<TT>, dim3(grid), dim3(256), 0, s, descs, g); break;
         HYRES_B(1) HYRES_B(2) HYRES_B(3) HYRES_B(4) HYRES_B(5) HYRES_B(6) HYRES_B(7)
         HYRES_B(8) HYRES_B(9) HYRES_B(10) HYRES_B(11) HYRES_B(12) HYRES_B(13) HYRES_B(14)
 #undef HYRES_B

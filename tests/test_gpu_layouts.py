@@ -106,3 +106,24 @@ def test_batch_class_with_mixed_layouts(prec):
             assert int(b.info(i)["status"].cpu()[0]) & ~8 == 0, i
             assert torch.equal(b.info(i)["lam"], info1["lam"]), i
             assert torch.equal(b.X[i], X1), (i, p, lay)
+
+
+@pytest.mark.parametrize("p", [17, 40])
+def test_tiled_layouts_give_bitwise_equal_results(p):
+    """Sliding window: a padded cube and padded or windowed outputs (the
+    one-pass blend writes 16-byte pixel groups, unpadded runs or single
+    values) give the contiguous result bitwise."""
+    api = _api()
+    H, W, r, L, tile, ov = 150, 200, 3, 2, 96, 16
+    Y = _cube(900 + p, H, W, p, r, L)
+    say("tiled layouts p", p)
+    ref, info = api.denoise_tiled(torch.tensor(Y, device="cuda"), r, L, tile=tile, overlap=ov, precision="mixed")
+    ref = ref.clone()
+    assert int(info["status"].cpu()[0]) & ~8 == 0
+    X, info = api.denoise_tiled(_padded(Y, 3), r, L, tile=tile, overlap=ov, precision="mixed")
+    assert int(info["status"].cpu()[0]) & ~8 == 0
+    assert torch.equal(X, ref), "padded Y"
+    for name, Xv in [("padded out", _padded(np.zeros_like(Y), 1)), ("window out", _window(np.zeros_like(Y), 204))]:
+        api.denoise_tiled(torch.tensor(Y, device="cuda"), r, L, tile=tile, overlap=ov, precision="mixed", X=Xv)
+        say("   ", name, "pitch", Xv.stride(1), "row pitch", Xv.stride(0))
+        assert torch.equal(Xv, ref), name

@@ -192,13 +192,13 @@ __global__ __launch_bounds__(256, LM == kVec || LM == kDense ? 2 : 1) void k_pro
     }
 }
 
+// X is written once and not read again here: non-temporal stores.
 template <int T>
 __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restrict__ descs,
                                                         const int* __restrict__ items, int ncubes) {
     constexpr int P16 = 16 * T;
     constexpr int LDO = P16 + 4;
     __shared__ __attribute__((aligned(16))) float ot[kPixTile * LDO];
-    __shared__ float s_w[kPixTile];          // blend weight per pixel (negative: first writer)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15, row = lane >> 4;
@@ -238,14 +238,6 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
             for (int i = 0; i < 4; ++i) ot[(16 * wave + 4 * row + i) * LDO + 16 * j + col] = acc[i];
         }
         const int64_t nleft = d.n - q0;
-        const bool blend = d.bwy != nullptr;
-        if (blend && threadIdx.x < kPixTile && threadIdx.x < nleft) {
-            const int64_t q = q0 + threadIdx.x;
-            const int64_t y = q / d.W, x = q - y * d.W;
-            bool first;
-            const float w = (float)blend_weight(d, y, x, &first);
-            s_w[threadIdx.x] = first ? -w : w;
-        }
         __syncthreads();
         if (d.xvec4) {
             // whole 64-pixel tiles per image row: the pixels are consecutive in memory
@@ -254,15 +246,9 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
             float* base = static_cast<float*>(d.X) + y0 * d.xrow_pitch + x0 * d.xpitch;
             for (int e = threadIdx.x; e < kPixTile * g4; e += 256) {
                 const int k = e / g4, g = e - k * g4;
-                if (k < nleft) {
-                    v4f* dst = reinterpret_cast<v4f*>(base + (int64_t)k * d.xpitch + 4 * g);
-                    v4f v = *reinterpret_cast<const v4f*>(ot + k * LDO + 4 * g);
-                    if (blend) {
-                        const float w = s_w[k];
-                        v = (__float_as_uint(w) >> 31) ? v * (-w) : *dst + v * w;
-                    }
-                    *dst = v;
-                }
+                if (k < nleft)
+                    __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(ot + k * LDO + 4 * g),
+                                                reinterpret_cast<v4f*>(base + (int64_t)k * d.xpitch + 4 * g));
             }
         } else if (d.xdense) {
             // unpadded pixels: the tile is 64 p consecutive floats, written as float4s
@@ -270,46 +256,27 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
             const int lim = (int)(nleft < kPixTile ? nleft : kPixTile) * p;
             for (int e = 4 * threadIdx.x; e < lim; e += 4 * 256) {
                 v4f v;
-                float w[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const int k = div_p(e + c, d.pmag);
+                    const int k = div_p(e + c, d.pmag);   // k < 64: e + 3 < 64 p
                     v[c] = ot[k * LDO + (e + c - k * p)];
-                    w[c] = blend ? s_w[k] : 0.f;        // k < 64: e + 3 < 64 p
                 }
                 if (e + 3 < lim) {
-                    v4f* dst = reinterpret_cast<v4f*>(base + e);
-                    if (blend) {
-                        const v4f old = *dst;
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            v[c] = (__float_as_uint(w[c]) >> 31) ? v[c] * (-w[c]) : old[c] + v[c] * w[c];
-                    }
-                    *dst = v;
+                    __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(base + e));
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if (e + c < lim) {
-                            float x = v[c];
-                            if (blend) x = (__float_as_uint(w[c]) >> 31) ? x * (-w[c]) : base[e + c] + x * w[c];
-                            base[e + c] = x;
-                        }
-                    }
+                    for (int c = 0; c < 4; ++c)
+                        if (e + c < lim) __builtin_nontemporal_store(v[c], base + e + c);
                 }
             }
         } else {
             for (int e = threadIdx.x; e < kPixTile * p; e += 256) {
-                const int k = e / p, b = e - k * p;
+                const int k = div_p(e, d.pmag), b = e - k * p;
                 if (k < nleft) {
                     const int64_t q = q0 + k;
                     const int64_t y = q / d.W, x = q - y * d.W;
-                    float* dst = static_cast<float*>(d.X) + y * d.xrow_pitch + x * d.xpitch + b;
-                    float v = ot[k * LDO + b];
-                    if (blend) {
-                        const float w = s_w[k];
-                        v = (__float_as_uint(w) >> 31) ? v * (-w) : *dst + v * w;
-                    }
-                    *dst = v;
+                    __builtin_nontemporal_store(ot[k * LDO + b],
+                                                static_cast<float*>(d.X) + y * d.xrow_pitch + x * d.xpitch + b);
                 }
             }
         }
@@ -321,8 +288,9 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
 // run, the matrix cores form that tile's Zhat Q (16 pixels by 16 bands per
 // wave and MFMA block), and each pixel adds its blend weight (the two 1-D
 // weights of the tile) times the product, tiles in raster order.  X is written
-// once, without reading it.  Blocks take contiguous runs of items, so the Q
-// fragments stay in registers across the runs inside one tile.
+// once, without reading it (non-temporal stores).  Blocks take contiguous runs
+// of items, so the Q fragments stay in registers across the runs inside one
+// tile.
 template <int T>
 __global__ __launch_bounds__(256) void k_blend_f32(const CubeDesc* __restrict__ descs, const BlendGrid g) {
     constexpr int P16 = 16 * T;
@@ -404,18 +372,18 @@ __global__ __launch_bounds__(256) void k_blend_f32(const CubeDesc* __restrict__ 
             const int g4 = p >> 2;
             for (int e = threadIdx.x; e < m * g4; e += 256) {
                 const int k = e / g4, gg = e - k * g4;
-                *reinterpret_cast<v4f*>(base + (int64_t)k * g.xpitch + 4 * gg) =
-                    *reinterpret_cast<const v4f*>(ot + k * LDO + 4 * gg);
+                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(ot + k * LDO + 4 * gg),
+                                            reinterpret_cast<v4f*>(base + (int64_t)k * g.xpitch + 4 * gg));
             }
         } else if (g.xmode == kDense) {
             for (int e = threadIdx.x; e < m * p; e += 256) {
                 const int k = div_p(e, pmag);
-                base[e] = ot[k * LDO + (e - k * p)];
+                __builtin_nontemporal_store(ot[k * LDO + (e - k * p)], base + e);
             }
         } else {
             for (int e = threadIdx.x; e < m * p; e += 256) {
                 const int k = div_p(e, pmag), b = e - k * p;
-                base[(int64_t)k * g.xpitch + b] = ot[k * LDO + b];
+                __builtin_nontemporal_store(ot[k * LDO + b], base + (int64_t)k * g.xpitch + b);
             }
         }
     }

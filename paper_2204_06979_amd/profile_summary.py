@@ -31,7 +31,8 @@ COPY_BYTES = 256 * 1024 * 1024
 STAGE_OF = [
     ("k_gram", "gram"), ("k_small", "small"), ("k_project", "project"), ("k_ritz", "project"),
     ("k_dwt_level", "dwt"), ("k_sure", "sure"), ("k_copy_f64", "sure"), ("k_idwt_level", "idwt"),
-    ("k_backproject", "backproject"), ("k_blend_axis", "backproject"), ("k_upload", "setup"),
+    ("k_backproject", "backproject"), ("k_blend_axis", "backproject"), ("k_blend_f32", "backproject"),
+    ("k_upload", "setup"),
 ]
 
 
@@ -87,8 +88,10 @@ def summarize(a) -> int:
     cf = copy_factor(a.cal_fetch, "FETCH_SIZE") if a.cal_fetch else None
     cw = copy_factor(a.cal_write, "WRITE_SIZE") if a.cal_write else None
     def steps_of(counts):
+        # one threshold-search start per cube group and solve
         s = sum(c for n, c in counts if "k_sure_init" in n)
-        return s or sum(c for n, c in counts if "k_small" in n) or 1
+        s = s or sum(c for n, c in counts if "k_small" in n) or 1
+        return max(1, s // max(1, a.groups))
     solves_t = steps_of([(n, c) for n, c, *_ in stats])
     solves_f = steps_of([(n, v[0]) for n, v in fetch.items()])
     solves_w = steps_of([(n, v[0]) for n, v in write.items()])
@@ -99,7 +102,8 @@ def summarize(a) -> int:
         for c in a.command:
             out.append("    %s" % c)
         out.append("")
-    out.append("Steps in the profiled run: %d (one threshold-search start each).\n" % solves_t)
+    out.append("Steps in the profiled run: %d (threshold-search starts / %d cube group%s per solve).\n"
+               % (solves_t, a.groups, "" if a.groups == 1 else "s"))
     out.append("| kernel | stage | calls | avg us | us per step | % time |")
     out.append("|---|---|---|---|---|---|")
     for name, calls, total, avg, pct in sorted(stats, key=lambda r: -r[2]):
@@ -159,6 +163,7 @@ def main(argv=None) -> int:
     s.add_argument("--workload", required=True)
     s.add_argument("--traffic-json")
     s.add_argument("--command", action="append")
+    s.add_argument("--groups", type=int, default=1, help="cube groups per solve (each starts its own search)")
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         return copy_run()

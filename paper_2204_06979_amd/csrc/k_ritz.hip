@@ -32,15 +32,16 @@ __global__ __launch_bounds__(256) void k_ritz_reduce(const CubeDesc* __restrict_
         const int64_t t1 = t0 + kRitzGroup < ntiles ? t0 + kRitzGroup : ntiles;
         const int e = threadIdx.x;
         const float* src = d.rpart + e;
-        // eight loads in flight, added in tile order
+        // 32 loads in flight (the partials come from the caches, latency-bound),
+        // added in tile order
         double s = 0.0;
         int64_t t = t0;
-        for (; t + 8 <= t1; t += 8) {
-            float v[8];
+        for (; t + 32 <= t1; t += 32) {
+            float v[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = src[(t + u) * 256];
+            for (int u = 0; u < 32; ++u) v[u] = src[(t + u) * 256];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += (double)v[u];
+            for (int u = 0; u < 32; ++u) s += (double)v[u];
         }
         for (; t < t1; ++t) s += (double)src[t * 256];
         d.rsum[(int64_t)g * 256 + e] = s;
@@ -60,7 +61,7 @@ __device__ __forceinline__ int ritz_partner(int x, int t, int m) {
 
 __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs, const int* __restrict__ cubes,
                                               int ncls) {
-    __shared__ double M[16][17], U[16][17];
+    __shared__ double Mb[2][16][17], Ub[2][16][17];   // Jacobi rounds alternate between the two
     __shared__ double cs[16], sn[16];
     __shared__ double v0[kMaxBands][kMaxRank];
     __shared__ int perm[16];
@@ -78,24 +79,26 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
         if (a < r && b < r) {
             const double* src = d.rsum + a * 16 + b;
             int k = 0;
-            for (; k + 8 <= d.rgroups; k += 8) {
-                double v[8];
+            for (; k + 16 <= d.rgroups; k += 16) {
+                double v[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(k + u) * 256];
+                for (int u = 0; u < 16; ++u) v[u] = src[(int64_t)(k + u) * 256];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) s += v[u];
+                for (int u = 0; u < 16; ++u) s += v[u];
             }
             for (; k < d.rgroups; ++k) s += src[(int64_t)k * 256];
         }
-        M[i][j] = s;
-        U[i][j] = i == j ? 1.0 : 0.0;
+        Mb[0][i][j] = s;
+        Ub[0][i][j] = i == j ? 1.0 : 0.0;
     }
     for (int e = tid; e < p * r; e += 256) {
         const int row = e / r, k = e - row * r;
         v0[row][k] = d.V[(int64_t)k * p + row];
     }
     __syncthreads();
+    int cb = 0;
     for (int sweep = 0; sweep < 12 && m > 1; ++sweep) {
+        const double (*M)[17] = Mb[cb];
         if (tid < 64) {
             double off = 0.0, dg = 0.0;
             for (int e = tid; e < 256; e += 64) {
@@ -115,6 +118,8 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
         __syncthreads();
         if (!(s_off > 1e-26 * s_diag)) break;     // off-diagonal below 1e-13 of the diagonal
         for (int t = 0; t < m - 1; ++t) {
+            const double (*M)[17] = Mb[cb];
+            const double (*U)[17] = Ub[cb];
             // rotation of every pair (x, y), x < y: [c s; -s c] diagonalises the 2 x 2 block
             if (tid < m) {
                 const int x = tid, y = ritz_partner(x, t, m);
@@ -131,21 +136,22 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
                 sn[x] = x == lo ? -s : s;   // J[partner][x]
             }
             __syncthreads();
-            double mv = 0.0, uv = 0.0;
+            // the rotated matrices go to the other buffer: no barrier between reads and writes
             if (i < m && j < m) {
                 const int pi = ritz_partner(i, t, m), pj = ritz_partner(j, t, m);
                 const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
-                mv = ci * (M[i][j] * cj + M[i][pj] * sj) + si * (M[pi][j] * cj + M[pi][pj] * sj);
-                uv = U[i][j] * cj + U[i][pj] * sj;
+                Mb[cb ^ 1][i][j] = ci * (M[i][j] * cj + M[i][pj] * sj) + si * (M[pi][j] * cj + M[pi][pj] * sj);
+                Ub[cb ^ 1][i][j] = U[i][j] * cj + U[i][pj] * sj;
+            } else {
+                Mb[cb ^ 1][i][j] = M[i][j];
+                Ub[cb ^ 1][i][j] = U[i][j];
             }
-            __syncthreads();
-            if (i < m && j < m) {
-                M[i][j] = mv;
-                U[i][j] = uv;
-            }
+            cb ^= 1;
             __syncthreads();
         }
     }
+    const double (*M)[17] = Mb[cb];
+    const double (*U)[17] = Ub[cb];
     // descending order of the Ritz values (ties: lower index first)
     if (tid < r) {
         int rank = 0;

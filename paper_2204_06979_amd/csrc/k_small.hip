@@ -294,11 +294,14 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 // A v with v = x - alpha e_{k+1} (x: column k below the diagonal)
                 // is A x - alpha A e_{k+1}: the products with x start before the
                 // norm that gives alpha is known
+                // LDS reads are unconditional (every index of the thread grid is
+                // inside the vectors) and masked by selects: no divergent branches
                 double xc[BC];
 #pragma unroll
                 for (int b = 0; b < BC; ++b) {
                     const int j = tc + COLS * b;
-                    xc[b] = (j > k && j < p) ? s_col[buf][j] : 0.0;
+                    const double cj = s_col[buf][j];
+                    xc[b] = (j > k && j < p) ? cj : 0.0;
                 }
                 double ps[BR];
 #pragma unroll
@@ -330,7 +333,8 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 for (int a = 0; a < BR; ++a) {
                     const int i = tr + ROWS * a;
                     if (ROWS * a + ROWS - 1 > k) {
-                        const double vi = (i > k + 1 && i < p) ? s_col[buf][i] : (i == k + 1 ? v1 : 0.0);
+                        const double ci = s_col[buf][i];
+                        const double vi = (i > k + 1 && i < p) ? ci : (i == k + 1 ? v1 : 0.0);
                         const double a1 = kk + 1 < COLS ? A[a][bb] : A[a][bb + 1 < BC ? bb + 1 : bb];
                         if (own1) ps[a] = fma(-alpha, a1, ps[a]);
                         q = fma(vi, ps[a], q);    // this thread's share of v^T A v
@@ -366,14 +370,16 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
 #pragma unroll
                 for (int b = 0; b < BC; ++b) {
                     const int j = tc + COLS * b;
-                    wc[b] = (j > k && j < p) ? s_ub[j] - K * vc[b] : 0.0;
+                    const double uj = s_ub[j];
+                    wc[b] = (j > k && j < p) ? uj - K * vc[b] : 0.0;
                 }
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
                     if (ROWS * a + ROWS - 1 > k) {
                         const int i = tr + ROWS * a;
-                        const double vi = (i > k + 1 && i < p) ? s_col[buf][i] : (i == k + 1 ? v1 : 0.0);
-                        const double wi = (i > k && i < p) ? s_ub[i] - K * vi : 0.0;
+                        const double ci = s_col[buf][i], ui = s_ub[i];
+                        const double vi = (i > k + 1 && i < p) ? ci : (i == k + 1 ? v1 : 0.0);
+                        const double wi = (i > k && i < p) ? ui - K * vi : 0.0;
 #pragma unroll
                         for (int b = 0; b < BC; ++b) {
                             if (COLS * b + COLS - 1 > k) A[a][b] = fma(-wi, vc[b], fma(-vi, wc[b], A[a][b]));

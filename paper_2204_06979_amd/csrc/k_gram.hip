@@ -300,7 +300,15 @@ __device__ __forceinline__ void gramb_wave(const __bf16* __restrict__ th, const 
 }
 
 // BF16 staging: a task is 8 consecutive pixels x 4 bands; its values are
-// split and written as 16-byte rows of the band-major hi and lo tiles.
+// split and written as 16-byte rows of the band-major hi and lo tiles.  Task
+// pairs differ in the pixel block, so that the 16-byte writes of 8 adjacent
+// lanes (4 band groups x 2 pixel blocks) fall in distinct banks; a wave's
+// loads are two runs of consecutive band groups.
+__device__ __forceinline__ void gramb_task(int task, int T, int& blk, int& g) {
+    const int half = task >> 1;
+    g = half % (4 * T);
+    blk = 2 * (half / (4 * T)) + (task & 1);
+}
 template <int T> __host__ __device__ constexpr int gramb_ntask() { return (kGramKB / 8) * 4 * T; }
 template <int T> __host__ __device__ constexpr int gramb_nt() {
     return (gramb_ntask<T>() + kGramThreads - 1) / kGramThreads;
@@ -314,7 +322,8 @@ __device__ __forceinline__ void gramb_fetch(const CubeDesc& d, int64_t q, int64_
 #pragma unroll
     for (int i = 0; i < gramb_nt<T>(); ++i) {
         const int task = tid + kGramThreads * i;
-        const int blk = task / (4 * T), g = task - blk * (4 * T);
+        int blk, g;
+        gramb_task(task, T, blk, g);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int k = 8 * blk + u;
@@ -333,7 +342,8 @@ __device__ __forceinline__ void gramb_stage(__bf16* __restrict__ th, __bf16* __r
 #pragma unroll
     for (int i = 0; i < gramb_nt<T>(); ++i) {
         const int task = tid + kGramThreads * i;
-        const int blk = task / (4 * T), g = task - blk * (4 * T);
+        int blk, g;
+        gramb_task(task, T, blk, g);
         if (task < gramb_ntask<T>()) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {

@@ -745,11 +745,30 @@ void group_by_small_class(Exec& x) {
     }
 }
 
-// Tile-grid groups: consecutive tiles in raster order, kMaxGroups of them.
+// Tile-grid groups: consecutive tiles in raster order, kMaxGroups of them, of
+// decreasing size (shares 8 : 7 : 6 : 4 of the tiles): the last group's small
+// solves end last, and the fewer tiles it holds, the sooner its remaining
+// stages (and then the blend) are done.
 void group_tiles(Exec& x) {
     x.ngroups = std::min(kMaxGroups, x.count);
     x.group_of.assign(x.count, 0);
-    for (int t = 0; t < x.count; ++t) x.group_of[t] = (int)((int64_t)t * x.ngroups / x.count);
+    if (x.ngroups < kMaxGroups) {
+        for (int t = 0; t < x.count; ++t) x.group_of[t] = t;
+        return;
+    }
+    static constexpr int kShare[kMaxGroups] = {8, 7, 6, 4};
+    int tot = 0;
+    for (int g = 0; g < kMaxGroups; ++g) tot += kShare[g];
+    int acc = 0, t = 0;
+    for (int g = 0; g < kMaxGroups; ++g) {
+        acc += kShare[g];
+        // tiles [t, end) form group g; every group keeps at least one tile
+        int end = (int)((int64_t)x.count * acc / tot);
+        end = std::max(end, t + 1);
+        end = std::min(end, x.count - (kMaxGroups - 1 - g));
+        if (g == kMaxGroups - 1) end = x.count;
+        for (; t < end; ++t) x.group_of[t] = g;
+    }
 }
 
 // Writes the descriptors and work tables into the workspace (stream-ordered).

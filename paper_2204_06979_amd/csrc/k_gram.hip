@@ -430,41 +430,51 @@ __device__ __forceinline__ void gramd_stage(__bf16* __restrict__ th, __bf16* __r
 }
 
 // FP64: chunk sums flushed into FP64 accumulators (else acc keeps summing the
-// whole slot in FP32).  M: load path.
+// whole slot in FP32).  M: load path.  The hi/lo tiles are double-buffered
+// (th, tl hold two tiles of 16T x kGramLDP each): while the matrix cores read
+// one chunk, the next is split and staged into the other buffer, one barrier
+// per chunk.
 template <int T, int P, int M, bool FP64>
 __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_t q1, __bf16* th, __bf16* tl,
                                            int lane, int wave, v4f (&acc)[TileMap<T, P>::S],
                                            double (&accd)[FP64 ? TileMap<T, P>::S : 1][4]) {
     constexpr int S = TileMap<T, P>::S;
+    constexpr int TS = 16 * T * kGramLDP;     // elements per buffer
     v4f rv[M == kVec ? gramb_nt<T>() : 1][8];
     float rd[M == kDense ? 8 * gramd_nt<T>() : 1];
     float rs[M == kScalar ? gram_nr<T>() : 1];
-    if (q0 < q1) {
-        if constexpr (M == kVec) gramb_fetch<T>(d, q0, q1, rv);
-        else if constexpr (M == kDense) gramd_fetch<T>(d, q0, q1, rd);
-        else gram_fetch<T, kScalar>(d, q0, q1, rs);
-    }
+    auto fetch = [&](int64_t q) {
+        if constexpr (M == kVec) gramb_fetch<T>(d, q, q1, rv);
+        else if constexpr (M == kDense) gramd_fetch<T>(d, q, q1, rd);
+        else gram_fetch<T, kScalar>(d, q, q1, rs);
+    };
+    auto stage = [&](int b) {
+        if constexpr (M == kVec) gramb_stage<T>(th + b * TS, tl + b * TS, rv);
+        else if constexpr (M == kDense) gramd_stage<T>(th + b * TS, tl + b * TS, d.p, d.pmag, rd);
+        else gramb_stage_scalar<T>(th + b * TS, tl + b * TS, rs);
+    };
+    if (q0 >= q1) return;
+    fetch(q0);
+    stage(0);
+    __syncthreads();
+    int cur = 0;
     for (int64_t q = q0; q < q1; q += kGramKB) {
-        __syncthreads();
-        if constexpr (M == kVec) gramb_stage<T>(th, tl, rv);
-        else if constexpr (M == kDense) gramd_stage<T>(th, tl, d.p, d.pmag, rd);
-        else gramb_stage_scalar<T>(th, tl, rs);
-        __syncthreads();
-        if (q + kGramKB < q1) {
-            if constexpr (M == kVec) gramb_fetch<T>(d, q + kGramKB, q1, rv);
-            else if constexpr (M == kDense) gramd_fetch<T>(d, q + kGramKB, q1, rd);
-            else gram_fetch<T, kScalar>(d, q + kGramKB, q1, rs);
-        }
+        const bool more = q + kGramKB < q1;
+        if (more) fetch(q + kGramKB);
+        const __bf16* h = th + cur * TS;
+        const __bf16* l = tl + cur * TS;
         switch (wave) {
-            case 0: gramb_wave<T, P, 0>(th, tl, lane, acc); break;
-            case 1: gramb_wave<T, P, 1>(th, tl, lane, acc); break;
-            case 2: gramb_wave<T, P, 2>(th, tl, lane, acc); break;
-            case 3: gramb_wave<T, P, 3>(th, tl, lane, acc); break;
-            case 4: gramb_wave<T, P, 4>(th, tl, lane, acc); break;
-            case 5: gramb_wave<T, P, 5>(th, tl, lane, acc); break;
-            case 6: gramb_wave<T, P, 6>(th, tl, lane, acc); break;
-            default: gramb_wave<T, P, 7>(th, tl, lane, acc); break;
+            case 0: gramb_wave<T, P, 0>(h, l, lane, acc); break;
+            case 1: gramb_wave<T, P, 1>(h, l, lane, acc); break;
+            case 2: gramb_wave<T, P, 2>(h, l, lane, acc); break;
+            case 3: gramb_wave<T, P, 3>(h, l, lane, acc); break;
+            case 4: gramb_wave<T, P, 4>(h, l, lane, acc); break;
+            case 5: gramb_wave<T, P, 5>(h, l, lane, acc); break;
+            case 6: gramb_wave<T, P, 6>(h, l, lane, acc); break;
+            default: gramb_wave<T, P, 7>(h, l, lane, acc); break;
         }
+        // the other buffer was last read before the previous barrier
+        if (more) stage(cur ^ 1);
         if constexpr (FP64) {
 #pragma unroll
             for (int q2 = 0; q2 < S; ++q2) {
@@ -473,6 +483,8 @@ __device__ __forceinline__ void gramb_slot(const CubeDesc& d, int64_t q0, int64_
                 acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
             }
         }
+        __syncthreads();
+        cur ^= 1;
     }
 }
 
@@ -490,8 +502,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
     constexpr int NT = TM::NT;
     constexpr int S = TM::S;
     constexpr bool FP64 = T < kGramSplitT;
-    __shared__ __attribute__((aligned(16))) __bf16 th[16 * T * kGramLDP];
-    __shared__ __attribute__((aligned(16))) __bf16 tl[16 * T * kGramLDP];
+    __shared__ __attribute__((aligned(16))) __bf16 th[2 * 16 * T * kGramLDP];
+    __shared__ __attribute__((aligned(16))) __bf16 tl[2 * 16 * T * kGramLDP];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int total = items[ncubes];

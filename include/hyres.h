@@ -216,9 +216,10 @@ typedef struct {
  * persistent launches (each kernel class is one launch over a prefix-summed
  * list of work items spanning every cube of the class), with the noise
  * regression and eigensolve of every cube in one launch per band-count class.
- * The cubes run in up to four groups by band-count class, each on one of the
- * handle's side streams (forked from and joined back into the caller's
- * stream), a group's Gram stage after the previous group's, so that one
+ * The cubes run in up to four groups by band-count class, the first on the
+ * caller's stream and the others on the handle's side streams (forked from
+ * and joined back into it), a group's Gram stage after the previous group's,
+ * so that one
  * group's eigensolves overlap the other groups' bandwidth-bound stages.
  * Each cube's results equal those of hyres_denoise on that cube alone.
  * All cubes share dtype and opt's precision, scope and flags (opt's rank and

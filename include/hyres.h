@@ -219,8 +219,8 @@ typedef struct {
  * The cubes run in up to four groups by band-count class, the first on the
  * caller's stream and the others on the handle's side streams (forked from
  * and joined back into it), a group's Gram stage after the previous group's,
- * so that one
- * group's eigensolves overlap the other groups' bandwidth-bound stages.
+ * so that one group's eigensolves overlap the other groups' bandwidth-bound
+ * stages.
  * Each cube's results equal those of hyres_denoise on that cube alone.
  * All cubes share dtype and opt's precision, scope and flags (opt's rank and
  * levels are not used: each cube carries its own). */

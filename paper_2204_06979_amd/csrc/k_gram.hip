@@ -160,29 +160,38 @@ __device__ __forceinline__ void gram_stage(float* __restrict__ tile, const CubeD
     }
 }
 
-// The FP32 partial Gram of pixels [q0, q1) of one slot (load path M).
+// The FP32 partial Gram of pixels [q0, q1) of one slot (load path M).  The
+// chunk tile is double-buffered (`tile` holds two of kGramKB x LDW floats):
+// the next chunk is staged while the matrix cores read the current one, one
+// barrier per chunk.
 template <int T, int P, int M>
 __device__ __forceinline__ void gram_slot(const CubeDesc& d, int64_t q0, int64_t q1, float* tile, int lane,
                                           int wave, v4f (&acc)[TileMap<T, P>::S],
                                           double (&accd)[TileMap<T, P>::S][4]) {
     constexpr int S = TileMap<T, P>::S;
+    constexpr int TS = kGramKB * gram_ldw<T>();
     float rg[gram_nr<T>()];
-    if (q0 < q1) gram_fetch<T, M>(d, q0, q1, rg);
+    if (q0 >= q1) return;
+    gram_fetch<T, M>(d, q0, q1, rg);
+    gram_stage<T, M>(tile, d, rg);
+    __syncthreads();
+    int cur = 0;
     for (int64_t q = q0; q < q1; q += kGramKB) {
-        __syncthreads();
-        gram_stage<T, M>(tile, d, rg);
-        __syncthreads();
-        if (q + kGramKB < q1) gram_fetch<T, M>(d, q + kGramKB, q1, rg);   // overlaps the MFMAs
+        const bool more = q + kGramKB < q1;
+        if (more) gram_fetch<T, M>(d, q + kGramKB, q1, rg);   // overlaps the MFMAs
+        const float* tb = tile + cur * TS;
         switch (wave) {
-            case 0: gram_wave<T, P, 0>(tile, lane, acc); break;
-            case 1: gram_wave<T, P, 1>(tile, lane, acc); break;
-            case 2: gram_wave<T, P, 2>(tile, lane, acc); break;
-            case 3: gram_wave<T, P, 3>(tile, lane, acc); break;
-            case 4: gram_wave<T, P, 4>(tile, lane, acc); break;
-            case 5: gram_wave<T, P, 5>(tile, lane, acc); break;
-            case 6: gram_wave<T, P, 6>(tile, lane, acc); break;
-            default: gram_wave<T, P, 7>(tile, lane, acc); break;
+            case 0: gram_wave<T, P, 0>(tb, lane, acc); break;
+            case 1: gram_wave<T, P, 1>(tb, lane, acc); break;
+            case 2: gram_wave<T, P, 2>(tb, lane, acc); break;
+            case 3: gram_wave<T, P, 3>(tb, lane, acc); break;
+            case 4: gram_wave<T, P, 4>(tb, lane, acc); break;
+            case 5: gram_wave<T, P, 5>(tb, lane, acc); break;
+            case 6: gram_wave<T, P, 6>(tb, lane, acc); break;
+            default: gram_wave<T, P, 7>(tb, lane, acc); break;
         }
+        // the other buffer was last read before the previous barrier
+        if (more) gram_stage<T, M>(tile + (cur ^ 1) * TS, d, rg);
         // FP32 sums over one chunk only; chunks accumulate in FP64
 #pragma unroll
         for (int q2 = 0; q2 < S; ++q2) {
@@ -190,6 +199,8 @@ __device__ __forceinline__ void gram_slot(const CubeDesc& d, int64_t q0, int64_t
             for (int i = 0; i < 4; ++i) accd[q2][i] += (double)acc[q2][i];
             acc[q2] = v4f{0.f, 0.f, 0.f, 0.f};
         }
+        __syncthreads();
+        cur ^= 1;
     }
 }
 
@@ -202,7 +213,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
     constexpr int LDW = gram_ldw<T>();
     constexpr int NT = TM::NT;
     constexpr int S = TM::S;
-    __shared__ __attribute__((aligned(16))) float tile[kGramKB * LDW];
+    __shared__ __attribute__((aligned(16))) float tile[2 * kGramKB * LDW];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int total = items[ncubes];

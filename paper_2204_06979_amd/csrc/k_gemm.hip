@@ -294,8 +294,6 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
 template <int T>
 __global__ __launch_bounds__(256) void k_blend_f32(const CubeDesc* __restrict__ descs, const BlendGrid g) {
     constexpr int P16 = 16 * T;
-    constexpr int LDO = P16 + 4;
-    __shared__ __attribute__((aligned(16))) float ot[kPixTile * LDO];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15, row = lane >> 4;
@@ -305,7 +303,6 @@ __global__ __launch_bounds__(256) void k_blend_f32(const CubeDesc* __restrict__ 
     const int64_t per = (total + gridDim.x - 1) / gridDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * per;
     const int64_t i1 = i0 + per < total ? i0 + per : total;
-    const uint32_t pmag = descs[0].pmag;
     int cur = -1;
     float bq[4][T];
     for (int64_t item = i0; item < i1; ++item) {
@@ -360,30 +357,18 @@ __global__ __launch_bounds__(256) void k_blend_f32(const CubeDesc* __restrict__ 
                 }
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < T; ++j)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ot[(16 * wave + 4 * row + i) * LDO + 16 * j + col] = acc[j][i];
-        __syncthreads();
+        // straight from the accumulators: 16 lanes store 16 consecutive bands
+        // of one pixel (64 bytes), no staging through LDS
         const int m = g.W - x0 < kPixTile ? g.W - x0 : kPixTile;   // pixels of the run
         float* base = static_cast<float*>(g.X) + (int64_t)y * g.xrow_pitch + (int64_t)x0 * g.xpitch;
-        if (g.xmode == kVec) {
-            const int g4 = p >> 2;
-            for (int e = threadIdx.x; e < m * g4; e += 256) {
-                const int k = e / g4, gg = e - k * g4;
-                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(ot + k * LDO + 4 * gg),
-                                            reinterpret_cast<v4f*>(base + (int64_t)k * g.xpitch + 4 * gg));
-            }
-        } else if (g.xmode == kDense) {
-            for (int e = threadIdx.x; e < m * p; e += 256) {
-                const int k = div_p(e, pmag);
-                __builtin_nontemporal_store(ot[k * LDO + (e - k * p)], base + e);
-            }
-        } else {
-            for (int e = threadIdx.x; e < m * p; e += 256) {
-                const int k = div_p(e, pmag), b = e - k * p;
-                __builtin_nontemporal_store(ot[k * LDO + b], base + (int64_t)k * g.xpitch + b);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int px = 16 * wave + 4 * row + i;
+            if (px < m) {
+                float* dst = base + (int64_t)px * g.xpitch + col;
+#pragma unroll
+                for (int j = 0; j < T; ++j)
+                    if (16 * j + col < p) __builtin_nontemporal_store(acc[j][i], dst + 16 * j);
             }
         }
     }

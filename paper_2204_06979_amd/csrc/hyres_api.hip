@@ -1820,9 +1820,6 @@ HYRES_API hyres_status hyres_denoise_tiled(hyres_handle* h, const void* Y, int H
         for (int i = 0; i < g.ny; ++i) b.sy[i] = g.ay.start[i];
         for (int i = 0; i < g.nx; ++i) b.sx[i] = g.ax.start[i];
         b.X = X; b.xpitch = x_pitch; b.xrow_pitch = x_row_pitch;
-        const bool vec = p % 4 == 0 && x_pitch % 4 == 0 && x_row_pitch % 4 == 0 &&
-                         reinterpret_cast<uintptr_t>(X) % 16 == 0;
-        b.xmode = vec ? kVec : x_pitch == p ? kDense : kScalar;
         x.blend1 = true;
     }
     group_tiles(x);

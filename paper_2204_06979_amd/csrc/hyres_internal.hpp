@@ -119,7 +119,6 @@ struct BlendGrid {
     int ny, nx, th, tw, H, W, p;
     int sy[kMaxTilesAxis], sx[kMaxTilesAxis];   // tile starts along y and x
     void* X; int64_t xpitch, xrow_pitch;        // the output image
-    int xmode;                                  // kVec (16-byte pixel groups), kDense or kScalar writes
 };
 
 // Everything the adjoint kernels need (one cube; passed by value).

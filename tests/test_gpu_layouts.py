@@ -111,8 +111,8 @@ def test_batch_class_with_mixed_layouts(prec):
 @pytest.mark.parametrize("p", [17, 40])
 def test_tiled_layouts_give_bitwise_equal_results(p):
     """Sliding window: a padded cube and padded or windowed outputs (the
-    one-pass blend writes 16-byte pixel groups, unpadded runs or single
-    values) give the contiguous result bitwise."""
+    one-pass blend addresses every pixel through the output's pitches) give
+    the contiguous result bitwise."""
     api = _api()
     H, W, r, L, tile, ov = 150, 200, 3, 2, 96, 16
     Y = _cube(900 + p, H, W, p, r, L)

@@ -67,9 +67,11 @@ typedef enum { HYRES_F32 = 0, HYRES_F64 = 1 } hyres_dtype;
 
 typedef enum {
     HYRES_PREC_NATIVE = 0,    /* every large product in the element type (FP32 or FP64) */
-    HYRES_PREC_MIXED = 1      /* FP32 cubes only: Gram, projection and back-projection on
-                                 BF16 MFMA (hi/lo split operands, FP32 accumulation), one
-                                 FP32 refinement pass of the subspace, FP64 small solves */
+    HYRES_PREC_MIXED = 1      /* FP32 cubes only: band Gram from split-BF16 MFMA products
+                                 (hi/lo operands, FP32 accumulation, FP64 across chunks);
+                                 FP64 noise regression and eigensolve; FP32 MFMA projection
+                                 and back-projection; one FP32 Rayleigh-Ritz refinement of
+                                 the subspace (r x r FP64 eigensolve of the projected Gram) */
 } hyres_precision;
 
 typedef enum {
@@ -132,6 +134,10 @@ int64_t hyres_coeff_count(int H, int W, int L);
 
 /* ---- noise estimation (regression of each band on the others) ----------- */
 
+/* Defined by: Section 2.1 -- HyRes removes Gaussian noise and is parameter-free,
+ * so the per-band noise level is estimated from the cube; the estimator is the
+ * multiple-regression one of HySime, which the same section names as part of
+ * the toolbox. */
 /* sigma_i^2 = RSS_i / n where RSS_i is the residual of the least-squares
  * regression, without intercept, of band i on the other p-1 bands, n = H*W.
  * Computed from the FP64 band Gram G = Y^T Y as 1 / (n [G^-1]_ii).
@@ -144,6 +150,8 @@ hyres_status hyres_estimate_noise(hyres_handle* h, const void* Y, int H, int W, 
 
 /* ---- spectral subspace -------------------------------------------------- */
 
+/* Defined by: Section 2.1 -- HyRes is a low-rank method: the cube is modelled
+ * in the span of the leading eigenvectors of the whitened band Gram. */
 /* Eigendecomposition of the whitened Gram C = D^-1 Y^T Y D^-1, D = diag(sigma)
  * (sigma == NULL means D = I).  V_out receives the top-r eigenvectors
  * (column-major p x r, sign rule as in hyres_outputs), evals_out all p
@@ -157,6 +165,8 @@ hyres_status hyres_subspace(hyres_handle* h, const void* Y, int H, int W, int p,
 
 /* ---- wavelet transforms ------------------------------------------------- */
 
+/* Defined by: Section 2.1 -- HyRes is wavelet-based: every component image is
+ * represented by its 2-D orthogonal wavelet coefficients. */
 /* Forward L-level periodised 2-D db2 transform of `batch` images x[batch][H][W]
  * (contiguous) into coeffs[batch][Nc], Nc = hyres_coeff_count(H, W, L).  An
  * odd length is extended by repeating its last sample before each step. */
@@ -173,6 +183,9 @@ hyres_status hyres_idwt2(hyres_handle* h, const void* coeffs, int batch, int H, 
 
 /* ---- SURE threshold ----------------------------------------------------- */
 
+/* Defined by: Section 2.1 -- HyRes is parameter-free: the per-component
+ * threshold is not a user parameter but the minimiser of Stein's unbiased
+ * risk estimate. */
 /* For each of `batch` coefficient vectors of length Nc (stride `stride`
  * elements) the exact minimiser, over t in {0} U {|b_k|}, of Stein's unbiased
  * risk estimate of soft thresholding at unit noise,
@@ -186,6 +199,9 @@ hyres_status hyres_sure_threshold(hyres_handle* h, const void* coeffs, int batch
 
 /* ---- the whole denoiser ------------------------------------------------- */
 
+/* Defined by: Section 2.1 (the HyRes method) and Section 3 (a cube resident on
+ * the GPU is processed there; Table 1 times this solve on the Houston 2013
+ * cube, Table 2 gives its energy). */
 /* X = HyRes(Y).  sigma_in (device [p]) and lambda_in (device [r]) override the
  * estimates when not NULL.  X has its own pitch and row pitch (same rules as
  * Y) and must not overlap Y. */
@@ -200,6 +216,9 @@ hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int W, int p,
 
 /* ---- batches of cubes ---------------------------------------------------- */
 
+/* Defined by: Section 3 (device residency) applied to many cubes at once; the
+ * paper times one cube per call, the batch is an execution form of the same
+ * solve (each cube's result is that of hyres_denoise). */
 /* One cube of a batch.  The struct itself is host memory; Y, X, sigma_in,
  * lambda_in and the pointers in `out` are device pointers with the meaning
  * they have in hyres_denoise.  Cubes may differ in H, W, p, rank and levels. */
@@ -251,6 +270,9 @@ hyres_status hyres_denoise_batched(hyres_handle* h, const hyres_cube* cubes, int
 
 /* ---- sliding-window denoising ------------------------------------------- */
 
+/* Defined by: Section 2.2.2 -- large cubes are denoised in spatial sections by
+ * a sliding window, and the sections are blended into one output (the paper
+ * uses it for network inference; here every section is a HyRes solve). */
 /* Tile starts along an axis of length `size`: 0, tile - overlap, 2 (tile -
  * overlap), ..., the last start clamped to size - tile so that the last tile
  * ends at the border (one tile at 0 when tile >= size).  starts: host array of
@@ -282,6 +304,11 @@ hyres_status hyres_denoise_tiled(hyres_handle* h, const void* Y, int H, int W, i
 
 /* ---- adjoint (reverse-mode derivative) ----------------------------------- */
 
+/* Defined by: Section 2.2 -- a HyRes step is trained inside a network (the
+ * MemNet variant with a trainable HyRes step before its layers), which needs
+ * the derivative of the solve with respect to its input and thresholds.
+ * Forward solves in HYRES_PREC_MIXED are refused (HYRES_E_UNSUPPORTED): their
+ * Ritz basis is not an eigenbasis of the Gram the adjoint differentiates. */
 /* Vector-Jacobian product of X = HyRes(Y; lambda) with the thresholds held as
  * inputs: given dX (same layout rules as Y) it writes dY = (dX/dY)^T dX
  * (through the noise estimate, the whitening, the eigenvectors, the
@@ -320,6 +347,8 @@ hyres_status hyres_sure_grad(hyres_handle* h, const void* coeffs, int batch, int
 
 /* ---- DWT tile autotuner -------------------------------------------------- */
 
+/* An execution aid with no counterpart in the paper: it changes launch shapes
+ * only, never a result. */
 /* Chooses, for every (element type, direction, level-width class) that the
  * batch's transforms use, the workgroup tile shape of the transform kernels
  * (64x4, 32x8, 16x16 or 128x2 threads) that runs fastest.  A level of width w
@@ -336,6 +365,33 @@ hyres_status hyres_autotune(hyres_handle* h, hyres_batch* batch, const char* cac
  * from the tuner or its cache, 0 for the built-in choice). */
 hyres_status hyres_tile_choice(hyres_handle* h, int dtype, int inverse, int width, int* tx, int* ty,
                                int* tuned);
+
+/* ---- host-only checks of a launch program ------------------------------- */
+
+/* What a launch program enqueues (counts over one solve). */
+typedef struct {
+    int launches;   /* kernel launches */
+    int records;    /* event records */
+    int waits;      /* stream waits on events */
+    int streams;    /* streams used, the caller's included */
+    int groups;     /* cube groups */
+} hyres_program_stats;
+
+/* Plans the launch program of a batch (only the shape fields, rank, levels and
+ * lambda_in of `cubes` are read; no pointer is dereferenced) or of a tile grid
+ * and walks it without touching a device, checking its stream order: every
+ * wait on an event follows a record of that event in the same program (a wait
+ * on an older record would, inside a graph capture, depend on work outside
+ * the capture), every side stream first waits on an event of the caller's
+ * stream and ends with a record that the caller's stream waits on.  Returns
+ * HYRES_E_HIP when the order breaks one of these rules, a planning error as
+ * the matching create call would, and fills `stats` (may be NULL).  The
+ * executor applies the same record-before-wait rule at run time and refuses
+ * (HYRES_E_HIP) to enqueue a program that breaks it. */
+hyres_status hyres_batch_check_program(const hyres_cube* cubes, int count, int dtype,
+                                       const hyres_options* opt, hyres_program_stats* stats);
+hyres_status hyres_tiled_check_program(int H, int W, int p, int tile, int overlap,
+                                       const hyres_options* opt, int dtype, hyres_program_stats* stats);
 
 /* ---- stage timing (benchmarks) ------------------------------------------ */
 

@@ -41,6 +41,11 @@ class Cube(C.Structure):
                 ("out", Outputs)]
 
 
+class ProgramStats(C.Structure):
+    _fields_ = [("launches", C.c_int), ("records", C.c_int), ("waits", C.c_int), ("streams", C.c_int),
+                ("groups", C.c_int)]
+
+
 vp, i32, i64, sz, dp = C.c_void_p, C.c_int, C.c_int64, C.c_size_t, C.c_void_p
 PI = C.POINTER(C.c_int)
 
@@ -82,6 +87,9 @@ SIGNATURES = {
                                      C.POINTER(Outputs), vp, i64, i64, vp, i64, i64, dp, vp, vp, sz, vp]),
     "hyres_sure_grad_workspace_size": (i32, [i32, i64, C.POINTER(sz)]),
     "hyres_sure_grad": (i32, [vp, vp, i32, i64, i64, i32, dp, dp, vp, sz, vp]),
+    "hyres_batch_check_program": (i32, [C.POINTER(Cube), i32, i32, C.POINTER(Options), C.POINTER(ProgramStats)]),
+    "hyres_tiled_check_program": (i32, [i32, i32, i32, i32, i32, C.POINTER(Options), i32,
+                                        C.POINTER(ProgramStats)]),
 }
 
 

@@ -780,89 +780,260 @@ hyres_status upload_exec(const Exec& x, hipStream_t s) {
     return HYRES_OK;
 }
 
-// Enqueues the program; `timed` wraps each stage in the handle's stage timers.
-// Consecutive small-solve launches (one per band-count class, each a handful of
-// workgroups) run beside each other: the first on `s`, the others on the
-// handle's side streams, forked from and joined back into `s` by events (a
-// capture of `s` records them as parallel branches).
-hyres_status run_grouped(const Exec& x, hipStream_t s, bool timed) {
+// Stream and event operations of a launch program.  A program names streams
+// by slot (0: the caller's stream, k >= 1: the handle's side stream k - 1) and
+// events by id (kEvFork, kEvJoin + k, kEvChain + k).  HipOps issues them;
+// DryOps only records them, for the host-side check of a program.
+constexpr int kEvFork = 0;
+constexpr int kEvJoin = 1;
+constexpr int kEvChain = 1 + hyres_handle::kSide;
+constexpr int kNumEv = 1 + 2 * hyres_handle::kSide;
+
+struct StreamOps {
+    virtual ~StreamOps() {}
+    virtual hipError_t record(int ev, int slot) = 0;
+    virtual hipError_t wait(int slot, int ev) = 0;
+    virtual hipError_t launch(const Launch& L, int slot) = 0;
+    virtual hipStream_t stream(int slot) = 0;   // null in a dry run
+};
+
+struct HipOps : StreamOps {
+    const Exec& x;
+    hipStream_t s;
+    bool capturing;   // the caller's stream is being captured into a graph
+    HipOps(const Exec& x_, hipStream_t s_, bool cap) : x(x_), s(s_), capturing(cap) {}
+    hipEvent_t event(int ev) const {
+        hyres_handle* h = x.h;
+        return ev == kEvFork ? h->fork : ev < kEvChain ? h->join[ev - kEvJoin] : h->chain[ev - kEvChain];
+    }
+    hipStream_t stream(int slot) override { return slot == 0 ? s : x.h->side[slot - 1]; }
+    // Under capture every enqueue must leave the stream in an active capture
+    // (a dependency the capture cannot represent invalidates it).
+    hipError_t captured(int slot) {
+        if (!capturing) return hipSuccess;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(stream(slot), &cs);
+        if (e != hipSuccess) return e;
+        return cs == hipStreamCaptureStatusActive ? hipSuccess : hipErrorStreamCaptureInvalidated;
+    }
+    hipError_t record(int ev, int slot) override {
+        hipError_t e = hipEventRecord(event(ev), stream(slot));
+        return e != hipSuccess ? e : captured(slot);
+    }
+    hipError_t wait(int slot, int ev) override {
+        hipError_t e = hipStreamWaitEvent(stream(slot), event(ev), 0);
+        return e != hipSuccess ? e : captured(slot);
+    }
+    hipError_t launch(const Launch& L, int slot) override {
+        hipError_t e = launch_one(x, L, stream(slot));
+        return e != hipSuccess ? e : captured(slot);
+    }
+};
+
+struct DryOps : StreamOps {
+    struct Op { char kind; int a, b; };   // 'r' (event a on slot b), 'w' (slot a waits on event b), 'l' (slot a)
+    std::vector<Op> ops;
+    hipError_t record(int ev, int slot) override { ops.push_back({'r', ev, slot}); return hipSuccess; }
+    hipError_t wait(int slot, int ev) override { ops.push_back({'w', slot, ev}); return hipSuccess; }
+    hipError_t launch(const Launch&, int slot) override { ops.push_back({'l', slot, 0}); return hipSuccess; }
+    hipStream_t stream(int) override { return nullptr; }
+};
+
+// Enqueues a program through `ops`, refusing any wait on an event that the
+// program has not recorded before it (such a wait would depend on whatever an
+// earlier call left in the event, and inside a graph capture on work outside
+// the capture).  Side streams that were forked are joined back into the
+// caller's stream on every return, errors included, so that a capture can
+// always be ended.
+struct ProgramRun {
+    const Exec& x;
+    StreamOps& ops;
+    bool rec[kNumEv] = {};
+    bool forked[hyres_handle::kSide + 1] = {};
+    ProgramRun(const Exec& x_, StreamOps& o) : x(x_), ops(o) {}
+    hyres_status record(int ev, int slot) {
+        if (ops.record(ev, slot) != hipSuccess) return HYRES_E_HIP;
+        rec[ev] = true;
+        return HYRES_OK;
+    }
+    hyres_status wait(int slot, int ev) {
+        if (!rec[ev]) return HYRES_E_HIP;
+        return ops.wait(slot, ev) != hipSuccess ? HYRES_E_HIP : HYRES_OK;
+    }
+    hyres_status fork(int slot) {
+        hyres_status st = wait(slot, kEvFork);
+        if (!st) forked[slot] = true;
+        return st;
+    }
+    // joins every forked side stream that is still apart into slot 0
+    hyres_status join_all() {
+        hyres_status first = HYRES_OK;
+        for (int k = 1; k <= hyres_handle::kSide; ++k) {
+            if (!forked[k]) continue;
+            hyres_status st = record(kEvJoin + k - 1, k);
+            if (!st) st = wait(0, kEvJoin + k - 1);
+            if (st && !first) first = st;
+            forked[k] = false;
+        }
+        return first;
+    }
+    hyres_status finish(hyres_status st) {
+        hyres_status j = join_all();
+        return st ? st : j;
+    }
+    hyres_status launch(const Launch& L, int slot) {
+        return ops.launch(L, slot) != hipSuccess ? HYRES_E_HIP : HYRES_OK;
+    }
+};
+
+// Cube groups: each group runs on its own stream (group 0 on the caller's),
+// forked from the caller's stream; group g's first launch waits for the end
+// of group g - 1's Gram stage; the joint launches (grp < 0) run on the
+// caller's stream after every group has been joined back.
+hyres_status run_grouped(const Exec& x, StreamOps& ops, bool timed) {
     hyres_handle* h = x.h;
     const int G = x.ngroups;
-    auto stream_of = [&](int g) { return g <= 0 ? s : h->side[g - 1]; };
+    ProgramRun pr(x, ops);
     // stage timers per group, on the group's stream (slot G: the joint launches)
     std::unique_ptr<StageTimer> tm[kMaxGroups + 1];
     int cur[kMaxGroups + 1];
     for (int g = 0; g <= G; ++g) cur[g] = -1;
-    HIPCHK(hipEventRecord(h->fork, s));
-    for (int g = 1; g < G; ++g) HIPCHK(hipStreamWaitEvent(h->side[g - 1], h->fork, 0));
+    hyres_status st = pr.record(kEvFork, 0);
+    for (int g = 1; g < G && !st; ++g) st = pr.fork(g);
     int prev = 0;
     bool joined = false;
-    auto join_all = [&]() -> hyres_status {
-        for (int g = 0; g < G; ++g) tm[g].reset();
-        for (int g = 1; g < G; ++g) {
-            HIPCHK(hipEventRecord(h->join[g - 1], h->side[g - 1]));
-            HIPCHK(hipStreamWaitEvent(s, h->join[g - 1], 0));
-        }
-        joined = true;
-        return HYRES_OK;
-    };
-    for (const Launch& L : x.prog) {
+    for (size_t k = 0; k < x.prog.size() && !st; ++k) {
+        const Launch& L = x.prog[k];
         if (L.grp < 0 && !joined) {
-            hyres_status st = join_all();
-            if (st) return st;
+            for (int g = 0; g < G; ++g) tm[g].reset();
+            if ((st = pr.join_all())) break;
+            joined = true;
         }
         if (L.grp > prev) {
             // this group's Gram stage follows the previous group's
-            HIPCHK(hipStreamWaitEvent(stream_of(L.grp), h->chain[L.grp - 1], 0));
+            if ((st = pr.wait(L.grp, kEvChain + L.grp - 1))) break;
             prev = L.grp;
         }
-        const hipStream_t a = L.grp < 0 ? s : stream_of(L.grp);
-        const int slot = L.grp < 0 ? G : L.grp;
-        if (timed && L.stage != cur[slot]) {
-            tm[slot].reset();
-            tm[slot].reset(new StageTimer(h, a, L.stage));
-            cur[slot] = L.stage;
+        const int slot = L.grp < 0 ? 0 : L.grp;
+        const int tslot = L.grp < 0 ? G : L.grp;
+        if (timed && ops.stream(slot) && L.stage != cur[tslot]) {
+            tm[tslot].reset();
+            tm[tslot].reset(new StageTimer(h, ops.stream(slot), L.stage));
+            cur[tslot] = L.stage;
         }
-        HIPCHK(launch_one(x, L, a));
-        if (L.chain && L.grp >= 0 && L.grp + 1 < G) HIPCHK(hipEventRecord(h->chain[L.grp], a));
+        if ((st = pr.launch(L, slot))) break;
+        if (L.chain && L.grp >= 0 && L.grp + 1 < G) st = pr.record(kEvChain + L.grp, slot);
     }
-    tm[G].reset();
-    if (!joined) return join_all();
-    return HYRES_OK;
+    for (int g = 0; g <= G; ++g) tm[g].reset();
+    return pr.finish(st);
 }
 
-hyres_status run_program(const Exec& x, hipStream_t s, bool timed) {
+// Enqueues the program; `timed` wraps each stage in the handle's stage timers.
+// Consecutive small-solve launches (one per band-count class, each a handful of
+// workgroups) run beside each other: the first on the caller's stream, the
+// others on the handle's side streams, forked from and joined back into it by
+// events (a capture of the caller's stream records them as parallel branches).
+hyres_status run_program(const Exec& x, StreamOps& ops, bool timed) {
     if (x.h) ++x.h->runs;
-    if (x.ngroups > 1 && x.h) return run_grouped(x, s, timed);
+    if (x.ngroups > 1 && x.h) return run_grouped(x, ops, timed);
+    ProgramRun pr(x, ops);
     std::unique_ptr<StageTimer> tm;
     int cur = -1;
     const size_t np = x.prog.size();
-    for (size_t k = 0; k < np; ++k) {
+    hyres_status st = HYRES_OK;
+    for (size_t k = 0; k < np && !st; ++k) {
         const Launch& L = x.prog[k];
-        if (timed && L.stage != cur) {
+        if (timed && ops.stream(0) && L.stage != cur) {
             tm.reset();
-            tm.reset(new StageTimer(x.h, s, L.stage));
+            tm.reset(new StageTimer(x.h, ops.stream(0), L.stage));
             cur = L.stage;
         }
         size_t m = 1;
         if (L.kind == K_SMALL && x.h && x.ngroups <= 1)
             while (k + m < np && m <= (size_t)hyres_handle::kSide && x.prog[k + m].kind == K_SMALL) ++m;
         if (m == 1) {
-            HIPCHK(launch_one(x, L, s));
+            st = pr.launch(L, 0);
             continue;
         }
-        HIPCHK(hipEventRecord(x.h->fork, s));
-        for (size_t i = 1; i < m; ++i) {
-            hipStream_t a = x.h->side[i - 1];
-            HIPCHK(hipStreamWaitEvent(a, x.h->fork, 0));
-            HIPCHK(launch_one(x, x.prog[k + i], a));
-            HIPCHK(hipEventRecord(x.h->join[i - 1], a));
+        if ((st = pr.record(kEvFork, 0))) break;
+        for (size_t i = 1; i < m && !st; ++i) {
+            if ((st = pr.fork((int)i))) break;
+            st = pr.launch(x.prog[k + i], (int)i);
         }
-        HIPCHK(launch_one(x, L, s));
-        for (size_t i = 1; i < m; ++i) HIPCHK(hipStreamWaitEvent(s, x.h->join[i - 1], 0));
+        if (!st) st = pr.launch(L, 0);
+        if (!st) st = pr.join_all();
         k += m - 1;
     }
+    tm.reset();
+    return pr.finish(st);
+}
+
+hyres_status run_program(const Exec& x, hipStream_t s, bool timed, bool capturing = false) {
+    HipOps ops(x, s, capturing);
+    return run_program(x, ops, timed);
+}
+
+// Host-side check of a program's stream order (no device is touched): the
+// program is run through DryOps, which refuses a wait on an event not yet
+// recorded; then every side stream must start with a wait (it joins the
+// caller's dependency chain) and end with a join record that the caller's
+// stream waits on, with nothing enqueued on the side stream after it.
+hyres_status dry_check(const Exec& x, hyres_program_stats* stats) {
+    DryOps ops;
+    hyres_status st = run_program(x, ops, false);
+    if (st) return st;
+    const auto& v = ops.ops;
+    int n_l = 0, n_r = 0, n_w = 0, used = 1;
+    for (int k = 1; k <= hyres_handle::kSide; ++k) {
+        int first = -1, last = -1;
+        for (int i = 0; i < (int)v.size(); ++i) {
+            const int slot = v[i].kind == 'r' ? v[i].b : v[i].a;
+            if (slot != k) continue;
+            if (first < 0) first = i;
+            last = i;
+        }
+        if (first < 0) continue;
+        ++used;
+        if (v[first].kind != 'w') return HYRES_E_HIP;
+        if (v[last].kind != 'r') return HYRES_E_HIP;
+        const int ev = v[last].a;
+        bool waited = false;
+        for (int i = last + 1; i < (int)v.size(); ++i) {
+            if (v[i].kind == 'r' && v[i].a == ev) break;          // re-recorded before any wait
+            if (v[i].kind == 'w' && v[i].a == 0 && v[i].b == ev) {
+                waited = true;
+                break;
+            }
+        }
+        if (!waited) return HYRES_E_HIP;
+    }
+    for (const auto& o : v) {
+        n_l += o.kind == 'l';
+        n_r += o.kind == 'r';
+        n_w += o.kind == 'w';
+    }
+    if (stats) {
+        stats->launches = n_l;
+        stats->records = n_r;
+        stats->waits = n_w;
+        stats->streams = used;
+        stats->groups = x.ngroups;
+    }
     return HYRES_OK;
+}
+
+// A handle with no device behind it, for host-only planning.
+void init_host_handle(hyres_handle& h) {
+    h.device = -1;
+    h.num_cu = 256;
+    h.prof_mask = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int w = 0; w < kWidthClasses; ++w) {
+                h.tile[a][b][w] = (unsigned char)default_tile(w);
+                h.tuned[a][b][w] = 0;
+                h.tile_us[a][b][w] = 0.f;
+            }
 }
 
 bool valid_dtype(int dt) { return dt == HYRES_F32 || dt == HYRES_F64; }
@@ -1436,7 +1607,7 @@ HYRES_API hyres_status hyres_batch_launch_graph(hyres_batch* b, hyres_stream_t s
     if (!b->exec) {
         if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-        st = run_program(b->x, b->cap, false);
+        st = run_program(b->x, b->cap, false, true);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->cap, &g);
         if (st || e != hipSuccess) {
@@ -1466,6 +1637,25 @@ HYRES_API hyres_status hyres_denoise_batched(hyres_handle* h, const hyres_cube* 
     return st;
 }
 
+HYRES_API hyres_status hyres_batch_check_program(const hyres_cube* cubes, int count, int dtype,
+                                                 const hyres_options* opt, hyres_program_stats* stats) {
+    hyres_handle h;
+    init_host_handle(h);
+    Exec x;
+    hyres_status st = plan_batch(x, &h, cubes, count, dtype, opt, false);
+    if (st) return st;
+    x.desc.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const hyres_cube& k = cubes[i];
+        hyres_outputs o{};
+        x.desc[i] = solve_desc(x.plan[i], nullptr, nullptr, k.p, (int64_t)k.W * k.p, nullptr, k.p,
+                               (int64_t)k.W * k.p, nullptr, k.lambda_in, opt->flags, &o);
+    }
+    group_by_small_class(x);
+    build_program(x, kAllStages);
+    return dry_check(x, stats);
+}
+
 // ------------------------------------------------------------- adjoint
 namespace {
 
@@ -1486,6 +1676,9 @@ hyres_status plan_backward(BwdPlan& b, hyres_handle* h, int H, int W, int p, con
     if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
     hyres_status st = check_opts(opt, p, dtype);
     if (st) return st;
+    // a mixed-precision forward keeps a Rayleigh-Ritz basis that is not an
+    // eigenbasis of the Gram the eigen-adjoint differentiates
+    if (opt->precision == HYRES_PREC_MIXED) return HYRES_E_UNSUPPORTED;
     one_cube(b.fwd, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
     if ((st = plan_cubes(b.fwd, kAllParts))) return st;
     const CubePlan& c = b.fwd.plan[0];
@@ -1833,6 +2026,30 @@ HYRES_API hyres_status hyres_denoise_tiled(hyres_handle* h, const void* Y, int H
                        at<double>(workspace, g.o_bwx), at<unsigned char>(workspace, g.o_bcx));
     HIPCHK(hipGetLastError());
     return run_program(x, s, true);
+}
+
+HYRES_API hyres_status hyres_tiled_check_program(int H, int W, int p, int tile, int overlap,
+                                                 const hyres_options* opt, int dtype, hyres_program_stats* stats) {
+    hyres_handle h;
+    init_host_handle(h);
+    Exec x;
+    TileGrid g;
+    hyres_status st = plan_tiled(x, g, &h, H, W, p, tile, overlap, opt, dtype);
+    if (st) return st;
+    x.desc.resize(x.count);
+    for (int t = 0; t < x.count; ++t) {
+        hyres_outputs o{};
+        x.desc[t] = solve_desc(x.plan[t], nullptr, nullptr, p, (int64_t)W * p, nullptr, p, (int64_t)W * p,
+                               nullptr, nullptr, opt->flags, &o);
+        x.desc[t].bpass = x.pass_of[t];
+    }
+    if (dtype == HYRES_F32) {
+        x.bg.ny = g.ny; x.bg.nx = g.nx; x.bg.th = g.th; x.bg.tw = g.tw; x.bg.H = H; x.bg.W = W; x.bg.p = p;
+        x.blend1 = true;
+    }
+    group_tiles(x);
+    build_program(x, kAllStages);
+    return dry_check(x, stats);
 }
 
 // ------------------------------------------------------------- autotuner

@@ -304,6 +304,90 @@ def test_tile_grid_for_the_sliding_window_workload():
     assert np.all(O.tile_weights_1d(0, 512, 2048, 32)[:32] == 1.0)
 
 
+def test_blend_ramp_is_a_raised_cosine_at_half_sample_phase():
+    # The ramp must give a partition of unity wherever two tiles overlap by
+    # exactly `overlap` samples (the ramp-down of one tile and the ramp-up of
+    # the next cover the same samples): f(k) + f(ov - 1 - k) = 1.  A phase of
+    # k instead of k + 1/2 breaks this, and so does a ramp that reaches 0 or 1.
+    for ov in (8, 32):
+        up = O.tile_weights_1d(1, 4 * ov, 10 * ov, ov)[:ov]          # start > 0: ramp-up only at the front
+        down = O.tile_weights_1d(0, 4 * ov, 10 * ov, ov)[-ov:]       # ends inside the image: ramp-down
+        np.testing.assert_allclose(up + down, 1.0, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(up, down[::-1], rtol=0, atol=0)
+        # strictly inside (0, 1), strictly increasing, mean exactly 1/2
+        assert np.all(up > 0) and np.all(up < 1) and np.all(np.diff(up) > 0)
+        assert abs(up.sum() - ov / 2) < 1e-13
+        # a raised cosine: 2 f - 1 = -cos(pi (k + 1/2) / ov), the Chebyshev
+        # nodes, whose squares sum to ov / 2 (a linear ramp gives about ov / 3)
+        assert abs(((2 * up - 1) ** 2).sum() - ov / 2) < 1e-12
+        # and it has zero slope at both ends in the continuum limit: f(0) is
+        # O(1/ov^2), far below a linear ramp's 1/(2 ov)
+        assert up[0] < 3.0 / ov ** 2
+
+
+def test_blend_weights_sum_to_one_across_every_nominal_overlap_of_the_2048_grid():
+    starts = synth.tile_starts(2048, 512, 32)
+    wsum = np.zeros(2048)
+    for s in starts:
+        wsum[s:s + 512] += O.tile_weights_1d(s, 512, 2048, 32)
+    # tiles 0..3 step by 480, so neighbours overlap by exactly 32 samples; the
+    # clamped last tile (start 1536) overlaps the fourth over 416 samples
+    for s in starts[1:4]:
+        np.testing.assert_allclose(wsum[s:s + 32], 1.0, rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(wsum[:480], 1.0)
+    np.testing.assert_array_equal(wsum[512:960], 1.0)
+    assert np.all(wsum[1568:1920] == 2.0)          # both tiles at full weight
+    # the blended output is still a convex combination: normalised weights
+    # of the tiles covering each sample sum to 1
+    assert np.all(wsum > 0)
+
+
+def test_detail_scope_threshold_minimises_sure_over_the_details_only():
+    cube = synth.config_cube(1)
+    r, L = 4, 3
+    out = O.hyres(cube.Y, r, L, detail_only=True)
+    H, W, _ = cube.Y.shape
+    hL, wL = O.level_shapes(H, W, L)[-1]
+    nd = out["B"].shape[1] - hL * wL
+    for i in range(r):
+        det = out["B"][i, :nd]
+        # brute force over every candidate of the definition, details only
+        cands = np.concatenate([[0.0], np.abs(det)])
+        vals = np.array([O.sure_at(det, t) for t in cands])
+        best = vals.min()
+        assert abs(out["sure"][i] - best) <= 1e-9 * max(1.0, abs(best))
+        assert out["lam"][i] == cands[vals == best].min()
+
+
+def test_detail_scope_keeps_the_coarse_approximation():
+    # With thresholds above every detail magnitude the detail scope keeps only
+    # LL_L: each component image becomes its level-L approximation, an
+    # orthogonal projection (even sizes): idempotent, and the removed part is
+    # orthogonal to it.
+    cube = synth.config_cube(1)
+    r, L = 4, 3
+    base = O.hyres(cube.Y, r, L, detail_only=True)
+    lam = np.abs(base["B"]).max(axis=1) * 2.0
+    out = O.hyres(cube.Y, r, L, lam=lam, detail_only=True)
+    H, W, _ = cube.Y.shape
+    hL, wL = O.level_shapes(H, W, L)[-1]
+    nc = O.coeff_count(H, W, L)
+    Xw = out["X"].reshape(H * W, -1) / out["sigma"]
+    Zh = (Xw @ out["V"]).T.reshape(r, H, W)          # V orthonormal: recovers the denoised images
+    for i in range(r):
+        z = base["Z"][i]
+        c = np.zeros(nc)
+        c[nc - hL * wL:] = O.dwt2(z, L)[nc - hL * wL:]
+        pz = O.idwt2(c, H, W, L)
+        np.testing.assert_allclose(Zh[i], pz, atol=1e-10 * np.abs(z).max())
+        c2 = O.dwt2(pz, L)
+        np.testing.assert_allclose(c2[: nc - hL * wL], 0.0, atol=1e-10 * np.abs(z).max())
+        assert abs(float(((z - pz) * pz).sum())) <= 1e-9 * float((z * z).sum())
+    # and with a zero threshold the detail scope is the plain PCA truncation too
+    out0 = O.hyres(cube.Y, r, L, lam=np.zeros(r), detail_only=True)
+    np.testing.assert_allclose(out0["X"], O.hyres(cube.Y, r, L, lam=np.zeros(r))["X"], atol=1e-11)
+
+
 def test_single_tile_equals_plain():
     cube = synth.config_cube(1)
     out = O.hyres_tiled(cube.Y, 4, 3, 64, 8, [0], [0])

@@ -794,7 +794,8 @@ struct StreamOps {
     virtual hipError_t record(int ev, int slot) = 0;
     virtual hipError_t wait(int slot, int ev) = 0;
     virtual hipError_t launch(const Launch& L, int slot) = 0;
-    virtual hipStream_t stream(int slot) = 0;   // null in a dry run
+    virtual hipStream_t stream(int slot) = 0;   // the stream of a slot (slot 0 may be the null stream)
+    virtual bool live() const = 0;              // enqueues on a device (false: a host-only dry run)
 };
 
 struct HipOps : StreamOps {
@@ -807,6 +808,7 @@ struct HipOps : StreamOps {
         return ev == kEvFork ? h->fork : ev < kEvChain ? h->join[ev - kEvJoin] : h->chain[ev - kEvChain];
     }
     hipStream_t stream(int slot) override { return slot == 0 ? s : x.h->side[slot - 1]; }
+    bool live() const override { return true; }
     // Under capture every enqueue must leave the stream in an active capture
     // (a dependency the capture cannot represent invalidates it).
     hipError_t captured(int slot) {
@@ -837,6 +839,7 @@ struct DryOps : StreamOps {
     hipError_t wait(int slot, int ev) override { ops.push_back({'w', slot, ev}); return hipSuccess; }
     hipError_t launch(const Launch&, int slot) override { ops.push_back({'l', slot, 0}); return hipSuccess; }
     hipStream_t stream(int) override { return nullptr; }
+    bool live() const override { return false; }
 };
 
 // Enqueues a program through `ops`, refusing any wait on an event that the
@@ -916,7 +919,7 @@ hyres_status run_grouped(const Exec& x, StreamOps& ops, bool timed) {
         }
         const int slot = L.grp < 0 ? 0 : L.grp;
         const int tslot = L.grp < 0 ? G : L.grp;
-        if (timed && ops.stream(slot) && L.stage != cur[tslot]) {
+        if (timed && ops.live() && L.stage != cur[tslot]) {
             tm[tslot].reset();
             tm[tslot].reset(new StageTimer(h, ops.stream(slot), L.stage));
             cur[tslot] = L.stage;
@@ -943,7 +946,7 @@ hyres_status run_program(const Exec& x, StreamOps& ops, bool timed) {
     hyres_status st = HYRES_OK;
     for (size_t k = 0; k < np && !st; ++k) {
         const Launch& L = x.prog[k];
-        if (timed && ops.stream(0) && L.stage != cur) {
+        if (timed && ops.live() && L.stage != cur) {
             tm.reset();
             tm.reset(new StageTimer(x.h, ops.stream(0), L.stage));
             cur = L.stage;

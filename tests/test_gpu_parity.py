@@ -275,3 +275,32 @@ def test_noise_flags_nonfinite_and_dependent_bands():
     Y[:, :, 7] = Y[:, :, 3]                       # a duplicated band: the Gram is singular
     _, info = api.denoise(torch.tensor(Y, device="cuda"), 4, 3)
     assert int(info["status"].cpu()[0]) & 1
+
+
+@pytest.mark.parametrize("side_stream", [False, True])
+def test_stage_timers_time_every_stage(side_stream):
+    """The stage timers record every stage of a solve, on torch's default (null)
+    stream as on a stream of its own."""
+    import ctypes as C
+    from paper_2204_06979_amd import _lib as L
+    api = _api()
+    lib = L.lib()
+    cube = synth.mixing_cube(7, 96, 80, 40, 4, 12.0, 3, dtype=np.float32, keep_clean=False)
+    Yt = torch.tensor(cube.Y, device="cuda")
+    h = api._handle(Yt.device)
+    s = torch.cuda.Stream() if side_stream else torch.cuda.default_stream()
+    nst = 7
+    lib.hyres_profile_enable(h, (1 << nst) - 1)
+    try:
+        with torch.cuda.stream(s):
+            api.denoise(Yt, 4, 3)
+            api.denoise(Yt, 4, 3)
+        torch.cuda.synchronize()
+        ms = (C.c_double * nst)()
+        cnt = (C.c_int * nst)()
+        L.check(lib.hyres_profile_read(h, ms, cnt), "profile read")
+    finally:
+        lib.hyres_profile_enable(h, 0)
+    say("stage ms", list(ms), "counts", list(cnt))
+    assert list(cnt) == [2] * nst
+    assert all(m > 0.0 for m in ms)

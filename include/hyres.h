@@ -214,6 +214,31 @@ hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int W, int p,
                            int64_t x_row_pitch, const hyres_outputs* out,
                            void* workspace, size_t workspace_bytes, hyres_stream_t stream);
 
+/* ---- the whole denoiser without a workspace ------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ * hyres_denoise with the same arguments minus the workspace: the scratch is a
+ * fixed array of HYRES_NOALLOC_SCRATCH_BYTES in the library's code object, one
+ * per device, resolved when a handle is created on that device and held until
+ * the process ends.  The call allocates nothing (no hipMalloc, no library
+ * allocation).  Solves whose hyres_denoise_workspace_size exceeds the array
+ * return HYRES_E_WORKSPACE (the 349 x 1905 x 144 cube at rank 8 needs 61 MiB
+ * in FP32 and 71 MiB in mixed precision).  Every call on a device shares that
+ * device's array and leaves its last contents there (the solve rewrites
+ * everything it reads before reading it): calls that overlap on one device,
+ * on different streams or from different handles, race and must be ordered
+ * by the caller.  X, sigma, V, evals, lambda and gap equal hyres_denoise's bit
+ * for bit; the SURE minima agree to rounding (their FP64 sums are formed with
+ * device atomics in either call). */
+#define HYRES_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+hyres_status hyres_denoise_noalloc(hyres_handle* h, const void* Y, int H, int W, int p,
+                                   int64_t pitch, int64_t row_pitch, int dtype,
+                                   const hyres_options* opt, const double* sigma_in,
+                                   const double* lambda_in, void* X, int64_t x_pitch,
+                                   int64_t x_row_pitch, const hyres_outputs* out,
+                                   hyres_stream_t stream);
+
 /* ---- batches of cubes ---------------------------------------------------- */
 
 /* Defined by: Section 3 (device residency) applied to many cubes at once; the

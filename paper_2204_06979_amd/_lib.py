@@ -22,6 +22,7 @@ DEV_NOT_PD, DEV_NONFINITE, DEV_EIGH_NOCONV, DEV_DEGENERATE, DEV_SURE_INEXACT = 1
 
 
 FLAG_ALL_EVALS = 1
+NOALLOC_SCRATCH_BYTES = 96 << 20     # HYRES_NOALLOC_SCRATCH_BYTES
 
 
 class Options(C.Structure):
@@ -69,6 +70,8 @@ SIGNATURES = {
     "hyres_profile_read": (i32, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "hyres_denoise": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp, vp, i64, i64,
                             C.POINTER(Outputs), vp, sz, vp]),
+    "hyres_denoise_noalloc": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp, vp, i64,
+                                    i64, C.POINTER(Outputs), vp]),
     "hyres_batch_workspace_size": (i32, [C.POINTER(Cube), i32, i32, C.POINTER(Options), C.POINTER(sz)]),
     "hyres_batch_create": (i32, [vp, C.POINTER(Cube), i32, i32, C.POINTER(Options), vp, sz, vp,
                                  C.POINTER(C.c_void_p)]),

@@ -228,6 +228,44 @@ def denoise(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
     return X, dn.info()
 
 
+def denoise_noalloc(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
+                    sigma: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
+                    scope: str = "all", out: Optional[Dict[str, torch.Tensor]] = None,
+                    X: Optional[torch.Tensor] = None):
+    """``denoise`` through ``hyres_denoise_noalloc``: the library takes its scratch
+    from a fixed per-device array instead of a workspace.  The caller may pass
+    the output cube ``X`` and the ``out`` tensors (sigma, V (rank x p), evals,
+    lam, sure, gap, status) so that the call itself allocates nothing; those it
+    omits are allocated here, before the call."""
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    dev = Y.device
+    dt = _dtype_code(Y)
+    opt = L.Options(rank, levels, L.PREC_MIXED if precision == "mixed" else L.PREC_NATIVE,
+                    L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL, 0)
+    o = dict(out) if out is not None else {}
+    shapes = dict(sigma=(p,), V=(rank, p), evals=(p,), lam=(rank,), sure=(rank,), gap=(1,))
+    for k, shp in shapes.items():
+        if k not in o:
+            o[k] = torch.empty(shp, dtype=torch.float64, device=dev)
+    if "status" not in o:
+        o["status"] = torch.zeros(1, dtype=torch.int32, device=dev)
+    if X is None:
+        X = torch.empty(H, W, p, dtype=Y.dtype, device=dev)
+    sg = None if sigma is None else sigma.to(device=dev, dtype=torch.float64).contiguous()
+    lm = None if lam is None else lam.to(device=dev, dtype=torch.float64).contiguous()
+    pitch, rp = _cube_strides(Y)
+    xp, xrp = _cube_strides(X)
+    outs = L.Outputs(o["sigma"].data_ptr(), o["V"].data_ptr(), o["evals"].data_ptr(), o["lam"].data_ptr(),
+                     o["sure"].data_ptr(), o["gap"].data_ptr(), o["status"].data_ptr())
+    L.check(L.lib().hyres_denoise_noalloc(_handle(dev), Y.data_ptr(), H, W, p, pitch, rp, dt, C.byref(opt),
+                                          _ptr(sg), _ptr(lm), X.data_ptr(), xp, xrp, C.byref(outs),
+                                          _stream(dev)), "hyres_denoise_noalloc")
+    info = dict(o)
+    info["V"] = o["V"].T
+    return X, info
+
+
 class Batch:
     """A planned batch of independent cubes (uneven H, W, p, rank, levels).
 

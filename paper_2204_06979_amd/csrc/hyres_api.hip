@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -88,9 +89,37 @@ struct hyres_handle {
     hipStream_t side[kSide];
     hipEvent_t fork, join[kSide];
     hipEvent_t chain[kSide];       // end of a cube group's Gram stage (groups of a batch or tile grid)
+    void* scratch = nullptr;       // device address of this device's no-allocation scratch array
 };
 
+// Scratch of hyres_denoise_noalloc: a file-scope array that every device
+// holds its own copy of from code-object load to process end.  In host code the
+// name `scratch` is only a host-side stand-in; kernels get the device address
+// that hipGetSymbolAddress gives with the device current (scratch_address).
+static __device__ __align__(256) unsigned char scratch[HYRES_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices];      // resolved device address per device (null: not yet)
+
+// The device address of `scratch` on `device`, which must be current.
+// Resolved once per device and kept.
+hipError_t scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
+
 hipEvent_t prof_event(hyres_handle* h) {
     if (!h->pool.empty()) {
         hipEvent_t e = h->pool.back();
@@ -1166,6 +1195,8 @@ HYRES_API hyres_status hyres_create(hyres_handle** handle, int device) {
                  hipEventCreateWithFlags(&h->join[i], hipEventDisableTiming) == hipSuccess &&
                  hipEventCreateWithFlags(&h->chain[i], hipEventDisableTiming) == hipSuccess;
         }
+        // the device address of this device's no-allocation scratch, with the device current
+        ok = ok && scratch_address(device, &h->scratch) == hipSuccess;
         (void)hipSetDevice(prev);
         if (!ok) {
             hyres_destroy(h);
@@ -1485,11 +1516,13 @@ HYRES_API hyres_status hyres_denoise_workspace_size(int H, int W, int p, const h
     return HYRES_OK;
 }
 
-HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
-                                     int64_t row_pitch, int dtype, const hyres_options* opt,
-                                     const double* sigma_in, const double* lambda_in, void* X, int64_t x_pitch,
-                                     int64_t x_row_pitch, const hyres_outputs* out, void* workspace,
-                                     size_t workspace_bytes, hyres_stream_t stream) {
+// One solve of one cube.  noalloc: the workspace is the device's no-allocation
+// scratch (the plan must fit it; the stage timers stay off, they create events).
+static hyres_status denoise_one(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                int64_t row_pitch, int dtype, const hyres_options* opt, const double* sigma_in,
+                                const double* lambda_in, void* X, int64_t x_pitch, int64_t x_row_pitch,
+                                const hyres_outputs* out, bool noalloc, void* workspace, size_t workspace_bytes,
+                                hyres_stream_t stream) {
     if (!h || !X) return HYRES_E_NULL;
     hyres_status st = check_cube(Y, H, W, p, pitch, row_pitch, dtype);
     if (st) return st;
@@ -1499,7 +1532,13 @@ HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int 
     one_cube(x, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
     x.plan[0].has_lambda = lambda_in != nullptr;
     if ((st = plan_cubes(x, kAllParts))) return st;
-    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
+    if (noalloc) {
+        if (!h->scratch) return HYRES_E_HIP;
+        if (x.lay.total > HYRES_NOALLOC_SCRATCH_BYTES) return HYRES_E_WORKSPACE;
+        workspace = h->scratch;
+    } else if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) {
+        return st;
+    }
     if ((st = set_device(h))) return st;
     x.ws = workspace;
     x.desc.assign(1, solve_desc(x.plan[0], workspace, Y, pitch, row_pitch, X, x_pitch, x_row_pitch, sigma_in,
@@ -1507,7 +1546,25 @@ HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int 
     build_program(x, kAllStages);
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_exec(x, s))) return st;
-    return run_program(x, s, true);
+    return run_program(x, s, !noalloc);
+}
+
+HYRES_API hyres_status hyres_denoise(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                     int64_t row_pitch, int dtype, const hyres_options* opt,
+                                     const double* sigma_in, const double* lambda_in, void* X, int64_t x_pitch,
+                                     int64_t x_row_pitch, const hyres_outputs* out, void* workspace,
+                                     size_t workspace_bytes, hyres_stream_t stream) {
+    return denoise_one(h, Y, H, W, p, pitch, row_pitch, dtype, opt, sigma_in, lambda_in, X, x_pitch, x_row_pitch,
+                       out, false, workspace, workspace_bytes, stream);
+}
+
+HYRES_API hyres_status hyres_denoise_noalloc(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                             int64_t row_pitch, int dtype, const hyres_options* opt,
+                                             const double* sigma_in, const double* lambda_in, void* X,
+                                             int64_t x_pitch, int64_t x_row_pitch, const hyres_outputs* out,
+                                             hyres_stream_t stream) {
+    return denoise_one(h, Y, H, W, p, pitch, row_pitch, dtype, opt, sigma_in, lambda_in, X, x_pitch, x_row_pitch,
+                       out, true, nullptr, 0, stream);
 }
 
 // ------------------------------------------------------------- batches

@@ -1,16 +1,26 @@
 #!/usr/bin/env python3
 """HyRes solve throughput on one MI355X.
 
-Default workload: a synthetic 349 x 1905 x 144 FP32 cube (the shape of the
+Headline workload: a synthetic 349 x 1905 x 144 FP32 cube (the shape of the
 Houston 2013 scene the paper evaluates on), rank 8, 4 wavelet levels,
 per-band SNR drawn in 5-20 dB.  One step = one complete HyRes solve (noise
 estimate, eigensolve, projection, transforms, SURE thresholds, inverse,
-back-projection) with the cube already resident in HBM.  Prints one JSON line.
+back-projection) with the cube already resident in HBM.  Two copies of the
+cube are resident and the steps alternate between them, so no step reads a
+cube that the previous step left in the last-level cache.
 
-``--workload batch`` times the 64-cube batch (uneven sizes, one HIP graph
-replay per step, DWT tiles autotuned first) and ``--workload tiled`` the
-2048 x 2048 x 224 sliding-window solve (25 tiles of 512^2, 32 px overlap);
-both print the same JSON contract for their workload.
+Every step is bracketed by its own pair of HIP events on the solve stream: the
+line's ms_per_step is the mean over the K timed steps, and the paper's Olympic
+score (fastest and slowest dropped, mean of the rest) is reported beside it
+with the spread of the kept steps.
+
+By default the line also carries, under config.workloads, the other
+workloads: the 64 x 64 x 32 FP64 cube (rank 4, 3 levels), the 256 x 256 x 191
+forward + backward (rank 6), the batch of 64 uneven cubes (one HIP graph
+replay per step) and the 2048 x 2048 x 224 sliding window (25 tiles of 512^2,
+32 px overlap), each with its rate, whole-solve algorithmic HBM bandwidth and
+its error against the FP64 oracle.  ``--workload single|small|grad|batch|tiled``
+runs one workload alone (the profiled runs use ``single``).
 """
 from __future__ import annotations
 
@@ -18,6 +28,7 @@ import argparse
 import ctypes as C
 import json
 import os
+import platform
 import sys
 import time
 
@@ -33,6 +44,32 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_TFLOPS = 78.6
 PEAK_TFLOPS = {"native": 157.3, "mixed": 2500.0}    # FP32 matrix / BF16 dense matrix
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------- work counts
+def solve_bytes(shapes, elem=4, blended_output=None):
+    """Algorithmic HBM bytes of one solve of the cubes ``shapes`` = [(H, W, p, r, L)]:
+    the cube read twice (Gram pass, projection pass) and the output written
+    once, plus per component the image written and read, the coefficients
+    written, read by the threshold search and read by the inverse, and the
+    denoised image written and read.  Intermediate transform levels are not
+    counted (they can be fused away).  ``blended_output`` = (H, W, p): a
+    sliding window writes one blended output instead of one per tile."""
+    from paper_2204_06979_amd.api import coeff_count
+    b = 0.0
+    for (H, W, p, r, L) in shapes:
+        n = H * W
+        nc = coeff_count(H, W, L)
+        out = 0 if blended_output else n * p
+        b += elem * (2.0 * n * p + out) + elem * r * (4.0 * n + 3.0 * nc)
+    if blended_output:
+        H, W, p = blended_output
+        b += elem * float(H) * W * p
+    return b
 
 
 def stage_work(shapes, precision):
@@ -78,7 +115,7 @@ def roofline_of(stage, work, ms, traffic):
 
 def load_traffic(workload, stage):
     """HBM bytes per launch sequence of `stage` from the committed counter summary, if it covers
-    this workload and stage."""
+    this workload and stage (entries are removed when their kernels change)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -88,6 +125,7 @@ def load_traffic(workload, stage):
         return None
 
 
+# ------------------------------------------------------------------ timing
 class Timer:
     """Per-stage times through the library's stage timers (HIP events on the solve stream)."""
 
@@ -99,31 +137,39 @@ class Timer:
         ms = (C.c_double * 7)()
         cnt = (C.c_int * 7)()
         self.lib.hyres_profile_enable(self.h, (1 << len(STAGES)) - 1 if mask is None else mask)
-        for _ in range(reps):
-            run()
+        for i in range(reps):
+            run(i)
         torch.cuda.synchronize()
         self._lib.check(self.lib.hyres_profile_read(self.h, ms, cnt), "profile read")
         self.lib.hyres_profile_enable(self.h, 0)
         return {STAGES[i]: ms[i] / max(cnt[i], 1) for i in range(7) if cnt[i]}
 
 
-def timed_steps(run, steps, dom_bit, timer):
-    """Time `steps` runs with events on the current stream; the dominant stage
-    is timed at the same time by the library's stage timers."""
+def olympic(per_step):
+    """The paper's scoring: drop the fastest and the slowest run, mean of the rest."""
+    a = sorted(per_step)
+    kept = a[1:-1] if len(a) >= 3 else a
+    return {"mean_ms": float(np.mean(kept)), "min_ms": float(kept[0]), "max_ms": float(kept[-1]),
+            "std_ms": float(np.std(kept)), "runs": len(a), "kept": len(kept)}
+
+
+def timed_steps(run, steps, dom_bit=None, timer=None):
+    """Time exactly `steps` steps, each between its own HIP events on the current
+    stream (no host synchronisation inside the timed region); the dominant
+    stage is timed at the same time by the library's stage timers."""
     import torch
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ms = (C.c_double * 7)()
     cnt = (C.c_int * 7)()
     if dom_bit is not None:
         timer.lib.hyres_profile_enable(timer.h, 1 << dom_bit)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):
-        run()
-    ev1.record(stream)
+    evs[0].record(stream)
+    for i in range(steps):
+        run(i)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     dom_ms = None
@@ -131,46 +177,30 @@ def timed_steps(run, steps, dom_bit, timer):
         timer._lib.check(timer.lib.hyres_profile_read(timer.h, ms, cnt), "profile read")
         timer.lib.hyres_profile_enable(timer.h, 0)
         dom_ms = ms[dom_bit] / max(cnt[dom_bit], 1)
-    return ev0.elapsed_time(ev1) / steps, wall, dom_ms
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    total = evs[0].elapsed_time(evs[steps])
+    return {"ms_per_step": total / steps, "olympic": olympic(per), "wall_s": wall, "dom_ms": dom_ms}
 
 
-def measure_single(api, timer, Y, dims, precision, steps, warmup, workload):
-    import torch
-    H, W, p, r, L = dims
-    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32, precision=precision, device=Y.device)
-    for _ in range(max(warmup, 1)):
-        dn.run(Y)
-    torch.cuda.synchronize()
-    stage_ms = timer.stages(lambda: dn.run(Y))
-    work = stage_work([dims], precision)
-    dom = max(stage_ms, key=lambda k: stage_ms[k])
-    ms_step, wall, dom_ms = timed_steps(lambda: dn.run(Y), steps, STAGES.index(dom), timer)
-    rl = {k: roofline_of(k, work, stage_ms[k], None) for k in stage_ms}
-    return dict(dn=dn, ms_step=ms_step, wall=wall, stage_ms=stage_ms, dom=dom,
-                roofline=roofline_of(dom, work, dom_ms, load_traffic(workload + "/" + precision, dom)),
-                stage_rooflines=rl, status=int(dn.status.cpu()[0]))
+def x_errors(X, ref):
+    X = np.asarray(X, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    d = X - ref
+    return {"X_rel": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "X_max_elem_rel": float(np.abs(d).max() / np.abs(ref).max())}
 
 
-def parity_single(api, cube, Y, dims, res):
-    from oracle import hyres_oracle as O
-    H, W, p, r, L = dims
-    c0 = time.perf_counter()
-    ref = O.hyres(cube.Y.astype(np.float64), r, L)
-    cpu_s = time.perf_counter() - c0
-    for prec, m in res.items():
-        dn = m["dn"]
-        X = dn.run(Y).double().cpu().numpy()
-        V = dn.V.T.cpu().numpy()
-        cosines = np.linalg.svd(V.T @ ref["V"], compute_uv=False)
-        m["errors"] = {
-            "X_rel": float(np.linalg.norm(X - ref["X"]) / np.linalg.norm(ref["X"])),
-            "sigma_max_rel": float(np.max(np.abs(dn.sigma.cpu().numpy() / ref["sigma"] - 1))),
-            "evals_top_r_max_rel": float(np.max(np.abs(dn.evals.cpu().numpy()[:r] / ref["evals"][:r] - 1))),
-            "subspace_max_angle_rad": float(np.arccos(np.clip(cosines.min(), -1.0, 1.0))),
-            "V_max_abs_diff": float(np.max(np.abs(V - ref["V"]))),
-            "lambda_max_rel_diff": float(np.max(np.abs(dn.lam.cpu().numpy() - ref["lam"]) / ref["lam"])),
-        }
-    return cpu_s
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
 
 
 def cpu_cores():
@@ -181,6 +211,48 @@ def cpu_cores():
         return len(os.sched_getaffinity(0))
 
 
+def time_oracle(fn, min_runs=3, max_runs=15, budget_s=20.0):
+    """Runs the oracle at least `min_runs` times (more while the budget lasts,
+    at most `max_runs`); returns (Olympic mean seconds, runs, last result)."""
+    ts, out = [], None
+    while len(ts) < max_runs:
+        t0 = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t0)
+        if len(ts) >= min_runs and sum(ts) + ts[-1] > budget_s:
+            break
+    o = olympic(ts)
+    return o["mean_ms"], len(ts), out      # seconds (olympic() is unit-agnostic)
+
+
+def rate_entry(voxels, t, bytes_):
+    o = t["olympic"]["mean_ms"]
+    return {"voxels_per_s": voxels / (t["ms_per_step"] * 1e-3), "ms_per_step": t["ms_per_step"],
+            "olympic": t["olympic"], "wall_s": t["wall_s"],
+            "algorithmic_bytes_per_step": bytes_, "hbm_gbs": bytes_ / (o * 1e-3) / 1e9,
+            "hbm_frac": bytes_ / (o * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+# ------------------------------------------------------------ headline (c2)
+def measure_single(api, timer, Ys, dims, precision, steps, warmup, workload):
+    import torch
+    H, W, p, r, L = dims
+    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32, precision=precision, device=Ys[0].device)
+    run = lambda i: dn.run(Ys[i % len(Ys)])       # noqa: E731
+    for i in range(max(warmup, 1)):
+        run(i)
+    torch.cuda.synchronize()
+    stage_ms = timer.stages(run)
+    work = stage_work([dims], precision)
+    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    t = timed_steps(run, steps, STAGES.index(dom), timer)
+    rl = {k: roofline_of(k, work, stage_ms[k], None) for k in stage_ms}
+    e = rate_entry(float(H * W * p), t, solve_bytes([dims]))
+    e.update(stages_ms=stage_ms, stage_rooflines=rl,
+             roofline=roofline_of(dom, work, t["dom_ms"], load_traffic(workload + "/" + precision, dom)))
+    return dn, e
+
+
 def run_single(args, api, timer, synth):
     import torch
     cfg = synth.CONFIG_SHAPES[2]
@@ -188,31 +260,148 @@ def run_single(args, api, timer, synth):
     H, W, p, r, L = dims
     t0 = time.time()
     cube = synth.config_cube(2, keep_clean=False)
-    print("bench: generated %dx%dx%d cube in %.1f s" % (H, W, p, time.time() - t0), file=sys.stderr, flush=True)
+    log("generated %dx%dx%d cube in %.1f s" % (H, W, p, time.time() - t0))
     Y = torch.tensor(cube.Y, device="cuda")
+    Ys = [Y, Y.clone()]          # two resident copies, alternated step by step
     precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
-    res = {}
+    res, dns = {}, {}
     for prec in precs:
-        res[prec] = measure_single(api, timer, Y, dims, prec, args.steps, args.warmup, "single")
-        print("bench: %s %.3f ms/solve" % (prec, res[prec]["ms_step"]), file=sys.stderr, flush=True)
-    cpu_s = None
+        dns[prec], res[prec] = measure_single(api, timer, Ys, dims, prec, args.steps, args.warmup, "single")
+        log("%s %.3f ms/solve (olympic %.3f)" % (prec, res[prec]["ms_per_step"], res[prec]["olympic"]["mean_ms"]))
+    cpu = None
     if not args.no_parity or not args.no_cpu_baseline:
-        cpu_s = parity_single(api, cube, Y, dims, res)
+        from oracle import hyres_oracle as O
+        Y64 = cube.Y.astype(np.float64)
+        cpu_s, runs, ref = time_oracle(lambda: O.hyres(Y64, r, L), min_runs=3,
+                                       max_runs=1 if args.no_cpu_baseline else 15)
+        cpu = (cpu_s, "Olympic mean of %d oracle solves of the same %dx%dx%d cube (FP64 numpy), %.2f s each"
+               % (runs, H, W, p, cpu_s))
+        for prec, m in res.items():
+            dn = dns[prec]
+            X = dn.run(Y).double().cpu().numpy()
+            V = dn.V.T.cpu().numpy()
+            cosines = np.linalg.svd(V.T @ ref["V"], compute_uv=False)
+            err = x_errors(X, ref["X"])
+            err.update({
+                "sigma_max_rel": float(np.max(np.abs(dn.sigma.cpu().numpy() / ref["sigma"] - 1))),
+                "evals_top_r_max_rel": float(np.max(np.abs(dn.evals.cpu().numpy()[:r] / ref["evals"][:r] - 1))),
+                "subspace_max_angle_rad": float(np.arccos(np.clip(cosines.min(), -1.0, 1.0))),
+                "V_max_abs_diff": float(np.max(np.abs(V - ref["V"]))),
+                "lambda_max_rel_diff": float(np.max(np.abs(dn.lam.cpu().numpy() - ref["lam"]) / ref["lam"])),
+                "gap_ratio": float(dn.gap.cpu()[0]),
+            })
+            m["errors_vs_fp64_oracle"] = err
+    for prec in res:
+        res[prec]["device_status"] = int(dns[prec].status.cpu()[0])
     workload = ("HyRes solve of a %dx%dx%d FP32 cube (Houston-2013 shape), rank %d, %d db2 levels, "
-                "per-band SNR 5-20 dB, linear-mixing synthetic" % dims)
-    sample = "one full oracle solve of the same %dx%dx%d cube (FP64 numpy)" % (H, W, p)
-    return res, float(H * W * p), workload, cpu_s, sample
+                "per-band SNR 5-20 dB, linear-mixing synthetic; two resident copies alternated" % dims)
+    return res, float(H * W * p), workload, cpu
 
 
-def run_batch(args, api, timer, synth):
+# ------------------------------------------------------- other workloads
+def run_small_fp64(args, api, synth):
+    """64 x 64 x 32 FP64 cube, rank 4, 3 levels (the oracle finishes it in milliseconds)."""
     import torch
+    from oracle import hyres_oracle as O
+    cube = synth.config_cube(1, keep_clean=False)
+    H, W, p = cube.Y.shape
+    r, L = 4, 3
+    Y = torch.tensor(cube.Y, device="cuda")
+    Ys = [Y, Y.clone()]
+    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float64, device=Y.device)
+    run = lambda i: dn.run(Ys[i % 2])       # noqa: E731
+    for i in range(max(args.warmup, 1)):
+        run(i)
+    t = timed_steps(run, args.steps)
+    e = rate_entry(float(H * W * p), t, solve_bytes([(H, W, p, r, L)], elem=8))
+    cpu_s, runs, ref = time_oracle(lambda: O.hyres(cube.Y, r, L), min_runs=15, max_runs=15)
+    e["errors_vs_fp64_oracle"] = x_errors(dn.run(Y).cpu().numpy(), ref["X"])
+    e["oracle_s"] = cpu_s
+    e["oracle_runs"] = runs
+    e["device_status"] = int(dn.status.cpu()[0])
+    e["workload"] = "64x64x32 FP64 cube, rank 4, 3 levels, 10 dB, native FP64"
+    return e
+
+
+def run_grad(args, api, synth):
+    """Forward + backward of the 256 x 256 x 191 FP32 cube (rank 6, 4 levels) at
+    fixed thresholds; the gradient is compared with torch autograd through the
+    FP64 oracle forward on the CPU."""
+    import torch
+    from oracle import hyres_oracle as O
+    from oracle import grad as OG
+    cube = synth.config_cube(4, keep_clean=False)
+    Y = cube.Y
+    H, W, p = Y.shape
+    r, L = 6, 4
+    Yt = torch.tensor(Y, device="cuda")
+    ref = O.hyres(Y.astype(np.float64), r, L)
+    # thresholds away from every kink: near each SURE threshold, the middle of
+    # the widest gap between the 32 nearest coefficient magnitudes
+    lam_np = np.empty(r)
+    for k in range(r):
+        a = np.sort(np.abs(ref["B"][k]))
+        i0 = int(np.searchsorted(a, ref["lam"][k]))
+        w = a[max(0, i0 - 16):i0 + 16]
+        g = int(np.argmax(np.diff(w)))
+        lam_np[k] = 0.5 * (w[g] + w[g + 1])
+    lam = torch.tensor(lam_np, device="cuda")
+    R = np.random.default_rng(2).standard_normal(Y.shape).astype(np.float32)
+    dX = torch.tensor(R, device="cuda")
+    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32, device=Yt.device)
+    Ys = [Yt, Yt.clone()]
+    out = {}
+
+    def step(i):
+        Yi = Ys[i % 2]
+        dn.run(Yi, None, lam)
+        out["g"] = api.denoise_backward(dn, Yi, dX)
+
+    for i in range(max(args.warmup, 1)):
+        step(i)
+    t = timed_steps(step, args.steps)
+    fwd = timed_steps(lambda i: dn.run(Ys[i % 2], None, lam), args.steps)
+    nbytes = 2.0 * solve_bytes([(H, W, p, r, L)])      # backward: the forward's count (dX, Y, dY; images, coefficients)
+    e = rate_entry(float(H * W * p), t, nbytes)
+    e["forward_ms_per_step"] = fwd["ms_per_step"]
+    e["backward_over_forward"] = (t["ms_per_step"] - fwd["ms_per_step"]) / fwd["ms_per_step"]
+    step(0)
+    torch.cuda.synchronize()
+    dY, dlam, st = out["g"]
+    Yg = torch.tensor(Y, dtype=torch.float64, requires_grad=True)
+    lg = torch.tensor(lam_np, dtype=torch.float64, requires_grad=True)
+    Xo = OG.hyres_forward(Yg, lg, r, L, sign_ref=torch.tensor(dn.V.T.cpu().numpy(), dtype=torch.float64))
+    (Xo * torch.tensor(R, dtype=torch.float64)).sum().backward()
+    gY, gl = Yg.grad.numpy(), lg.grad.numpy()
+    e["errors_vs_fp64_oracle_gradient"] = {
+        "dY_rel": float(np.linalg.norm(dY.double().cpu().numpy() - gY) / np.linalg.norm(gY)),
+        "dlambda_rel": float(np.linalg.norm(dlam.cpu().numpy() - gl) / np.linalg.norm(gl))}
+    e["device_status"] = int(st.cpu()[0])
+    e["workload"] = ("forward + backward (vector-Jacobian product wrt the cube and the thresholds) of a "
+                     "256x256x191 FP32 cube, rank 6, 4 levels, thresholds held fixed")
+    return e
+
+
+def run_batch(args, api, synth, precs):
+    """64 uneven cubes, one HIP graph replay per step, transform tiles tuned first."""
+    import torch
+    from oracle import hyres_oracle as O
     t0 = time.time()
     cubes = synth.config3_cubes()
-    print("bench: generated %d cubes in %.1f s" % (len(cubes), time.time() - t0), file=sys.stderr, flush=True)
+    log("generated %d cubes in %.1f s" % (len(cubes), time.time() - t0))
     Yt = [torch.tensor(c.Y, device="cuda") for c in cubes]
     shapes = [(c.Y.shape[0], c.Y.shape[1], c.Y.shape[2], c.rank, c.levels) for c in cubes]
-    precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
+    total = float(sum(c.Y.size for c in cubes))
+    nbytes = solve_bytes(shapes)
+    # the oracle on the smallest cube of each band-count class
+    pick = {}
+    for i, c in enumerate(cubes):
+        q = c.Y.shape[2]
+        if q not in pick or c.Y.size < cubes[pick[q]].Y.size:
+            pick[q] = i
+    order = sorted(pick.values())
     res = {}
+    refs = None
     for prec in precs:
         b = api.Batch(Yt, [c.rank for c in cubes], [c.levels for c in cubes], precision=prec)
         b.run()
@@ -220,95 +409,93 @@ def run_batch(args, api, timer, synth):
                    else args.tune_cache)
         for _ in range(max(args.warmup, 1)):
             b.launch_graph()
-        torch.cuda.synchronize()
-        stage_ms = timer.stages(b.run)
-        work = stage_work(shapes, prec)
-        dom = max(stage_ms, key=lambda k: stage_ms[k])
-        ms_step, wall, _ = timed_steps(b.launch_graph, args.steps, None, timer)
-        _, _, dom_ms = timed_steps(b.run, 3, STAGES.index(dom), timer)
-        status = max(int(b.info(i)["status"].cpu()[0]) for i in range(len(cubes)))
-        res[prec] = dict(batch=b, ms_step=ms_step, wall=wall, stage_ms=stage_ms, dom=dom,
-                         roofline=roofline_of(dom, work, dom_ms, load_traffic("batch/" + prec, dom)),
-                         stage_rooflines={k: roofline_of(k, work, stage_ms[k], None) for k in stage_ms},
-                         status=status)
-        print("bench: batch %s %.3f ms/step (graph)" % (prec, ms_step), file=sys.stderr, flush=True)
-    cpu_s = None
-    sample = None
-    if not args.no_parity or not args.no_cpu_baseline:
-        from oracle import hyres_oracle as O
-        # the oracle on the smallest cubes of the batch, scaled by voxels
-        order = sorted(range(len(cubes)), key=lambda i: cubes[i].Y.size)[:4]
-        c0 = time.perf_counter()
-        vox = 0
-        refs = {}
-        for i in order:
-            c = cubes[i]
-            refs[i] = O.hyres(c.Y.astype(np.float64), c.rank, c.levels)
-            vox += c.Y.size
-        cpu_s = (time.perf_counter() - c0) * sum(c.Y.size for c in cubes) / vox
-        sample = "oracle solves of the 4 smallest of the 64 cubes (%d voxels), scaled to the batch" % vox
-        for prec, m in res.items():
-            b = m["batch"]
-            errs = []
-            for i in order:
-                X = b.X[i].double().cpu().numpy()
-                errs.append(float(np.linalg.norm(X - refs[i]["X"]) / np.linalg.norm(refs[i]["X"])))
-            m["errors"] = {"X_rel_max_over_sampled_cubes": max(errs)}
-    total = float(sum(c.Y.size for c in cubes))
-    workload = ("batched HyRes of 64 uneven FP32 cubes (H, W in [128, 512], p in {103, 128, 191, 224}, "
-                "rank 4-12, 4 db2 levels, 10 dB), one HIP graph replay per step, %.3f G voxels" % (total / 1e9))
-    return res, total, workload, cpu_s, sample
+        t = timed_steps(lambda i: b.launch_graph(), args.steps)
+        e = rate_entry(total, t, nbytes)
+        e["device_status"] = max(int(b.info(i)["status"].cpu()[0]) for i in range(len(cubes)))
+        if refs is None:
+            c0 = time.perf_counter()
+            refs = {i: O.hyres(cubes[i].Y.astype(np.float64), cubes[i].rank, cubes[i].levels) for i in order}
+            vox = sum(cubes[i].Y.size for i in order)
+            cpu = (time.perf_counter() - c0) * total / vox
+        errs = [x_errors(b.X[i].double().cpu().numpy(), refs[i]["X"]) for i in order]
+        e["errors_vs_fp64_oracle"] = {"cubes": order,
+                                      "X_rel_max": max(x["X_rel"] for x in errs),
+                                      "X_max_elem_rel_max": max(x["X_max_elem_rel"] for x in errs)}
+        res[prec] = e
+        log("batch %s %.3f ms/step (graph)" % (prec, t["ms_per_step"]))
+        del b
+    vox = sum(cubes[i].Y.size for i in order)
+    return {"workload": ("64 uneven FP32 cubes (H, W in [128, 512], p in {103, 128, 191, 224}, rank 4-12, "
+                         "4 db2 levels, 10 dB), %.3f G voxels, one HIP graph replay per step" % (total / 1e9)),
+            "precisions": res,
+            "oracle_estimate_s": cpu,
+            "oracle_sample": "one oracle solve of the smallest cube of each band count (%d voxels), "
+                             "scaled by voxels to the batch" % vox}
 
 
-def run_tiled(args, api, timer, synth):
+def run_tiled(args, api, synth, precs):
+    """2048 x 2048 x 224 sliding window (25 tiles of 512^2, 32 px overlap)."""
     import torch
+    from oracle import hyres_oracle as O
     t0 = time.time()
     cube = synth.config_cube(5, keep_clean=False)
-    H, W, p = cube.Y.shape
-    r, L, tile, ov = 10, 4, 512, 32
-    print("bench: generated %dx%dx%d cube in %.1f s" % (H, W, p, time.time() - t0), file=sys.stderr, flush=True)
-    Y = torch.tensor(cube.Y, device="cuda")
+    Yh = cube.Y
     del cube
+    H, W, p = Yh.shape
+    r, L, tile, ov = 10, 4, 512, 32
+    log("generated %dx%dx%d cube in %.1f s" % (H, W, p, time.time() - t0))
+    Y = torch.tensor(Yh, device="cuda")
     X = torch.empty_like(Y)
-    starts_y, starts_x = api.tile_grid(H, tile, ov), api.tile_grid(W, tile, ov)
-    shapes = [(tile, tile, p, r, L)] * (len(starts_y) * len(starts_x))
-    precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
+    sy, sx = api.tile_grid(H, tile, ov), api.tile_grid(W, tile, ov)
+    shapes = [(tile, tile, p, r, L)] * (len(sy) * len(sx))
+    nbytes = solve_bytes(shapes, blended_output=(H, W, p))
+    # a window on the corner where tiles (0,0), (0,1), (1,0) and (1,1) overlap
+    y0, y1, x0, x1 = 470, 522, 470, 522
+    wy = [O.tile_weights_1d(s, tile, H, ov) for s in sy[:2]]
+    wx = [O.tile_weights_1d(s, tile, W, ov) for s in sx[:2]]
     res = {}
+    cpu = None
     for prec in precs:
-        run = lambda: api.denoise_tiled(Y, r, L, tile=tile, overlap=ov, precision=prec, X=X)   # noqa: E731
-        for _ in range(max(args.warmup, 1)):
-            _, info = run()
-        torch.cuda.synchronize()
-        stage_ms = timer.stages(run)
-        work = stage_work(shapes, prec)
-        dom = max(stage_ms, key=lambda k: stage_ms[k])
-        ms_step, wall, dom_ms = timed_steps(run, args.steps, STAGES.index(dom), timer)
-        res[prec] = dict(ms_step=ms_step, wall=wall, stage_ms=stage_ms, dom=dom,
-                         roofline=roofline_of(dom, work, dom_ms, load_traffic("tiled/" + prec, dom)),
-                         stage_rooflines={k: roofline_of(k, work, stage_ms[k], None) for k in stage_ms},
-                         status=int(info["status"].cpu()[0]))
-        print("bench: tiled %s %.3f ms/step" % (prec, ms_step), file=sys.stderr, flush=True)
-    cpu_s = None
-    sample = None
-    if not args.no_cpu_baseline:
-        from oracle import hyres_oracle as O
-        sub = Y[:tile, :tile].cpu().numpy().astype(np.float64)
+        run = lambda i: api.denoise_tiled(Y, r, L, tile=tile, overlap=ov, precision=prec, X=X)   # noqa: E731
+        for i in range(max(args.warmup, 1)):
+            _, info = run(i)
+        t = timed_steps(run, args.steps)
+        e = rate_entry(float(H * W * p), t, nbytes)
+        e["device_status"] = int(info["status"].cpu()[0])
+        lam = info["lam"].cpu().numpy()
+        acc = np.zeros((y1 - y0, x1 - x0, p))
+        ws = np.zeros((y1 - y0, x1 - x0))
         c0 = time.perf_counter()
-        O.hyres(sub, r, L)
-        cpu_s = (time.perf_counter() - c0) * len(shapes) * H * W / (len(shapes) * tile * tile)
-        sample = "oracle solve of one 512x512x224 tile, scaled to the 25 tiles (blend not timed)"
-    workload = ("sliding-window HyRes of a %dx%dx%d FP32 cube, 25 tiles of 512x512 with 32 px overlap, "
-                "rank 10, 4 db2 levels, SNR 5-15 dB + dead columns + 1%% impulses" % (H, W, p))
-    return res, float(H * W * p), workload, cpu_s, sample
+        for iy in range(2):
+            a, b = max(y0, sy[iy]), min(y1, sy[iy] + tile)
+            for ix in range(2):
+                c0, c1 = max(x0, sx[ix]), min(x1, sx[ix] + tile)
+                sub = Yh[sy[iy]:sy[iy] + tile, sx[ix]:sx[ix] + tile].astype(np.float64)
+                Xt = O.hyres(sub, r, L, lam=lam[iy * len(sx) + ix])["X"]
+                w2 = wy[iy][a - sy[iy]:b - sy[iy], None] * wx[ix][None, c0 - sx[ix]:c1 - sx[ix]]
+                acc[a - y0:b - y0, c0 - x0:c1 - x0] += w2[:, :, None] * Xt[a - sy[iy]:b - sy[iy], c0 - sx[ix]:c1 - sx[ix]]
+                ws[a - y0:b - y0, c0 - x0:c1 - x0] += w2
+        if cpu is None:
+            cpu = (time.perf_counter() - c0) / 4 * len(shapes)
+        e["errors_vs_fp64_oracle"] = dict(window=[y0, y1, x0, x1], thresholds="device's",
+                                          **x_errors(X[y0:y1, x0:x1].double().cpu().numpy(), acc / ws[:, :, None]))
+        res[prec] = e
+        log("tiled %s %.3f ms/step" % (prec, t["ms_per_step"]))
+    return {"workload": ("sliding-window HyRes of a %dx%dx%d FP32 cube, 25 tiles of 512x512 with 32 px overlap, "
+                         "rank 10, 4 db2 levels, SNR 5-15 dB + dead columns + 1%% impulses" % (H, W, p)),
+            "precisions": res,
+            "oracle_estimate_s": cpu,
+            "oracle_sample": "oracle solves of the 4 tiles around one seam corner (at the device's thresholds), "
+                             "scaled to the 25 tiles (blend not timed)"}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=["native", "mixed", "both"])
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "tiled"])
+    ap.add_argument("--workload", default="all", choices=["all", "single", "small", "grad", "batch", "tiled"])
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -325,18 +512,38 @@ def main() -> int:
     torch.cuda.set_device(dev)
     lib = _lib.lib()
     timer = Timer(_lib, lib, api._handle(dev))
-    runner = {"single": run_single, "batch": run_batch, "tiled": run_tiled}[args.workload]
-    res, voxels, workload, cpu_s, sample = runner(args, api, timer, synth)
+    precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
+    others = {}
+    if args.workload in ("small", "grad", "batch", "tiled"):
+        # one secondary workload alone: its own line
+        fn = {"small": lambda: run_small_fp64(args, api, synth), "grad": lambda: run_grad(args, api, synth),
+              "batch": lambda: run_batch(args, api, synth, precs),
+              "tiled": lambda: run_tiled(args, api, synth, precs)}[args.workload]
+        e = fn()
+        print(json.dumps({"metric": METRIC, "workload": args.workload, "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "result": e}))
+        return 0
+
+    res, voxels, workload, cpu = run_single(args, api, timer, synth)
+    if args.workload == "all":
+        for name, fn in (("small_64x64x32_fp64", lambda: run_small_fp64(args, api, synth)),
+                         ("grad_256x256x191_fwd_bwd", lambda: run_grad(args, api, synth)),
+                         ("batch64", lambda: run_batch(args, api, synth, precs)),
+                         ("tiled_2048x2048x224", lambda: run_tiled(args, api, synth, precs))):
+            t0 = time.time()
+            others[name] = fn()
+            log("%s done in %.1f s" % (name, time.time() - t0))
+            torch.cuda.empty_cache()
     head_prec = "mixed" if "mixed" in res else next(iter(res))
     head = res[head_prec]
     out = {
         "metric": METRIC,
-        "value": voxels / (head["ms_step"] * 1e-3),
+        "value": voxels / (head["ms_per_step"] * 1e-3),
         "unit": "voxels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -346,15 +553,13 @@ def main() -> int:
         "roofline": head["roofline"],
     }
     for prec, m in res.items():
-        e = {"voxels_per_s": voxels / (m["ms_step"] * 1e-3), "ms_per_step": m["ms_step"], "wall_s": m["wall"],
-             "stages_ms": m["stage_ms"], "roofline": m["roofline"], "stage_rooflines": m["stage_rooflines"],
-             "device_status": m["status"]}
-        if "errors" in m:
-            e["errors_vs_fp64_oracle"] = m["errors"]
-        out["config"][prec] = e
-    if cpu_s is not None and not args.no_cpu_baseline:
+        out["config"][prec] = m
+    if others:
+        out["config"]["workloads"] = others
+    if cpu is not None and not args.no_cpu_baseline:
+        cpu_s, sample = cpu
         out["cpu_baseline"] = {"value": voxels / cpu_s, "unit": "voxels/s", "cores": int(cpu_cores()),
-                               "kind": "oracle", "sample": "%s, %.1f s" % (sample, cpu_s)}
+                               "kind": "oracle", "sample": sample, "cpu_model": cpu_info()}
     print(json.dumps(out))
     return 0
 

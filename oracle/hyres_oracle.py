@@ -41,7 +41,7 @@ __all__ = [
     "DB2", "HAAR", "highpass", "dwt1_axis", "idwt1_axis", "dwt2", "idwt2",
     "level_shapes", "coeff_count", "sure_curve", "sure_threshold",
     "soft_threshold", "noise_estimate", "subspace", "hyres", "hyres_tiled",
-    "tile_weights_1d", "oracle_gram",
+    "tile_weights_1d", "oracle_gram", "hysime_rank", "truncation_df", "truncation_sure", "sure_rank",
 ]
 
 # ---------------------------------------------------------------------------
@@ -249,13 +249,66 @@ def subspace(Yw: np.ndarray, r: int) -> Tuple[np.ndarray, np.ndarray]:
 
 
 # ---------------------------------------------------------------------------
+# Rank selection: the subspace dimension chosen from the data
+def hysime_rank(evals: np.ndarray, n: int, r_max: int) -> int:
+    """HySime subspace identification applied to the whitened cube.
+
+    HySime keeps the eigen-directions e of the signal correlation (data
+    correlation R_y minus noise correlation R_n) along which the data power
+    e^T R_y e exceeds twice the noise power e^T R_n e: including e changes the
+    mean-square error of the projection estimate by -e^T R_y e + 2 e^T R_n e.
+    After whitening by the per-band noise levels, R_n = I and R_y = C / n, so
+    the directions are the eigenvectors of C and the change is 2 - lambda / n.
+    The count is capped to [1, r_max].
+    """
+    delta = 2.0 - np.asarray(evals, dtype=np.float64) / float(n)
+    k = int(np.sum(delta < 0.0))
+    return min(max(k, 1), int(r_max))
+
+
+def truncation_df(evals: np.ndarray, n: int, r: int) -> float:
+    """Divergence (degrees of freedom) of the rank-r truncated SVD of an
+    n x p matrix (n >= p, distinct singular values), in terms of the squared
+    singular values lambda (the eigenvalues of its Gram, descending):
+        r (n - p + 1) + r (r - 1) + 2 sum_{i <= r < j} lambda_i / (lambda_i - lambda_j),
+    the spectral-estimator divergence sum_i [f_i' + (n - p) f_i / s_i] +
+    2 sum_{i != j} s_i f_i / (s_i^2 - s_j^2) with f_i = s_i for i <= r, else 0."""
+    lam = np.asarray(evals, dtype=np.float64)
+    p = lam.size
+    df = r * (n - p + 1) + r * (r - 1)
+    for i in range(r):
+        for j in range(r, p):
+            df += 2.0 * lam[i] / (lam[i] - lam[j])
+    return float(df)
+
+
+def truncation_sure(evals: np.ndarray, n: int, r: int) -> float:
+    """Stein's unbiased risk estimate (unit noise) of the rank-r truncation of
+    the whitened n x p cube: ||Yw - Yw_r||^2 - n p + 2 df(r), where the
+    residual is the sum of the discarded eigenvalues."""
+    lam = np.asarray(evals, dtype=np.float64)
+    p = lam.size
+    return float(np.sum(lam[r:]) - n * p + 2.0 * truncation_df(lam, n, r))
+
+
+def sure_rank(evals: np.ndarray, n: int, r_max: int) -> int:
+    """The rank in [1, r_max] minimising truncation_sure (smallest on ties)."""
+    vals = [truncation_sure(evals, n, r) for r in range(1, int(r_max) + 1)]
+    return 1 + int(np.argmin(vals))
+
+
+# ---------------------------------------------------------------------------
 # The whole denoiser
 def hyres(Y: np.ndarray, r: int, L: int, sigma: Optional[np.ndarray] = None,
           lam: Optional[Sequence[float]] = None, V: Optional[np.ndarray] = None,
-          h: np.ndarray = DB2, detail_only: bool = False) -> Dict[str, np.ndarray]:
+          h: np.ndarray = DB2, detail_only: bool = False,
+          rank_rule: Optional[str] = None) -> Dict[str, np.ndarray]:
     """Run O1..O10 on an H x W x p cube.  Everything is float64.
 
     ``sigma``, ``lam`` and ``V`` may be supplied to bypass their estimation.
+    ``rank_rule`` "hysime" or "sure": ``r`` is the largest rank, and the rank
+    used is chosen from the eigenvalues of the whitened Gram (hysime_rank,
+    sure_rank); the result then carries ``rank``.
     Returns a dict with X (denoised, H x W x p), sigma, V, evals (all,
     descending, of the whitened Gram), lam, sure (minimum SURE per component),
     gap (evals[r-1] / evals[r]), Z (component images), B (coefficients).
@@ -268,6 +321,13 @@ def hyres(Y: np.ndarray, r: int, L: int, sigma: Optional[np.ndarray] = None,
         sigma = noise_estimate(Y2)                               # O2
     sigma = np.asarray(sigma, dtype=np.float64)
     Yw = Y2 / sigma[None, :]                                     # O3
+    rank = None
+    if rank_rule is not None:
+        if V is not None:
+            raise ValueError("a given basis fixes the rank")
+        _, ev_all = subspace(Yw, 1)
+        rank = hysime_rank(ev_all, n, r) if rank_rule == "hysime" else sure_rank(ev_all, n, r)
+        r = rank
     if V is None:
         V, evals = subspace(Yw, r)                               # O4
     else:
@@ -297,8 +357,11 @@ def hyres(Y: np.ndarray, r: int, L: int, sigma: Optional[np.ndarray] = None,
     Xw = Zh.reshape(r, n).T @ V.T                                # O10
     X = (Xw * sigma[None, :]).reshape(H, W, p)
     gap = evals[r - 1] / evals[r] if r < p else float("inf")
-    return dict(X=X, sigma=sigma, V=V, evals=evals, lam=lam_out, sure=sure_out,
-                gap=gap, Z=Z.T.reshape(r, H, W), B=B)
+    out = dict(X=X, sigma=sigma, V=V, evals=evals, lam=lam_out, sure=sure_out,
+               gap=gap, Z=Z.T.reshape(r, H, W), B=B)
+    if rank is not None:
+        out["rank"] = rank
+    return out
 
 
 # ---------------------------------------------------------------------------

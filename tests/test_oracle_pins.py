@@ -435,3 +435,92 @@ def test_oracle_gradient_matches_central_differences():
         fd = float((OG.hyres_forward(Y, lam + e, r, L, ref) * Wt).sum()
                    - (OG.hyres_forward(Y, lam - e, r, L, ref) * Wt).sum()) / (2 * h)
         assert abs(fd - float(gl[i])) <= 1e-5 * max(1.0, abs(float(gl[i])))
+
+
+# ---------------------------------------------------------------- rank selection
+def _truncate(Y, r):
+    U, s, Vt = np.linalg.svd(Y, full_matrices=False)
+    return (U[:, :r] * s[:r]) @ Vt[:r]
+
+
+def test_truncation_df_matches_numerical_divergence():
+    """df(r) of the rank-r truncated SVD against the trace of its Jacobian by
+    central differences (numpy's SVD as the map; no formula shared)."""
+    rng = np.random.default_rng(21)
+    n, p = 9, 4
+    Y = rng.standard_normal((n, p)) * np.array([3.0, 2.0, 1.2, 0.7])
+    lam = np.sort(np.linalg.eigvalsh(Y.T @ Y))[::-1]
+    h = 1e-6
+    for r in (1, 2, 3):
+        div = 0.0
+        for i in range(n):
+            for j in range(p):
+                E = np.zeros_like(Y)
+                E[i, j] = h
+                div += (_truncate(Y + E, r)[i, j] - _truncate(Y - E, r)[i, j]) / (2 * h)
+        assert abs(div - O.truncation_df(lam, n, r)) <= 1e-6 * abs(div), (r, div, O.truncation_df(lam, n, r))
+
+
+def test_truncation_sure_is_unbiased():
+    """Mean of SURE(r) over noise draws against the mean squared error of the
+    rank-r truncation of X + N(0, 1) for a fixed rank-2 X (CLT bound)."""
+    rng = np.random.default_rng(22)
+    n, p = 30, 6
+    X = (rng.standard_normal((n, 2)) * np.array([4.0, 2.5])) @ rng.standard_normal((2, p))
+    M = 3000
+    for r in (1, 2, 3):
+        sure = np.empty(M)
+        err = np.empty(M)
+        for m in range(M):
+            Y = X + rng.standard_normal((n, p))
+            lam = np.sort(np.linalg.eigvalsh(Y.T @ Y))[::-1]
+            sure[m] = O.truncation_sure(lam, n, r)
+            err[m] = np.sum((_truncate(Y, r) - X) ** 2)
+        d = sure - err
+        assert abs(d.mean()) <= 4.0 * d.std() / np.sqrt(M), (r, d.mean(), d.std())
+
+
+def test_sure_rank_is_the_argmin_and_prefers_the_smaller_rank():
+    lam = np.array([900.0, 300.0, 61.0, 40.5, 40.0, 39.5, 39.0])
+    n = 40
+    vals = [O.truncation_sure(lam, n, r) for r in range(1, 6)]
+    assert O.sure_rank(lam, n, 5) == 1 + int(np.argmin(vals))
+    # a flat tail of noise eigenvalues is not worth its degrees of freedom
+    assert O.sure_rank(lam, n, 5) <= 3
+
+
+def test_hysime_count_equals_the_projection_mse_rule():
+    """The whitened-frame count against HySime's own increments
+    -e^T R_y e + 2 e^T R_n e, evaluated with the correlation matrices along the
+    eigenvectors of R_y - R_n (R_n = I after whitening)."""
+    rng = np.random.default_rng(23)
+    n, p = 400, 12
+    S = rng.standard_normal((n, 3)) @ (rng.standard_normal((3, p)) * np.array([[3.0], [1.6], [1.05]]))
+    Yw = S + rng.standard_normal((n, p))
+    Ry = Yw.T @ Yw / n
+    Rn = np.eye(p)
+    _, E = np.linalg.eigh(Ry - Rn)
+    delta = np.array([-E[:, i] @ Ry @ E[:, i] + 2.0 * E[:, i] @ Rn @ E[:, i] for i in range(p)])
+    k = int(np.sum(delta < 0))
+    lam = np.sort(np.linalg.eigvalsh(Yw.T @ Yw))[::-1]
+    assert O.hysime_rank(lam, n, p - 1) == min(max(k, 1), p - 1)
+    assert O.hysime_rank(lam, n, 2) == min(k, 2)
+
+
+def test_hysime_recovers_a_strong_rank():
+    """A rank-3 signal well above twice the noise power, white unit noise."""
+    rng = np.random.default_rng(24)
+    n, p = 2000, 20
+    S = rng.standard_normal((n, 3)) @ (rng.standard_normal((3, p)) * 3.0)
+    Yw = S + rng.standard_normal((n, p))
+    lam = np.sort(np.linalg.eigvalsh(Yw.T @ Yw))[::-1]
+    assert O.hysime_rank(lam, n, 10) == 3
+
+
+@pytest.mark.parametrize("rule", ["hysime", "sure"])
+def test_hyres_with_a_rank_rule_is_hyres_at_that_rank(rule):
+    cube = synth.config_cube(1, keep_clean=False)
+    a = O.hyres(cube.Y, 8, 3, rank_rule=rule)
+    b = O.hyres(cube.Y, a["rank"], 3)
+    assert 1 <= a["rank"] <= 8
+    assert np.array_equal(a["X"], b["X"])

@@ -102,6 +102,25 @@ typedef struct {
 /* Compute all p eigenvalues of the whitened Gram (otherwise only the top r+1,
  * which the solve needs, are computed and written to hyres_outputs.evals). */
 #define HYRES_FLAG_ALL_EVALS 1
+/* Data-chosen rank (Section 2.1: HyRes is parameter-free, and HySime, the
+ * subspace identification the section names beside it, chooses the subspace
+ * from the data).  With either flag, options.rank is the largest rank r_max
+ * and the rank k used is chosen on the device from the eigenvalues lambda of
+ * the whitened Gram C (n = H W pixels); components k..r_max-1 are zero (their
+ * columns of V are zero and they contribute nothing to X), and k is written
+ * to hyres_outputs.rank.
+ *   HYRES_FLAG_RANK_HYSIME: HySime in the whitened frame, where the noise
+ *     correlation is the identity: k = #{i : lambda_i > 2 n}, the directions
+ *     whose data power exceeds twice the noise power, clamped to [1, r_max].
+ *   HYRES_FLAG_RANK_SURE: the k in [1, r_max] minimising Stein's unbiased
+ *     risk estimate of the rank-k truncation of the whitened cube,
+ *     sum_{j>k} lambda_j - n p + 2 df(k), df(k) = k (n - p + 1) + k (k - 1)
+ *     + 2 sum_{i<=k<j} lambda_i / (lambda_i - lambda_j) (smallest k on ties;
+ *     needs every eigenvalue, so it implies HYRES_FLAG_ALL_EVALS).
+ * The two flags exclude each other (HYRES_E_UNSUPPORTED), as do they and
+ * hyres_denoise_backward. */
+#define HYRES_FLAG_RANK_HYSIME 2
+#define HYRES_FLAG_RANK_SURE 4
 
 /* Optional device outputs of a solve (any pointer may be NULL). */
 typedef struct {
@@ -112,8 +131,9 @@ typedef struct {
                               all p with HYRES_FLAG_ALL_EVALS */
     double* lambda;  /* [r]   soft thresholds */
     double* sure;    /* [r]   SURE at the thresholds */
-    double* gap;     /* [1]   evals[r-1] / evals[r] (Inf when r == p) */
+    double* gap;     /* [1]   evals[k-1] / evals[k] for the rank k used (Inf when k == p) */
     int*    status;  /* [1]   HYRES_DEV_* bits, OR-ed (the caller zeroes it) */
+    int*    rank;    /* [1]   the rank used (options.rank unless a HYRES_FLAG_RANK_* flag chose it) */
 } hyres_outputs;
 
 /* ---- handle ------------------------------------------------------------- */

@@ -22,6 +22,7 @@ DEV_NOT_PD, DEV_NONFINITE, DEV_EIGH_NOCONV, DEV_DEGENERATE, DEV_SURE_INEXACT = 1
 
 
 FLAG_ALL_EVALS = 1
+FLAG_RANK_HYSIME, FLAG_RANK_SURE = 2, 4
 NOALLOC_SCRATCH_BYTES = 96 << 20     # HYRES_NOALLOC_SCRATCH_BYTES
 
 
@@ -32,7 +33,7 @@ class Options(C.Structure):
 
 class Outputs(C.Structure):
     _fields_ = [("sigma", C.c_void_p), ("V", C.c_void_p), ("evals", C.c_void_p), ("lambda_", C.c_void_p),
-                ("sure", C.c_void_p), ("gap", C.c_void_p), ("status", C.c_void_p)]
+                ("sure", C.c_void_p), ("gap", C.c_void_p), ("status", C.c_void_p), ("rank", C.c_void_p)]
 
 
 class Cube(C.Structure):

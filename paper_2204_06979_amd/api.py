@@ -64,6 +64,17 @@ def _need_cuda(t: torch.Tensor, name: str) -> None:
         raise ValueError("%s must be a GPU tensor" % name)
 
 
+def _flags(all_evals: bool, rank_rule: Optional[str]) -> int:
+    f = L.FLAG_ALL_EVALS if all_evals else 0
+    if rank_rule == "hysime":
+        f |= L.FLAG_RANK_HYSIME
+    elif rank_rule == "sure":
+        f |= L.FLAG_RANK_SURE
+    elif rank_rule is not None:
+        raise ValueError("rank_rule must be None, 'hysime' or 'sure'")
+    return f
+
+
 def coeff_count(H: int, W: int, levels: int) -> int:
     n = L.lib().hyres_coeff_count(H, W, levels)
     if n <= 0:
@@ -171,14 +182,14 @@ class Denoiser:
     once, so ``run`` only enqueues kernels (and can be captured in a graph)."""
 
     def __init__(self, H: int, W: int, p: int, rank: int, levels: int, dtype=torch.float32,
-                 precision: str = "native", scope: str = "all", device=None, all_evals: bool = False):
+                 precision: str = "native", scope: str = "all", device=None, all_evals: bool = False,
+                 rank_rule: Optional[str] = None):
         self.device = torch.device(device if device is not None else "cuda")
         self.H, self.W, self.p, self.r, self.L = H, W, p, rank, levels
         self.dtype = dtype
         self.dt = L.HYRES_F32 if dtype == torch.float32 else L.HYRES_F64
         self.opt = L.Options(rank, levels, L.PREC_MIXED if precision == "mixed" else L.PREC_NATIVE,
-                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL,
-                             L.FLAG_ALL_EVALS if all_evals else 0)
+                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL, _flags(all_evals, rank_rule))
         lib = L.lib()
         nb = C.c_size_t()
         L.check(lib.hyres_denoise_workspace_size(H, W, p, C.byref(self.opt), self.dt, C.byref(nb)),
@@ -193,9 +204,10 @@ class Denoiser:
         self.sure = torch.empty(rank, dtype=torch.float64, device=dev)
         self.gap = torch.empty(1, dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.rank = torch.zeros(1, dtype=torch.int32, device=dev)
         self.out = L.Outputs(self.sigma.data_ptr(), self.V.data_ptr(), self.evals.data_ptr(),
                              self.lam.data_ptr(), self.sure.data_ptr(), self.gap.data_ptr(),
-                             self.status.data_ptr())
+                             self.status.data_ptr(), self.rank.data_ptr())
         self.X = torch.empty(H, W, p, dtype=dtype, device=dev)
 
     def run(self, Y: torch.Tensor, sigma: Optional[torch.Tensor] = None,
@@ -211,17 +223,19 @@ class Denoiser:
 
     def info(self) -> Dict[str, torch.Tensor]:
         return dict(sigma=self.sigma, V=self.V.T, evals=self.evals, lam=self.lam, sure=self.sure,
-                    gap=self.gap, status=self.status)
+                    gap=self.gap, status=self.status, rank=self.rank)
 
 
 def denoise(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
             sigma: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
-            scope: str = "all", all_evals: bool = False):
-    """HyRes denoising of one H x W x p cube; returns (X, info)."""
+            scope: str = "all", all_evals: bool = False, rank_rule: Optional[str] = None):
+    """HyRes denoising of one H x W x p cube; returns (X, info).  With
+    ``rank_rule`` ("hysime" or "sure") ``rank`` is the largest rank and
+    info["rank"] the one the device chose."""
     _need_cuda(Y, "Y")
     H, W, p = Y.shape
     dn = Denoiser(H, W, p, rank, levels, dtype=Y.dtype, precision=precision, scope=scope, device=Y.device,
-                  all_evals=all_evals)
+                  all_evals=all_evals, rank_rule=rank_rule)
     sg = None if sigma is None else sigma.to(device=Y.device, dtype=torch.float64).contiguous()
     lm = None if lam is None else lam.to(device=Y.device, dtype=torch.float64).contiguous()
     X = dn.run(Y, sg, lm)
@@ -256,8 +270,10 @@ def denoise_noalloc(Y: torch.Tensor, rank: int, levels: int, precision: str = "n
     lm = None if lam is None else lam.to(device=dev, dtype=torch.float64).contiguous()
     pitch, rp = _cube_strides(Y)
     xp, xrp = _cube_strides(X)
+    if "rank" not in o:
+        o["rank"] = torch.zeros(1, dtype=torch.int32, device=dev)
     outs = L.Outputs(o["sigma"].data_ptr(), o["V"].data_ptr(), o["evals"].data_ptr(), o["lam"].data_ptr(),
-                     o["sure"].data_ptr(), o["gap"].data_ptr(), o["status"].data_ptr())
+                     o["sure"].data_ptr(), o["gap"].data_ptr(), o["status"].data_ptr(), o["rank"].data_ptr())
     L.check(L.lib().hyres_denoise_noalloc(_handle(dev), Y.data_ptr(), H, W, p, pitch, rp, dt, C.byref(opt),
                                           _ptr(sg), _ptr(lm), X.data_ptr(), xp, xrp, C.byref(outs),
                                           _stream(dev)), "hyres_denoise_noalloc")
@@ -277,7 +293,7 @@ class Batch:
     """
 
     def __init__(self, cubes, ranks, levels, precision: str = "native", scope: str = "all",
-                 sigmas=None, lams=None, all_evals: bool = False):
+                 sigmas=None, lams=None, all_evals: bool = False, rank_rule: Optional[str] = None):
         if len(cubes) == 0:
             raise ValueError("empty batch")
         Y0 = cubes[0]
@@ -291,8 +307,7 @@ class Batch:
         if len(ranks) != count or len(levels) != count:
             raise ValueError("ranks and levels need one entry per cube")
         self.opt = L.Options(0, 0, L.PREC_MIXED if precision == "mixed" else L.PREC_NATIVE,
-                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL,
-                             L.FLAG_ALL_EVALS if all_evals else 0)
+                             L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL, _flags(all_evals, rank_rule))
         dev = self.device
         self.Y = list(cubes)
         self.X, self._info, self._keep = [], [], []
@@ -311,7 +326,8 @@ class Batch:
                        lam=torch.empty(r, dtype=torch.float64, device=dev),
                        sure=torch.empty(r, dtype=torch.float64, device=dev),
                        gap=torch.empty(1, dtype=torch.float64, device=dev),
-                       status=torch.zeros(1, dtype=torch.int32, device=dev))
+                       status=torch.zeros(1, dtype=torch.int32, device=dev),
+                       rank=torch.zeros(1, dtype=torch.int32, device=dev))
             sg = None if sigmas is None or sigmas[i] is None else \
                 sigmas[i].to(device=dev, dtype=torch.float64).contiguous()
             lm = None if lams is None or lams[i] is None else \
@@ -319,7 +335,7 @@ class Batch:
             self._keep += [sg, lm]
             out = L.Outputs(inf["sigma"].data_ptr(), inf["V"].data_ptr(), inf["evals"].data_ptr(),
                             inf["lam"].data_ptr(), inf["sure"].data_ptr(), inf["gap"].data_ptr(),
-                            inf["status"].data_ptr())
+                            inf["status"].data_ptr(), inf["rank"].data_ptr())
             xp, xrp = _cube_strides(X)
             arr[i] = L.Cube(Y.data_ptr(), H, W, p, pitch, rp, X.data_ptr(), xp, xrp, r, levels[i],
                             _ptr(sg), _ptr(lm), out)

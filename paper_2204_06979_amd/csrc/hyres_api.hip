@@ -1134,6 +1134,8 @@ hyres_status check_opts(const hyres_options* opt, int p, int dtype) {
     if (!opt) return HYRES_E_NULL;
     hyres_status st = check_rank_levels(opt->rank, opt->levels, p);
     if (st) return st;
+    constexpr int kRankFlags = HYRES_FLAG_RANK_HYSIME | HYRES_FLAG_RANK_SURE;
+    if ((opt->flags & kRankFlags) == kRankFlags) return HYRES_E_UNSUPPORTED;
     return check_prec_scope(opt->precision, opt->scope, dtype);
 }
 
@@ -1153,7 +1155,9 @@ CubeDesc solve_desc(const CubePlan& c, void* ws, const void* Y, int64_t pitch, i
     d.xdense = dense_ok(X, c.W, c.p, x_pitch, x_row_pitch, c.dtype);
     d.sigma_in = sigma_in;
     d.lambda_in = lambda_in;
-    d.mode = (sigma_in ? 0 : 1) | 2 | 8 | ((flags & HYRES_FLAG_ALL_EVALS) ? 16 : 0);
+    d.mode = (sigma_in ? 0 : 1) | 2 | 8 | ((flags & (HYRES_FLAG_ALL_EVALS | HYRES_FLAG_RANK_SURE)) ? 16 : 0) |
+             ((flags & HYRES_FLAG_RANK_HYSIME) ? kModeRankHySime : 0) |
+             ((flags & HYRES_FLAG_RANK_SURE) ? kModeRankSure : 0);
     if (out) {
         if (out->sigma) d.sigma = out->sigma;
         if (out->V) d.V = out->V;
@@ -1162,6 +1166,7 @@ CubeDesc solve_desc(const CubePlan& c, void* ws, const void* Y, int64_t pitch, i
         if (out->lambda) d.lambda = out->lambda;
         if (out->sure) d.sure = out->sure;
         d.status = out->status;
+        d.rank_out = out->rank;
     }
     return d;
 }
@@ -1739,6 +1744,8 @@ hyres_status plan_backward(BwdPlan& b, hyres_handle* h, int H, int W, int p, con
     // a mixed-precision forward keeps a Rayleigh-Ritz basis that is not an
     // eigenbasis of the Gram the eigen-adjoint differentiates
     if (opt->precision == HYRES_PREC_MIXED) return HYRES_E_UNSUPPORTED;
+    // a data-chosen rank is piecewise constant; the adjoint takes the rank as given
+    if (opt->flags & (HYRES_FLAG_RANK_HYSIME | HYRES_FLAG_RANK_SURE)) return HYRES_E_UNSUPPORTED;
     one_cube(b.fwd, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
     if ((st = plan_cubes(b.fwd, kAllParts))) return st;
     const CubePlan& c = b.fwd.plan[0];

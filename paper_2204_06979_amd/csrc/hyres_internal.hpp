@@ -53,6 +53,8 @@ constexpr int kModeThreshold = 8;  // the inverse transform soft-thresholds its 
 constexpr int kModeAllEvals = 16;  // every eigenvalue
 constexpr int kModeZeroPad = 32;   // analysis with a zero extra sample (transpose of the inverse)
 constexpr int kModeFold = 64;      // synthesis folding the extra sample (transpose of the analysis)
+constexpr int kModeRankHySime = 128;   // rank chosen by HySime on the whitened cube
+constexpr int kModeRankSure = 256;     // rank chosen by SURE of the truncated whitened cube
 
 // Everything a kernel needs to know about one cube.  Pointers are device pointers.
 struct CubeDesc {
@@ -75,6 +77,7 @@ struct CubeDesc {
     double* V;                              // p x r column-major
     double* evals;                          // p, descending
     double* gap;                            // 1
+    int* rank_out;                          // 1: the rank used (may be null)
     float* P32; float* Q32;                 // (16T x 16) projection and (16 x 16T) back-projection
     double* P64; double* Q64;               // (p x r) and (r x p)
     float* rpart;                           // Rayleigh-Ritz: T^T T per 64-pixel tile, 16 x 16 (mixed solves)

@@ -149,6 +149,8 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     __shared__ double s_red[4];
     __shared__ double s_vav[NW];                     // per-wave shares of v^T A v
     __shared__ int s_kb[kMaxRank];                   // twist indices
+    __shared__ double s_cross[kMaxRank][kMaxRank + 1];   // rank by SURE: sum_{j>=k} l_i / (l_i - l_j), [i][k]
+    __shared__ int s_rank;                           // rank used
     __shared__ int s_flags;
 
     if (t == 0) s_flags = 0;
@@ -465,6 +467,53 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
         }
         __syncthreads();
 
+        // ----------------------------------------------- data-chosen rank
+        // (eigenvalues in s_ev, descending).  HySime on the whitened cube:
+        // every eigenvalue above twice the noise power n.  SURE: the rank k
+        // minimising sum_{j>=k} lambda_j - n p + 2 df(k) (0-based j), df(k) =
+        // k (n - p + 1) + k (k - 1) + 2 sum_{i<k<=j} lambda_i / (lambda_i -
+        // lambda_j), every eigenvalue known; the cross sums are spread over
+        // the threads, one (i, k) pair each.
+        if (t == 0) s_rank = r;
+        if (d.mode & kModeRankSure) {
+            for (int e = t; e < r * r; e += NTH) {
+                const int i = e / r, k = e % r + 1;
+                double acc = 0.0;
+                if (i < k) {
+                    const double li = s_ev[i];
+                    for (int j = k; j < p; ++j) acc += li / (li - s_ev[j]);
+                }
+                s_cross[i][k] = acc;
+            }
+            __syncthreads();
+            if (t == 0) {
+                const double n = (double)d.n, pp = (double)p;
+                double tail = 0.0;                       // sum_{j >= k} lambda_j
+                for (int j = r; j < p; ++j) tail += s_ev[j];
+                double best = __builtin_inf();
+                int bk = 1;
+                for (int k = r; k >= 1; --k) {
+                    double cr = 0.0;
+                    for (int i = 0; i < k; ++i) cr += s_cross[i][k];
+                    const double df = k * (n - pp + 1.0) + k * (k - 1.0) + 2.0 * cr;
+                    const double sv = tail - n * pp + 2.0 * df;
+                    if (sv <= best) {     // descending k: the last minimum is the smallest rank
+                        best = sv;
+                        bk = k;
+                    }
+                    tail += s_ev[k - 1];
+                }
+                s_rank = bk;
+            }
+        } else if ((d.mode & kModeRankHySime) && t == 0) {
+            const double thr = 2.0 * (double)d.n;
+            int k = 0;
+            while (k < r && s_ev[k] > thr) ++k;
+            s_rank = k < 1 ? 1 : k;
+        }
+        __syncthreads();
+        const int kr = s_rank;
+
         HYRES_STAMP(d, 3);
         // ---------------------------- eigenvectors of the tridiagonal matrix
         // Twisted factorisation at each eigenvalue mu: the top-down pivots D_i
@@ -696,7 +745,8 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                     for (int q = 0; q < 4; ++q) {
                         const int i = lane + 64 * q;
                         if (i < p) {
-                            const double val = zr[v][q] * sgn;
+                            // components beyond the chosen rank are zero
+                            const double val = g < kr ? zr[v][q] * sgn : 0.0;
                             bad |= !__builtin_isfinite(val);
                             s_z[g][i] = val;
                             d.V[(int64_t)g * p + i] = val;
@@ -724,11 +774,12 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
         }
         if (t == 0) {
             double gp = __builtin_inf();
-            if (r < p) {
-                gp = s_ev[r - 1] / s_ev[r];
+            if (kr < p) {
+                gp = s_ev[kr - 1] / s_ev[kr];
                 if (!(gp >= 1.0 + 1e-6)) flags |= HYRES_DEV_DEGENERATE;
             }
             d.gap[0] = gp;
+            if (d.rank_out) *d.rank_out = kr;
         }
     }
     if (flags) atomicOr(&s_flags, flags);

@@ -153,3 +153,16 @@ def test_batch_workspace_and_validation():
     bp = C.c_void_p()
     assert lib.hyres_batch_create(C.cast(fake, C.c_void_p), cubes, 3, L.HYRES_F32, C.byref(opt), None, 0, None,
                                   C.byref(bp)) == 1
+
+
+def test_rank_flags_validation():
+    """Both rank rules at once, and a data-chosen rank with the adjoint, are refused."""
+    L, lib = _lib()
+    nb = C.c_size_t()
+    for f in (L.FLAG_RANK_HYSIME, L.FLAG_RANK_SURE):
+        assert lib.hyres_denoise_workspace_size(64, 64, 32, C.byref(L.Options(8, 3, 0, 0, f)), L.HYRES_F32,
+                                                C.byref(nb)) == 0
+        assert lib.hyres_denoise_backward_workspace_size(64, 64, 32, C.byref(L.Options(8, 3, 0, 0, f)),
+                                                         L.HYRES_F32, C.byref(nb)) == 6
+    both = L.Options(8, 3, 0, 0, L.FLAG_RANK_HYSIME | L.FLAG_RANK_SURE)
+    assert lib.hyres_denoise_workspace_size(64, 64, 32, C.byref(both), L.HYRES_F32, C.byref(nb)) == 6

@@ -147,19 +147,27 @@ def test_subspace_matches_oracle():
 
 
 # ------------------------------------------------------------- end to end
-def _check_denoise(Y, r, L, tol, sigma=None, lam=None, name="", precision="native", scope="all"):
+def _check_denoise(Y, r, L, tol, sigma=None, lam=None, name="", precision="native", scope="all",
+                   rank_rule=None):
     api = _api()
-    say("denoise", name, Y.shape, Y.dtype, "r", r, "L", L, precision, scope)
+    say("denoise", name, Y.shape, Y.dtype, "r", r, "L", L, precision, scope, rank_rule)
     Yt = torch.tensor(Y, device="cuda")
     X, info = api.denoise(Yt, r, L, precision=precision,
                           sigma=None if sigma is None else torch.tensor(sigma),
-                          lam=None if lam is None else torch.tensor(lam), scope=scope)
+                          lam=None if lam is None else torch.tensor(lam), scope=scope, rank_rule=rank_rule)
     X = X.cpu().numpy()
     st = int(info["status"].cpu()[0])
     assert st & ~8 == 0, st
     det = scope == "detail"
-    ref = O.hyres(Y.astype(np.float64), r, L, sigma=sigma, lam=lam, detail_only=det)
-    lam_g = info["lam"].cpu().numpy()
+    ref = O.hyres(Y.astype(np.float64), r, L, sigma=sigma, lam=lam, detail_only=det, rank_rule=rank_rule)
+    if rank_rule is not None:
+        # the device's choice is the oracle's; the components beyond it are zero
+        k = int(info["rank"].cpu()[0])
+        say("   rank", rank_rule, "device", k, "oracle", ref["rank"])
+        assert k == ref["rank"], (k, ref["rank"])
+        assert not info["V"][:, k:].any()
+        r = k
+    lam_g = info["lam"].cpu().numpy()[:r]
     if lam is None:
         eps = SP.EPS["mixed" if precision == "mixed" else Y.dtype.name]
         other = False
@@ -178,6 +186,7 @@ def _check_denoise(Y, r, L, tol, sigma=None, lam=None, name="", precision="nativ
         # the SURE candidate set of the detail scope excludes LL_L
         if other:
             ref = O.hyres(Y.astype(np.float64), r, L, sigma=sigma, lam=lam_g, detail_only=det)
+            ref["rank"] = r
     e, emax = PM.errors(X, ref["X"])
     say("   rel err", e, "max err / max", emax, "lam gpu", lam_g, "lam ref", ref["lam"])
     PM.assert_close(X, ref["X"], tol, name)
@@ -253,6 +262,17 @@ def test_denoise_fp32_native_224_bands_matches_oracle():
     Y = (c.Y + 1e-3 * np.random.default_rng(224).standard_normal(c.Y.shape)).astype(np.float32)
     _check_denoise(Y, 10, 4, 1e-5, name="p224-native")
     _check_denoise(Y, 10, 4, 1e-3, name="p224-mixed", precision="mixed")
+
+
+@pytest.mark.parametrize("rule", ["hysime", "sure"])
+def test_denoise_with_data_chosen_rank(rule):
+    """The rank chosen on the device (HySime, or SURE of the truncated whitened
+    cube) equals the oracle's, and the solve at that rank matches: the
+    64 x 64 x 32 FP64 cube and the 349 x 1905 x 144 FP32 cube, largest rank 8."""
+    cube = synth.config_cube(1, keep_clean=False)
+    _check_denoise(cube.Y, 8, 3, 1e-10, name="c1-" + rule, rank_rule=rule)
+    cube = synth.config_cube(2, keep_clean=False)
+    _check_denoise(cube.Y, 8, 4, 1e-5, name="c2-" + rule, rank_rule=rule)
 
 
 def test_denoise_is_deterministic():

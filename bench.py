@@ -465,7 +465,7 @@ def run_tiled(args, api, synth, precs):
         lam = info["lam"].cpu().numpy()
         acc = np.zeros((y1 - y0, x1 - x0, p))
         ws = np.zeros((y1 - y0, x1 - x0))
-        c0 = time.perf_counter()
+        t_or = time.perf_counter()
         for iy in range(2):
             a, b = max(y0, sy[iy]), min(y1, sy[iy] + tile)
             for ix in range(2):
@@ -476,7 +476,7 @@ def run_tiled(args, api, synth, precs):
                 acc[a - y0:b - y0, c0 - x0:c1 - x0] += w2[:, :, None] * Xt[a - sy[iy]:b - sy[iy], c0 - sx[ix]:c1 - sx[ix]]
                 ws[a - y0:b - y0, c0 - x0:c1 - x0] += w2
         if cpu is None:
-            cpu = (time.perf_counter() - c0) / 4 * len(shapes)
+            cpu = (time.perf_counter() - t_or) / 4 * len(shapes)
         e["errors_vs_fp64_oracle"] = dict(window=[y0, y1, x0, x1], thresholds="device's",
                                           **x_errors(X[y0:y1, x0:x1].double().cpu().numpy(), acc / ws[:, :, None]))
         res[prec] = e

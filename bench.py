@@ -489,13 +489,76 @@ def run_tiled(args, api, synth, precs):
                              "scaled to the 25 tiles (blend not timed)"}
 
 
+# VALU lane-operations per band and sweep of the l1-l1 stage: forward
+# elimination with the fused shrinkage and Bregman updates (t: 2, clip: 1,
+# h - s + b1: 2, v: 2, clip: 1, u - b2 and its mask: 3, rhs: 3, pivot: 2) and
+# the back substitution (1).
+L1_OPS_PER_BAND_SWEEP = 17
+# FP32 vector peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def run_hyminor(args, api, synth):
+    """HyMiNoR on the 349 x 1905 x 144 FP32 cube: HyRes (rank 8, 4 levels,
+    native FP32), then the l1-l1 sparse-noise stage (lam 0.55, mu1 = mu2 = 1,
+    50 sweeps) in place; the stage is also timed alone on the device's HyRes
+    output and checked against the oracle on 2000 sampled pixels."""
+    import torch
+    from oracle import hyminor_oracle as HM
+    cube = synth.config_cube(2, keep_clean=False)
+    Yh = cube.Y
+    H, W, p = Yh.shape
+    r, L = 8, 4
+    lam, mu1, mu2, K = 0.55, 1.0, 1.0, 50
+    Y = torch.tensor(Yh, device="cuda")
+    Ys = [Y, Y.clone()]
+    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32, device=Y.device)
+    l1 = api.L.L1Options(lam, mu1, mu2, K)
+    run = lambda i: dn.run_hyminor(Ys[i % 2], l1)        # noqa: E731
+    for i in range(max(args.warmup, 1)):
+        run(i)
+    t = timed_steps(run, args.steps)
+    n = H * W
+    e = rate_entry(float(n * p), t, solve_bytes([(H, W, p, r, L)]) + 2.0 * n * p * 4)
+    # the stage alone on the device's HyRes output
+    X1 = dn.run(Y).clone()
+    Xs = torch.empty_like(X1)
+    stage = lambda i: api.l1l1_spectral(X1, lam, mu1, mu2, K, X=Xs)     # noqa: E731
+    for i in range(max(args.warmup, 1)):
+        stage(i)
+    ts = timed_steps(stage, args.steps)
+    ms = ts["olympic"]["mean_ms"]
+    ops = float(L1_OPS_PER_BAND_SWEEP) * p * K * n
+    achieved = ops / (ms * 1e-3) / 1e12
+    e["l1l1_ms"] = ms
+    e["l1l1_olympic"] = ts["olympic"]
+    e["roofline_l1l1"] = {"bound": "alu", "kernel": "l1l1", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                          "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel_ms": ms}
+    rng = np.random.default_rng(4)
+    idx = torch.tensor(rng.choice(n, 2000, replace=False), device="cuda")
+    h = X1.reshape(n, p)[idx].cpu().numpy().astype(np.float64)
+    got = Xs.reshape(n, p)[idx].cpu().numpy()
+    t0 = time.perf_counter()
+    ref = HM.l1l1_split_bregman(h, lam, mu1, mu2, K)
+    cpu_stage = (time.perf_counter() - t0) * n / 2000
+    e["errors_vs_fp64_oracle_stage"] = dict(pixels=2000, **x_errors(got, ref))
+    e["oracle_stage_estimate_s"] = cpu_stage
+    e["oracle_stage_sample"] = "oracle l1-l1 iteration on 2000 sampled pixels, scaled by pixels to the cube"
+    e["device_status"] = int(dn.status.cpu()[0])
+    e["workload"] = ("HyMiNoR of the 349x1905x144 FP32 cube: HyRes rank 8, 4 levels, native FP32, then the "
+                     "per-pixel l1-l1 spectral stage, lam 0.55, mu1 = mu2 = 1, 50 sweeps")
+    log("hyminor %.3f ms/step, l1l1 stage %.3f ms (%.2f of the VALU peak)" % (t["ms_per_step"], ms,
+                                                                                achieved / VALU_PEAK_TOPS))
+    return e
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=["native", "mixed", "both"])
-    ap.add_argument("--workload", default="all", choices=["all", "single", "small", "grad", "batch", "tiled"])
+    ap.add_argument("--workload", default="all", choices=["all", "single", "small", "grad", "batch", "tiled", "hyminor"])
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -514,11 +577,12 @@ def main() -> int:
     timer = Timer(_lib, lib, api._handle(dev))
     precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
     others = {}
-    if args.workload in ("small", "grad", "batch", "tiled"):
+    if args.workload in ("small", "grad", "batch", "tiled", "hyminor"):
         # one secondary workload alone: its own line
         fn = {"small": lambda: run_small_fp64(args, api, synth), "grad": lambda: run_grad(args, api, synth),
               "batch": lambda: run_batch(args, api, synth, precs),
-              "tiled": lambda: run_tiled(args, api, synth, precs)}[args.workload]
+              "tiled": lambda: run_tiled(args, api, synth, precs),
+              "hyminor": lambda: run_hyminor(args, api, synth)}[args.workload]
         e = fn()
         print(json.dumps({"metric": METRIC, "workload": args.workload, "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "result": e}))
@@ -529,7 +593,8 @@ def main() -> int:
         for name, fn in (("small_64x64x32_fp64", lambda: run_small_fp64(args, api, synth)),
                          ("grad_256x256x191_fwd_bwd", lambda: run_grad(args, api, synth)),
                          ("batch64", lambda: run_batch(args, api, synth, precs)),
-                         ("tiled_2048x2048x224", lambda: run_tiled(args, api, synth, precs))):
+                         ("tiled_2048x2048x224", lambda: run_tiled(args, api, synth, precs)),
+                         ("hyminor_349x1905x144", lambda: run_hyminor(args, api, synth))):
             t0 = time.time()
             others[name] = fn()
             log("%s done in %.1f s" % (name, time.time() - t0))

@@ -134,6 +134,10 @@ typedef struct {
     double* gap;     /* [1]   evals[k-1] / evals[k] for the rank k used (Inf when k == p) */
     int*    status;  /* [1]   HYRES_DEV_* bits, OR-ed (the caller zeroes it) */
     int*    rank;    /* [1]   the rank used (options.rank unless a HYRES_FLAG_RANK_* flag chose it) */
+    double* eig_check; /* [2] accuracy of the FP64 eigensolve, on the whitened Gram C it decomposed
+                              (before the Rayleigh-Ritz refinement of the mixed path), over the k
+                              eigenpairs used: [0] ||C V - V Lambda||_F / ||C||_F, [1] max |V^T V - I|;
+                              computed only when this pointer is set (a few microseconds) */
 } hyres_outputs;
 
 /* ---- handle ------------------------------------------------------------- */
@@ -258,6 +262,54 @@ hyres_status hyres_denoise_noalloc(hyres_handle* h, const void* Y, int H, int W,
                                    const double* lambda_in, void* X, int64_t x_pitch,
                                    int64_t x_row_pitch, const hyres_outputs* out,
                                    hyres_stream_t stream);
+
+/* ---- HyMiNoR: HyRes, then the sparse-noise stage ------------------------- */
+
+/* Defined by: Section 2.1 -- HyMiNoR is built on HyRes: after HyRes has removed
+ * the Gaussian noise, the sparse noise that remains is removed by an l1-l1
+ * problem solved with split Bregman.  The paper states neither the problem nor
+ * the iteration; this library takes, per pixel spectrum h (p bands),
+ *     x = argmin_x ||h - x||_1 + lam ||D x||_1,   (D x)_i = x_{i+1} - x_i,
+ * (l1 data term: a few bands may move far; l1 first-order spectral roughness:
+ * spectral edges are kept), by split Bregman with s = h - x and u = D x,
+ * penalties mu1 and mu2, every auxiliary and Bregman variable starting at 0:
+ *     x  <- (mu1 I + mu2 D^T D)^-1 (mu1 (h - s + b1) + mu2 D^T (u - b2))
+ *     s  <- soft(h - x + b1, 1/mu1),   u <- soft(D x + b2, lam/mu2)
+ *     b1 <- b1 + h - x - s,            b2 <- b2 + D x - u
+ * for `iters` sweeps; the result is the x of the last sweep.  lam is
+ * dimensionless (the problem is 1-homogeneous in h); 1/mu1 and lam/mu2 are
+ * thresholds in the units of h.  An isolated one-band spike is removed when
+ * lam > 1/2. */
+typedef struct {
+    double lam;      /* >= 0 */
+    double mu1;      /* > 0 */
+    double mu2;      /* > 0 */
+    int    iters;    /* >= 1 */
+} hyres_l1l1_options;
+
+/* The sparse-noise stage alone on an H x W x p cube Hc (device, dtype
+ * HYRES_F32 or HYRES_F64, pitch / row_pitch as for Y, 1 <= p <= 224; FP64
+ * cubes of more than 224 bands are not handled).  Each pixel's spectrum is read
+ * whole before its result is written, so X may be Hc itself (same pitches);
+ * otherwise X must not overlap Hc.  Needs no workspace.  Computed in the
+ * cube's precision (the tridiagonal factors are formed in FP64).
+ * HYRES_E_SHAPE for bad sizes, pitches or options (mu1 or mu2 <= 0, lam < 0,
+ * iters < 1, non-finite values). */
+hyres_status hyres_l1l1_spectral(hyres_handle* h, const void* Hc, int H, int W, int p,
+                                 int64_t pitch, int64_t row_pitch, int dtype,
+                                 const hyres_l1l1_options* opt, void* X, int64_t x_pitch,
+                                 int64_t x_row_pitch, hyres_stream_t stream);
+
+/* HyMiNoR: hyres_denoise (same arguments, options, outputs and workspace:
+ * hyres_denoise_workspace_size gives its size), then hyres_l1l1_spectral on
+ * its output, in place in X.  The outputs describe the HyRes stage. */
+hyres_status hyres_hyminor(hyres_handle* h, const void* Y, int H, int W, int p,
+                           int64_t pitch, int64_t row_pitch, int dtype,
+                           const hyres_options* opt, const double* sigma_in,
+                           const double* lambda_in, const hyres_l1l1_options* l1,
+                           void* X, int64_t x_pitch, int64_t x_row_pitch,
+                           const hyres_outputs* out, void* workspace, size_t workspace_bytes,
+                           hyres_stream_t stream);
 
 /* ---- batches of cubes ---------------------------------------------------- */
 

@@ -33,7 +33,12 @@ class Options(C.Structure):
 
 class Outputs(C.Structure):
     _fields_ = [("sigma", C.c_void_p), ("V", C.c_void_p), ("evals", C.c_void_p), ("lambda_", C.c_void_p),
-                ("sure", C.c_void_p), ("gap", C.c_void_p), ("status", C.c_void_p), ("rank", C.c_void_p)]
+                ("sure", C.c_void_p), ("gap", C.c_void_p), ("status", C.c_void_p), ("rank", C.c_void_p),
+                ("eig_check", C.c_void_p)]
+
+
+class L1Options(C.Structure):
+    _fields_ = [("lam", C.c_double), ("mu1", C.c_double), ("mu2", C.c_double), ("iters", C.c_int)]
 
 
 class Cube(C.Structure):
@@ -71,6 +76,9 @@ SIGNATURES = {
     "hyres_profile_read": (i32, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "hyres_denoise": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp, vp, i64, i64,
                             C.POINTER(Outputs), vp, sz, vp]),
+    "hyres_l1l1_spectral": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(L1Options), vp, i64, i64, vp]),
+    "hyres_hyminor": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp,
+                            C.POINTER(L1Options), vp, i64, i64, C.POINTER(Outputs), vp, sz, vp]),
     "hyres_denoise_noalloc": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp, vp, i64,
                                     i64, C.POINTER(Outputs), vp]),
     "hyres_batch_workspace_size": (i32, [C.POINTER(Cube), i32, i32, C.POINTER(Options), C.POINTER(sz)]),

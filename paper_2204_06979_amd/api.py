@@ -183,7 +183,7 @@ class Denoiser:
 
     def __init__(self, H: int, W: int, p: int, rank: int, levels: int, dtype=torch.float32,
                  precision: str = "native", scope: str = "all", device=None, all_evals: bool = False,
-                 rank_rule: Optional[str] = None):
+                 rank_rule: Optional[str] = None, check_eigs: bool = False):
         self.device = torch.device(device if device is not None else "cuda")
         self.H, self.W, self.p, self.r, self.L = H, W, p, rank, levels
         self.dtype = dtype
@@ -205,9 +205,10 @@ class Denoiser:
         self.gap = torch.empty(1, dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.rank = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.eig_check = torch.zeros(2, dtype=torch.float64, device=dev) if check_eigs else None
         self.out = L.Outputs(self.sigma.data_ptr(), self.V.data_ptr(), self.evals.data_ptr(),
                              self.lam.data_ptr(), self.sure.data_ptr(), self.gap.data_ptr(),
-                             self.status.data_ptr(), self.rank.data_ptr())
+                             self.status.data_ptr(), self.rank.data_ptr(), _ptr(self.eig_check))
         self.X = torch.empty(H, W, p, dtype=dtype, device=dev)
 
     def run(self, Y: torch.Tensor, sigma: Optional[torch.Tensor] = None,
@@ -221,24 +222,75 @@ class Denoiser:
                                       _stream(self.device)), "hyres_denoise")
         return X
 
+    def run_hyminor(self, Y: torch.Tensor, l1: "L.L1Options", sigma: Optional[torch.Tensor] = None,
+                    lam: Optional[torch.Tensor] = None, X: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """HyRes, then the sparse-noise stage in place in X (hyres_hyminor)."""
+        pitch, rp = _cube_strides(Y)
+        X = self.X if X is None else X
+        xp, xrp = _cube_strides(X)
+        L.check(L.lib().hyres_hyminor(_handle(self.device), Y.data_ptr(), self.H, self.W, self.p, pitch, rp,
+                                      self.dt, C.byref(self.opt), _ptr(sigma), _ptr(lam), C.byref(l1),
+                                      X.data_ptr(), xp, xrp, C.byref(self.out), self._ws, self.ws_bytes,
+                                      _stream(self.device)), "hyres_hyminor")
+        return X
+
     def info(self) -> Dict[str, torch.Tensor]:
-        return dict(sigma=self.sigma, V=self.V.T, evals=self.evals, lam=self.lam, sure=self.sure,
+        info = dict(sigma=self.sigma, V=self.V.T, evals=self.evals, lam=self.lam, sure=self.sure,
                     gap=self.gap, status=self.status, rank=self.rank)
+        if self.eig_check is not None:
+            info["eig_resid"], info["eig_orth"] = self.eig_check[0:1], self.eig_check[1:2]
+        return info
 
 
 def denoise(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
             sigma: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
-            scope: str = "all", all_evals: bool = False, rank_rule: Optional[str] = None):
+            scope: str = "all", all_evals: bool = False, rank_rule: Optional[str] = None,
+            check_eigs: bool = False):
     """HyRes denoising of one H x W x p cube; returns (X, info).  With
     ``rank_rule`` ("hysime" or "sure") ``rank`` is the largest rank and
-    info["rank"] the one the device chose."""
+    info["rank"] the one the device chose.  With ``check_eigs`` info also holds
+    the eigensolve's relative residual ``eig_resid`` and orthonormality error
+    ``eig_orth``."""
     _need_cuda(Y, "Y")
     H, W, p = Y.shape
     dn = Denoiser(H, W, p, rank, levels, dtype=Y.dtype, precision=precision, scope=scope, device=Y.device,
-                  all_evals=all_evals, rank_rule=rank_rule)
+                  all_evals=all_evals, rank_rule=rank_rule, check_eigs=check_eigs)
     sg = None if sigma is None else sigma.to(device=Y.device, dtype=torch.float64).contiguous()
     lm = None if lam is None else lam.to(device=Y.device, dtype=torch.float64).contiguous()
     X = dn.run(Y, sg, lm)
+    return X, dn.info()
+
+
+def l1l1_spectral(Hc: torch.Tensor, lam: float = 1.0, mu1: float = 1.0, mu2: float = 1.0, iters: int = 50,
+                  X: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """HyMiNoR's sparse-noise stage alone: per pixel spectrum h of the
+    H x W x p cube ``Hc``, ``iters`` split-Bregman sweeps of
+    argmin_x ||h - x||_1 + lam ||D x||_1 (D the first-order spectral
+    difference; penalties mu1, mu2).  ``X`` may be ``Hc`` (in place)."""
+    _need_cuda(Hc, "Hc")
+    H, W, p = Hc.shape
+    X = torch.empty_like(Hc) if X is None else X
+    pitch, rp = _cube_strides(Hc)
+    xp, xrp = _cube_strides(X)
+    o = L.L1Options(float(lam), float(mu1), float(mu2), int(iters))
+    L.check(L.lib().hyres_l1l1_spectral(_handle(Hc.device), Hc.data_ptr(), H, W, p, pitch, rp, _dtype_code(Hc),
+                                        C.byref(o), X.data_ptr(), xp, xrp, _stream(Hc.device)),
+            "hyres_l1l1_spectral")
+    return X
+
+
+def hyminor(Y: torch.Tensor, rank: int, levels: int, lam: float = 1.0, mu1: float = 1.0, mu2: float = 1.0,
+            iters: int = 50, precision: str = "native", sigma: Optional[torch.Tensor] = None,
+            hyres_lam: Optional[torch.Tensor] = None, rank_rule: Optional[str] = None):
+    """HyMiNoR: HyRes of the cube, then the sparse-noise stage on its output;
+    returns (X, info) with info describing the HyRes stage."""
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    dn = Denoiser(H, W, p, rank, levels, dtype=Y.dtype, precision=precision, device=Y.device,
+                  rank_rule=rank_rule)
+    sg = None if sigma is None else sigma.to(device=Y.device, dtype=torch.float64).contiguous()
+    lm = None if hyres_lam is None else hyres_lam.to(device=Y.device, dtype=torch.float64).contiguous()
+    X = dn.run_hyminor(Y, L.L1Options(float(lam), float(mu1), float(mu2), int(iters)), sg, lm)
     return X, dn.info()
 
 

@@ -11,6 +11,7 @@
 // prefix-summed work-item table over the whole cube list, in which cubes
 // outside the class own no items; the kernels are persistent over that table.
 #include <algorithm>
+#include <cmath>
 #include <functional>
 #include <cstdio>
 #include <cstring>
@@ -1167,6 +1168,7 @@ CubeDesc solve_desc(const CubePlan& c, void* ws, const void* Y, int64_t pitch, i
         if (out->sure) d.sure = out->sure;
         d.status = out->status;
         d.rank_out = out->rank;
+        d.eig_check = out->eig_check;
     }
     return d;
 }
@@ -1570,6 +1572,62 @@ HYRES_API hyres_status hyres_denoise_noalloc(hyres_handle* h, const void* Y, int
                                              hyres_stream_t stream) {
     return denoise_one(h, Y, H, W, p, pitch, row_pitch, dtype, opt, sigma_in, lambda_in, X, x_pitch, x_row_pitch,
                        out, true, nullptr, 0, stream);
+}
+
+// ------------------------------------------------------------- HyMiNoR
+static hyres_status check_l1l1(int H, int W, int p, int64_t pitch, int64_t row_pitch, int dtype,
+                               const hyres_l1l1_options* o, int64_t x_pitch, int64_t x_row_pitch) {
+    if (!o) return HYRES_E_NULL;
+    if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
+    if (H < 1 || W < 1 || p < 1 || p > kMaxBands) return HYRES_E_SHAPE;
+    if (pitch < p || row_pitch < (int64_t)(W - 1) * pitch + p) return HYRES_E_SHAPE;
+    if (x_pitch < p || x_row_pitch < (int64_t)(W - 1) * x_pitch + p) return HYRES_E_SHAPE;
+    if ((int64_t)H * W > (int64_t)1 << 31) return HYRES_E_UNSUPPORTED;
+    if (!(o->mu1 > 0.0) || !(o->mu2 > 0.0) || !(o->lam >= 0.0) || o->iters < 1 ||
+        !std::isfinite(o->mu1) || !std::isfinite(o->mu2) || !std::isfinite(o->lam))
+        return HYRES_E_SHAPE;
+    int S = 0, M = 0;
+    if (!l1l1_shape(p, dtype, &S, &M)) return HYRES_E_UNSUPPORTED;
+    return HYRES_OK;
+}
+
+static hyres_status enqueue_l1l1(hyres_handle* h, const void* Hc, int H, int W, int p, int64_t pitch,
+                                 int64_t row_pitch, int dtype, const hyres_l1l1_options* o, void* X, int64_t x_pitch,
+                                 int64_t x_row_pitch, hipStream_t s) {
+    L1Args a{};
+    a.Hc = Hc; a.pitch = pitch; a.row_pitch = row_pitch;
+    a.X = X; a.xpitch = x_pitch; a.xrow_pitch = x_row_pitch;
+    a.H = H; a.W = W; a.p = p; a.iters = o->iters; a.dtype = dtype;
+    a.lam = o->lam; a.mu1 = o->mu1; a.mu2 = o->mu2;
+    return launch_l1l1(a, h->num_cu, s) == hipSuccess ? HYRES_OK : HYRES_E_HIP;
+}
+
+HYRES_API hyres_status hyres_l1l1_spectral(hyres_handle* h, const void* Hc, int H, int W, int p, int64_t pitch,
+                                           int64_t row_pitch, int dtype, const hyres_l1l1_options* opt, void* X,
+                                           int64_t x_pitch, int64_t x_row_pitch, hyres_stream_t stream) {
+    if (!h || !Hc || !X) return HYRES_E_NULL;
+    hyres_status st = check_l1l1(H, W, p, pitch, row_pitch, dtype, opt, x_pitch, x_row_pitch);
+    if (st) return st;
+    // in place only with the same layout (each pixel is read whole before it is written)
+    if (X == Hc && (pitch != x_pitch || row_pitch != x_row_pitch)) return HYRES_E_SHAPE;
+    if ((st = set_device(h))) return st;
+    return enqueue_l1l1(h, Hc, H, W, p, pitch, row_pitch, dtype, opt, X, x_pitch, x_row_pitch,
+                        (hipStream_t)stream);
+}
+
+HYRES_API hyres_status hyres_hyminor(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                     int64_t row_pitch, int dtype, const hyres_options* opt,
+                                     const double* sigma_in, const double* lambda_in, const hyres_l1l1_options* l1,
+                                     void* X, int64_t x_pitch, int64_t x_row_pitch, const hyres_outputs* out,
+                                     void* workspace, size_t workspace_bytes, hyres_stream_t stream) {
+    if (!h || !Y || !X) return HYRES_E_NULL;
+    hyres_status st = check_l1l1(H, W, p, pitch, row_pitch, dtype, l1, x_pitch, x_row_pitch);
+    if (st) return st;
+    st = denoise_one(h, Y, H, W, p, pitch, row_pitch, dtype, opt, sigma_in, lambda_in, X, x_pitch, x_row_pitch,
+                     out, false, workspace, workspace_bytes, stream);
+    if (st) return st;
+    return enqueue_l1l1(h, X, H, W, p, x_pitch, x_row_pitch, dtype, l1, X, x_pitch, x_row_pitch,
+                        (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------- batches

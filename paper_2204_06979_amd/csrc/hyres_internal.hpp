@@ -78,6 +78,7 @@ struct CubeDesc {
     double* evals;                          // p, descending
     double* gap;                            // 1
     int* rank_out;                          // 1: the rank used (may be null)
+    double* eig_check;                      // 2: eigenpair residual and orthonormality (may be null)
     float* P32; float* Q32;                 // (16T x 16) projection and (16 x 16T) back-projection
     double* P64; double* Q64;               // (p x r) and (r x p)
     float* rpart;                           // Rayleigh-Ritz: T^T T per 64-pixel tile, 16 x 16 (mixed solves)
@@ -114,6 +115,17 @@ struct CubeDesc {
     uint32_t pmag;                          // floor(2^32 / p) + 1: e / p == umulhi(e, pmag) for 0 <= e < 64 p
     unsigned long long* dbg;                // phase time stamps (timing builds only; null otherwise)
 };
+
+// Per-pixel spectral l1-l1 problem by split Bregman (HyMiNoR's sparse stage).
+constexpr int kL1MaxSeg = 64;      // bands of one pixel held by one lane
+struct L1Args {
+    const void* Hc; int64_t pitch, row_pitch;
+    void* X;        int64_t xpitch, xrow_pitch;
+    int H, W, p, iters, dtype;
+    double lam, mu1, mu2;
+};
+bool l1l1_shape(int p, int dtype, int* S, int* M);
+hipError_t launch_l1l1(const L1Args& a, int num_cu, hipStream_t st);
 
 // Tile grid of a sliding-window solve (FP32), for the back-projection that
 // blends the tiles in one pass over the output image.

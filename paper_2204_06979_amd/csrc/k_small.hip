@@ -151,6 +151,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     __shared__ int s_kb[kMaxRank];                   // twist indices
     __shared__ double s_cross[kMaxRank][kMaxRank + 1];   // rank by SURE: sum_{j>=k} l_i / (l_i - l_j), [i][k]
     __shared__ int s_rank;                           // rank used
+    __shared__ double s_chk[3][NW];                  // eigenpair check: residual, norm of C, orthonormality
     __shared__ int s_flags;
 
     if (t == 0) s_flags = 0;
@@ -770,6 +771,51 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
             if (ok) {
                 d.P64[(int64_t)i * r + g] = v / s;
                 d.Q64[(int64_t)g * p + i] = v * s;
+            }
+        }
+        if (d.eig_check) {
+            // accuracy of the computed eigenpairs of C = D^-1 G D^-1 (G is intact):
+            // ||C V - V Lambda||_F / ||C||_F and max |V^T V - I| over the kr used
+            double rs = 0.0, cs = 0.0, os = 0.0;
+            for (int e = t; e < p * kr; e += NTH) {
+                const int g = e / p, i = e - g * p;
+                const double* gi = d.G + (int64_t)i * p;
+                const double si = s_sig[i];
+                double acc = 0.0;
+                for (int j = 0; j < p; ++j) acc = fma(gi[j] / (si * s_sig[j]), s_z[g][j], acc);
+                const double res = fma(-s_ev[g], s_z[g][i], acc);
+                rs = fma(res, res, rs);
+            }
+            for (int e = t; e < p * p; e += NTH) {
+                const int i = e / p, j = e - i * p;
+                const double c = d.G[e] / (s_sig[i] * s_sig[j]);
+                cs = fma(c, c, cs);
+            }
+            for (int e = t; e < kr * kr; e += NTH) {
+                const int g = e / kr, k = e - g * kr;
+                double dot = 0.0;
+                for (int i = 0; i < p; ++i) dot = fma(s_z[g][i], s_z[k][i], dot);
+                os = fmax(os, fabs(dot - (g == k ? 1.0 : 0.0)));
+            }
+            rs = wave_sum(rs);
+            cs = wave_sum(cs);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) os = fmax(os, __shfl_xor(os, o, 64));
+            if (lane == 0) {
+                s_chk[0][wave] = rs;
+                s_chk[1][wave] = cs;
+                s_chk[2][wave] = os;
+            }
+            __syncthreads();
+            if (t == 0) {
+                double a = 0.0, b = 0.0, m = 0.0;
+                for (int w = 0; w < NW; ++w) {
+                    a += s_chk[0][w];
+                    b += s_chk[1][w];
+                    m = fmax(m, s_chk[2][w]);
+                }
+                d.eig_check[0] = b > 0.0 ? sqrt(a / b) : 0.0;
+                d.eig_check[1] = m;
             }
         }
         if (t == 0) {

@@ -275,6 +275,41 @@ def test_denoise_with_data_chosen_rank(rule):
     _check_denoise(cube.Y, 8, 4, 1e-5, name="c2-" + rule, rank_rule=rule)
 
 
+@pytest.mark.parametrize("case", ["fp64", "fp32", "mixed-224", "sure-rank"])
+def test_eigensolve_diagnostics(case):
+    """The eigensolve's own accuracy report: ||C V - V Lambda|| / ||C|| and
+    max |V^T V - I| over the eigenpairs used, on the device, at FP64 rounding
+    level; the host recomputes the residual of the returned pairs on the FP64
+    Gram of the cube (FP32 cubes: at the level of the device's FP32 chunk sums;
+    the mixed path returns the FP32 Rayleigh-Ritz pairs)."""
+    api = _api()
+    if case == "mixed-224":
+        c = synth.mixing_cube(224, 96, 80, 224, 6, 12.0, 3, dtype=np.float32, keep_clean=False)
+        Y = c.Y + np.float32(1e-3) * np.random.default_rng(224).standard_normal(c.Y.shape).astype(np.float32)
+        r, L, prec, rule = 10, 3, "mixed", None
+    else:
+        c = synth.mixing_cube(97, 97, 133, 40, 5, 12.0, 3, dtype=np.float64, keep_clean=False)
+        Y = c.Y + 1e-3 * np.random.default_rng(7).standard_normal(c.Y.shape)
+        Y = Y.astype(np.float32) if case == "fp32" else Y
+        r, L, prec, rule = 8, 3, "native", ("sure" if case == "sure-rank" else None)
+    say("eig diagnostics", case, Y.shape, Y.dtype, "r", r)
+    X, info = api.denoise(torch.tensor(Y, device="cuda"), r, L, precision=prec, rank_rule=rule, check_eigs=True)
+    resid, orth = float(info["eig_resid"].item()), float(info["eig_orth"].item())
+    k = int(info["rank"].item())
+    Yd = Y.astype(np.float64).reshape(-1, Y.shape[2])
+    s = info["sigma"].cpu().numpy()
+    Cm = (Yd.T @ Yd) / np.outer(s, s)
+    V = info["V"].cpu().numpy()[:, :k]
+    ev = info["evals"].cpu().numpy()[:k]
+    host = float(np.linalg.norm(Cm @ V - V * ev) / np.linalg.norm(Cm))
+    say("   rank", k, "device resid", resid, "orth", orth, "host resid of the returned pairs", host)
+    assert 0 < k <= r
+    assert resid <= 1e-13 and orth <= 1e-13
+    # FP32 cubes: the device Gram sums 64-pixel chunks in FP32 before FP64, so
+    # its exact eigenpairs sit that far from those of the FP64 Gram
+    assert host <= (1e-5 if prec == "mixed" else 1e-6 if Y.dtype == np.float32 else 1e-12)
+
+
 def test_denoise_is_deterministic():
     api = _api()
     cube = synth.config_cube(1, keep_clean=False)

@@ -552,13 +552,52 @@ def run_hyminor(args, api, synth):
     return e
 
 
+def run_forpdn(args, api, synth):
+    """FORPDN on the 349 x 1905 x 144 FP32 cube, 4 levels, thresholds by SURE;
+    checked against the oracle at the device's noise and thresholds on the
+    whole cube (the oracle run is the CPU baseline of this workload)."""
+    import torch
+    from oracle import forpdn_oracle as FO
+    cube = synth.config_cube(2, keep_clean=False)
+    Yh = cube.Y
+    H, W, p = Yh.shape
+    L = 4
+    Y = torch.tensor(Yh, device="cuda")
+    Ys = [Y, Y.clone()]
+    X = torch.empty_like(Y)
+    run = lambda i: api.forpdn(Ys[i % 2], L, X=X)        # noqa: E731
+    for i in range(max(args.warmup, 1)):
+        run(i)
+    t = timed_steps(run, args.steps)
+    n = H * W
+    # cube read twice (noise Gram, first analysis level), coefficients written
+    # and read by the group Grams, the smoother and the synthesis (about one
+    # cube each way), X written
+    nbytes = 4.0 * n * p * 7
+    e = rate_entry(float(n * p), t, nbytes)
+    _, info = api.forpdn(Y, L, X=X)
+    lam = info["lam"].cpu().numpy()
+    sig = info["sigma"].cpu().numpy()
+    t0 = time.perf_counter()
+    ref = FO.forpdn(Yh.astype(np.float64), L, sigma=sig, lam=lam)
+    e["oracle_s"] = time.perf_counter() - t0
+    e["oracle_sample"] = "one oracle run of the whole cube at the device's noise and thresholds (no grid search)"
+    e["errors_vs_fp64_oracle"] = x_errors(X.cpu().numpy(), ref["X"])
+    e["lambda"] = [float(v) for v in lam]
+    e["device_status"] = int(info["status"].cpu()[0])
+    e["workload"] = ("FORPDN of the 349x1905x144 FP32 cube: regression noise, 4 db2 levels, first-order "
+                     "spectral roughness smoother per wavelet group with SURE-chosen thresholds")
+    log("forpdn %.3f ms/step" % t["ms_per_step"])
+    return e
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=["native", "mixed", "both"])
-    ap.add_argument("--workload", default="all", choices=["all", "single", "small", "grad", "batch", "tiled", "hyminor"])
+    ap.add_argument("--workload", default="all", choices=["all", "single", "small", "grad", "batch", "tiled", "hyminor", "forpdn"])
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -577,12 +616,13 @@ def main() -> int:
     timer = Timer(_lib, lib, api._handle(dev))
     precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
     others = {}
-    if args.workload in ("small", "grad", "batch", "tiled", "hyminor"):
+    if args.workload in ("small", "grad", "batch", "tiled", "hyminor", "forpdn"):
         # one secondary workload alone: its own line
         fn = {"small": lambda: run_small_fp64(args, api, synth), "grad": lambda: run_grad(args, api, synth),
               "batch": lambda: run_batch(args, api, synth, precs),
               "tiled": lambda: run_tiled(args, api, synth, precs),
-              "hyminor": lambda: run_hyminor(args, api, synth)}[args.workload]
+              "hyminor": lambda: run_hyminor(args, api, synth),
+              "forpdn": lambda: run_forpdn(args, api, synth)}[args.workload]
         e = fn()
         print(json.dumps({"metric": METRIC, "workload": args.workload, "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "result": e}))
@@ -594,7 +634,8 @@ def main() -> int:
                          ("grad_256x256x191_fwd_bwd", lambda: run_grad(args, api, synth)),
                          ("batch64", lambda: run_batch(args, api, synth, precs)),
                          ("tiled_2048x2048x224", lambda: run_tiled(args, api, synth, precs)),
-                         ("hyminor_349x1905x144", lambda: run_hyminor(args, api, synth))):
+                         ("hyminor_349x1905x144", lambda: run_hyminor(args, api, synth)),
+                         ("forpdn_349x1905x144", lambda: run_forpdn(args, api, synth))):
             t0 = time.time()
             others[name] = fn()
             log("%s done in %.1f s" % (name, time.time() - t0))

@@ -311,6 +311,38 @@ hyres_status hyres_hyminor(hyres_handle* h, const void* Y, int H, int W, int p,
                            const hyres_outputs* out, void* workspace, size_t workspace_bytes,
                            hyres_stream_t stream);
 
+/* ---- FORPDN: first-order spectral roughness penalty denoising ------------ */
+
+/* Defined by: Section 2.1 -- FORPDN is a full-rank, wavelet-based method for
+ * additive Gaussian noise (first-order spectral roughness penalty); the paper
+ * prints nothing more, and this library takes:
+ *   sigma: the per-band noise of the HyRes estimator (sigma_in overrides);
+ *   the whitened bands Y / sigma are transformed by the same L-level periodised
+ *   2-D db2 wavelet as HyRes; the coefficients of one position across the p
+ *   bands form a vector, and the vectors fall into L + 1 groups (the three
+ *   detail subbands of level l = 1..L, then the coarsest approximation);
+ *   every vector c of group j becomes (I + lam_j D^T D)^-1 c, D the
+ *   first-order spectral difference (the minimiser of ||c - x||^2 +
+ *   lam_j ||D x||^2); lam_j minimises Stein's unbiased risk estimate of that
+ *   smoother at unit noise over lam = 10^(t/10), t = -40..40 (the smallest on
+ *   ties; lambda_in [L+1] overrides); X is the inverse transform times sigma.
+ * Y, X: H x W x p cubes (dtype HYRES_F32 or HYRES_F64, pitches as for Y in
+ * hyres_denoise; X must not overlap Y), 2 <= p <= 224, 1 <= levels <= 8 with
+ * every level's input at least 4 x 4.  Outputs (device, any may be NULL):
+ * sigma_out [p], lambda_out [L+1], sure_out [L+1] (SURE at the chosen lam),
+ * status (HYRES_DEV_* bits of the noise estimate, OR-ed; the caller zeroes it).
+ * The workspace (hyres_forpdn_workspace_size; sigma_given != 0 when sigma_in
+ * will be passed) holds the position-major coefficients (about one cube),
+ * two approximation buffers and the per-group Gram partial sums. */
+hyres_status hyres_forpdn_workspace_size(int H, int W, int p, int levels, int dtype, int sigma_given,
+                                         size_t* bytes);
+hyres_status hyres_forpdn(hyres_handle* h, const void* Y, int H, int W, int p,
+                          int64_t pitch, int64_t row_pitch, int dtype, int levels,
+                          const double* sigma_in, const double* lambda_in, void* X,
+                          int64_t x_pitch, int64_t x_row_pitch, double* sigma_out,
+                          double* lambda_out, double* sure_out, int* status,
+                          void* workspace, size_t workspace_bytes, hyres_stream_t stream);
+
 /* ---- batches of cubes ---------------------------------------------------- */
 
 /* Defined by: Section 3 (device residency) applied to many cubes at once; the

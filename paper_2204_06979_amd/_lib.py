@@ -79,6 +79,9 @@ SIGNATURES = {
     "hyres_l1l1_spectral": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(L1Options), vp, i64, i64, vp]),
     "hyres_hyminor": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp,
                             C.POINTER(L1Options), vp, i64, i64, C.POINTER(Outputs), vp, sz, vp]),
+    "hyres_forpdn_workspace_size": (i32, [i32, i32, i32, i32, i32, i32, C.POINTER(sz)]),
+    "hyres_forpdn": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, i32, dp, dp, vp, i64, i64, dp, dp, dp, vp, vp,
+                           sz, vp]),
     "hyres_denoise_noalloc": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp, vp, i64,
                                     i64, C.POINTER(Outputs), vp]),
     "hyres_batch_workspace_size": (i32, [C.POINTER(Cube), i32, i32, C.POINTER(Options), C.POINTER(sz)]),

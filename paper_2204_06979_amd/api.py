@@ -294,6 +294,38 @@ def hyminor(Y: torch.Tensor, rank: int, levels: int, lam: float = 1.0, mu1: floa
     return X, dn.info()
 
 
+def forpdn(Y: torch.Tensor, levels: int, sigma: Optional[torch.Tensor] = None,
+           lam: Optional[torch.Tensor] = None, X: Optional[torch.Tensor] = None):
+    """FORPDN of one H x W x p cube (hyres_forpdn): whitened bands, the db2
+    wavelet, and per wavelet group the first-order spectral roughness smoother
+    with its threshold chosen by SURE.  Returns (X, info) with sigma, lam and
+    sure (levels + 1 groups) and status."""
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    dev = Y.device
+    dt = _dtype_code(Y)
+    lib = L.lib()
+    sg = None if sigma is None else sigma.to(device=dev, dtype=torch.float64).contiguous()
+    lm = None if lam is None else lam.to(device=dev, dtype=torch.float64).contiguous()
+    nb = C.c_size_t()
+    L.check(lib.hyres_forpdn_workspace_size(H, W, p, levels, dt, int(sg is not None), C.byref(nb)),
+            "forpdn workspace size")
+    buf, ws = _workspace(nb.value, dev)
+    X = torch.empty(H, W, p, dtype=Y.dtype, device=dev) if X is None else X
+    info = dict(sigma=torch.empty(p, dtype=torch.float64, device=dev),
+                lam=torch.empty(levels + 1, dtype=torch.float64, device=dev),
+                sure=torch.empty(levels + 1, dtype=torch.float64, device=dev),
+                status=torch.zeros(1, dtype=torch.int32, device=dev))
+    pitch, rp = _cube_strides(Y)
+    xp, xrp = _cube_strides(X)
+    L.check(lib.hyres_forpdn(_handle(dev), Y.data_ptr(), H, W, p, pitch, rp, dt, levels, _ptr(sg), _ptr(lm),
+                             X.data_ptr(), xp, xrp, info["sigma"].data_ptr(), info["lam"].data_ptr(),
+                             info["sure"].data_ptr(), info["status"].data_ptr(), ws, nb.value, _stream(dev)),
+            "hyres_forpdn")
+    del buf     # stream-ordered reuse by the caching allocator
+    return X, info
+
+
 def denoise_noalloc(Y: torch.Tensor, rank: int, levels: int, precision: str = "native",
                     sigma: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
                     scope: str = "all", out: Optional[Dict[str, torch.Tensor]] = None,

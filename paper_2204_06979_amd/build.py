@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhyres.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["k_gram.hip", "k_small.hip", "k_gemm.hip", "k_dwt.hip", "k_sure.hip", "k_adjoint.hip", "k_ritz.hip", "k_l1l1.hip",
+SOURCES = ["k_gram.hip", "k_small.hip", "k_gemm.hip", "k_dwt.hip", "k_sure.hip", "k_adjoint.hip", "k_ritz.hip", "k_l1l1.hip", "k_forpdn.hip",
            "hyres_api.hip"]
 
 FLAGS = [

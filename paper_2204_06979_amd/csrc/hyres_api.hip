@@ -1630,6 +1630,194 @@ HYRES_API hyres_status hyres_hyminor(hyres_handle* h, const void* Y, int H, int 
                         (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------- FORPDN
+namespace {
+// Workspace of one FORPDN solve: the noise program (unless sigma is given),
+// the position-major coefficients, two approximation buffers, the Gram
+// program over the L + 1 coefficient groups, and the small outputs.
+struct ForpdnPlan {
+    Exec noise, grams;
+    bool need_noise = true;
+    int H = 0, W = 0, p = 0, L = 0, dtype = 0, G = 0;
+    int lh[kMaxLevels + 1] = {0}, lw[kMaxLevels + 1] = {0};
+    int64_t loff[kMaxLevels + 1] = {0}, ll_off = 0, nc = 0;
+    int64_t goff[kForpdnMaxGroups + 1] = {0};
+    size_t o_noise = 0, o_grams = 0, o_coef = 0, o_tmp[2] = {0, 0}, o_sigma = 0, o_lambda = 0, o_sure = 0;
+    size_t total = 0;
+};
+
+uint32_t pmag_of(int p) { return (uint32_t)(0xffffffffu / (uint32_t)p) + 1u; }
+
+hyres_status plan_forpdn(ForpdnPlan& f, hyres_handle* h, int H, int W, int p, int L, int dtype, bool need_noise) {
+    if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
+    if (p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
+    if (!level_geometry(H, W, L, f.lh, f.lw, f.loff, &f.ll_off, &f.nc)) return HYRES_E_SHAPE;
+    if ((int64_t)H * W > (int64_t)1 << 31 || f.nc * p > ((int64_t)1 << 40)) return HYRES_E_UNSUPPORTED;
+    f.H = H; f.W = W; f.p = p; f.L = L; f.dtype = dtype; f.G = L + 1;
+    f.need_noise = need_noise;
+    for (int l = 1; l <= L; ++l) f.goff[l - 1] = f.loff[l];
+    f.goff[L] = f.ll_off;
+    f.goff[L + 1] = f.nc;
+    Layout lay;
+    const int es = esize(dtype);
+    if (need_noise) {
+        one_cube(f.noise, h, H, W, p, 1, 1, dtype, 0);
+        hyres_status st = plan_cubes(f.noise, P_GRAM | P_SMALL);
+        if (st) return st;
+        f.o_noise = lay.add(f.noise.lay.total);
+    }
+    f.o_coef = lay.add((size_t)f.nc * p * es);
+    f.o_tmp[0] = lay.add((size_t)f.lh[1] * f.lw[1] * p * es);
+    f.o_tmp[1] = lay.add(L >= 2 ? (size_t)f.lh[2] * f.lw[2] * p * es : 0);
+    // the coefficient groups as "cubes" of positions for the Gram kernels:
+    // the three detail blocks of level l (3 h_l rows of w_l), then LL_L
+    Exec& g = f.grams;
+    g.h = h;
+    g.count = f.G;
+    g.dtype = dtype;
+    g.precision = HYRES_PREC_NATIVE;
+    g.plan.resize(f.G);
+    for (int j = 0; j < f.G; ++j) {
+        CubePlan& c = g.plan[j];
+        c.H = j < L ? 3 * f.lh[j + 1] : f.lh[L];
+        c.W = j < L ? f.lw[j + 1] : f.lw[L];
+        c.p = p; c.r = 1; c.L = 0; c.dtype = dtype; c.scope = 0; c.precision = HYRES_PREC_NATIVE;
+    }
+    plan_exec(g, P_GRAM);
+    f.o_grams = lay.add(g.lay.total);
+    f.o_sigma = lay.add((size_t)p * 8);
+    f.o_lambda = lay.add((size_t)f.G * 8);
+    f.o_sure = lay.add((size_t)f.G * 8);
+    f.total = lay.total;
+    return HYRES_OK;
+}
+}  // namespace
+
+HYRES_API hyres_status hyres_forpdn_workspace_size(int H, int W, int p, int levels, int dtype, int sigma_given,
+                                                   size_t* bytes) {
+    if (!bytes) return HYRES_E_NULL;
+    ForpdnPlan f;
+    hyres_status st = plan_forpdn(f, nullptr, H, W, p, levels, dtype, !sigma_given);
+    if (st) return st;
+    *bytes = f.total;
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_forpdn(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                    int64_t row_pitch, int dtype, int levels, const double* sigma_in,
+                                    const double* lambda_in, void* X, int64_t x_pitch, int64_t x_row_pitch,
+                                    double* sigma_out, double* lambda_out, double* sure_out, int* status,
+                                    void* workspace, size_t workspace_bytes, hyres_stream_t stream) {
+    if (!h || !X) return HYRES_E_NULL;
+    hyres_status st = check_cube(Y, H, W, p, pitch, row_pitch, dtype);
+    if (st) return st;
+    if (x_pitch < p || x_row_pitch < (int64_t)(W - 1) * x_pitch + p) return HYRES_E_SHAPE;
+    ForpdnPlan f;
+    if ((st = plan_forpdn(f, h, H, W, p, levels, dtype, sigma_in == nullptr))) return st;
+    if ((st = check_ws(workspace, workspace_bytes, f.total))) return st;
+    if ((st = set_device(h))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int es = esize(dtype);
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    double* sigma = sigma_out ? sigma_out : reinterpret_cast<double*>(ws + f.o_sigma);
+    double* lambda = lambda_out ? lambda_out : reinterpret_cast<double*>(ws + f.o_lambda);
+    double* sure = sure_out ? sure_out : reinterpret_cast<double*>(ws + f.o_sure);
+    unsigned char* coef = ws + f.o_coef;
+    unsigned char* tmp[2] = {ws + f.o_tmp[0], ws + f.o_tmp[1]};
+    const double* sg = sigma_in;
+    // F1: noise (the regression estimator of HyRes)
+    if (f.need_noise) {
+        Exec& x = f.noise;
+        x.ws = ws + f.o_noise;
+        CubeDesc d = make_desc(x.plan[0], x.ws);
+        d.Y = Y; d.pitch = pitch; d.row_pitch = row_pitch;
+        d.vec4 = vec4_ok(Y, W, p, pitch, row_pitch, dtype);
+        d.dense = dense_ok(Y, W, p, pitch, row_pitch, dtype);
+        d.sigma = sigma;
+        d.status = status;
+        d.mode = kModeSigma;
+        x.desc.assign(1, d);
+        build_program(x, S_GRAM | S_SMALL);
+        if ((st = upload_exec(x, s))) return st;
+        if ((st = run_program(x, s, false))) return st;
+        sg = sigma;
+    } else if (sigma_out) {
+        if (hipMemcpyAsync(sigma_out, sigma_in, (size_t)p * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return HYRES_E_HIP;
+    }
+    // F2: analysis, level by level (the first divides by sigma on load);
+    // LL_l (l < L) in tmp[(l - 1) & 1], LL_L in the coefficients
+    const uint32_t pm = pmag_of(p);
+    for (int l = 1; l <= levels; ++l) {
+        VLevel a{};
+        if (l == 1) {
+            a.in = Y; a.ip = pitch; a.irow = row_pitch;
+        } else {
+            a.in = tmp[(l - 2) & 1]; a.ip = p; a.irow = (int64_t)f.lw[l - 1] * p;
+        }
+        a.scale = l == 1 ? sg : nullptr;
+        a.ll = l == levels ? coef + (size_t)f.ll_off * p * es : tmp[(l - 1) & 1];
+        a.det = coef + (size_t)f.loff[l] * p * es;
+        a.Hin = f.lh[l - 1]; a.Win = f.lw[l - 1]; a.h = f.lh[l]; a.w = f.lw[l]; a.p = p; a.pmag = pm;
+        if (launch_vdwt_level(dtype, a, h->num_cu, s) != hipSuccess) return HYRES_E_HIP;
+    }
+    // F5: band Gram of every group, then the thresholds
+    {
+        Exec& x = f.grams;
+        x.ws = ws + f.o_grams;
+        x.desc.resize(f.G);
+        for (int j = 0; j < f.G; ++j) {
+            CubeDesc d = make_desc(x.plan[j], x.ws);
+            const void* gy = coef + (size_t)f.goff[j] * p * es;
+            const int64_t rp = (int64_t)x.plan[j].W * p;
+            d.Y = gy; d.pitch = p; d.row_pitch = rp;
+            d.vec4 = vec4_ok(gy, x.plan[j].W, p, p, rp, dtype);
+            d.dense = dense_ok(gy, x.plan[j].W, p, p, rp, dtype);
+            x.desc[j] = d;
+        }
+        build_program(x, S_GRAM);
+        if ((st = upload_exec(x, s))) return st;
+        if ((st = run_program(x, s, false))) return st;
+        FLambda la{};
+        for (int j = 0; j < f.G; ++j) {
+            la.G[j] = x.desc[j].G;
+            la.count[j] = f.goff[j + 1] - f.goff[j];
+        }
+        la.lambda_in = lambda_in;
+        la.lambda = lambda;
+        la.sure = sure;
+        la.p = p;
+        if (launch_forpdn_lambda(la, f.G, s) != hipSuccess) return HYRES_E_HIP;
+    }
+    // F4: the smoother on every coefficient vector
+    {
+        FFilter ff{};
+        ff.coef = coef;
+        ff.npos = f.nc;
+        for (int j = 0; j <= f.G; ++j) ff.goff[j] = f.goff[j];
+        ff.lambda = lambda;
+        ff.p = p;
+        ff.groups = f.G;
+        ff.pmag = pm;
+        if (launch_forpdn_filter(dtype, ff, h->num_cu, s) != hipSuccess) return HYRES_E_HIP;
+    }
+    // F6: synthesis, coarsest level first; the last level writes X times sigma
+    for (int l = levels; l >= 1; --l) {
+        VSyn a{};
+        a.ll = l == levels ? coef + (size_t)f.ll_off * p * es : tmp[(l - 1) & 1];
+        a.det = coef + (size_t)f.loff[l] * p * es;
+        if (l == 1) {
+            a.out = X; a.op = x_pitch; a.orow = x_row_pitch;
+        } else {
+            a.out = tmp[(l - 2) & 1]; a.op = p; a.orow = (int64_t)f.lw[l - 1] * p;
+        }
+        a.scale = l == 1 ? sg : nullptr;
+        a.Hin = f.lh[l - 1]; a.Win = f.lw[l - 1]; a.h = f.lh[l]; a.w = f.lw[l]; a.p = p; a.pmag = pm;
+        if (launch_vidwt_level(dtype, a, h->num_cu, s) != hipSuccess) return HYRES_E_HIP;
+    }
+    return HYRES_OK;
+}
+
 // ------------------------------------------------------------- batches
 struct hyres_batch {
     hyres_handle* h = nullptr;

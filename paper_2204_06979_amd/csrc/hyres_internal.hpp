@@ -127,6 +127,46 @@ struct L1Args {
 bool l1l1_shape(int p, int dtype, int* S, int* M);
 hipError_t launch_l1l1(const L1Args& a, int num_cu, hipStream_t st);
 
+// FORPDN: one analysis / synthesis level of the wavelet on position-major
+// vectors (p bands per position), the per-group threshold choice and the
+// spectral smoother.
+constexpr int kForpdnMaxGroups = kMaxLevels + 1;
+constexpr int kForpdnGrid = 81;    // lam = 10^(t/10), t = -40..40
+struct VLevel {
+    const void* in; int64_t ip, irow;       // input level (element strides of a position and a row)
+    const double* scale;                    // per-band divisor on load (sigma at the first level) or null
+    void* ll;                               // LL output, h x w positions, dense
+    void* det;                              // LH, HL, HH blocks of h x w positions each
+    int Hin, Win, h, w, p;
+    uint32_t pmag;                          // floor(2^32 / p) + 1
+};
+struct VSyn {
+    const void* ll; const void* det;        // this level's LL and detail blocks (dense)
+    void* out; int64_t op, orow;            // the level below (element strides)
+    const double* scale;                    // per-band factor on store (sigma at the last level) or null
+    int Hin, Win, h, w, p;
+    uint32_t pmag;
+};
+struct FLambda {
+    const double* G[kForpdnMaxGroups];      // p x p band Gram of each group's coefficient vectors
+    int64_t count[kForpdnMaxGroups];        // vectors per group
+    const double* lambda_in;                // given thresholds or null
+    double* lambda; double* sure;           // per group
+    int p;
+};
+struct FFilter {
+    void* coef; int64_t npos;               // position-major coefficients (p per position)
+    int64_t goff[kForpdnMaxGroups + 1];     // first position of each group
+    const double* lambda;
+    int p, groups;
+    uint32_t pmag;
+};
+hipError_t launch_vdwt_level(int dtype, const VLevel& a, int num_cu, hipStream_t s);
+hipError_t launch_vidwt_level(int dtype, const VSyn& a, int num_cu, hipStream_t s);
+hipError_t launch_forpdn_lambda(const FLambda& a, int groups, hipStream_t s);
+size_t forpdn_filter_lds(int dtype, int p, int groups);
+hipError_t launch_forpdn_filter(int dtype, const FFilter& a, int num_cu, hipStream_t s);
+
 // Tile grid of a sliding-window solve (FP32), for the back-projection that
 // blends the tiles in one pass over the output image.
 constexpr int kMaxTilesAxis = 64;

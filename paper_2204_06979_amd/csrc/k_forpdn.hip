@@ -36,93 +36,126 @@ __device__ __forceinline__ int ext_index(int i, int N, int Ne) {
 }
 }  // namespace
 
+// A thread computes a 2 x 2 block of output positions of one band: the 6 x 6
+// input window is read once (9 loads per position instead of 16).
 template <typename T>
 __global__ __launch_bounds__(256) void k_vdwt_level(VLevel a) {
-    const T h0 = (T)kH0, h1 = (T)kH1, h2 = (T)kH2, h3 = (T)kH3;
-    const T g0 = (T)kG0, g1 = (T)kG1, g2 = (T)kG2, g3 = (T)kG3;
+    const T hf[4] = {(T)kH0, (T)kH1, (T)kH2, (T)kH3};
+    const T gf[4] = {(T)kG0, (T)kG1, (T)kG2, (T)kG3};
     const int p = a.p;
     const int Hext = a.Hin + (a.Hin & 1), Wext = a.Win + (a.Win & 1);
-    const int64_t npos = (int64_t)a.h * a.w;
-    constexpr int PB = 64;                                  // positions per block
-    const int64_t nblk = (npos + PB - 1) / PB;
-    const int span = PB * p;
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int bh = (a.h + 1) / 2, bw = (a.w + 1) / 2;         // 2 x 2 blocks of outputs
+    const int64_t nq = (int64_t)bh * bw;
+    constexpr int QB = 64;                                   // blocks per work item
+    const int64_t nitem = (nq + QB - 1) / QB;
+    const int span = QB * p;
+    const int64_t sub = (int64_t)a.h * a.w * p;              // one detail block
+    for (int64_t it = blockIdx.x; it < nitem; it += gridDim.x) {
         for (int e = threadIdx.x; e < span; e += blockDim.x) {
-            const int pl = (int)__umulhi((uint32_t)e, a.pmag);   // e / p
-            const int b = e - pl * p;
-            const int64_t pos = blk * PB + pl;
-            if (pos >= npos) break;
-            const int y = (int)(pos / a.w), x = (int)(pos - (int64_t)y * a.w);
+            const int ql = (int)__umulhi((uint32_t)e, a.pmag);   // e / p
+            const int b = e - ql * p;
+            const int64_t q = it * QB + ql;
+            if (q >= nq) break;
+            const int by = (int)(q / bw), bx = (int)(q - (int64_t)by * bw);
+            const int y0 = 2 * by, x0 = 2 * bx;
             const T sc = a.scale ? (T)(1.0 / a.scale[b]) : (T)1;
             const T* in = static_cast<const T*>(a.in) + b;
-            int cx[4];
+            int64_t cx[6];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cx[c] = ext_index(2 * x + c, a.Win, Wext);
-            T rl[4], rh[4];
+            for (int c = 0; c < 6; ++c) cx[c] = (int64_t)ext_index(2 * x0 + c, a.Win, Wext) * a.ip;
+            // along x first (two output columns), in tap order
+            T rl[6][2], rh[6][2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int iy = ext_index(2 * y + r, a.Hin, Hext);
-                const T* row = in + (int64_t)iy * a.irow;
-                const T v0 = row[(int64_t)cx[0] * a.ip] * sc, v1 = row[(int64_t)cx[1] * a.ip] * sc;
-                const T v2 = row[(int64_t)cx[2] * a.ip] * sc, v3 = row[(int64_t)cx[3] * a.ip] * sc;
-                // along x first, in tap order
-                rl[r] = h0 * v0 + h1 * v1 + h2 * v2 + h3 * v3;
-                rh[r] = g0 * v0 + g1 * v1 + g2 * v2 + g3 * v3;
+            for (int r = 0; r < 6; ++r) {
+                const T* row = in + (int64_t)ext_index(2 * y0 + r, a.Hin, Hext) * a.irow;
+                T v[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) v[c] = row[cx[c]] * sc;
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    rl[r][o] = hf[0] * v[2 * o] + hf[1] * v[2 * o + 1] + hf[2] * v[2 * o + 2] + hf[3] * v[2 * o + 3];
+                    rh[r][o] = gf[0] * v[2 * o] + gf[1] * v[2 * o + 1] + gf[2] * v[2 * o + 2] + gf[3] * v[2 * o + 3];
+                }
             }
-            const T ll = h0 * rl[0] + h1 * rl[1] + h2 * rl[2] + h3 * rl[3];
-            const T hl = g0 * rl[0] + g1 * rl[1] + g2 * rl[2] + g3 * rl[3];
-            const T lh = h0 * rh[0] + h1 * rh[1] + h2 * rh[2] + h3 * rh[3];
-            const T hh = g0 * rh[0] + g1 * rh[1] + g2 * rh[2] + g3 * rh[3];
-            T* det = static_cast<T*>(a.det) + pos * p + b;
-            det[0] = lh;
-            det[npos * p] = hl;
-            det[2 * npos * p] = hh;
-            static_cast<T*>(a.ll)[pos * p + b] = ll;
+#pragma unroll
+            for (int oy = 0; oy < 2; ++oy) {
+                const int y = y0 + oy;
+#pragma unroll
+                for (int ox = 0; ox < 2; ++ox) {
+                    const int x = x0 + ox;
+                    if (y < a.h && x < a.w) {
+                        // rows 2 oy .. 2 oy + 3 of the window
+                        const T l0 = rl[2 * oy][ox], l1 = rl[2 * oy + 1][ox], l2 = rl[2 * oy + 2][ox], l3 = rl[2 * oy + 3][ox];
+                        const T h0 = rh[2 * oy][ox], h1 = rh[2 * oy + 1][ox], h2 = rh[2 * oy + 2][ox], h3 = rh[2 * oy + 3][ox];
+                        const T ll = hf[0] * l0 + hf[1] * l1 + hf[2] * l2 + hf[3] * l3;
+                        const T hl = gf[0] * l0 + gf[1] * l1 + gf[2] * l2 + gf[3] * l3;
+                        const T lh = hf[0] * h0 + hf[1] * h1 + hf[2] * h2 + hf[3] * h3;
+                        const T hh = gf[0] * h0 + gf[1] * h1 + gf[2] * h2 + gf[3] * h3;
+                        const int64_t o = ((int64_t)y * a.w + x) * p + b;
+                        T* det = static_cast<T*>(a.det) + o;
+                        det[0] = lh;
+                        det[sub] = hl;
+                        det[2 * sub] = hh;
+                        static_cast<T*>(a.ll)[o] = ll;
+                    }
+                }
+            }
         }
     }
 }
 
+// A thread computes a 2 x 2 block of output pixels of one band: pixels
+// (2Y + py, 2X + px) all take the coefficients at rows Y and Y - 1 and columns
+// X and X - 1 (mod the subband size), taps py, py + 2 and px, px + 2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_vidwt_level(VSyn a) {
     const T hf[4] = {(T)kH0, (T)kH1, (T)kH2, (T)kH3};
     const T gf[4] = {(T)kG0, (T)kG1, (T)kG2, (T)kG3};
     const int p = a.p;
-    const int Hext = a.Hin + (a.Hin & 1), Wext = a.Win + (a.Win & 1);
-    const int64_t npos = (int64_t)a.Hin * a.Win;
-    const int64_t nsub = (int64_t)a.h * a.w;
-    constexpr int PB = 64;
-    const int64_t nblk = (npos + PB - 1) / PB;
-    const int span = PB * p;
+    const int64_t nq = (int64_t)a.h * a.w;                   // one block per subband position
+    constexpr int QB = 64;
+    const int64_t nitem = (nq + QB - 1) / QB;
+    const int span = QB * p;
     const T* LL = static_cast<const T*>(a.ll);
     const T* LH = static_cast<const T*>(a.det);
-    const T* HL = LH + nsub * p;
-    const T* HH = HL + nsub * p;
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const T* HL = LH + nq * p;
+    const T* HH = HL + nq * p;
+    for (int64_t it = blockIdx.x; it < nitem; it += gridDim.x) {
         for (int e = threadIdx.x; e < span; e += blockDim.x) {
-            const int pl = (int)__umulhi((uint32_t)e, a.pmag);
-            const int b = e - pl * p;
-            const int64_t pos = blk * PB + pl;
-            if (pos >= npos) break;
-            const int iy = (int)(pos / a.Win), ix = (int)(pos - (int64_t)iy * a.Win);
-            // taps m of parity i, and the coefficient k with (2k + m) mod Next == i
-            const int my0 = iy & 1, my1 = my0 + 2;
-            const int ky0 = (iy - my0) >> 1, ky1 = ((iy - my1 + Hext) % Hext) >> 1;
-            const int mx0 = ix & 1, mx1 = mx0 + 2;
-            const int kx0 = (ix - mx0) >> 1, kx1 = ((ix - mx1 + Wext) % Wext) >> 1;
-            auto at = [&](const T* s, int ky, int kx) { return s[((int64_t)ky * a.w + kx) * p + b]; };
-            // along y first (lo_x from LL and HL, hi_x from LH and HH), then along x
-            T lo[2], hi[2];
+            const int ql = (int)__umulhi((uint32_t)e, a.pmag);
+            const int b = e - ql * p;
+            const int64_t q = it * QB + ql;
+            if (q >= nq) break;
+            const int Y = (int)(q / a.w), X = (int)(q - (int64_t)Y * a.w);
+            const int Ym = Y == 0 ? a.h - 1 : Y - 1, Xm = X == 0 ? a.w - 1 : X - 1;
+            const int64_t i00 = ((int64_t)Y * a.w + X) * p + b, i01 = ((int64_t)Y * a.w + Xm) * p + b;
+            const int64_t i10 = ((int64_t)Ym * a.w + X) * p + b, i11 = ((int64_t)Ym * a.w + Xm) * p + b;
+            // [row Y or Y - 1][column X or X - 1]
+            const T ll[2][2] = {{LL[i00], LL[i01]}, {LL[i10], LL[i11]}};
+            const T hl[2][2] = {{HL[i00], HL[i01]}, {HL[i10], HL[i11]}};
+            const T lh[2][2] = {{LH[i00], LH[i01]}, {LH[i10], LH[i11]}};
+            const T hh[2][2] = {{HH[i00], HH[i01]}, {HH[i10], HH[i11]}};
+            const T sc = a.scale ? (T)a.scale[b] : (T)1;
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int kx = c ? kx1 : kx0;
-                lo[c] = (hf[my0] * at(LL, ky0, kx) + gf[my0] * at(HL, ky0, kx)) +
-                        (hf[my1] * at(LL, ky1, kx) + gf[my1] * at(HL, ky1, kx));
-                hi[c] = (hf[my0] * at(LH, ky0, kx) + gf[my0] * at(HH, ky0, kx)) +
-                        (hf[my1] * at(LH, ky1, kx) + gf[my1] * at(HH, ky1, kx));
+            for (int py = 0; py < 2; ++py) {
+                const int iy = 2 * Y + py;
+                if (iy >= a.Hin) continue;
+                // along y first: lo_x from LL and HL, hi_x from LH and HH (taps py then py + 2)
+                T lo[2], hi[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    lo[c] = (hf[py] * ll[0][c] + gf[py] * hl[0][c]) + (hf[py + 2] * ll[1][c] + gf[py + 2] * hl[1][c]);
+                    hi[c] = (hf[py] * lh[0][c] + gf[py] * hh[0][c]) + (hf[py + 2] * lh[1][c] + gf[py + 2] * hh[1][c]);
+                }
+#pragma unroll
+                for (int px = 0; px < 2; ++px) {
+                    const int ix = 2 * X + px;
+                    if (ix >= a.Win) continue;
+                    T v = (hf[px] * lo[0] + gf[px] * hi[0]) + (hf[px + 2] * lo[1] + gf[px + 2] * hi[1]);
+                    if (a.scale) v *= sc;
+                    static_cast<T*>(a.out)[(int64_t)iy * a.orow + (int64_t)ix * a.op + b] = v;
+                }
             }
-            T v = (hf[mx0] * lo[0] + gf[mx0] * hi[0]) + (hf[mx1] * lo[1] + gf[mx1] * hi[1]);
-            if (a.scale) v *= (T)a.scale[b];
-            static_cast<T*>(a.out)[(int64_t)iy * a.orow + (int64_t)ix * a.op + b] = v;
         }
     }
 }
@@ -148,14 +181,18 @@ __global__ __launch_bounds__(256) void k_forpdn_lambda(FLambda a) {
     for (int sidx = t; sidx < 2 * p - 1; sidx += NT) {
         double acc = 0.0;
         const int r0 = sidx < p ? 0 : sidx - p + 1, r1 = sidx < p ? sidx : p - 1;
+#pragma unroll 8
         for (int r = r0; r <= r1; ++r) acc += G[(int64_t)r * p + (sidx - r)];
         s_A[sidx] = acc;
     }
     for (int d = t; d < p; d += NT) {
         double acc = 0.0;
+#pragma unroll 8
         for (int c = 0; c + d < p; ++c) acc += G[(int64_t)(c + d) * p + c];
-        if (d > 0)
+        if (d > 0) {
+#pragma unroll 8
             for (int c = 0; c + d < p; ++c) acc += G[(int64_t)c * p + (c + d)];
+        }
         s_B[d] = acc;
     }
     __syncthreads();
@@ -229,6 +266,8 @@ __global__ __launch_bounds__(64) void k_forpdn_filter(FFilter a) {
         const int cnt = npos - pos0 < 64 ? (int)(npos - pos0) : 64;
         const int span = cnt * p;
         T* src = coef + pos0 * p;
+        // eight loads in flight per lane before their LDS stores
+#pragma unroll 8
         for (int e = lane; e < span; e += 64) {
             const int r = (int)__umulhi((uint32_t)e, a.pmag);
             s_row[r * SP + (e - r * p)] = src[e];
@@ -245,17 +284,20 @@ __global__ __launch_bounds__(64) void k_forpdn_filter(FFilter a) {
             T* row = s_row + lane * SP;
             T z = row[0] * inv[0];
             row[0] = z;
+#pragma unroll 8
             for (int i = 1; i < p; ++i) {
                 z = fma(lam, z, row[i]) * inv[i];
                 row[i] = z;
             }
             T x = z;
+#pragma unroll 8
             for (int i = p - 2; i >= 0; --i) {
                 x = fma(f[i], x, row[i]);
                 row[i] = x;
             }
         }
         __syncthreads();
+#pragma unroll 8
         for (int e = lane; e < span; e += 64) {
             const int r = (int)__umulhi((uint32_t)e, a.pmag);
             src[e] = s_row[r * SP + (e - r * p)];
@@ -265,7 +307,7 @@ __global__ __launch_bounds__(64) void k_forpdn_filter(FFilter a) {
 }
 
 hipError_t launch_vdwt_level(int dtype, const VLevel& a, int num_cu, hipStream_t s) {
-    const int64_t nblk = ((int64_t)a.h * a.w + 63) / 64;
+    const int64_t nblk = ((int64_t)((a.h + 1) / 2) * ((a.w + 1) / 2) + 63) / 64;
     const int grid = (int)std::min<int64_t>(std::max<int64_t>(nblk, 1), (int64_t)num_cu * 8);
     if (dtype == HYRES_F32) hipLaunchKernelGGL(k_vdwt_level<float>, dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_vdwt_level<double>, dim3(grid), dim3(256), 0, s, a);
@@ -273,7 +315,7 @@ hipError_t launch_vdwt_level(int dtype, const VLevel& a, int num_cu, hipStream_t
 }
 
 hipError_t launch_vidwt_level(int dtype, const VSyn& a, int num_cu, hipStream_t s) {
-    const int64_t nblk = ((int64_t)a.Hin * a.Win + 63) / 64;
+    const int64_t nblk = ((int64_t)a.h * a.w + 63) / 64;
     const int grid = (int)std::min<int64_t>(std::max<int64_t>(nblk, 1), (int64_t)num_cu * 8);
     if (dtype == HYRES_F32) hipLaunchKernelGGL(k_vidwt_level<float>, dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_vidwt_level<double>, dim3(grid), dim3(256), 0, s, a);

@@ -104,6 +104,8 @@ def summarize(a) -> int:
         out.append("")
     out.append("Steps in the profiled run: %d (threshold-search starts / %d cube group%s per solve).\n"
                % (solves_t, a.groups, "" if a.groups == 1 else "s"))
+    for n in a.note or []:
+        out.append(n + "\n")
     out.append("| kernel | stage | calls | avg us | us per step | % time |")
     out.append("|---|---|---|---|---|---|")
     for name, calls, total, avg, pct in sorted(stats, key=lambda r: -r[2]):
@@ -163,6 +165,7 @@ def main(argv=None) -> int:
     s.add_argument("--workload", required=True)
     s.add_argument("--traffic-json")
     s.add_argument("--command", action="append")
+    s.add_argument("--note", action="append", help="a line of text under the step count")
     s.add_argument("--groups", type=int, default=1, help="cube groups per solve (each starts its own search)")
     a = ap.parse_args(argv)
     if a.cmd == "copy":

@@ -32,7 +32,8 @@ STAGE_OF = [
     ("k_gram", "gram"), ("k_small", "small"), ("k_project", "project"), ("k_ritz", "project"),
     ("k_dwt_level", "dwt"), ("k_sure", "sure"), ("k_copy_f64", "sure"), ("k_idwt_level", "idwt"),
     ("k_backproject", "backproject"), ("k_blend_axis", "backproject"), ("k_blend_f32", "backproject"),
-    ("k_upload", "setup"), ("k_l1l1", "l1l1"),
+    ("k_upload", "setup"), ("k_l1l1", "l1l1"), ("k_vdwt", "dwt"), ("k_vidwt", "idwt"),
+    ("k_forpdn_filter", "smoother"), ("k_forpdn_lambda", "threshold"),
 ]
 
 

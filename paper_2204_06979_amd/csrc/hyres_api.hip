@@ -1978,7 +1978,7 @@ struct BwdPlan {
     Layout lay;
     int slots = 1, nchunk = 1;
     size_t o_desc = 0, o_tab = 0, o_A = 0, o_dB = 0, o_tmp = 0, o_part = 0, o_dQ = 0, o_dPt = 0, o_lpart = 0,
-           o_aug = 0, o_W = 0, o_Ginv = 0, o_dC = 0, o_dG2 = 0;
+           o_gsc = 0, o_W = 0, o_Ginv = 0, o_dC = 0, o_dG2 = 0;
 };
 
 hyres_status plan_backward(BwdPlan& b, hyres_handle* h, int H, int W, int p, const hyres_options* opt, int dtype) {
@@ -2002,14 +2002,14 @@ hyres_status plan_backward(BwdPlan& b, hyres_handle* h, int H, int W, int p, con
     b.o_A = L.add((size_t)r * c.nz * es);
     b.o_dB = L.add((size_t)r * c.ncs * es);
     b.o_tmp = L.add((size_t)std::max<int64_t>(1, r * c.tps) * es);
-    b.slots = (int)std::max<int64_t>(1, std::min<int64_t>(256, cdiv(c.n, 2048)));
+    b.slots = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(c.n, 256)));
     b.o_part = L.add((size_t)b.slots * r * p * 8);
     b.o_dQ = L.add((size_t)r * p * 8);
     b.o_dPt = L.add((size_t)r * p * 8);
     const int64_t lim = c.scope == HYRES_SCOPE_DETAIL ? c.ll_off : c.nc;
     b.nchunk = (int)std::max<int64_t>(1, cdiv(lim, adj_chunk()));
     b.o_lpart = L.add((size_t)r * b.nchunk * 8);
-    b.o_aug = L.add((size_t)(r + 1) * 2 * p * p * 8);
+    b.o_gsc = L.add((size_t)p * 8);
     b.o_W = L.add((size_t)p * r * 8);
     b.o_Ginv = L.add((size_t)p * p * 8);
     b.o_dC = L.add((size_t)p * p * 8);
@@ -2094,7 +2094,7 @@ HYRES_API hyres_status hyres_denoise_backward(hyres_handle* h, const void* Y, in
     a.dQ = at<double>(workspace, b.o_dQ);
     a.dPt = at<double>(workspace, b.o_dPt);
     a.lpart = at<double>(workspace, b.o_lpart);
-    a.aug = at<double>(workspace, b.o_aug);
+    a.gsc = at<double>(workspace, b.o_gsc);
     a.Wsol = at<double>(workspace, b.o_W);
     a.Ginv = at<double>(workspace, b.o_Ginv);
     a.dC = at<double>(workspace, b.o_dC);

@@ -199,14 +199,15 @@ struct AdjDesc {
     double* dQ;              // r x p
     double* dPt;             // r x p (dP transposed)
     double* lpart;           // r x nchunk
-    double* aug;             // (r + 1) augmented systems of p x 2p
     double* Wsol;            // p x r, column-major
     double* Ginv;            // p x p
     double* dC;              // p x p
     double* dG2;             // p x p: 2 dG
+    double* gsc;             // p: n sigma_j^3 dsigma_j / 2
     int slots, nchunk;
     int* status;
 };
+hipError_t launch_adj_sweep(const AdjDesc& a, hipStream_t s);
 
 #ifdef HYRES_PHASE_TIMING
 #define HYRES_STAMP(d, i) \

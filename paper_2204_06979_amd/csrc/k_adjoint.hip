@@ -12,9 +12,10 @@
 //   dZ = W^T dB              (synthesis, extra sample folded back)  (transform kernels)
 //   dP = Y^T dZ,  dY  = dZ P^T + 2 Y dG                        (k_adj_xprod, k_adj_dy)
 //   dV = D^-1 dP + D dQ^T,  dsigma from P, Q and C
-//   eigenvectors: dC = sum_k sym(w_k u_k^T), w_k = sum_{i != k} u_i u_i^T dV_k / (lambda_k - lambda_i),
-//     obtained from (lambda_k I - C + lambda_k u_k u_k^T) w_k = (I - u_k u_k^T) dV_k   (k_adj_solve)
-//   dG = D^-1 dC D^-1 + G^-1 diag(n sigma_j^3 dsigma_j / 2) G^-1                        (k_adj_combine)
+//   eigenvectors: dC = sum_k sym(w_k u_k^T), w_k = sum_{i != k} u_i u_i^T dV_k / (lambda_k - lambda_i):
+//     explicit inside the top-r subspace, outside it from the positive definite
+//     (lambda_k I - C + U Lambda U^T) y = (I - U U^T) dV_k   (k_adj_sweep, with G^-1)
+//   dG = D^-1 dC D^-1 + G^-1 diag(n sigma_j^3 dsigma_j / 2) G^-1      (k_adj_dc, k_adj_dg)
 // Small dense algebra runs in FP64 in one workgroup per system; the pixel
 // loops run in the element type of the cube with FP64 accumulation where
 // they reduce over pixels.
@@ -113,6 +114,7 @@ __global__ void k_adj_reduce(const double* __restrict__ part, int slots, int E, 
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     double s = 0.0;
+#pragma unroll 8
     for (int i = 0; i < slots; ++i) s += part[(int64_t)i * E + e];
     out[e] = s;
 }
@@ -182,151 +184,52 @@ __global__ void k_chunk_reduce(const double* __restrict__ part, int nchunk, int 
     out[k] = twice_lambda ? 2.0 * lambda[k] * s : s;
 }
 
-// Gauss-Jordan elimination with partial pivoting of the p x m row-major
-// matrix M (first p columns the system, the rest right-hand sides) in one
-// workgroup; afterwards the right-hand columns hold the solution.
-__device__ bool gauss_jordan(double* M, int p, int m, double* rowbuf, double* colbuf, double* rv, int* ri) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    bool ok = true;
-    for (int j = 0; j < p; ++j) {
-        // pivot: largest magnitude in column j at or below row j (lowest row on ties)
-        double best = -1.0;
-        int bi = p;
-        for (int i = j + tid; i < p; i += nt) {
-            const double v = fabs(M[(int64_t)i * m + j]);
-            if (v > best) {
-                best = v;
-                bi = i;
-            }
-        }
-        rv[tid] = best;
-        ri[tid] = bi;
-        __syncthreads();
-        for (int o = nt / 2; o >= 1; o >>= 1) {
-            if (tid < o) {
-                const double ov = rv[tid + o];
-                const int oi = ri[tid + o];
-                if (ov > rv[tid] || (ov == rv[tid] && oi < ri[tid])) {
-                    rv[tid] = ov;
-                    ri[tid] = oi;
-                }
-            }
-            __syncthreads();
-        }
-        const int piv = ri[0];
-        const double pv = M[(int64_t)piv * m + j];
-        if (!(fabs(pv) > 0.0)) ok = false;
-        __syncthreads();
-        // swap rows j and piv into the row buffer (normalised) and row piv
-        for (int c = j + tid; c < m; c += nt) {
-            const double a = M[(int64_t)j * m + c], b = M[(int64_t)piv * m + c];
-            rowbuf[c] = b / pv;
-            if (piv != j) M[(int64_t)piv * m + c] = a;
-        }
-        for (int i = tid; i < p; i += nt) colbuf[i] = i == j ? 0.0 : (i == piv ? M[(int64_t)j * m + j]
-                                                                               : M[(int64_t)i * m + j]);
-        __syncthreads();
-        // eliminate column j from every other row; row j becomes the pivot row
-        const int w = m - j;
-        for (int e = tid; e < p * w; e += nt) {
-            const int i = e / w, c = j + (e - i * w);
-            if (i == j) {
-                M[(int64_t)i * m + c] = rowbuf[c];
-            } else {
-                const double f = colbuf[i];
-                M[(int64_t)i * m + c] = fma(-f, rowbuf[c], M[(int64_t)i * m + c]);
-            }
-        }
-        __syncthreads();
-    }
-    return ok;
-}
-
-// One workgroup per system: k < r the eigenvector system of component k,
-// k == r the inverse of G.
-__global__ __launch_bounds__(1024) void k_adj_solve(AdjDesc a) {
-    __shared__ double rowbuf[2 * kMaxBands], colbuf[kMaxBands], rv[1024];
-    __shared__ int ri[1024];
-    __shared__ double rhs[kMaxBands], u[kMaxBands], sdot;
-    const int p = a.p, r = a.r, k = blockIdx.x, tid = threadIdx.x;
-    const int m = k < r ? p + 1 : 2 * p;
-    double* M = a.aug + (int64_t)k * p * 2 * p;
-    if (k < r) {
-        const double lk = a.evals[k];
-        for (int j = tid; j < p; j += blockDim.x) {
-            const double s = a.sigma[j];
-            u[j] = a.V[(int64_t)k * p + j];
-            rhs[j] = a.dPt[(int64_t)k * p + j] / s + s * a.dQ[(int64_t)k * p + j];   // dV[:, k]
-        }
-        __syncthreads();
-        if (tid < 64) {
-            double d = 0.0;
-            for (int j = tid; j < p; j += 64) d = fma(u[j], rhs[j], d);
-            d = wave_sum(d);
-            if (tid == 0) sdot = d;
-        }
-        __syncthreads();
-        for (int e = tid; e < p * m; e += blockDim.x) {
-            const int i = e / m, c = e - i * m;
-            double v;
-            if (c < p) {
-                const double cij = a.G[(int64_t)i * p + c] / (a.sigma[i] * a.sigma[c]);
-                v = (i == c ? lk : 0.0) - cij + lk * u[i] * u[c];
-            } else {
-                v = rhs[i] - u[i] * sdot;
-            }
-            M[(int64_t)i * m + c] = v;
-        }
-    } else {
-        for (int e = tid; e < p * m; e += blockDim.x) {
-            const int i = e / m, c = e - i * m;
-            M[(int64_t)i * m + c] = c < p ? a.G[(int64_t)i * p + c] : (c - p == i ? 1.0 : 0.0);
-        }
-    }
-    __syncthreads();
-    const bool ok = gauss_jordan(M, p, m, rowbuf, colbuf, rv, ri);
-    if (!ok && tid == 0) set_status(a.status, HYRES_DEV_NOT_PD);
-    if (k < r) {
-        for (int i = tid; i < p; i += blockDim.x) a.Wsol[(int64_t)k * p + i] = M[(int64_t)i * m + p];
-    } else {
-        for (int e = tid; e < p * p; e += blockDim.x) {
-            const int i = e / p, c = e - i * p;
-            a.Ginv[e] = M[(int64_t)i * m + p + c];
-        }
-    }
-}
-
-// dC, dsigma and dG (one workgroup).
-__global__ __launch_bounds__(1024) void k_adj_combine(AdjDesc a) {
-    __shared__ double gsc[kMaxBands];
+// dC = sum_k sym(w_k v_k^T) and the noise term gsc_j = n sigma_j^3 dsigma_j / 2
+// (one workgroup; w_k from the eigen-adjoint sweeps).
+__global__ __launch_bounds__(1024) void k_adj_dc(AdjDesc a) {
+    __shared__ double sw[kMaxRank][kMaxBands], sv[kMaxRank][kMaxBands], ssig[kMaxBands];
     const int p = a.p, r = a.r, tid = threadIdx.x;
     const double n = (double)a.n;
+    for (int e = tid; e < r * p; e += blockDim.x) {
+        sw[e / p][e % p] = a.Wsol[e];
+        sv[e / p][e % p] = a.V[e];
+    }
+    for (int j = tid; j < p; j += blockDim.x) ssig[j] = a.sigma[j];
+    __syncthreads();
     for (int e = tid; e < p * p; e += blockDim.x) {
         const int i = e / p, j = e - i * p;
         double s = 0.0;
-        for (int k = 0; k < r; ++k)
-            s += a.Wsol[(int64_t)k * p + i] * a.V[(int64_t)k * p + j] + a.Wsol[(int64_t)k * p + j] * a.V[(int64_t)k * p + i];
+        for (int k = 0; k < r; ++k) s += sw[k][i] * sv[k][j] + sw[k][j] * sv[k][i];
         a.dC[e] = 0.5 * s;
     }
     __syncthreads();
     for (int j = tid; j < p; j += blockDim.x) {
-        const double sj = a.sigma[j];
+        const double sj = ssig[j];
         double ds = 0.0;
         for (int k = 0; k < r; ++k) {
-            const double v = a.V[(int64_t)k * p + j];
+            const double v = sv[k][j];
             ds += -a.dPt[(int64_t)k * p + j] * v / (sj * sj) + a.dQ[(int64_t)k * p + j] * v;
         }
         double t = 0.0;
-        for (int i = 0; i < p; ++i) t = fma(a.dC[(int64_t)i * p + j], a.G[(int64_t)i * p + j] / (a.sigma[i] * sj), t);
+#pragma unroll 8
+        for (int i = 0; i < p; ++i) t = fma(a.dC[(int64_t)i * p + j], a.G[(int64_t)i * p + j] / (ssig[i] * sj), t);
         ds -= 2.0 * t / sj;
-        gsc[j] = 0.5 * n * sj * sj * sj * ds;
+        a.gsc[j] = 0.5 * n * sj * sj * sj * ds;
     }
+}
+
+// dG2 = 2 (D^-1 dC D^-1 + G^-1 diag(gsc) G^-1), one row per workgroup.
+__global__ __launch_bounds__(256) void k_adj_dg(AdjDesc a) {
+    __shared__ double srow[kMaxBands];
+    const int p = a.p, i = blockIdx.x, tid = threadIdx.x;
+    for (int l = tid; l < p; l += blockDim.x) srow[l] = a.Ginv[(int64_t)i * p + l] * a.gsc[l];
     __syncthreads();
-    for (int e = tid; e < p * p; e += blockDim.x) {
-        const int i = e / p, j = e - i * p;
-        double s = a.dC[e] / (a.sigma[i] * a.sigma[j]);
-        for (int l = 0; l < p; ++l) s = fma(a.Ginv[(int64_t)i * p + l] * gsc[l], a.Ginv[(int64_t)l * p + j], s);
-        a.dG2[e] = 2.0 * s;
+    const double si = a.sigma[i];
+    for (int j = tid; j < p; j += blockDim.x) {
+        double s = a.dC[(int64_t)i * p + j] / (si * a.sigma[j]);
+#pragma unroll 8
+        for (int l = 0; l < p; ++l) s = fma(srow[l], a.Ginv[(int64_t)l * p + j], s);
+        a.dG2[(int64_t)i * p + j] = 2.0 * s;
     }
 }
 
@@ -407,8 +310,10 @@ hipError_t launch_adjoint_post(const AdjDesc& a, int dtype, hipStream_t s) {
         hipLaunchKernelGGL(k_adj_xprod<float>, dim3(a.slots), dim3(256), 0, s, a, a.A, a.Y, a.pitch, a.row_pitch);
     const int E = a.r * a.p;
     hipLaunchKernelGGL(k_adj_reduce, dim3((E + 255) / 256), dim3(256), 0, s, a.part, a.slots, E, a.dPt);
-    hipLaunchKernelGGL(k_adj_solve, dim3(a.r + 1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_adj_combine, dim3(1), dim3(1024), 0, s, a);
+    hipError_t e = launch_adj_sweep(a, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_dc, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_adj_dg, dim3(a.p), dim3(256), 0, s, a);
     const dim3 grid((unsigned)((a.n + kDyPix - 1) / kDyPix), (unsigned)((a.p + kDyCol - 1) / kDyCol));
     if (dtype == HYRES_F64) hipLaunchKernelGGL(k_adj_dy<double>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_adj_dy<float>, grid, dim3(256), 0, s, a);

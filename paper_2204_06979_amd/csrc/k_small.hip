@@ -125,6 +125,97 @@ __device__ __forceinline__ void group_maxmin(double& lo, double& hi, int M) {
     hi = ha < hb ? ha : hb;
 }
 
+// Gauss-Jordan sweep of the symmetric positive definite p x p matrix M held
+// in the register tile A (thread (tr, tc) of the ROWS x COLS grid holds the
+// entries (tr + ROWS a, tc + COLS b); entries beyond p hold the identity).
+// Afterwards A = -M^-1.  diag: the diagonal of M in LDS, for the pivot test (a
+// pivot below 1e-12 of its diagonal entry is replaced by 1 and reported as
+// HYRES_DEV_NOT_PD).  Every thread of the block takes part (barriers).
+template <int BR, int BC, int ROWS, int COLS>
+__device__ __forceinline__ int gj_sweep(double (&A)[BR][BC], int p, int tr, int tc, const double* diag,
+                                        double (*s_col)[kSmallP], double (*s_col2)[kSmallP]) {
+    constexpr int NTH = ROWS * COLS;
+    int flags = 0;
+    // pivots in pairs (k0, k1): one barrier per pair.  The column k1 after
+    // the k0 step is formed from the two broadcast columns exactly as the
+    // k0 step forms it in the registers of its owners, so the result is
+    // that of sweeping the pivots one at a time.  Grids of more than 512
+    // threads (a tighter register budget) sweep one pivot per barrier.
+    constexpr bool kPairs = NTH <= 512;
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) {
+        for (int kk = 0; kk < COLS; kk += kPairs ? 2 : 1) {
+            const int k0 = COLS * bb + kk, k1 = k0 + 1;
+            if (k0 >= p) break;
+            const bool two = kPairs && k1 < p;
+            const int buf = (kPairs ? k0 >> 1 : k0) & 1;
+            if (tc == kk) {
+#pragma unroll
+                for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
+            }
+            if (two && tc == kk + 1) {
+#pragma unroll
+                for (int a = 0; a < BR; ++a) s_col2[buf][tr + ROWS * a] = A[a][bb];
+            }
+            __syncthreads();
+            // the pivot is the regression residual of band k on the bands swept so far
+            double d0 = s_col[buf][k0];
+            if (!(d0 > 1e-12 * diag[k0])) {
+                flags |= HYRES_DEV_NOT_PD;
+                d0 = 1.0;
+            }
+            const double inv0 = 1.0 / d0;
+            double cj[BC];
+#pragma unroll
+            for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + COLS * b];
+#pragma unroll
+            for (int a = 0; a < BR; ++a) {
+                const int i = tr + ROWS * a;
+                const double ci = s_col[buf][i] * inv0;
+                if (i == k0) {
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv0;
+                    if (tc == kk) A[a][bb] = -inv0;
+                } else {
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
+                    if (tc == kk) A[a][bb] = ci;
+                }
+            }
+            if (two) {
+                const double ck1 = s_col[buf][k1];
+                // column k1 after the k0 step
+                auto ep = [&](int i) {
+                    return i == k0 ? ck1 * inv0 : fma(-(s_col[buf][i] * inv0), ck1, s_col2[buf][i]);
+                };
+                double d1 = ep(k1);
+                if (!(d1 > 1e-12 * diag[k1])) {
+                    flags |= HYRES_DEV_NOT_PD;
+                    d1 = 1.0;
+                }
+                const double inv1 = 1.0 / d1;
+#pragma unroll
+                for (int b = 0; b < BC; ++b) cj[b] = ep(tc + COLS * b);
+#pragma unroll
+                for (int a = 0; a < BR; ++a) {
+                    const int i = tr + ROWS * a;
+                    const double ci = ep(i) * inv1;
+                    if (i == k1) {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv1;
+                        if (tc == kk + 1) A[a][bb] = -inv1;
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
+                        if (tc == kk + 1) A[a][bb] = ci;
+                    }
+                }
+            }
+        }
+    }
+    return flags;
+}
+
 template <int BR, int BC, int ROWS, int COLS>
 __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restrict__ descs,
                                                        const int* __restrict__ cubes, int ncls) {
@@ -171,83 +262,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     if (d.mode & 1) {
         // diagonal of G for the pivot test (s_ev is free until the eigenvalues)
         for (int i = t; i < p; i += NTH) s_ev[i] = d.G[(int64_t)i * p + i];
-        // pivots in pairs (k0, k1): one barrier per pair.  The column k1 after
-        // the k0 step is formed from the two broadcast columns exactly as the
-        // k0 step forms it in the registers of its owners, so the result is
-        // that of sweeping the pivots one at a time.  Grids of more than 512
-        // threads (a tighter register budget) sweep one pivot per barrier.
-        constexpr bool kPairs = NTH <= 512;
-#pragma unroll
-        for (int bb = 0; bb < BC; ++bb) {
-            for (int kk = 0; kk < COLS; kk += kPairs ? 2 : 1) {
-                const int k0 = COLS * bb + kk, k1 = k0 + 1;
-                if (k0 >= p) break;
-                const bool two = kPairs && k1 < p;
-                const int buf = (kPairs ? k0 >> 1 : k0) & 1;
-                if (tc == kk) {
-#pragma unroll
-                    for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
-                }
-                if (two && tc == kk + 1) {
-#pragma unroll
-                    for (int a = 0; a < BR; ++a) s_col2[buf][tr + ROWS * a] = A[a][bb];
-                }
-                __syncthreads();
-                // the pivot is the regression residual of band k on the bands swept so far
-                double d0 = s_col[buf][k0];
-                if (!(d0 > 1e-12 * s_ev[k0])) {
-                    flags |= HYRES_DEV_NOT_PD;
-                    d0 = 1.0;
-                }
-                const double inv0 = 1.0 / d0;
-                double cj[BC];
-#pragma unroll
-                for (int b = 0; b < BC; ++b) cj[b] = s_col[buf][tc + COLS * b];
-#pragma unroll
-                for (int a = 0; a < BR; ++a) {
-                    const int i = tr + ROWS * a;
-                    const double ci = s_col[buf][i] * inv0;
-                    if (i == k0) {
-#pragma unroll
-                        for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv0;
-                        if (tc == kk) A[a][bb] = -inv0;
-                    } else {
-#pragma unroll
-                        for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
-                        if (tc == kk) A[a][bb] = ci;
-                    }
-                }
-                if (two) {
-                    const double ck1 = s_col[buf][k1];
-                    // column k1 after the k0 step
-                    auto ep = [&](int i) {
-                        return i == k0 ? ck1 * inv0 : fma(-(s_col[buf][i] * inv0), ck1, s_col2[buf][i]);
-                    };
-                    double d1 = ep(k1);
-                    if (!(d1 > 1e-12 * s_ev[k1])) {
-                        flags |= HYRES_DEV_NOT_PD;
-                        d1 = 1.0;
-                    }
-                    const double inv1 = 1.0 / d1;
-#pragma unroll
-                    for (int b = 0; b < BC; ++b) cj[b] = ep(tc + COLS * b);
-#pragma unroll
-                    for (int a = 0; a < BR; ++a) {
-                        const int i = tr + ROWS * a;
-                        const double ci = ep(i) * inv1;
-                        if (i == k1) {
-#pragma unroll
-                            for (int b = 0; b < BC; ++b) A[a][b] = cj[b] * inv1;
-                            if (tc == kk + 1) A[a][bb] = -inv1;
-                        } else {
-#pragma unroll
-                            for (int b = 0; b < BC; ++b) A[a][b] = fma(-ci, cj[b], A[a][b]);
-                            if (tc == kk + 1) A[a][bb] = ci;
-                        }
-                    }
-                }
-            }
-        }
+        flags |= gj_sweep<BR, BC, ROWS, COLS>(A, p, tr, tc, s_ev, s_col, s_col2);
         // after sweeping every index, A = -G^-1
 #pragma unroll
         for (int a = 0; a < BR; ++a)
@@ -832,6 +847,126 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     __syncthreads();
     if (t == 0 && s_flags) set_status(d.status, s_flags);
     HYRES_STAMP(d, 7);
+}
+
+// Eigen-adjoint systems (block k < r) and the inverse Gram (block r), one
+// workgroup each, by the register sweep above.  For component k the system is
+// (lambda_k I - C_perp) y = (I - U U^T) dV_k, C_perp = C - U Lambda U^T with the
+// top r eigenpairs (U, Lambda) of C removed: it is symmetric positive
+// definite (eigenvalue lambda_k on the top-r directions, lambda_k - lambda_i > 0
+// on the others), so the sweep needs no pivoting.  y is the part of the
+// eigenvector derivative outside the top-r subspace; inside it the derivative
+// is explicit:  w_k = y + sum_{i<r, i!=k} u_i (u_i^T dV_k) / (lambda_k - lambda_i),
+// the same w_k as the solution of (lambda_k I - C + lambda_k u_k u_k^T) w =
+// (I - u_k u_k^T) dV_k.  dV_k = D^-1 dP_k + D dQ_k.
+template <int BR, int BC, int ROWS, int COLS>
+__global__ __launch_bounds__(ROWS * COLS) void k_adj_sweep(AdjDesc a) {
+    constexpr int NTH = ROWS * COLS;
+    constexpr int NW = NTH / 64;
+    __shared__ double s_col[2][kSmallP];
+    __shared__ double s_col2[2][kSmallP];
+    __shared__ double s_diag[kSmallP], s_sig[kSmallP], s_rhs[kSmallP];
+    __shared__ double s_u[kMaxRank][kSmallP];
+    __shared__ double s_ev[kMaxRank], s_dot[kMaxRank];
+    __shared__ double s_part[kSmallP][COLS];          // row partial sums of M^-1 rhs
+    const int p = a.p, r = a.r, k = blockIdx.x;
+    const int t = threadIdx.x, tc = t % COLS, tr = t / COLS, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    for (int i = t; i < p; i += NTH) s_sig[i] = a.sigma[i];
+    for (int e = t; e < r * p; e += NTH) s_u[e / p][e % p] = a.V[e];
+    if (t < r) s_ev[t] = a.evals[t];
+    __syncthreads();
+    const bool eig = k < r;
+    const double lk = eig ? s_ev[k] : 0.0;
+    if (eig) {
+        for (int i = t; i < p; i += NTH) s_rhs[i] = a.dPt[(int64_t)k * p + i] / s_sig[i] + s_sig[i] * a.dQ[(int64_t)k * p + i];
+        __syncthreads();
+        for (int m = wave; m < r; m += NW) {
+            double d = 0.0;
+            for (int i = lane; i < p; i += 64) d = fma(s_u[m][i], s_rhs[i], d);
+            d = wave_sum(d);
+            if (lane == 0) s_dot[m] = d;
+        }
+        __syncthreads();
+        for (int i = t; i < p; i += NTH) {
+            double v = s_rhs[i];
+            for (int m = 0; m < r; ++m) v = fma(-s_u[m][i], s_dot[m], v);
+            s_rhs[i] = v;
+            double dg = lk - a.G[(int64_t)i * p + i] / (s_sig[i] * s_sig[i]);
+            for (int m = 0; m < r; ++m) dg = fma(s_ev[m] * s_u[m][i], s_u[m][i], dg);
+            s_diag[i] = dg;
+        }
+    } else {
+        for (int i = t; i < p; i += NTH) s_diag[i] = a.G[(int64_t)i * p + i];
+    }
+    double A[BR][BC];
+#pragma unroll
+    for (int aa = 0; aa < BR; ++aa)
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+            const int i = tr + ROWS * aa, j = tc + COLS * b;
+            double v = i == j ? 1.0 : 0.0;
+            if (i < p && j < p) {
+                const double g = a.G[(int64_t)i * p + j];
+                if (eig) {
+                    v = (i == j ? lk : 0.0) - g / (s_sig[i] * s_sig[j]);
+                    for (int m = 0; m < r; ++m) v = fma(s_ev[m] * s_u[m][i], s_u[m][j], v);
+                } else {
+                    v = g;
+                }
+            }
+            A[aa][b] = v;
+        }
+    __syncthreads();
+    const int flags = gj_sweep<BR, BC, ROWS, COLS>(A, p, tr, tc, s_diag, s_col, s_col2);
+    if (flags && t == 0) set_status(a.status, flags);
+    if (eig) {
+        // y = M^-1 rhs = -A rhs: partial sums over this thread's columns, then rows in column order
+#pragma unroll
+        for (int aa = 0; aa < BR; ++aa) {
+            double part = 0.0;
+#pragma unroll
+            for (int b = 0; b < BC; ++b) {
+                const int j = tc + COLS * b;
+                part = fma(A[aa][b], j < p ? s_rhs[j] : 0.0, part);
+            }
+            s_part[tr + ROWS * aa][tc] = part;
+        }
+        __syncthreads();
+        for (int i = t; i < p; i += NTH) {
+            double y = 0.0;
+            for (int c = 0; c < COLS; ++c) y -= s_part[i][c];
+            for (int m = 0; m < r; ++m)
+                if (m != k) y = fma(s_u[m][i], s_dot[m] / (lk - s_ev[m]), y);
+            a.Wsol[(int64_t)k * p + i] = y;
+        }
+    } else {
+#pragma unroll
+        for (int aa = 0; aa < BR; ++aa)
+#pragma unroll
+            for (int b = 0; b < BC; ++b) {
+                const int i = tr + ROWS * aa, j = tc + COLS * b;
+                if (i < p && j < p) a.Ginv[(int64_t)i * p + j] = -A[aa][b];
+            }
+    }
+}
+
+hipError_t launch_adj_sweep(const AdjDesc& a, hipStream_t s) {
+    const int p = a.p;
+    const dim3 grid(a.r + 1);
+#define HYRES_A(BR, BC, RW, CL) hipLaunchKernelGGL((k_adj_sweep<BR, BC, RW, CL>), grid, dim3(RW * CL), 0, s, a)
+    if (p <= 32) HYRES_A(2, 2, 16, 16);
+    else if (p <= 64) HYRES_A(4, 4, 16, 16);
+    else if (p <= 96) HYRES_A(6, 6, 16, 16);
+    else if (p <= 128) HYRES_A(8, 8, 16, 16);
+    else if (p <= 144) HYRES_A(5, 9, 32, 16);
+    else if (p <= 160) HYRES_A(5, 10, 32, 16);
+    else if (p <= 176) HYRES_A(11, 6, 16, 32);
+    else if (p <= 192) HYRES_A(8, 6, 24, 32);
+    else if (p <= 224) HYRES_A(7, 7, 32, 32);
+    else return hipErrorInvalidValue;
+#undef HYRES_A
+    return hipGetLastError();
 }
 
 // Kernel variant for p bands: (BR, BC, ROWS).

@@ -18,6 +18,10 @@ other readings in the design notes), in the whitened frame of HyRes
   W3  alternate K times:
         V <- the orthonormal factor of the polar decomposition of Yw^T W F
              (the maximiser of tr(V^T Yw^T W F) over V^T V = I: Procrustes);
+             a component whose coefficients are all zero (the SURE threshold
+             can zero a whole component) does not enter the objective, so
+             its column is free: it keeps its previous direction, made
+             orthonormal to the other columns (Gram-Schmidt, in index order);
         F <- soft(W^T Yw V, lam)          (the F step of HyRes with the new V);
   W4  X = (W F V^T) * sigma.
 For even image sizes W is orthogonal and each half-step does not increase J.
@@ -30,13 +34,30 @@ import numpy as np
 
 from oracle import hyres_oracle as HO
 
-__all__ = ["polar_factor", "objective", "wsrrr"]
+__all__ = ["polar_factor", "procrustes_step", "objective", "wsrrr"]
 
 
 def polar_factor(M: np.ndarray) -> np.ndarray:
     """Orthonormal factor of M (p x r, full column rank): U Q^T for M = U S Q^T."""
     U, _, Qt = np.linalg.svd(M, full_matrices=False)
     return U @ Qt
+
+
+def procrustes_step(M: np.ndarray, V_prev: np.ndarray) -> np.ndarray:
+    """W3's V step: the polar factor of the columns of M that are not zero
+    (squared norm above 1e-24 of the largest); each zero column takes the
+    previous direction, orthonormalised against the columns already set."""
+    nrm = np.sum(M * M, axis=0)
+    live = nrm > 1e-24 * nrm.max()
+    V = np.zeros_like(V_prev)
+    V[:, live] = polar_factor(M[:, live])
+    for k in np.flatnonzero(~live):
+        v = V_prev[:, k].copy()
+        for j in range(V.shape[1]):
+            if live[j] or j < k:
+                v -= (V[:, j] @ v) * V[:, j]
+        V[:, k] = v / np.linalg.norm(v)
+    return V
 
 
 def _f_step(Yw: np.ndarray, V: np.ndarray, lam: np.ndarray, H: int, W: int, L: int):
@@ -68,7 +89,7 @@ def wsrrr(Y: np.ndarray, r: int, L: int, iters: int, sigma: Optional[np.ndarray]
     F, Zh = _f_step(Yw, V, lam_, H, Wd, L)
     hist = [objective(Yw, F, Zh, V, lam_)]
     for _ in range(iters):                                             # W3
-        V = polar_factor(Yw.T @ Zh)
+        V = procrustes_step(Yw.T @ Zh, V)
         if history:
             hist.append(objective(Yw, F, Zh, V, lam_))
         F, Zh = _f_step(Yw, V, lam_, H, Wd, L)

@@ -63,3 +63,19 @@ def test_zero_iterations_is_hyres():
     cube = synth.config_cube(1, keep_clean=False)
     out = WS.wsrrr(cube.Y, 4, 3, 0)
     np.testing.assert_allclose(out["X"], out["hyres_X"], rtol=0, atol=1e-12)
+
+
+def test_a_zero_component_keeps_its_direction():
+    rng = np.random.default_rng(6)
+    Vp, _ = np.linalg.qr(rng.standard_normal((9, 3)))
+    M = rng.standard_normal((9, 3))
+    M[:, 1] = 0.0
+    V = WS.procrustes_step(M, Vp)
+    np.testing.assert_allclose(V.T @ V, np.eye(3), atol=1e-12)
+    np.testing.assert_allclose(V[:, [0, 2]], WS.polar_factor(M[:, [0, 2]]), atol=1e-12)
+    # column 1: the previous direction with its parts along the other two removed
+    v = Vp[:, 1] - V[:, [0, 2]] @ (V[:, [0, 2]].T @ Vp[:, 1])
+    np.testing.assert_allclose(V[:, 1], v / np.linalg.norm(v), atol=1e-12)
+    # nothing zero: the plain polar factor
+    M2 = rng.standard_normal((9, 3))
+    np.testing.assert_allclose(WS.procrustes_step(M2, Vp), WS.polar_factor(M2), atol=1e-12)

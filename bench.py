@@ -552,6 +552,40 @@ def run_hyminor(args, api, synth):
     return e
 
 
+def run_wsrrr(args, api, synth):
+    """WSRRR on the 349 x 1905 x 144 FP32 cube: HyRes (rank 8, 4 levels, native
+    FP32), then 5 Procrustes / soft-threshold alternations at its thresholds;
+    checked against the oracle at the device's noise and thresholds."""
+    import torch
+    from oracle import wsrrr_oracle as WO
+    cube = synth.config_cube(2, keep_clean=False)
+    Yh = cube.Y
+    H, W, p = Yh.shape
+    r, L, K = 8, 4, 5
+    Y = torch.tensor(Yh, device="cuda")
+    Ys = [Y, Y.clone()]
+    run = lambda i: api.wsrrr(Ys[i % 2], r, L, K)        # noqa: E731
+    for i in range(max(args.warmup, 1)):
+        run(i)
+    t = timed_steps(run, args.steps)
+    n = H * W
+    # the HyRes solve, then per alternation: Y and Zh read for Y^T Zh, the
+    # projection (Y read, Z written), the two transforms, Zh written
+    per_iter = 4.0 * (2 * n * p + 4 * n * r) + solve_bytes([(H, W, p, r, L)]) - 4.0 * (n * r + n * p)
+    e = rate_entry(float(n * p), t, solve_bytes([(H, W, p, r, L)]) + K * per_iter)
+    X, info = api.wsrrr(Y, r, L, K)
+    t0 = time.perf_counter()
+    ref = WO.wsrrr(Yh.astype(np.float64), r, L, K, sigma=info["sigma"].cpu().numpy(), lam=info["lam"].cpu().numpy())
+    e["oracle_s"] = time.perf_counter() - t0
+    e["oracle_sample"] = "one oracle run of the whole cube at the device's noise and thresholds"
+    e["errors_vs_fp64_oracle"] = x_errors(X.cpu().numpy(), ref["X"])
+    e["device_status"] = int(info["status"].cpu()[0])
+    e["workload"] = ("WSRRR of the 349x1905x144 FP32 cube: HyRes rank 8, 4 levels, native FP32, then 5 "
+                     "alternations of the Procrustes and soft-threshold steps")
+    log("wsrrr %.3f ms/step" % t["ms_per_step"])
+    return e
+
+
 def run_forpdn(args, api, synth):
     """FORPDN on the 349 x 1905 x 144 FP32 cube, 4 levels, thresholds by SURE;
     checked against the oracle at the device's noise and thresholds on the
@@ -597,7 +631,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=["native", "mixed", "both"])
-    ap.add_argument("--workload", default="all", choices=["all", "single", "small", "grad", "batch", "tiled", "hyminor", "forpdn"])
+    ap.add_argument("--workload", default="all", choices=["all", "single", "small", "grad", "batch", "tiled", "hyminor", "forpdn", "wsrrr"])
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -616,13 +650,14 @@ def main() -> int:
     timer = Timer(_lib, lib, api._handle(dev))
     precs = ["native", "mixed"] if args.precision == "both" else [args.precision]
     others = {}
-    if args.workload in ("small", "grad", "batch", "tiled", "hyminor", "forpdn"):
+    if args.workload in ("small", "grad", "batch", "tiled", "hyminor", "forpdn", "wsrrr"):
         # one secondary workload alone: its own line
         fn = {"small": lambda: run_small_fp64(args, api, synth), "grad": lambda: run_grad(args, api, synth),
               "batch": lambda: run_batch(args, api, synth, precs),
               "tiled": lambda: run_tiled(args, api, synth, precs),
               "hyminor": lambda: run_hyminor(args, api, synth),
-              "forpdn": lambda: run_forpdn(args, api, synth)}[args.workload]
+              "forpdn": lambda: run_forpdn(args, api, synth),
+              "wsrrr": lambda: run_wsrrr(args, api, synth)}[args.workload]
         e = fn()
         print(json.dumps({"metric": METRIC, "workload": args.workload, "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "result": e}))
@@ -635,7 +670,8 @@ def main() -> int:
                          ("batch64", lambda: run_batch(args, api, synth, precs)),
                          ("tiled_2048x2048x224", lambda: run_tiled(args, api, synth, precs)),
                          ("hyminor_349x1905x144", lambda: run_hyminor(args, api, synth)),
-                         ("forpdn_349x1905x144", lambda: run_forpdn(args, api, synth))):
+                         ("forpdn_349x1905x144", lambda: run_forpdn(args, api, synth)),
+                         ("wsrrr_349x1905x144", lambda: run_wsrrr(args, api, synth))):
             t0 = time.time()
             others[name] = fn()
             log("%s done in %.1f s" % (name, time.time() - t0))

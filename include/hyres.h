@@ -311,6 +311,31 @@ hyres_status hyres_hyminor(hyres_handle* h, const void* Y, int H, int W, int p,
                            const hyres_outputs* out, void* workspace, size_t workspace_bytes,
                            hyres_stream_t stream);
 
+/* ---- WSRRR: wavelet-based sparse reduced-rank regression ----------------- */
+
+/* Defined by: Section 2.1 -- WSRRR is a low-rank, wavelet-based method for
+ * Gaussian noise that can also extract features; the paper prints nothing
+ * more, and this library takes, in the whitened frame of HyRes (Yw = Y / sigma):
+ * the model Yw = W F V^T + noise with F the wavelet coefficients of r component
+ * images and V^T V = I, fitted by minimising 1/2 ||Yw - W F V^T||^2 +
+ * sum_i lambda_i ||f_i||_1; it starts from the HyRes solve (its sigma,
+ * subspace, SURE thresholds, which then stay fixed, and coefficients) and
+ * alternates `iters` times the Procrustes step V <- polar factor of
+ * Yw^T W F with the soft-threshold step F <- soft(W^T Yw V, lambda);
+ * X = W F V^T sigma.  iters = 0 is hyres_denoise.  Native precision only
+ * (HYRES_PREC_MIXED and the HYRES_FLAG_RANK_* flags: HYRES_E_UNSUPPORTED);
+ * other arguments, outputs (V: the final subspace) and the layout rules as for
+ * hyres_denoise; the workspace comes from hyres_wsrrr_workspace_size.  A
+ * component thresholded to zero leaves the polar factor rank deficient:
+ * HYRES_DEV_DEGENERATE in the status word. */
+hyres_status hyres_wsrrr_workspace_size(int H, int W, int p, const hyres_options* opt, int dtype,
+                                        size_t* bytes);
+hyres_status hyres_wsrrr(hyres_handle* h, const void* Y, int H, int W, int p,
+                         int64_t pitch, int64_t row_pitch, int dtype, const hyres_options* opt,
+                         int iters, const double* sigma_in, const double* lambda_in, void* X,
+                         int64_t x_pitch, int64_t x_row_pitch, const hyres_outputs* out,
+                         void* workspace, size_t workspace_bytes, hyres_stream_t stream);
+
 /* ---- FORPDN: first-order spectral roughness penalty denoising ------------ */
 
 /* Defined by: Section 2.1 -- FORPDN is a full-rank, wavelet-based method for

@@ -79,6 +79,9 @@ SIGNATURES = {
     "hyres_l1l1_spectral": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(L1Options), vp, i64, i64, vp]),
     "hyres_hyminor": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), dp, dp,
                             C.POINTER(L1Options), vp, i64, i64, C.POINTER(Outputs), vp, sz, vp]),
+    "hyres_wsrrr_workspace_size": (i32, [i32, i32, i32, C.POINTER(Options), i32, C.POINTER(sz)]),
+    "hyres_wsrrr": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, C.POINTER(Options), i32, dp, dp, vp, i64, i64,
+                          C.POINTER(Outputs), vp, sz, vp]),
     "hyres_forpdn_workspace_size": (i32, [i32, i32, i32, i32, i32, i32, C.POINTER(sz)]),
     "hyres_forpdn": (i32, [vp, vp, i32, i32, i32, i64, i64, i32, i32, dp, dp, vp, i64, i64, dp, dp, dp, vp, vp,
                            sz, vp]),

@@ -294,6 +294,44 @@ def hyminor(Y: torch.Tensor, rank: int, levels: int, lam: float = 1.0, mu1: floa
     return X, dn.info()
 
 
+def wsrrr(Y: torch.Tensor, rank: int, levels: int, iters: int = 5, sigma: Optional[torch.Tensor] = None,
+          lam: Optional[torch.Tensor] = None, scope: str = "all"):
+    """WSRRR of one H x W x p cube (hyres_wsrrr): HyRes, then ``iters``
+    alternations of the Procrustes step for the subspace and the
+    soft-threshold step for the wavelet coefficients at HyRes's thresholds.
+    Returns (X, info) as ``denoise`` (V: the final subspace)."""
+    _need_cuda(Y, "Y")
+    H, W, p = Y.shape
+    dev = Y.device
+    dt = _dtype_code(Y)
+    lib = L.lib()
+    opt = L.Options(rank, levels, L.PREC_NATIVE, L.SCOPE_ALL if scope == "all" else L.SCOPE_DETAIL, 0)
+    nb = C.c_size_t()
+    L.check(lib.hyres_wsrrr_workspace_size(H, W, p, C.byref(opt), dt, C.byref(nb)), "wsrrr workspace size")
+    buf, ws = _workspace(nb.value, dev)
+    o = dict(sigma=torch.empty(p, dtype=torch.float64, device=dev),
+             V=torch.empty(rank, p, dtype=torch.float64, device=dev),
+             evals=torch.empty(p, dtype=torch.float64, device=dev),
+             lam=torch.empty(rank, dtype=torch.float64, device=dev),
+             sure=torch.empty(rank, dtype=torch.float64, device=dev),
+             gap=torch.empty(1, dtype=torch.float64, device=dev),
+             status=torch.zeros(1, dtype=torch.int32, device=dev),
+             rank=torch.zeros(1, dtype=torch.int32, device=dev))
+    outs = L.Outputs(o["sigma"].data_ptr(), o["V"].data_ptr(), o["evals"].data_ptr(), o["lam"].data_ptr(),
+                     o["sure"].data_ptr(), o["gap"].data_ptr(), o["status"].data_ptr(), o["rank"].data_ptr())
+    X = torch.empty(H, W, p, dtype=Y.dtype, device=dev)
+    sg = None if sigma is None else sigma.to(device=dev, dtype=torch.float64).contiguous()
+    lm = None if lam is None else lam.to(device=dev, dtype=torch.float64).contiguous()
+    pitch, rp = _cube_strides(Y)
+    xp, xrp = _cube_strides(X)
+    L.check(lib.hyres_wsrrr(_handle(dev), Y.data_ptr(), H, W, p, pitch, rp, dt, C.byref(opt), int(iters), _ptr(sg),
+                            _ptr(lm), X.data_ptr(), xp, xrp, C.byref(outs), ws, nb.value, _stream(dev)),
+            "hyres_wsrrr")
+    del buf     # stream-ordered reuse by the caching allocator
+    o["V"] = o["V"].T
+    return X, o
+
+
 def forpdn(Y: torch.Tensor, levels: int, sigma: Optional[torch.Tensor] = None,
            lam: Optional[torch.Tensor] = None, X: Optional[torch.Tensor] = None):
     """FORPDN of one H x W x p cube (hyres_forpdn): whitened bands, the db2

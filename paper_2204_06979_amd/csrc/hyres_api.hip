@@ -1630,6 +1630,86 @@ HYRES_API hyres_status hyres_hyminor(hyres_handle* h, const void* Y, int H, int 
                         (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------- WSRRR
+namespace {
+// The HyRes workspace of the cube, then Y^T Zh (r x p) and its per-slot partial sums.
+struct WsrrrPlan {
+    Exec x;
+    int slots = 1;
+    size_t o_M = 0, o_part = 0;
+};
+
+hyres_status plan_wsrrr(WsrrrPlan& w, hyres_handle* h, int H, int W, int p, const hyres_options* opt, int dtype,
+                        int iters) {
+    if (!opt) return HYRES_E_NULL;
+    hyres_status st = check_opts(opt, p, dtype);
+    if (st) return st;
+    if (opt->precision != HYRES_PREC_NATIVE || (opt->flags & (HYRES_FLAG_RANK_HYSIME | HYRES_FLAG_RANK_SURE)))
+        return HYRES_E_UNSUPPORTED;
+    if (iters < 0) return HYRES_E_SHAPE;
+    one_cube(w.x, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
+    if ((st = plan_cubes(w.x, kAllParts))) return st;
+    const CubePlan& c = w.x.plan[0];
+    w.slots = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(c.n, 256)));
+    w.o_M = w.x.lay.add((size_t)c.r * p * 8);
+    w.o_part = w.x.lay.add((size_t)w.slots * c.r * p * 8);
+    return HYRES_OK;
+}
+}  // namespace
+
+HYRES_API hyres_status hyres_wsrrr_workspace_size(int H, int W, int p, const hyres_options* opt, int dtype,
+                                                  size_t* bytes) {
+    if (!bytes) return HYRES_E_NULL;
+    if (!valid_dtype(dtype)) return HYRES_E_DTYPE;
+    if (H < 1 || W < 1 || p < 2 || p > kMaxBands) return HYRES_E_SHAPE;
+    WsrrrPlan w;
+    hyres_status st = plan_wsrrr(w, nullptr, H, W, p, opt, dtype, 0);
+    if (st) return st;
+    *bytes = w.x.lay.total;
+    return HYRES_OK;
+}
+
+HYRES_API hyres_status hyres_wsrrr(hyres_handle* h, const void* Y, int H, int W, int p, int64_t pitch,
+                                   int64_t row_pitch, int dtype, const hyres_options* opt, int iters,
+                                   const double* sigma_in, const double* lambda_in, void* X, int64_t x_pitch,
+                                   int64_t x_row_pitch, const hyres_outputs* out, void* workspace,
+                                   size_t workspace_bytes, hyres_stream_t stream) {
+    if (!h || !X) return HYRES_E_NULL;
+    hyres_status st = check_cube(Y, H, W, p, pitch, row_pitch, dtype);
+    if (st) return st;
+    if (x_pitch < p || x_row_pitch < (int64_t)(W - 1) * x_pitch + p) return HYRES_E_SHAPE;
+    WsrrrPlan w;
+    if ((st = plan_wsrrr(w, h, H, W, p, opt, dtype, iters))) return st;
+    Exec& x = w.x;
+    x.plan[0].has_lambda = lambda_in != nullptr;
+    if ((st = check_ws(workspace, workspace_bytes, x.lay.total))) return st;
+    if ((st = set_device(h))) return st;
+    x.ws = workspace;
+    x.desc.assign(1, solve_desc(x.plan[0], workspace, Y, pitch, row_pitch, X, x_pitch, x_row_pitch, sigma_in,
+                                lambda_in, opt->flags, out));
+    const CubeDesc& d = x.desc[0];
+    hipStream_t s = (hipStream_t)stream;
+    // HyRes up to the denoised component images (noise, subspace, thresholds)
+    build_program(x, kAllStages & ~S_BP);
+    if ((st = upload_exec(x, s)) || (st = run_program(x, s, false))) return st;
+    AdjDesc a;
+    std::memset(&a, 0, sizeof(a));
+    a.W = W; a.p = p; a.r = d.r; a.n = d.n; a.nz = d.nz;
+    a.slots = w.slots;
+    a.part = at<double>(workspace, w.o_part);
+    double* M = at<double>(workspace, w.o_M);
+    for (int it = 0; it < iters; ++it) {
+        // V <- polar factor of Yw^T Zh, then F <- soft(W^T Yw V, lambda) with the thresholds held
+        HIPCHK(launch_planes_cube(dtype, a, d.Z, Y, pitch, row_pitch, M, s));
+        HIPCHK(launch_polar(x.descs(), M, s));
+        build_program(x, S_PROJ | S_DWT | S_IDWT);
+        if ((st = upload_exec(x, s)) || (st = run_program(x, s, false))) return st;
+    }
+    build_program(x, S_BP);
+    if ((st = upload_exec(x, s))) return st;
+    return run_program(x, s, false);
+}
+
 // ------------------------------------------------------------- FORPDN
 namespace {
 // Workspace of one FORPDN solve: the noise program (unless sigma is given),

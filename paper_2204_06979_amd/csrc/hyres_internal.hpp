@@ -208,6 +208,9 @@ struct AdjDesc {
     int* status;
 };
 hipError_t launch_adj_sweep(const AdjDesc& a, hipStream_t s);
+hipError_t launch_planes_cube(int dtype, const AdjDesc& a, const void* planes, const void* cube, int64_t cp,
+                              int64_t crp, double* out, hipStream_t s);
+hipError_t launch_polar(const CubeDesc* descs, const double* M, hipStream_t s);
 
 #ifdef HYRES_PHASE_TIMING
 #define HYRES_STAMP(d, i) \

@@ -320,6 +320,18 @@ hipError_t launch_adjoint_post(const AdjDesc& a, int dtype, hipStream_t s) {
     return hipGetLastError();
 }
 
+// out[k][b] = sum over the pixels of planes[k][q] cube[q][b] (r x p, FP64 sums).
+hipError_t launch_planes_cube(int dtype, const AdjDesc& a, const void* planes, const void* cube, int64_t cp,
+                              int64_t crp, double* out, hipStream_t s) {
+    if (dtype == HYRES_F64)
+        hipLaunchKernelGGL(k_adj_xprod<double>, dim3(a.slots), dim3(256), 0, s, a, planes, cube, cp, crp);
+    else
+        hipLaunchKernelGGL(k_adj_xprod<float>, dim3(a.slots), dim3(256), 0, s, a, planes, cube, cp, crp);
+    const int E = a.r * a.p;
+    hipLaunchKernelGGL(k_adj_reduce, dim3((E + 255) / 256), dim3(256), 0, s, a.part, a.slots, E, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_sure_grad(int dtype, const void* coef, int64_t stride, int64_t N, int batch, const double* lambda,
                             double* part, int nchunk, double* out, hipStream_t s) {
     const dim3 grid(nchunk, batch);

@@ -59,6 +59,72 @@ __device__ __forceinline__ int ritz_partner(int x, int t, int m) {
     return y == x ? 0 : y;
 }
 
+// Cyclic Jacobi on the symmetric m x m matrix Mb[0] (m even, at most 16;
+// Ub[0] the identity): the pairs of each round come from the circle schedule,
+// every rotation of a round is applied at once, and the two buffers
+// alternate.  Returns the buffer holding the diagonalised matrix and the
+// accumulated rotations.  Called by all 256 threads of the block
+// (thread (i, j) = (tid / 16, tid % 16)).
+__device__ __forceinline__ int jacobi16(double (*Mb)[16][17], double (*Ub)[16][17], double* cs, double* sn, int m, double* s_off,
+                        double* s_diag) {
+    const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
+    int cb = 0;
+    for (int sweep = 0; sweep < 12 && m > 1; ++sweep) {
+        const double (*M)[17] = Mb[cb];
+        if (tid < 64) {
+            double off = 0.0, dg = 0.0;
+            for (int e = tid; e < 256; e += 64) {
+                const int a = e >> 4, b = e & 15;
+                if (a < m && b < m) {
+                    if (a == b) dg += M[a][a] * M[a][a];
+                    else off += M[a][b] * M[a][b];
+                }
+            }
+            off = wave_sum(off);
+            dg = wave_sum(dg);
+            if (tid == 0) {
+                *s_off = off;
+                *s_diag = dg;
+            }
+        }
+        __syncthreads();
+        if (!(*s_off > 1e-26 * *s_diag)) break;     // off-diagonal below 1e-13 of the diagonal
+        for (int t = 0; t < m - 1; ++t) {
+            const double (*M)[17] = Mb[cb];
+            const double (*U)[17] = Ub[cb];
+            // rotation of every pair (x, y), x < y: [c s; -s c] diagonalises the 2 x 2 block
+            if (tid < m) {
+                const int x = tid, y = ritz_partner(x, t, m);
+                const int lo = x < y ? x : y, hi = x < y ? y : x;
+                double c = 1.0, s = 0.0;
+                const double apq = M[lo][hi];
+                if (apq != 0.0) {
+                    const double tau = (M[hi][hi] - M[lo][lo]) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                }
+                cs[x] = c;
+                sn[x] = x == lo ? -s : s;   // J[partner][x]
+            }
+            __syncthreads();
+            // the rotated matrices go to the other buffer: no barrier between reads and writes
+            if (i < m && j < m) {
+                const int pi = ritz_partner(i, t, m), pj = ritz_partner(j, t, m);
+                const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
+                Mb[cb ^ 1][i][j] = ci * (M[i][j] * cj + M[i][pj] * sj) + si * (M[pi][j] * cj + M[pi][pj] * sj);
+                Ub[cb ^ 1][i][j] = U[i][j] * cj + U[i][pj] * sj;
+            } else {
+                Mb[cb ^ 1][i][j] = M[i][j];
+                Ub[cb ^ 1][i][j] = U[i][j];
+            }
+            cb ^= 1;
+            __syncthreads();
+        }
+    }
+    return cb;
+}
+
 __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs, const int* __restrict__ cubes,
                                               int ncls) {
     __shared__ double Mb[2][16][17], Ub[2][16][17];   // Jacobi rounds alternate between the two
@@ -96,60 +162,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
         v0[row][k] = d.V[(int64_t)k * p + row];
     }
     __syncthreads();
-    int cb = 0;
-    for (int sweep = 0; sweep < 12 && m > 1; ++sweep) {
-        const double (*M)[17] = Mb[cb];
-        if (tid < 64) {
-            double off = 0.0, dg = 0.0;
-            for (int e = tid; e < 256; e += 64) {
-                const int a = e >> 4, b = e & 15;
-                if (a < m && b < m) {
-                    if (a == b) dg += M[a][a] * M[a][a];
-                    else off += M[a][b] * M[a][b];
-                }
-            }
-            off = wave_sum(off);
-            dg = wave_sum(dg);
-            if (tid == 0) {
-                s_off = off;
-                s_diag = dg;
-            }
-        }
-        __syncthreads();
-        if (!(s_off > 1e-26 * s_diag)) break;     // off-diagonal below 1e-13 of the diagonal
-        for (int t = 0; t < m - 1; ++t) {
-            const double (*M)[17] = Mb[cb];
-            const double (*U)[17] = Ub[cb];
-            // rotation of every pair (x, y), x < y: [c s; -s c] diagonalises the 2 x 2 block
-            if (tid < m) {
-                const int x = tid, y = ritz_partner(x, t, m);
-                const int lo = x < y ? x : y, hi = x < y ? y : x;
-                double c = 1.0, s = 0.0;
-                const double apq = M[lo][hi];
-                if (apq != 0.0) {
-                    const double tau = (M[hi][hi] - M[lo][lo]) / (2.0 * apq);
-                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
-                    s = tt * c;
-                }
-                cs[x] = c;
-                sn[x] = x == lo ? -s : s;   // J[partner][x]
-            }
-            __syncthreads();
-            // the rotated matrices go to the other buffer: no barrier between reads and writes
-            if (i < m && j < m) {
-                const int pi = ritz_partner(i, t, m), pj = ritz_partner(j, t, m);
-                const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
-                Mb[cb ^ 1][i][j] = ci * (M[i][j] * cj + M[i][pj] * sj) + si * (M[pi][j] * cj + M[pi][pj] * sj);
-                Ub[cb ^ 1][i][j] = U[i][j] * cj + U[i][pj] * sj;
-            } else {
-                Mb[cb ^ 1][i][j] = M[i][j];
-                Ub[cb ^ 1][i][j] = U[i][j];
-            }
-            cb ^= 1;
-            __syncthreads();
-        }
-    }
+    const int cb = jacobi16(Mb, Ub, cs, sn, m, &s_off, &s_diag);
     const double (*M)[17] = Mb[cb];
     const double (*U)[17] = Ub[cb];
     // descending order of the Ritz values (ties: lower index first)
@@ -208,6 +221,111 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
         d.gap[0] = gp;
         if (!(gp >= 1.0 + 1e-6)) set_status(d.status, HYRES_DEV_DEGENERATE);
     }
+}
+
+// WSRRR's Procrustes step: the orthonormal factor of the polar decomposition
+// of Mw = D^-1 (Y^T Zh) (p x r; M holds Y^T Zh transposed, r x p), V = Mw
+// (Mw^T Mw)^-1/2 from the Jacobi eigendecomposition of the r x r matrix
+// Mw^T Mw, over the components whose column of Mw is not zero (squared norm
+// above 1e-24 of the largest).  A zero column (a component thresholded to
+// zero) leaves its direction free: it keeps the previous one, orthonormalised
+// against the other columns in index order.  Written as the cube's subspace
+// with its projection and back-projection matrices.
+__global__ __launch_bounds__(256) void k_polar(const CubeDesc* __restrict__ descs, const double* __restrict__ M) {
+    __shared__ double Mb[2][16][17], Ub[2][16][17];
+    __shared__ double cs[16], sn[16];
+    __shared__ double mw[kMaxBands][kMaxRank], vold[kMaxBands][kMaxRank], vnew[kMaxBands][kMaxRank];
+    __shared__ double S[16][17];
+    __shared__ double s_off, s_diag, s_nmax;
+    __shared__ int live[16];
+    const CubeDesc& d = descs[0];
+    const int r = d.r, p = d.p, tid = threadIdx.x, i = tid >> 4, j = tid & 15, lane = tid & 63;
+    const int m = (r + 1) & ~1;
+    for (int e = tid; e < r * p; e += 256) {
+        const int k = e / p, b = e - k * p;
+        mw[b][k] = M[e] / d.sigma[b];
+        vold[b][k] = d.V[e];
+    }
+    __syncthreads();
+    double g = 0.0;
+    if (i < r && j < r)
+        for (int b = 0; b < p; ++b) g = fma(mw[b][i], mw[b][j], g);
+    Mb[0][i][j] = g;
+    Ub[0][i][j] = i == j ? 1.0 : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int k = 0; k < r; ++k) mx = fmax(mx, Mb[0][k][k]);
+        s_nmax = mx;
+    }
+    __syncthreads();
+    if (tid < 16) live[tid] = tid < r && Mb[0][tid][tid] > 1e-24 * s_nmax;
+    __syncthreads();
+    if (!(live[i] && live[j])) Mb[0][i][j] = 0.0;      // the zero components stay decoupled
+    __syncthreads();
+    const int cb = jacobi16(Mb, Ub, cs, sn, m, &s_off, &s_diag);
+    double sv = 0.0;
+    if (i < r && j < r)
+        for (int k = 0; k < r; ++k)
+            if (live[k]) sv += Ub[cb][i][k] * Ub[cb][j][k] / sqrt(Mb[cb][k][k]);
+    S[i][j] = sv;
+    __syncthreads();
+    for (int e = tid; e < p * r; e += 256) {
+        const int row = e / r, k = e - row * r;
+        double v = 0.0;
+        if (live[k])
+            for (int jj = 0; jj < r; ++jj) v = fma(mw[row][jj], S[jj][k], v);
+        vnew[row][k] = v;
+    }
+    __syncthreads();
+    // free columns, in index order, by one wave
+    if (tid < 64) {
+        for (int k = 0; k < r; ++k) {
+            if (live[k]) continue;
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = lane + 64 * q < p ? vold[lane + 64 * q][k] : 0.0;
+            for (int jj = 0; jj < r; ++jj) {
+                if (!(live[jj] || jj < k)) continue;
+                double dt = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (lane + 64 * q < p) dt = fma(vnew[lane + 64 * q][jj], v[q], dt);
+                dt = wave_sum(dt);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (lane + 64 * q < p) v[q] = fma(-dt, vnew[lane + 64 * q][jj], v[q]);
+            }
+            double nn = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) nn = fma(v[q], v[q], nn);
+            nn = wave_sum(nn);
+            const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (lane + 64 * q < p) vnew[lane + 64 * q][k] = v[q] * inv;
+        }
+    }
+    __syncthreads();
+    const int P16 = 16 * d.T;
+    for (int e = tid; e < P16 * 16; e += 256) {
+        const int row = e >> 4, k = e & 15;
+        const bool ok = row < p && k < r;
+        const double v = ok ? vnew[row][k] : 0.0;
+        const double sg = row < p ? d.sigma[row] : 1.0;
+        d.P32[e] = (float)(v / sg);
+        d.Q32[(int64_t)k * P16 + row] = (float)(v * sg);
+        if (ok) {
+            d.V[(int64_t)k * p + row] = v;
+            d.P64[(int64_t)row * r + k] = v / sg;
+            d.Q64[(int64_t)k * p + row] = v * sg;
+        }
+    }
+}
+
+hipError_t launch_polar(const CubeDesc* descs, const double* M, hipStream_t s) {
+    hipLaunchKernelGGL(k_polar, dim3(1), dim3(256), 0, s, descs, M);
+    return hipGetLastError();
 }
 
 // Z <- Z R (r x r rotation), in place.

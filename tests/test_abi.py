@@ -166,3 +166,25 @@ def test_rank_flags_validation():
                                                          L.HYRES_F32, C.byref(nb)) == 6
     both = L.Options(8, 3, 0, 0, L.FLAG_RANK_HYSIME | L.FLAG_RANK_SURE)
     assert lib.hyres_denoise_workspace_size(64, 64, 32, C.byref(both), L.HYRES_F32, C.byref(nb)) == 6
+
+
+def test_method_workspace_validation():
+    """WSRRR takes native precision and a given rank only; FORPDN's workspace
+    grows with the levels and shrinks when sigma is given; bad shapes are refused."""
+    L, lib = _lib()
+    nb = C.c_size_t()
+    assert lib.hyres_wsrrr_workspace_size(64, 64, 32, C.byref(L.Options(4, 3, L.PREC_NATIVE, 0, 0)), L.HYRES_F32,
+                                          C.byref(nb)) == 0
+    assert nb.value > 0
+    assert lib.hyres_wsrrr_workspace_size(64, 64, 32, C.byref(L.Options(4, 3, L.PREC_MIXED, 0, 0)), L.HYRES_F32,
+                                          C.byref(nb)) == 6
+    assert lib.hyres_wsrrr_workspace_size(64, 64, 32, C.byref(L.Options(4, 3, 0, 0, L.FLAG_RANK_SURE)),
+                                          L.HYRES_F32, C.byref(nb)) == 6
+    sizes = []
+    for given in (0, 1):
+        assert lib.hyres_forpdn_workspace_size(64, 64, 32, 3, L.HYRES_F32, given, C.byref(nb)) == 0
+        sizes.append(nb.value)
+    assert sizes[1] < sizes[0]
+    assert lib.hyres_forpdn_workspace_size(64, 64, 32, 0, L.HYRES_F32, 0, C.byref(nb)) == 2
+    assert lib.hyres_forpdn_workspace_size(6, 64, 32, 2, L.HYRES_F32, 0, C.byref(nb)) == 2    # level 2 below 4 x 4
+    assert lib.hyres_forpdn_workspace_size(64, 64, 1, 2, L.HYRES_F32, 0, C.byref(nb)) == 2

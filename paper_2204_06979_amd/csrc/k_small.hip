@@ -246,6 +246,13 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
     __shared__ int s_flags;
 
     if (t == 0) s_flags = 0;
+    // the Householder step reads the broadcast column and u over the whole column
+    // range of the thread grid, which can reach past its row range: zero first
+    for (int i = t; i < kSmallP; i += NTH) {
+        s_col[0][i] = s_col[1][i] = 0.0;
+        s_ub[i] = 0.0;
+    }
+    __syncthreads();
     int flags = 0;
     HYRES_STAMP(d, 0);
     double A[BR][BC];
@@ -305,8 +312,14 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 if (k >= p - 2) break;
                 const int buf = k & 1;
                 if (tc == kk) {
+                    // column k below the diagonal; the entries at and above it go out as
+                    // zeros (rows beyond p are zero already), so readers need no masks
 #pragma unroll
-                    for (int a = 0; a < BR; ++a) s_col[buf][tr + ROWS * a] = A[a][bb];
+                    for (int a = 0; a < BR; ++a) {
+                        const int i = tr + ROWS * a;
+                        s_col[buf][i] = i > k ? A[a][bb] : 0.0;
+                        if (i == k) s_dd[k] = A[a][bb];
+                    }
                 }
                 __syncthreads();
                 // A v with v = x - alpha e_{k+1} (x: column k below the diagonal)
@@ -316,11 +329,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 // inside the vectors) and masked by selects: no divergent branches
                 double xc[BC];
 #pragma unroll
-                for (int b = 0; b < BC; ++b) {
-                    const int j = tc + COLS * b;
-                    const double cj = s_col[buf][j];
-                    xc[b] = (j > k && j < p) ? cj : 0.0;
-                }
+                for (int b = 0; b < BC; ++b) xc[b] = s_col[buf][tc + COLS * b];
                 double ps[BR];
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                     const int i = tr + ROWS * a;
                     if (ROWS * a + ROWS - 1 > k) {
                         const double ci = s_col[buf][i];
-                        const double vi = (i > k + 1 && i < p) ? ci : (i == k + 1 ? v1 : 0.0);
+                        const double vi = i == k + 1 ? v1 : ci;
                         const double a1 = kk + 1 < COLS ? A[a][bb] : A[a][bb + 1 < BC ? bb + 1 : bb];
                         if (own1) ps[a] = fma(-alpha, a1, ps[a]);
                         q = fma(vi, ps[a], q);    // this thread's share of v^T A v
@@ -373,7 +382,6 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 }
                 if (lane == 0) s_vav[wave] = q;
                 if (t == 0) {
-                    s_dd[k] = s_col[buf][k];
                     s_ee[k] = alpha;
                     s_hb[k] = beta;
                 }
@@ -389,15 +397,15 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                 for (int b = 0; b < BC; ++b) {
                     const int j = tc + COLS * b;
                     const double uj = s_ub[j];
-                    wc[b] = (j > k && j < p) ? uj - K * vc[b] : 0.0;
+                    wc[b] = j > k ? uj - K * vc[b] : 0.0;      // u and v vanish beyond p
                 }
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {
                     if (ROWS * a + ROWS - 1 > k) {
                         const int i = tr + ROWS * a;
                         const double ci = s_col[buf][i], ui = s_ub[i];
-                        const double vi = (i > k + 1 && i < p) ? ci : (i == k + 1 ? v1 : 0.0);
-                        const double wi = (i > k && i < p) ? ui - K * vi : 0.0;
+                        const double vi = i == k + 1 ? v1 : ci;
+                        const double wi = i > k ? ui - K * vi : 0.0;
 #pragma unroll
                         for (int b = 0; b < BC; ++b) {
                             if (COLS * b + COLS - 1 > k) A[a][b] = fma(-wi, vc[b], fma(-vi, wc[b], A[a][b]));

@@ -368,11 +368,15 @@ __global__ __launch_bounds__(ROWS * COLS) void k_small(const CubeDesc* __restric
                     }
                 }
                 q = wave_sum(q);
+                // v = x with v1 at k + 1: column k + 1 is register column bb of thread
+                // column kk + 1, or register column bb + 1 of thread column 0
                 double vc[BC];
 #pragma unroll
-                for (int b = 0; b < BC; ++b) {
-                    const int j = tc + COLS * b;
-                    vc[b] = j == k + 1 ? v1 : xc[b];
+                for (int b = 0; b < BC; ++b) vc[b] = xc[b];
+                if (kk + 1 < COLS) {
+                    if (tc == kk + 1) vc[bb] = v1;
+                } else if constexpr (bb + 1 < BC) {
+                    if (tc == 0) vc[bb + 1] = v1;
                 }
 #pragma unroll
                 for (int a = 0; a < BR; ++a) {

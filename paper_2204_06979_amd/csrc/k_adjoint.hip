@@ -26,6 +26,7 @@ namespace hyres {
 
 
 constexpr int kAdjChunk = 16384;   // coefficients per threshold-adjoint block
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 int adj_chunk() { return kAdjChunk; }
 
@@ -60,63 +61,81 @@ __global__ __launch_bounds__(256) void k_adj_apply(AdjDesc a) {
         if (k < r) out[(int64_t)k * a.nz + q] = (T)acc[k];
 }
 
-// part[slot][k][b] = sum over the slot's pixels of planes[k][q] * cube[q][b].
-constexpr int kXPix = 32;
-template <typename T>
+// part[slot][k][b] = sum over the slot's pixels of planes[k][q] * cube[q][b],
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64): D (16 bands x 16
+// components) += A (16 bands x 4 pixels) B (4 pixels x 16 components), one
+// accumulator per 16-band tile.  A lane takes pixel lane / 16 of the step and
+// band / component lane % 16 of the tile; D holds band lane / 16 + 4 v and
+// component lane % 16 in its element v (the FP64 layout, unlike the FP32
+// one's 4 (lane / 16) + v).  Each wave runs a quarter of the
+// slot's pixels; the waves' sums are added in wave order through LDS.
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_adj_xprod(AdjDesc a, const void* planes, const void* cube, int64_t cp,
                                                    int64_t crp) {
-    __shared__ double ct[kXPix][kMaxBands + 1];
-    __shared__ double pt[kMaxRank][kXPix];
+    __shared__ double red[kMaxRank][NT * 16];
     const int p = a.p, r = a.r, E = r * p;
-    constexpr int NE = (kMaxRank * kMaxBands + 255) / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kk = lane >> 4, jj = lane & 15;
     const int slot = blockIdx.x;
     int64_t per = (a.n + a.slots - 1) / a.slots;
-    per = (per + kXPix - 1) / kXPix * kXPix;
+    per = (per + 15) / 16 * 16;
     const int64_t q0 = (int64_t)slot * per;
     const int64_t q1 = q0 + per < a.n ? q0 + per : a.n;
-    double acc[NE];
+    const int64_t quarter = per / 4;
+    const int64_t w0 = q0 + wave * quarter;
+    const int64_t w1 = w0 + quarter < q1 ? w0 + quarter : q1;
+    const T* pl = static_cast<const T*>(planes) + (int64_t)jj * a.nz;
+    v4d acc[NT];
 #pragma unroll
-    for (int j = 0; j < NE; ++j) acc[j] = 0.0;
-    const T* pl = static_cast<const T*>(planes);
-    for (int64_t t0 = q0; t0 < q1; t0 += kXPix) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kXPix * p; e += 256) {
-            const int k = e / p, b = e - k * p;
-            const int64_t q = t0 + k;
-            ct[k][b] = q < q1 ? (double)adj_pix<T>(cube, q, a.W, cp, crp)[b] : 0.0;
-        }
-        for (int e = threadIdx.x; e < kXPix * r; e += 256) {
-            const int k = e / kXPix, j = e - k * kXPix;
-            const int64_t q = t0 + j;
-            pt[k][j] = q < q1 ? (double)pl[(int64_t)k * a.nz + q] : 0.0;
-        }
-        __syncthreads();
+    for (int t = 0; t < NT; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    // the lane's pixel, tracked as (y, x) while it advances by 4
+    int64_t q = w0 + kk;
+    int64_t y = q / a.W, x = q - y * a.W;
+    for (int64_t qs = w0; qs < w1; qs += 4) {
+        const bool in = q < w1;
+        const double bv = (in && jj < r) ? (double)pl[q] : 0.0;
+        const T* row = static_cast<const T*>(cube) + y * crp + x * cp;
 #pragma unroll
-        for (int j = 0; j < NE; ++j) {
-            const int e = threadIdx.x + 256 * j;
-            if (e < E) {
-                const int k = e / p, b = e - k * p;
-                double s = acc[j];
-                for (int i = 0; i < kXPix; ++i) s = fma(pt[k][i], ct[i][b], s);
-                acc[j] = s;
-            }
+        for (int t = 0; t < NT; ++t) {
+            const int band = 16 * t + jj;
+            const double av = (in && band < p) ? (double)row[band] : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        }
+        q += 4;
+        x += 4;
+        while (x >= a.W) {
+            x -= a.W;
+            ++y;
         }
     }
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
 #pragma unroll
-    for (int j = 0; j < NE; ++j) {
-        const int e = threadIdx.x + 256 * j;
-        if (e < E) a.part[(int64_t)slot * E + e] = acc[j];
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int band = 16 * t + kk + 4 * v;
+                    if (jj < r) red[jj][band] = w == 0 ? acc[t][v] : red[jj][band] + acc[t][v];
+                }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < E; e += 256) {
+        const int k = e / p, b = e - k * p;
+        a.part[(int64_t)slot * E + e] = red[k][b];
     }
 }
 
-// out[e] = sum over slots of part[slot][e], in slot order.
-__global__ void k_adj_reduce(const double* __restrict__ part, int slots, int E, double* __restrict__ out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
+// out[e] = sum over slots of part[slot][e]: one wave per entry, each lane
+// summing the slots congruent to it in slot order, then the wave's fixed tree.
+__global__ __launch_bounds__(64) void k_adj_reduce(const double* __restrict__ part, int slots, int E,
+                                                   double* __restrict__ out) {
+    const int e = blockIdx.x, lane = threadIdx.x;
     double s = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < slots; ++i) s += part[(int64_t)i * E + e];
-    out[e] = s;
+#pragma unroll 4
+    for (int i = lane; i < slots; i += 64) s += part[(int64_t)i * E + e];
+    s = wave_sum(s);
+    if (lane == 0) out[e] = s;
 }
 
 template <typename T>
@@ -278,18 +297,37 @@ __global__ __launch_bounds__(256) void k_adj_dy(AdjDesc a) {
 }
 
 // ---------------------------------------------------------------- launchers
+
+template <typename T>
+hipError_t launch_xprod_t(const AdjDesc& a, const void* planes, const void* cube, int64_t cp, int64_t crp,
+                          hipStream_t s) {
+    const int nt = (a.p + 15) / 16;
+#define HYRES_X(N) \
+    case N: hipLaunchKernelGGL((k_adj_xprod<T, N>), dim3(a.slots), dim3(256), 0, s, a, planes, cube, cp, crp); break;
+    switch (nt) {
+        HYRES_X(1) HYRES_X(2) HYRES_X(3) HYRES_X(4) HYRES_X(5) HYRES_X(6) HYRES_X(7)
+        HYRES_X(8) HYRES_X(9) HYRES_X(10) HYRES_X(11) HYRES_X(12) HYRES_X(13) HYRES_X(14)
+        default: return hipErrorInvalidValue;
+    }
+#undef HYRES_X
+    return hipGetLastError();
+}
+
+hipError_t launch_xprod(int dtype, const AdjDesc& a, const void* planes, const void* cube, int64_t cp, int64_t crp,
+                        hipStream_t s) {
+    return dtype == HYRES_F64 ? launch_xprod_t<double>(a, planes, cube, cp, crp, s)
+                              : launch_xprod_t<float>(a, planes, cube, cp, crp, s);
+}
+
 hipError_t launch_adjoint_pre(const AdjDesc& a, int dtype, hipStream_t s) {
     // dZh and dQ
     const unsigned gb = (unsigned)((a.n + 255) / 256);
-    if (dtype == HYRES_F64) {
-        hipLaunchKernelGGL(k_adj_apply<double>, dim3(gb), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_adj_xprod<double>, dim3(a.slots), dim3(256), 0, s, a, a.Zh, a.dX, a.dxp, a.dxrp);
-    } else {
-        hipLaunchKernelGGL(k_adj_apply<float>, dim3(gb), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(k_adj_xprod<float>, dim3(a.slots), dim3(256), 0, s, a, a.Zh, a.dX, a.dxp, a.dxrp);
-    }
+    if (dtype == HYRES_F64) hipLaunchKernelGGL(k_adj_apply<double>, dim3(gb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_adj_apply<float>, dim3(gb), dim3(256), 0, s, a);
+    hipError_t e = launch_xprod(dtype, a, a.Zh, a.dX, a.dxp, a.dxrp, s);
+    if (e != hipSuccess) return e;
     const int E = a.r * a.p;
-    hipLaunchKernelGGL(k_adj_reduce, dim3((E + 255) / 256), dim3(256), 0, s, a.part, a.slots, E, a.dQ);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(E), dim3(64), 0, s, a.part, a.slots, E, a.dQ);
     return hipGetLastError();
 }
 
@@ -304,13 +342,11 @@ hipError_t launch_adjoint_thresh(const AdjDesc& a, int dtype, hipStream_t s) {
 
 hipError_t launch_adjoint_post(const AdjDesc& a, int dtype, hipStream_t s) {
     // dP^T, the small FP64 algebra, then dY
-    if (dtype == HYRES_F64)
-        hipLaunchKernelGGL(k_adj_xprod<double>, dim3(a.slots), dim3(256), 0, s, a, a.A, a.Y, a.pitch, a.row_pitch);
-    else
-        hipLaunchKernelGGL(k_adj_xprod<float>, dim3(a.slots), dim3(256), 0, s, a, a.A, a.Y, a.pitch, a.row_pitch);
+    hipError_t e = launch_xprod(dtype, a, a.A, a.Y, a.pitch, a.row_pitch, s);
+    if (e != hipSuccess) return e;
     const int E = a.r * a.p;
-    hipLaunchKernelGGL(k_adj_reduce, dim3((E + 255) / 256), dim3(256), 0, s, a.part, a.slots, E, a.dPt);
-    hipError_t e = launch_adj_sweep(a, s);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(E), dim3(64), 0, s, a.part, a.slots, E, a.dPt);
+    e = launch_adj_sweep(a, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_dc, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_adj_dg, dim3(a.p), dim3(256), 0, s, a);
@@ -323,12 +359,10 @@ hipError_t launch_adjoint_post(const AdjDesc& a, int dtype, hipStream_t s) {
 // out[k][b] = sum over the pixels of planes[k][q] cube[q][b] (r x p, FP64 sums).
 hipError_t launch_planes_cube(int dtype, const AdjDesc& a, const void* planes, const void* cube, int64_t cp,
                               int64_t crp, double* out, hipStream_t s) {
-    if (dtype == HYRES_F64)
-        hipLaunchKernelGGL(k_adj_xprod<double>, dim3(a.slots), dim3(256), 0, s, a, planes, cube, cp, crp);
-    else
-        hipLaunchKernelGGL(k_adj_xprod<float>, dim3(a.slots), dim3(256), 0, s, a, planes, cube, cp, crp);
+    hipError_t e = launch_xprod(dtype, a, planes, cube, cp, crp, s);
+    if (e != hipSuccess) return e;
     const int E = a.r * a.p;
-    hipLaunchKernelGGL(k_adj_reduce, dim3((E + 255) / 256), dim3(256), 0, s, a.part, a.slots, E, out);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(E), dim3(64), 0, s, a.part, a.slots, E, out);
     return hipGetLastError();
 }
 

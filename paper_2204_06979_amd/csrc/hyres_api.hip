@@ -1175,6 +1175,18 @@ CubeDesc solve_desc(const CubePlan& c, void* ws, const void* Y, int64_t pitch, i
 
 }  // namespace
 
+namespace hyres {
+CubeView cube_view(const void* Y, int W, int p, int64_t n, int64_t pitch, int64_t row_pitch, int dtype) {
+    CubeView v;
+    v.Y = Y; v.pitch = pitch; v.row_pitch = row_pitch;
+    v.n = n; v.W = W; v.p = p;
+    v.vec4 = vec4_ok(Y, W, p, pitch, row_pitch, dtype);
+    v.dense = dense_ok(Y, W, p, pitch, row_pitch, dtype);
+    v.pmag = (uint32_t)((((uint64_t)1) << 32) / (uint64_t)p + 1);
+    return v;
+}
+}  // namespace hyres
+
 // =========================================================================
 HYRES_API hyres_status hyres_create(hyres_handle** handle, int device) {
     if (!handle) return HYRES_E_NULL;

@@ -315,13 +315,25 @@ __device__ __forceinline__ void set_status(int* st, int bits) {
 constexpr int kVec = 0, kDense = 1, kScalar = 2;
 constexpr int kAnyLayout = 3;      // a launch whose cubes take different paths (chosen per cube)
 
-__device__ __forceinline__ int load_mode(const CubeDesc& d) { return d.vec4 ? kVec : d.dense ? kDense : kScalar; }
+// An FP32 cube as the 64-pixel tile loaders see it (a CubeDesc carries the
+// same fields under the same names): pixel q = y W + x at Y + y row_pitch +
+// x pitch, flags as in CubeDesc.
+struct CubeView {
+    const void* Y; int64_t pitch, row_pitch;
+    int64_t n; int W, p;
+    int vec4, dense;
+    uint32_t pmag;
+};
+// The view of an FP32 cube with its load-path flags (host).
+CubeView cube_view(const void* Y, int W, int p, int64_t n, int64_t pitch, int64_t row_pitch, int dtype);
+template <typename D>
+__device__ __forceinline__ int load_mode(const D& d) { return d.vec4 ? kVec : d.dense ? kDense : kScalar; }
 
 // e / p for 0 <= e < 64 p (exact while e p < 2^32) with the per-cube multiplier
 __device__ __forceinline__ int div_p(int e, uint32_t pmag) { return (int)__umulhi((uint32_t)e, pmag); }
 
-template <typename T>
-__device__ __forceinline__ const T* pixel_ptr(const CubeDesc& d, int64_t q) {
+template <typename T, typename D>
+__device__ __forceinline__ const T* pixel_ptr(const D& d, int64_t q) {
     int64_t y = q / d.W, x = q - y * d.W;
     return static_cast<const T*>(d.Y) + y * d.row_pitch + x * d.pitch;
 }

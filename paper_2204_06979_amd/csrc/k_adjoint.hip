@@ -19,7 +19,7 @@
 // Small dense algebra runs in FP64 in one workgroup per system; the pixel
 // loops run in the element type of the cube with FP64 accumulation where
 // they reduce over pixels.
-#include "hyres_internal.hpp"
+#include "tile_stage.hpp"
 
 namespace hyres {
 
@@ -36,7 +36,7 @@ __device__ __forceinline__ const T* adj_pix(const void* base, int64_t q, int W, 
     return static_cast<const T*>(base) + y * rpitch + x * pitch;
 }
 
-// dZh[k][q] = sum_b dX[q][b] Q[k][b]: one pixel per thread, Q staged in LDS.
+// FP64 cubes: dZh[k][q] = sum_b dX[q][b] Q[k][b], one pixel per thread, Q staged in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_apply(AdjDesc a) {
     __shared__ double sq[kMaxRank * kMaxBands];
@@ -61,8 +61,124 @@ __global__ __launch_bounds__(256) void k_adj_apply(AdjDesc a) {
         if (k < r) out[(int64_t)k * a.nz + q] = (T)acc[k];
 }
 
-// part[slot][k][b] = sum over the slot's pixels of planes[k][q] * cube[q][b],
-// on the FP64 matrix cores (v_mfma_f64_16x16x4f64): D (16 bands x 16
+// FP32 cubes: dZh = dX Q^T on the matrix cores, as the projection computes
+// Z = Y P: a 64-pixel tile of dX per block staged through LDS, a 16-pixel x
+// 16-component output tile per wave, Q^T as FP32 B fragments in registers
+// (v_mfma_f32_16x16x4f32, four accumulator chains).  One tile per block, so
+// that few registers stay live and several blocks share a compute unit.
+template <int NT, int LM>
+__global__ __launch_bounds__(256, 2) void k_adj_apply_f32(AdjDesc a, CubeView dx) {
+    constexpr int LDW = proj_ldw<NT>();
+    __shared__ __attribute__((aligned(16))) float tile[kPixTile * LDW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
+    const int p = a.p, r = a.r;
+    const int64_t q0 = (int64_t)blockIdx.x * kPixTile;
+    {
+        v4f r4[proj_nv4<NT>()];
+        int zlo = 16 * NT;
+        proj_fetch<NT, LM>(dx, q0, r4);
+        proj_stage<NT, LM>(tile, dx, zlo, r4);
+    }
+    float bf[4 * NT];
+#pragma unroll
+    for (int s = 0; s < 4 * NT; ++s) {
+        const int b = 4 * s + row;
+        bf[s] = (b < p && col < r) ? (float)a.Q64[(int64_t)col * p + b] : 0.f;
+    }
+    __syncthreads();
+    v4f ac[4] = {};
+    const float* arow = tile + (16 * wave + col) * LDW + row;
+#pragma unroll
+    for (int s = 0; s < 4 * NT; ++s) {
+        ac[s & 3] = mfma4(arow[4 * s], bf[s], ac[s & 3]);
+        if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    const v4f acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
+    // lane holds component col of pixels q0 + 16 wave + 4 row + i (the planes
+    // are padded to whole tiles; the tile rows past the cube are zero)
+    if (col < r)
+        *reinterpret_cast<v4f*>(static_cast<float*>(a.A) + (int64_t)col * a.nz + q0 + 16 * wave + 4 * row) = acc;
+}
+
+// FP32 cubes: part[slot][k][b] = sum over the slot's pixels of
+// planes[k][q] * cube[q][b] with the cube staged through LDS as 64-pixel tiles
+// (coalesced loads, the next tile prefetched into registers) on the matrix
+// cores (v_mfma_f32_16x16x4f32: FP32 products summed in FP32 over one tile,
+// then added in FP64).  A wave owns every fourth 16-band tile of the result
+// (rotated with the block, so that the waves with one tile more fall on
+// different SIMDs) over all 64 pixels of a tile: step (m, s) takes pixel
+// 16 m + 4 (lane / 16) + s, so a lane's plane values of one m are one 16-byte
+// load and the cube values one LDS read per band tile.  A block runs the
+// tiles slot, slot + slots, ...; no sum across waves is needed.
+template <int NT, int LM>
+__global__ __launch_bounds__(256, LM == kScalar ? 1 : 2) void k_adj_xprod_f32(AdjDesc a, const float* __restrict__ planes,
+                                                                           CubeView cv) {
+    constexpr int LDW = proj_ldw<NT>();
+    constexpr int NW = (NT + 3) / 4;               // band tiles per wave, at most
+    __shared__ __attribute__((aligned(16))) float tile[kPixTile * LDW];
+    const int p = a.p, r = a.r, E = r * p;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kk = lane >> 4, jj = lane & 15;
+    const int rot = (wave + blockIdx.x) & 3;       // this wave's band tiles: rot, rot + 4, ...
+    const int64_t ntiles = (a.n + kPixTile - 1) / kPixTile;
+    double accd[NW][4];
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accd[w][v] = 0.0;
+    v4f r4[proj_nv4<NT>()];
+    int zlo = 16 * NT;
+    int64_t t = blockIdx.x;
+    if (t < ntiles) proj_fetch<NT, LM>(cv, t * kPixTile, r4);
+    for (; t < ntiles; t += gridDim.x) {
+        const int64_t q0 = t * kPixTile;
+        v4f bv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            bv[m] = v4f{0.f, 0.f, 0.f, 0.f};
+            if (jj < r) bv[m] = *reinterpret_cast<const v4f*>(planes + (int64_t)jj * a.nz + q0 + 16 * m + 4 * kk);
+        }
+        __syncthreads();
+        proj_stage<NT, LM>(tile, cv, zlo, r4);
+        __syncthreads();
+        if (t + gridDim.x < ntiles) proj_fetch<NT, LM>(cv, (t + gridDim.x) * kPixTile, r4);
+        v4f acc[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) acc[w] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int64_t qb = q0 + 16 * m + 4 * kk;
+            const float* arow = tile + (16 * m + 4 * kk) * LDW + 16 * rot + jj;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                // pixels past the cube: their tile rows are zero, their plane values unknown
+                const float b = qb + s < a.n ? bv[m][s] : 0.f;
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+                    if (rot + 4 * w < NT) acc[w] = mfma4(arow[s * LDW + 64 * w], b, acc[w]);
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accd[w][v] += (double)acc[w][v];
+    }
+    // lane holds band 16 u + 4 kk + v and component jj of band tile u = rot + 4 w
+    if (jj < r) {
+        double* out = a.part + (int64_t)blockIdx.x * E + (int64_t)jj * p;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int band = 16 * (rot + 4 * w) + 4 * kk + v;
+                if (rot + 4 * w < NT && band < p) out[band] = accd[w][v];
+            }
+    }
+}
+
+// FP64 cubes: part[slot][k][b] = sum over the slot's pixels of planes[k][q] *
+// cube[q][b], on the FP64 matrix cores (v_mfma_f64_16x16x4f64): D (16 bands x 16
 // components) += A (16 bands x 4 pixels) B (4 pixels x 16 components), one
 // accumulator per 16-band tile.  A lane takes pixel lane / 16 of the step and
 // band / component lane % 16 of the tile; D holds band lane / 16 + 4 v and
@@ -252,8 +368,8 @@ __global__ __launch_bounds__(256) void k_adj_dg(AdjDesc a) {
     }
 }
 
-// dY[q][b] = sum_k dZ[k][q] P[b][k] + sum_j Y[q][j] dG2[j][b]; a block owns
-// 32 pixels x 32 bands.
+// FP64 cubes: dY[q][b] = sum_k dZ[k][q] P[b][k] + sum_j Y[q][j] dG2[j][b]; a
+// block owns 32 pixels x 32 bands.
 constexpr int kDyPix = 32, kDyCol = 32;
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_dy(AdjDesc a) {
@@ -296,6 +412,87 @@ __global__ __launch_bounds__(256) void k_adj_dy(AdjDesc a) {
     }
 }
 
+// FP32 cubes: dY = Y dG2 + dZ P^T on the matrix cores.  A block owns one
+// 64-pixel tile of Y, staged through LDS, and four 16-band column tiles of dY
+// (one per wave; blockIdx.y picks the group).  Each wave keeps its column of
+// dG2 and of P^T as FP32 B fragments in registers and computes 16 pixels x
+// 16 bands per accumulator, four pixel groups (v_mfma_f32_16x16x4f32, four
+// accumulator chains).  One tile per block: the loads of the tile, the
+// fragments and dZ are all in flight at once, and other blocks of the compute
+// unit cover their latency.
+template <int NT, int LM>
+__global__ __launch_bounds__(256, 2) void k_adj_dy_f32(AdjDesc a, CubeView yv) {
+    constexpr int LDW = proj_ldw<NT>();
+    __shared__ __attribute__((aligned(16))) float tile[kPixTile * LDW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, row = lane >> 4;
+    const int p = a.p, r = a.r;
+    const int ct = 4 * blockIdx.y + wave;          // column tile of this wave
+    const int b = 16 * ct + col;                   // its output band
+    const int64_t q0 = (int64_t)blockIdx.x * kPixTile;
+    {
+        v4f r4[proj_nv4<NT>()];
+        int zlo = 16 * NT;
+        proj_fetch<NT, LM>(yv, q0, r4);
+        proj_stage<NT, LM>(tile, yv, zlo, r4);
+    }
+    float bg[4 * NT], bp[4];
+#pragma unroll
+    for (int s = 0; s < 4 * NT; ++s) {
+        const int j = 4 * s + row;
+        bg[s] = (j < p && b < p) ? (float)a.dG2[(int64_t)j * p + b] : 0.f;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + row;
+        bp[s] = (k < r && b < p) ? (float)a.P64[(int64_t)b * r + k] : 0.f;
+    }
+    // A fragments of dZ P^T: dZ[comp 4 s + row][pixel q0 + 16 g + col] (the
+    // planes are padded to whole tiles)
+    const int R4 = (r + 3) >> 2;
+    const float* zp = static_cast<const float*>(a.A) + q0 + col;
+    float az[4][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + row;
+            az[g][s] = (s < R4 && k < r) ? zp[(int64_t)k * a.nz + 16 * g] : 0.f;
+        }
+    __syncthreads();
+    if (16 * ct >= p) return;                      // a wave past the last band tile
+    // pixel indices in 32 bits (n <= 2^31, so q + 63 < 2^32)
+    const unsigned n = (unsigned)a.n, Wd = (unsigned)a.W;
+    float* dy = static_cast<float*>(a.dY);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        v4f ac[4] = {};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (s < R4) ac[s] = mfma4(az[g][s], bp[s], ac[s]);
+        const float* arow = tile + (16 * g + col) * LDW + row;
+#pragma unroll
+        for (int s = 0; s < 4 * NT; ++s) {
+            ac[s & 3] = mfma4(arow[4 * s], bg[s], ac[s & 3]);
+            if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+        const v4f acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
+        // lane holds band b of pixels q0 + 16 g + 4 row + i
+        if (b < p) {
+            const unsigned qa = (unsigned)q0 + 16 * g + 4 * row;
+            unsigned y = qa / Wd, x = qa - y * Wd;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (qa + i < n) dy[(int64_t)y * a.dyrp + (int64_t)x * a.dyp + b] = acc[i];
+                if (++x == Wd) {
+                    x = 0;
+                    ++y;
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <typename T>
@@ -313,17 +510,49 @@ hipError_t launch_xprod_t(const AdjDesc& a, const void* planes, const void* cube
     return hipGetLastError();
 }
 
+// FP32 tile kernels specialised on the cube's load path (one path per kernel
+// keeps the staging registers low).
+#define LAUNCH_LM(K, N, view, grid, ...)                                                   \
+    do {                                                                                   \
+        if ((view).vec4) hipLaunchKernelGGL((K<N, kVec>), grid, dim3(256), 0, s, __VA_ARGS__); \
+        else if ((view).dense) hipLaunchKernelGGL((K<N, kDense>), grid, dim3(256), 0, s, __VA_ARGS__); \
+        else hipLaunchKernelGGL((K<N, kScalar>), grid, dim3(256), 0, s, __VA_ARGS__);   \
+    } while (0)
+#define HYRES_NT_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+
 hipError_t launch_xprod(int dtype, const AdjDesc& a, const void* planes, const void* cube, int64_t cp, int64_t crp,
                         hipStream_t s) {
-    return dtype == HYRES_F64 ? launch_xprod_t<double>(a, planes, cube, cp, crp, s)
-                              : launch_xprod_t<float>(a, planes, cube, cp, crp, s);
+    if (dtype == HYRES_F64) return launch_xprod_t<double>(a, planes, cube, cp, crp, s);
+    const CubeView cv = cube_view(cube, a.W, a.p, a.n, cp, crp, HYRES_F32);
+    const float* pl = static_cast<const float*>(planes);
+    switch ((a.p + 15) / 16) {
+#define HYRES_X(N) \
+    case N: LAUNCH_LM(k_adj_xprod_f32, N, cv, dim3(a.slots), a, pl, cv); break;
+        HYRES_NT_CASES(HYRES_X)
+#undef HYRES_X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
+
 
 hipError_t launch_adjoint_pre(const AdjDesc& a, int dtype, hipStream_t s) {
     // dZh and dQ
-    const unsigned gb = (unsigned)((a.n + 255) / 256);
-    if (dtype == HYRES_F64) hipLaunchKernelGGL(k_adj_apply<double>, dim3(gb), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_adj_apply<float>, dim3(gb), dim3(256), 0, s, a);
+    if (dtype == HYRES_F64) {
+        const unsigned gb = (unsigned)((a.n + 255) / 256);
+        hipLaunchKernelGGL(k_adj_apply<double>, dim3(gb), dim3(256), 0, s, a);
+    } else {
+        const CubeView dx = cube_view(a.dX, a.W, a.p, a.n, a.dxp, a.dxrp, HYRES_F32);
+        const unsigned g = (unsigned)((a.n + kPixTile - 1) / kPixTile);
+        switch ((a.p + 15) / 16) {
+#define HYRES_X(N) \
+    case N: LAUNCH_LM(k_adj_apply_f32, N, dx, dim3(g), a, dx); break;
+            HYRES_NT_CASES(HYRES_X)
+#undef HYRES_X
+            default: return hipErrorInvalidValue;
+        }
+    }
     hipError_t e = launch_xprod(dtype, a, a.Zh, a.dX, a.dxp, a.dxrp, s);
     if (e != hipSuccess) return e;
     const int E = a.r * a.p;
@@ -350,9 +579,21 @@ hipError_t launch_adjoint_post(const AdjDesc& a, int dtype, hipStream_t s) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_dc, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_adj_dg, dim3(a.p), dim3(256), 0, s, a);
-    const dim3 grid((unsigned)((a.n + kDyPix - 1) / kDyPix), (unsigned)((a.p + kDyCol - 1) / kDyCol));
-    if (dtype == HYRES_F64) hipLaunchKernelGGL(k_adj_dy<double>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_adj_dy<float>, grid, dim3(256), 0, s, a);
+    if (dtype == HYRES_F64) {
+        const dim3 grid((unsigned)((a.n + kDyPix - 1) / kDyPix), (unsigned)((a.p + kDyCol - 1) / kDyCol));
+        hipLaunchKernelGGL(k_adj_dy<double>, grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    const CubeView yv = cube_view(a.Y, a.W, a.p, a.n, a.pitch, a.row_pitch, HYRES_F32);
+    const int nt = (a.p + 15) / 16, groups = (nt + 3) / 4;
+    const dim3 grid((unsigned)((a.n + kPixTile - 1) / kPixTile), (unsigned)groups);
+    switch (nt) {
+#define HYRES_X(N) \
+    case N: LAUNCH_LM(k_adj_dy_f32, N, yv, grid, a, yv); break;
+        HYRES_NT_CASES(HYRES_X)
+#undef HYRES_X
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -170,3 +170,48 @@ def test_adjoint_config4_fp32_against_oracle_gradient():
     el = rel(lt.grad.cpu().numpy(), gl)
     say("  dY rel err", e, "dlambda rel err", el, "oracle spread", s_y, s_l)
     assert e <= max(1e-4, 2.0 * s_y) and el <= max(1e-4, 2.0 * s_l)
+
+
+def _midgap_lambda(B, lam):
+    """A threshold near each SURE threshold but away from every kink: the
+    middle of the widest gap between the 32 coefficient magnitudes nearest it."""
+    out = np.empty(len(lam))
+    for k in range(len(lam)):
+        a = np.sort(np.abs(B[k]))
+        i0 = int(np.searchsorted(a, lam[k]))
+        w = a[max(0, i0 - 16):i0 + 16]
+        g = int(np.argmax(np.diff(w)))
+        out[k] = 0.5 * (w[g] + w[g + 1])
+    return out
+
+
+# FP32 cubes on each load path of the pixel products: 16-byte vectors (p % 4
+# == 0), dense rows (odd p), strided pixels (a window of a larger tensor);
+# pixel counts that do not fill the last 64-pixel tile
+@pytest.mark.parametrize("H,W,p,r,L,layout", [(64, 64, 32, 4, 3, "vec"), (37, 53, 20, 3, 2, "vec"),
+                                              (37, 53, 21, 3, 2, "dense"), (40, 45, 24, 4, 2, "strided"),
+                                              (33, 70, 150, 5, 2, "dense")])
+def test_adjoint_fp32_layouts_against_oracle_gradient(H, W, p, r, L, layout):
+    api = _api()
+    c = synth.mixing_cube(11, H, W, p, r, 10.0, L, dtype=np.float32, keep_clean=False)
+    Y = c.Y
+    Y64 = Y.astype(np.float64)
+    ref = O.hyres(Y64, r, L)
+    lam = _midgap_lambda(ref["B"], ref["lam"])
+    say("fp32 adjoint", layout, Y.shape, "r", r, "L", L)
+    if layout == "strided":
+        big = torch.zeros(H, W + 3, p + 5, device="cuda")
+        big[:, :W, :p] = torch.tensor(Y, device="cuda")
+        Yt = big[:, :W, :p]
+    else:
+        Yt = torch.tensor(Y, device="cuda")
+    R = np.random.default_rng(3).standard_normal(Y.shape).astype(np.float32)
+    dn = api.Denoiser(H, W, p, r, L, dtype=torch.float32)
+    dn.run(Yt, None, torch.tensor(lam, device="cuda"))
+    dY, dlam, st = api.denoise_backward(dn, Yt, torch.tensor(R, device="cuda"))
+    assert int(st.cpu()[0]) == 0
+    gY, gl = _oracle_grad(Y64, lam, r, L, dn.V.T.cpu().numpy(), R.astype(np.float64))
+    e = rel(dY.cpu().numpy(), gY)
+    el = rel(dlam.cpu().numpy(), gl)
+    say("  dY rel err", e, "dlambda rel err", el)
+    assert e <= 1e-4 and el <= 1e-4

@@ -35,6 +35,8 @@ CASES = {
     "c1-fp64": lambda: (synth.config_cube(1, keep_clean=False).Y, 4, 3, 5, 1e-10),
     "ragged-fp32": lambda: (synth.mixing_cube(97, 97, 133, 40, 4, 12.0, 3, dtype=np.float32,
                                               keep_clean=False).Y, 5, 3, 3, 1e-5),
+    "dense-fp32": lambda: (synth.mixing_cube(98, 61, 75, 37, 4, 12.0, 3, dtype=np.float32,
+                                             keep_clean=False).Y, 4, 3, 3, 1e-5),
     "c2-fp32": lambda: (synth.config_cube(2, keep_clean=False).Y, 8, 4, 3, 1e-5),
 }
 
@@ -65,3 +67,16 @@ def test_wsrrr_without_iterations_is_the_hyres_solve():
     X0, _ = api.wsrrr(Yt, 4, 3, 0)
     X1, _ = api.denoise(Yt, 4, 3)
     assert torch.equal(X0, X1)
+
+
+def test_wsrrr_strided_input():
+    """A window of a larger tensor (strided pixels) gives the contiguous result."""
+    api = _api()
+    cube = synth.mixing_cube(99, 45, 70, 28, 3, 12.0, 3, dtype=np.float32, keep_clean=False)
+    H, W, p = cube.Y.shape
+    big = torch.zeros(H, W + 2, p + 3, device="cuda")
+    big[:, :W, :p] = torch.tensor(cube.Y, device="cuda")
+    Xs, info = api.wsrrr(big[:, :W, :p], 4, 3, 3)
+    ref = WS.wsrrr(cube.Y.astype(np.float64), 4, 3, 3, sigma=info["sigma"].cpu().numpy(),
+                   lam=info["lam"].cpu().numpy())
+    PM.assert_close(Xs.cpu().numpy(), ref["X"], 1e-5, "strided")

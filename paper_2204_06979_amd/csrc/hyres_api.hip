@@ -619,7 +619,7 @@ void build_group(Exec& x, int stages, int grp) {
             for (int i = 0; i < N; ++i) {
                 if (!in_group(x, i, grp)) continue;
                 slots[i] = x.plan[i].rgroups;
-                pix[i] = cdiv(x.plan[i].n, 256);
+                pix[i] = cdiv(x.plan[i].nz, kRotPix);
                 ids.push_back(i);
             }
             int64_t ns, np;

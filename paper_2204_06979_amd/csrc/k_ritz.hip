@@ -19,32 +19,50 @@
 
 namespace hyres {
 
-// rsum[g][e] = sum over the tiles of group g of the FP32 tile products (FP64, tile order).
+// The r x r entries (a, b) of the tile products that the refinement reads,
+// spread over the 256 threads of a block: thread t takes entry t % E of part
+// t / E (E = r r, P = 256 / E parts).  Part k sums the items k, k + P, ... of
+// a range in order; the parts are then added in order (a fixed order for a
+// given rank, whatever the grid).
+__device__ __forceinline__ double ritz_part_sum(const float* __restrict__ src, int64_t i0, int64_t i1, int P,
+                                                int part) {
+    double s = 0.0;
+    int64_t i = i0 + part;
+    for (; i + 31 * (int64_t)P < i1; i += 32 * (int64_t)P) {
+        float v[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) v[u] = src[(i + u * (int64_t)P) * 256];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) s += (double)v[u];
+    }
+    for (; i < i1; i += P) s += (double)src[i * 256];
+    return s;
+}
+
+// rsum[g][a * 16 + b] = sum over the tiles of group g of the FP32 tile
+// products (FP64; the parts of the block in order).
 __global__ __launch_bounds__(256) void k_ritz_reduce(const CubeDesc* __restrict__ descs,
                                                      const int* __restrict__ items, int ncubes) {
+    __shared__ double part_s[256];
     const int total = items[ncubes];
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int c = find_cube(items, ncubes, item);
         const CubeDesc& d = descs[c];
         const int g = item - items[c];
+        const int r = d.r, E = r * r, P = 256 / E;
         const int64_t ntiles = (d.n + kPixTile - 1) / kPixTile;
         const int64_t t0 = (int64_t)g * kRitzGroup;
         const int64_t t1 = t0 + kRitzGroup < ntiles ? t0 + kRitzGroup : ntiles;
-        const int e = threadIdx.x;
-        const float* src = d.rpart + e;
-        // 32 loads in flight (the partials come from the caches, latency-bound),
-        // added in tile order
-        double s = 0.0;
-        int64_t t = t0;
-        for (; t + 32 <= t1; t += 32) {
-            float v[32];
-#pragma unroll
-            for (int u = 0; u < 32; ++u) v[u] = src[(t + u) * 256];
-#pragma unroll
-            for (int u = 0; u < 32; ++u) s += (double)v[u];
+        const int t = threadIdx.x, e = t % E, pt = t / E;
+        const int a = e / r, b = e - a * r;
+        __syncthreads();
+        part_s[t] = pt < P ? ritz_part_sum(d.rpart + a * 16 + b, t0, t1, P, pt) : 0.0;
+        __syncthreads();
+        if (t < E) {
+            double s = part_s[t];
+            for (int k = 1; k < P; ++k) s += part_s[t + k * E];
+            d.rsum[(int64_t)g * 256 + a * 16 + b] = s;
         }
-        for (; t < t1; ++t) s += (double)src[t * 256];
-        d.rsum[(int64_t)g * 256 + e] = s;
     }
 }
 
@@ -133,28 +151,42 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
     __shared__ int perm[16];
     __shared__ double sgn[16];
     __shared__ double s_off, s_diag;
+    __shared__ double s_part[256];
     const int cube = cubes[blockIdx.x];
     const CubeDesc& d = descs[cube];
     const int r = d.r, p = d.p, tid = threadIdx.x;
     const int i = tid >> 4, j = tid & 15;
     const int m = (r + 1) & ~1;                   // even size; a padding index stays decoupled
-    // M from the group sums (upper triangle summed, mirrored; group order)
+    // M from the group sums: thread (entry tid % E, part tid / E) sums the
+    // groups part, part + P, ... in order, the parts are added in order, and
+    // the upper entry is mirrored (M exactly symmetric)
     {
-        const int a = i <= j ? i : j, b = i <= j ? j : i;
+        const int E = r * r, P = 256 / E;
+        const int e = tid % E, pt = tid / E;
+        const int a = e / r, b = e - a * r;
         double s = 0.0;
-        if (a < r && b < r) {
+        if (pt < P) {
             const double* src = d.rsum + a * 16 + b;
-            int k = 0;
-            for (; k + 16 <= d.rgroups; k += 16) {
+            int k = pt;
+            for (; k + 15 * P < d.rgroups; k += 16 * P) {
                 double v[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) v[u] = src[(int64_t)(k + u) * 256];
+                for (int u = 0; u < 16; ++u) v[u] = src[(int64_t)(k + u * P) * 256];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) s += v[u];
             }
-            for (; k < d.rgroups; ++k) s += src[(int64_t)k * 256];
+            for (; k < d.rgroups; k += P) s += src[(int64_t)k * 256];
         }
-        Mb[0][i][j] = s;
+        s_part[tid] = s;
+        __syncthreads();
+        const int ai = i <= j ? i : j, bj = i <= j ? j : i;
+        double m = 0.0;
+        if (ai < r && bj < r) {
+            const int eu = ai * r + bj;
+            m = s_part[eu];
+            for (int k = 1; k < P; ++k) m += s_part[eu + k * E];
+        }
+        Mb[0][i][j] = m;
         Ub[0][i][j] = i == j ? 1.0 : 0.0;
     }
     for (int e = tid; e < p * r; e += 256) {
@@ -328,7 +360,9 @@ hipError_t launch_polar(const CubeDesc* descs, const double* M, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Z <- Z R (r x r rotation), in place.
+// Z <- Z R (r x r rotation), in place: four pixels per thread (16-byte
+// accesses; the planes are padded to whole 64-pixel tiles, so an item never
+// reads or writes past a plane).
 __global__ __launch_bounds__(256) void k_ritz_rotate(const CubeDesc* __restrict__ descs,
                                                      const int* __restrict__ items, int ncubes) {
     __shared__ float R[kMaxRank][kMaxRank + 1];
@@ -343,20 +377,22 @@ __global__ __launch_bounds__(256) void k_ritz_rotate(const CubeDesc* __restrict_
             __syncthreads();
             cur = c;
         }
-        const int64_t q = (int64_t)(item - items[c]) * 256 + threadIdx.x;
-        if (q >= d.n) continue;
+        const int64_t q = (int64_t)(item - items[c]) * kRotPix + 4 * threadIdx.x;
+        if (q >= d.nz) continue;
         const int r = d.r;
-        float* z = static_cast<float*>(d.Z);
-        float in[kMaxRank];
+        float* z = static_cast<float*>(d.Z) + q;
+        v4f in[kMaxRank];
 #pragma unroll
-        for (int k = 0; k < kMaxRank; ++k) in[k] = k < r ? z[(int64_t)k * d.nz + q] : 0.f;
+        for (int k = 0; k < kMaxRank; ++k)
+            in[k] = k < r ? *reinterpret_cast<const v4f*>(z + (int64_t)k * d.nz) : v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < kMaxRank; ++k) {
             if (k < r) {
-                float s = 0.f;
+                v4f s = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int jj = 0; jj < kMaxRank; ++jj) s = fmaf(in[jj], R[jj][k], s);
-                z[(int64_t)k * d.nz + q] = s;
+                for (int jj = 0; jj < kMaxRank; ++jj)
+                    if (jj < r) s += in[jj] * R[jj][k];
+                *reinterpret_cast<v4f*>(z + (int64_t)k * d.nz) = s;
             }
         }
     }

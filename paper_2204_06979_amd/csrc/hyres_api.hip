@@ -26,7 +26,7 @@
 #define HYRES_API extern "C" __attribute__((visibility("default")))
 
 namespace hyres {
-hipError_t launch_gram_f32(int T, int lm, const CubeDesc*, const int*, int, int, hipStream_t);
+hipError_t launch_gram_f32(int T, int lm, const CubeDesc*, const int*, int, int, hipStream_t, bool wide);
 hipError_t launch_gram_bf16(int T, int lm, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_gram_reduce_f32(int T, const CubeDesc*, const int*, int, hipStream_t);
 hipError_t launch_gram_f64(const CubeDesc*, int, int, int, hipStream_t);
@@ -560,6 +560,9 @@ void build_group(Exec& x, int stages, int grp) {
                 }
                 L.b = vec ? kVec : dense ? kDense : scalar ? kScalar : kAnyLayout;
             }
+            // native FP32 Gram of fewer slots than half the compute units (a
+            // small cube alone): each slot's tiles split over several blocks
+            if (kind == K_GRAM_F32 && x.h && tot * 2 < x.h->num_cu) L.grid2 = 1;
             x.prog.push_back(L);
             if (kind == K_GRAM_F32 || kind == K_GRAM_BF16) {
                 std::vector<int> ids;
@@ -733,7 +736,7 @@ void build_program(Exec& x, int stages) {
 hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
     const CubeDesc* D = x.descs();
     switch (L.kind) {
-        case K_GRAM_F32: return launch_gram_f32(L.key, L.b, D, x.table(L.a), L.n, L.grid, s);
+        case K_GRAM_F32: return launch_gram_f32(L.key, L.b, D, x.table(L.a), L.n, L.grid, s, L.grid2 != 0);
         case K_GRAM_BF16: return launch_gram_bf16(L.key, L.b, D, x.table(L.a), L.n, L.grid, s);
         case K_GRAM_RED: return launch_gram_reduce_f32(L.key, D, x.table(L.a), L.n, s);
         case K_GRAM_F64: return launch_gram_f64(D, L.a, L.key, L.grid, s);

@@ -316,6 +316,22 @@ __device__ __forceinline__ void set_status(int* st, int bits) {
 constexpr int kVec = 0, kDense = 1, kScalar = 2;
 constexpr int kAnyLayout = 3;      // a launch whose cubes take different paths (chosen per cube)
 
+// Global-memory views of device pointers.  A pointer read from a descriptor in
+// memory is generic to the compiler, and generic accesses compile to FLAT
+// instructions, which count against the LDS wait counter as well: every wait
+// for an LDS read then also waits for the global loads in flight (a tile
+// prefetched during the matrix work stalls it).  Accesses through a pointer
+// derived from gmem() (with arithmetic on it, or kept in its own type) are
+// global_* instructions.  The address-space qualifier exists in the device
+// pass only; the host pass sees plain pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HYRES_GLOBAL __attribute__((address_space(1)))
+#else
+#define HYRES_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ HYRES_GLOBAL T* gmem(T* p) { return (HYRES_GLOBAL T*)p; }
+
 // An FP32 cube as the 64-pixel tile loaders see it (a CubeDesc carries the
 // same fields under the same names): pixel q = y W + x at Y + y row_pitch +
 // x pitch, flags as in CubeDesc.
@@ -336,7 +352,7 @@ __device__ __forceinline__ int div_p(int e, uint32_t pmag) { return (int)__umulh
 template <typename T, typename D>
 __device__ __forceinline__ const T* pixel_ptr(const D& d, int64_t q) {
     int64_t y = q / d.W, x = q - y * d.W;
-    return static_cast<const T*>(d.Y) + y * d.row_pitch + x * d.pitch;
+    return gmem(static_cast<const T*>(d.Y)) + y * d.row_pitch + x * d.pitch;
 }
 
 }  // namespace hyres

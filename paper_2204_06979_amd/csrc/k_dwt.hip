@@ -38,7 +38,7 @@ __device__ __forceinline__ T soft(T v, T lam) {
 // Approximation buffer of level l (l >= 1) inside the temp area of a component.
 template <typename T>
 __device__ __forceinline__ T* ll_buf(const CubeDesc& d, int comp, int l) {
-    return static_cast<T*>(d.tmp) + (int64_t)comp * d.tps + ((l & 1) ? 0 : d.tmp_off2);
+    return gmem(static_cast<T*>(d.tmp)) + (int64_t)comp * d.tps + ((l & 1) ? 0 : d.tmp_off2);
 }
 
 template <typename T, int TX, int TY>
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(TX* TY) void k_dwt_level(const CubeDesc* __restrict
         const int comp = local / (ntx * nty);
         const int rem = local - comp * ntx * nty;
         const int oy0 = (rem / ntx) * TY, ox0 = (rem % ntx) * TX;
-        const T* src = level == 1 ? static_cast<const T*>(d.Z) + (int64_t)comp * d.nz
+        const T* src = level == 1 ? gmem(static_cast<const T*>(d.Z)) + (int64_t)comp * d.nz
                                   : ll_buf<T>(d, comp, level - 1);
         const int he = h + (h & 1), we = w + (w & 1);
         // the extra sample of an odd length repeats the last one, or is zero
@@ -111,11 +111,11 @@ __global__ __launch_bounds__(TX* TY) void k_dwt_level(const CubeDesc* __restrict
             const T hh = F::g0 * hi[0] + F::g1 * hi[1] + F::g2 * hi[2] + F::g3 * hi[3];
             const int64_t blk = (int64_t)h2 * w2;
             const int64_t o = (int64_t)oy * w2 + ox;
-            T* cf = static_cast<T*>(d.coef) + (int64_t)comp * d.ncs + d.loff[level];
+            T* cf = gmem(static_cast<T*>(d.coef)) + (int64_t)comp * d.ncs + d.loff[level];
             cf[o] = lh;
             cf[blk + o] = hl;
             cf[2 * blk + o] = hh;
-            T* llo = level == d.L ? static_cast<T*>(d.coef) + (int64_t)comp * d.ncs + d.ll_off
+            T* llo = level == d.L ? gmem(static_cast<T*>(d.coef)) + (int64_t)comp * d.ncs + d.ll_off
                                   : ll_buf<T>(d, comp, level);
             llo[o] = ll;
         }
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(TX* TY) void k_idwt_level(const CubeDesc* __restric
         const bool thr = (d.mode & 8) != 0;
         const T lam = thr ? (T)d.lambda[comp] : (T)0;
         const bool thr_ll = thr && level == d.L && d.scope == HYRES_SCOPE_ALL;
-        const T* cf = static_cast<const T*>(d.coef) + (int64_t)comp * d.ncs;
+        const T* cf = gmem(static_cast<const T*>(d.coef)) + (int64_t)comp * d.ncs;
         const T* det = cf + d.loff[level];
         const T* llsrc = level == d.L ? cf + d.ll_off : ll_buf<T>(d, comp, level);
         const int64_t blk = (int64_t)h2 * w2;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(TX* TY) void k_idwt_level(const CubeDesc* __restric
                 o10 += fy1 * r0b0 + fy3 * r1b0;
                 o11 += fy1 * r0b1 + fy3 * r1b1;
             }
-            T* dst = level == 1 ? static_cast<T*>(d.Z) + (int64_t)comp * d.nz
+            T* dst = level == 1 ? gmem(static_cast<T*>(d.Z)) + (int64_t)comp * d.nz
                                 : ll_buf<T>(d, comp, level - 1);
             const int y0 = 2 * s, x0 = 2 * u;
             if (d.mode & kModeFold) {

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256, LM == kVec || LM == kDense ? 2 : 1) void k_pro
         if (c != cur) {
             cur = c;
 #pragma unroll
-            for (int s = 0; s < 4 * T; ++s) bf[s] = d.P32[(4 * s + row) * 16 + col];
+            for (int s = 0; s < 4 * T; ++s) bf[s] = gmem(d.P32)[(4 * s + row) * 16 + col];
         }
         const int64_t q0 = (int64_t)(item - items[c]) * kPixTile;
         __syncthreads();
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256, LM == kVec || LM == kDense ? 2 : 1) void k_pro
         const v4f acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
         // lane holds component col of pixels q0 + 16 wave + 4 row + i
         if (col < d.r) {
-            float* z = static_cast<float*>(d.Z) + (int64_t)col * d.nz + q0 + 16 * wave + 4 * row;
+            float* z = gmem(static_cast<float*>(d.Z)) + (int64_t)col * d.nz + q0 + 16 * wave + 4 * row;
             *reinterpret_cast<v4f*>(z) = acc;
         }
         if (d.rpart) {
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256, LM == kVec || LM == kDense ? 2 : 1) void k_pro
             for (int i = 0; i < 4; ++i) s_m[wave][(4 * row + i) * 16 + col] = m[i];
             __syncthreads();
             const int e = threadIdx.x;
-            d.rpart[(q0 / kPixTile) * 256 + e] = ((s_m[0][e] + s_m[1][e]) + s_m[2][e]) + s_m[3][e];
+            gmem(d.rpart)[(q0 / kPixTile) * 256 + e] = ((s_m[0][e] + s_m[1][e]) + s_m[2][e]) + s_m[3][e];
         }
     }
 }
@@ -112,12 +112,12 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int j = 0; j < T; ++j) bq[q][j] = d.Q32[(4 * q + row) * P16 + 16 * j + col];
+                for (int j = 0; j < T; ++j) bq[q][j] = gmem(d.Q32)[(4 * q + row) * P16 + 16 * j + col];
         }
         const int64_t q0 = (int64_t)(item - items[c]) * kPixTile;
         // A fragments: Zhat[comp 4q + row][pixel q0 + 16 wave + col]
         float a[4];
-        const float* zh = static_cast<const float*>(d.Z);
+        const float* zh = gmem(static_cast<const float*>(d.Z));
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int comp = 4 * q + row;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
             // whole 64-pixel tiles per image row: the pixels are consecutive in memory
             const int g4 = p >> 2;
             const int64_t y0 = q0 / d.W, x0 = q0 - y0 * d.W;
-            float* base = static_cast<float*>(d.X) + y0 * d.xrow_pitch + x0 * d.xpitch;
+            float* base = gmem(static_cast<float*>(d.X)) + y0 * d.xrow_pitch + x0 * d.xpitch;
             for (int e = threadIdx.x; e < kPixTile * g4; e += 256) {
                 const int k = e / g4, g = e - k * g4;
                 if (k < nleft)
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
             }
         } else if (d.xdense) {
             // unpadded pixels: the tile is 64 p consecutive floats, written as float4s
-            float* base = static_cast<float*>(d.X) + (q0 / d.W) * d.xrow_pitch + (q0 % d.W) * p;
+            float* base = gmem(static_cast<float*>(d.X)) + (q0 / d.W) * d.xrow_pitch + (q0 % d.W) * p;
             const int lim = (int)(nleft < kPixTile ? nleft : kPixTile) * p;
             for (int e = 4 * threadIdx.x; e < lim; e += 4 * 256) {
                 v4f v;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_backproject_f32(const CubeDesc* __restr
                     const int64_t q = q0 + k;
                     const int64_t y = q / d.W, x = q - y * d.W;
                     __builtin_nontemporal_store(ot[k * LDO + b],
-                                                static_cast<float*>(d.X) + y * d.xrow_pitch + x * d.xpitch + b);
+                                                gmem(static_cast<float*>(d.X)) + y * d.xrow_pitch + x * d.xpitch + b);
                 }
             }
         }
@@ -221,14 +221,14 @@ __global__ __launch_bounds__(256) void k_blend_f32(const CubeDesc* __restrict__ 
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
 #pragma unroll
-                        for (int j = 0; j < T; ++j) bq[q][j] = d.Q32[(4 * q + row) * P16 + 16 * j + col];
+                        for (int j = 0; j < T; ++j) bq[q][j] = gmem(d.Q32)[(4 * q + row) * P16 + 16 * j + col];
                 }
                 const int r = d.r, R4 = (r + 3) >> 2;
                 // A fragments: Zhat[comp 4q + row] at the tile pixel of image column x0 + 16 wave + col
                 const int lxa = x0 + 16 * wave + col - sx;
                 const bool va = lxa >= 0 && lxa < g.tw;
                 const int64_t qa = (int64_t)ly * g.tw + (va ? lxa : 0);
-                const float* zh = static_cast<const float*>(d.Z);
+                const float* zh = gmem(static_cast<const float*>(d.Z));
                 float a[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -283,7 +283,7 @@ __global__ void k_project_f64(const CubeDesc* __restrict__ descs, int cube) {
         const double v = y[b];
         for (int g = 0; g < d.r; ++g) acc[g] = fma(v, d.P64[(int64_t)b * d.r + g], acc[g]);
     }
-    double* z = static_cast<double*>(d.Z);
+    double* z = gmem(static_cast<double*>(d.Z));
     for (int g = 0; g < d.r; ++g) z[(int64_t)g * d.nz + q] = acc[g];
 }
 
@@ -291,11 +291,11 @@ __global__ void k_backproject_f64(const CubeDesc* __restrict__ descs, int cube) 
     const CubeDesc& d = descs[cube];
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= d.n) return;
-    const double* zh = static_cast<const double*>(d.Z);
+    const double* zh = gmem(static_cast<const double*>(d.Z));
     double a[kMaxRank];
     for (int g = 0; g < d.r; ++g) a[g] = zh[(int64_t)g * d.nz + q];
     const int64_t y = q / d.W, x = q - y * d.W;
-    double* xo = static_cast<double*>(d.X) + y * d.xrow_pitch + x * d.xpitch;
+    double* xo = gmem(static_cast<double*>(d.X)) + y * d.xrow_pitch + x * d.xpitch;
     bool first = true;
     const double w = d.bwy ? blend_weight(d, y, x, &first) : 1.0;
     for (int b = 0; b < d.p; ++b) {

@@ -18,14 +18,15 @@ namespace hyres {
 
 // Upper 16x16 tiles of G in row-major order.  P = 0: all of them; P = 1..NP:
 // one of NP consecutive parts (for large T one launch per part keeps the
-// per-wave accumulators in registers, at the price of rereading Y).
-template <int T, int P = 0>
+// per-wave accumulators in registers, at the price of rereading Y; a program
+// of few slots splits every slot's tiles over NPX blocks of one launch).
+template <int T, int P = 0, int NPX = 0>
 struct TileMap {
     static constexpr int NT = T * (T + 1) / 2;    // all tiles (partial layout)
-    static constexpr int NP = T >= 13 ? 3 : 2;     // parts when split
+    static constexpr int NP = NPX ? NPX : (T >= 13 ? 3 : 2);   // parts when split
     static constexpr int T0 = P == 0 ? 0 : (P - 1) * NT / NP;
     static constexpr int T1 = P == 0 ? NT : P * NT / NP;
-    static constexpr int S = (T1 - T0 + 7) / 8;   // tiles per wave
+    static constexpr int S = (T1 - T0 + 7) / 8 > 0 ? (T1 - T0 + 7) / 8 : 1;   // tiles per wave
     __host__ __device__ static constexpr int ti(int t) {
         int i = 0, rem = t;
         while (rem >= T - i) { rem -= T - i; ++i; }
@@ -55,10 +56,10 @@ template <int T> __host__ __device__ constexpr int gram_nr() {
 // Wave WV owns the contiguous run of upper tiles [WV*S, WV*S + S) in row-major
 // order: the fragment of the tile row stays in registers while the column
 // fragment is loaded per tile.
-template <int T, int P, int WV>
+template <int T, int P, int WV, int NPX = 0>
 __device__ __forceinline__ void gram_wave(const float* __restrict__ tile, int lane,
-                                          v4f (&acc)[TileMap<T, P>::S]) {
-    using TM = TileMap<T, P>;
+                                          v4f (&acc)[TileMap<T, P, NPX>::S]) {
+    using TM = TileMap<T, P, NPX>;
     constexpr int LDW = gram_ldw<T>();
     constexpr int S = TM::S;
     const int col = lane & 15, row = lane >> 4;
@@ -164,11 +165,11 @@ __device__ __forceinline__ void gram_stage(float* __restrict__ tile, const CubeD
 // chunk tile is double-buffered (`tile` holds two of kGramKB x LDW floats):
 // the next chunk is staged while the matrix cores read the current one, one
 // barrier per chunk.
-template <int T, int P, int M>
+template <int T, int P, int M, int NPX = 0>
 __device__ __forceinline__ void gram_slot(const CubeDesc& d, int64_t q0, int64_t q1, float* tile, int lane,
-                                          int wave, v4f (&acc)[TileMap<T, P>::S],
-                                          double (&accd)[TileMap<T, P>::S][4]) {
-    constexpr int S = TileMap<T, P>::S;
+                                          int wave, v4f (&acc)[TileMap<T, P, NPX>::S],
+                                          double (&accd)[TileMap<T, P, NPX>::S][4]) {
+    constexpr int S = TileMap<T, P, NPX>::S;
     constexpr int TS = kGramKB * gram_ldw<T>();
     float rg[gram_nr<T>()];
     if (q0 >= q1) return;
@@ -181,14 +182,14 @@ __device__ __forceinline__ void gram_slot(const CubeDesc& d, int64_t q0, int64_t
         if (more) gram_fetch<T, M>(d, q + kGramKB, q1, rg);   // overlaps the MFMAs
         const float* tb = tile + cur * TS;
         switch (wave) {
-            case 0: gram_wave<T, P, 0>(tb, lane, acc); break;
-            case 1: gram_wave<T, P, 1>(tb, lane, acc); break;
-            case 2: gram_wave<T, P, 2>(tb, lane, acc); break;
-            case 3: gram_wave<T, P, 3>(tb, lane, acc); break;
-            case 4: gram_wave<T, P, 4>(tb, lane, acc); break;
-            case 5: gram_wave<T, P, 5>(tb, lane, acc); break;
-            case 6: gram_wave<T, P, 6>(tb, lane, acc); break;
-            default: gram_wave<T, P, 7>(tb, lane, acc); break;
+            case 0: gram_wave<T, P, 0, NPX>(tb, lane, acc); break;
+            case 1: gram_wave<T, P, 1, NPX>(tb, lane, acc); break;
+            case 2: gram_wave<T, P, 2, NPX>(tb, lane, acc); break;
+            case 3: gram_wave<T, P, 3, NPX>(tb, lane, acc); break;
+            case 4: gram_wave<T, P, 4, NPX>(tb, lane, acc); break;
+            case 5: gram_wave<T, P, 5, NPX>(tb, lane, acc); break;
+            case 6: gram_wave<T, P, 6, NPX>(tb, lane, acc); break;
+            default: gram_wave<T, P, 7, NPX>(tb, lane, acc); break;
         }
         // the other buffer was last read before the previous barrier
         if (more) gram_stage<T, M>(tile + (cur ^ 1) * TS, d, rg);
@@ -204,16 +205,15 @@ __device__ __forceinline__ void gram_slot(const CubeDesc& d, int64_t q0, int64_t
     }
 }
 
-// LM: the load path of every cube of the launch (the others are compiled out),
-// or kAnyLayout (chosen per cube).
-template <int T, int P, int LM>
-__global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __restrict__ descs,
-                                                          const int* __restrict__ items, int ncubes) {
-    using TM = TileMap<T, P>;
-    constexpr int LDW = gram_ldw<T>();
+// The slots of the launch (part P of NPX, or all tiles), the chunk tile in
+// `tile`.  LM: the load path of every cube of the launch (the others are
+// compiled out), or kAnyLayout (chosen per cube).
+template <int T, int P, int LM, int NPX>
+__device__ __forceinline__ void gram_f32_items(const CubeDesc* __restrict__ descs, const int* __restrict__ items,
+                                               int ncubes, float* tile) {
+    using TM = TileMap<T, P, NPX>;
     constexpr int NT = TM::NT;
     constexpr int S = TM::S;
-    __shared__ __attribute__((aligned(16))) float tile[2 * kGramKB * LDW];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int total = items[ncubes];
@@ -235,14 +235,14 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
             for (int i = 0; i < 4; ++i) accd[q][i] = 0.0;
         }
         if constexpr (LM != kAnyLayout) {
-            gram_slot<T, P, LM>(d, q0, q1, tile, lane, wave, acc, accd);
+            gram_slot<T, P, LM, NPX>(d, q0, q1, tile, lane, wave, acc, accd);
         } else {
             const int m = load_mode(d);
-            if (m == kVec) gram_slot<T, P, kVec>(d, q0, q1, tile, lane, wave, acc, accd);
-            else if (m == kDense) gram_slot<T, P, kDense>(d, q0, q1, tile, lane, wave, acc, accd);
-            else gram_slot<T, P, kScalar>(d, q0, q1, tile, lane, wave, acc, accd);
+            if (m == kVec) gram_slot<T, P, kVec, NPX>(d, q0, q1, tile, lane, wave, acc, accd);
+            else if (m == kDense) gram_slot<T, P, kDense, NPX>(d, q0, q1, tile, lane, wave, acc, accd);
+            else gram_slot<T, P, kScalar, NPX>(d, q0, q1, tile, lane, wave, acc, accd);
         }
-        float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
+        float* out = gmem(static_cast<float*>(d.gpart)) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
@@ -253,6 +253,33 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __res
             }
         }
     }
+}
+
+template <int T, int P, int LM>
+__global__ __launch_bounds__(kGramThreads) void k_gram_f32(const CubeDesc* __restrict__ descs,
+                                                          const int* __restrict__ items, int ncubes) {
+    __shared__ __attribute__((aligned(16))) float tile[2 * kGramKB * gram_ldw<T>()];
+    gram_f32_items<T, P, LM, 0>(descs, items, ncubes, tile);
+}
+
+// A program of few slots (a small cube alone): the tiles of every slot are
+// split over gram_wide_parts<T>() blocks (blockIdx.y), each staging the whole
+// chunk and computing its part.  Every tile of a slot is summed exactly as in
+// the one-block kernel, so G is the same to the bit.
+template <int T> __host__ __device__ constexpr int gram_wide_parts() {
+    return T * (T + 1) / 2 >= 64 ? 8 : T * (T + 1) / 2 >= 32 ? 4 : T * (T + 1) / 2 >= 16 ? 2 : 1;
+}
+
+template <int T, int LM>
+__global__ __launch_bounds__(kGramThreads) void k_gram_f32_wide(const CubeDesc* __restrict__ descs,
+                                                               const int* __restrict__ items, int ncubes) {
+    constexpr int NPX = gram_wide_parts<T>();
+    __shared__ __attribute__((aligned(16))) float tile[2 * kGramKB * gram_ldw<T>()];
+    const int part = blockIdx.y;
+    static_for<NPX>([&](auto pc) {
+        constexpr int pp = decltype(pc)::value;
+        if (part == pp) gram_f32_items<T, pp + 1, LM, NPX>(descs, items, ncubes, tile);
+    });
 }
 
 // ------------------------------------------------------------------------
@@ -543,7 +570,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_bf16(const CubeDesc* __re
             else if (m == kDense) gramb_slot<T, P, kDense, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
             else gramb_slot<T, P, kScalar, FP64>(d, q0, q1, th, tl, lane, wave, acc, accd);
         }
-        float* out = static_cast<float*>(d.gpart) + (int64_t)(d.gslot0 + slot) * NT * 256;
+        float* out = gmem(static_cast<float*>(d.gpart)) + (int64_t)(d.gslot0 + slot) * NT * 256;
         const int col = lane & 15, row = lane >> 4;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
@@ -577,7 +604,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce_f32(const CubeDesc* __restr
     const int e = blockIdx.x * 32 + lane;
     const bool live = e < NT * 256;
     const int64_t stride = (int64_t)NT * 256;
-    const float* pbase = static_cast<const float*>(d.gpart) + (int64_t)d.gslot0 * stride + (live ? e : 0);
+    const float* pbase = gmem(static_cast<const float*>(d.gpart)) + (int64_t)d.gslot0 * stride + (live ? e : 0);
     double s = 0.0;
     int sl = grp;
     for (; sl + 7 * kRedGroups < d.gslots; sl += 8 * kRedGroups) {
@@ -634,7 +661,7 @@ __global__ void k_gram_f64(const CubeDesc* __restrict__ descs, int cube) {
         s = fma(ya, yb, s);
     }
     if (bad) set_status(d.status, HYRES_DEV_NONFINITE);
-    static_cast<double*>(d.gpart)[(int64_t)(d.gslot0 + slot) * ntri + e] = s;
+    gmem(static_cast<double*>(d.gpart))[(int64_t)(d.gslot0 + slot) * ntri + e] = s;
 }
 
 __global__ void k_gram_reduce_f64(const CubeDesc* __restrict__ descs, int cube) {
@@ -646,7 +673,7 @@ __global__ void k_gram_reduce_f64(const CubeDesc* __restrict__ descs, int cube) 
     int a = 0, rem = e;
     while (rem >= p - a) { rem -= p - a; ++a; }
     const int b = a + rem;
-    const double* part = static_cast<const double*>(d.gpart) + (int64_t)d.gslot0 * ntri + e;
+    const double* part = gmem(static_cast<const double*>(d.gpart)) + (int64_t)d.gslot0 * ntri + e;
     double s = 0.0;
     for (int sl = 0; sl < d.gslots; ++sl) s += part[(int64_t)sl * ntri];
     d.G[(int64_t)a * p + b] = s;
@@ -681,7 +708,15 @@ static void launch_gram_parts(const CubeDesc* descs, const int* items, int ncube
 
 template <int T>
 static hipError_t launch_gram_t(int lm, const CubeDesc* descs, const int* items, int ncubes, int grid,
-                                hipStream_t s) {
+                                hipStream_t s, bool wide) {
+    // the split launch for the vector and dense load paths (strided cubes keep
+    // the one-block kernel)
+    if (wide && gram_wide_parts<T>() > 1 && (lm == kVec || lm == kDense)) {
+        const dim3 g((unsigned)grid, (unsigned)gram_wide_parts<T>());
+        if (lm == kVec) hipLaunchKernelGGL((k_gram_f32_wide<T, kVec>), g, dim3(kGramThreads), 0, s, descs, items, ncubes);
+        else hipLaunchKernelGGL((k_gram_f32_wide<T, kDense>), g, dim3(kGramThreads), 0, s, descs, items, ncubes);
+        return hipGetLastError();
+    }
     // with one load path compiled in, every tile's FP64 accumulators stay in
     // registers up to T = 14: one pass over Y
     if (lm == kVec) {
@@ -720,9 +755,9 @@ hipError_t launch_gram_bf16(int T, int lm, const CubeDesc* descs, const int* ite
 }
 
 hipError_t launch_gram_f32(int T, int lm, const CubeDesc* descs, const int* items, int ncubes, int grid,
-                           hipStream_t s) {
+                           hipStream_t s, bool wide) {
     switch (T) {
-#define HYRES_G(TT) case TT: return launch_gram_t<TT>(lm, descs, items, ncubes, grid, s);
+#define HYRES_G(TT) case TT: return launch_gram_t<TT>(lm, descs, items, ncubes, grid, s, wide);
         HYRES_G(1) HYRES_G(2) HYRES_G(3) HYRES_G(4) HYRES_G(5) HYRES_G(6) HYRES_G(7)
         HYRES_G(8) HYRES_G(9) HYRES_G(10) HYRES_G(11) HYRES_G(12) HYRES_G(13) HYRES_G(14)
 #undef HYRES_G

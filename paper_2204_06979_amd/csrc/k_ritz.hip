@@ -56,12 +56,12 @@ __global__ __launch_bounds__(256) void k_ritz_reduce(const CubeDesc* __restrict_
         const int t = threadIdx.x, e = t % E, pt = t / E;
         const int a = e / r, b = e - a * r;
         __syncthreads();
-        part_s[t] = pt < P ? ritz_part_sum(d.rpart + a * 16 + b, t0, t1, P, pt) : 0.0;
+        part_s[t] = pt < P ? ritz_part_sum(gmem(d.rpart) + a * 16 + b, t0, t1, P, pt) : 0.0;
         __syncthreads();
         if (t < E) {
             double s = part_s[t];
             for (int k = 1; k < P; ++k) s += part_s[t + k * E];
-            d.rsum[(int64_t)g * 256 + a * 16 + b] = s;
+            gmem(d.rsum)[(int64_t)g * 256 + a * 16 + b] = s;
         }
     }
 }
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
         const int a = e / r, b = e - a * r;
         double s = 0.0;
         if (pt < P) {
-            const double* src = d.rsum + a * 16 + b;
+            const double* src = gmem(d.rsum) + a * 16 + b;
             int k = pt;
             for (; k + 15 * P < d.rgroups; k += 16 * P) {
                 double v[16];
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void k_ritz_rotate(const CubeDesc* __restrict_
         const int64_t q = (int64_t)(item - items[c]) * kRotPix + 4 * threadIdx.x;
         if (q >= d.nz) continue;
         const int r = d.r;
-        float* z = static_cast<float*>(d.Z) + q;
+        float* z = gmem(static_cast<float*>(d.Z)) + q;
         v4f in[kMaxRank];
 #pragma unroll
         for (int k = 0; k < kMaxRank; ++k)

@@ -104,12 +104,12 @@ __global__ void k_sure_init(const CubeDesc* __restrict__ descs, const int* __res
         const int comp = item - items[c];
         const int64_t base = (int64_t)comp * kSureBins;
         for (int b = threadIdx.x; b < kSureBins; b += blockDim.x) {
-            d.hcnt[base + b] = 0;
-            d.hsum[base + b] = 0.0;
-            d.hmin[base + b] = ~0ull;
-            d.hmax[base + b] = 0;
+            gmem(d.hcnt)[base + b] = 0;
+            gmem(d.hsum)[base + b] = 0.0;
+            gmem(d.hmin)[base + b] = ~0ull;
+            gmem(d.hmax)[base + b] = 0;
         }
-        if (threadIdx.x < 4) d.sctr[4 * comp + threadIdx.x] = 0u;
+        if (threadIdx.x < 4) gmem(d.sctr)[4 * comp + threadIdx.x] = 0u;
         if (threadIdx.x == 0) {
             SureState st;
             st.klo = 0;
@@ -239,7 +239,7 @@ __device__ void sure_hist_range(const CubeDesc& d, int comp, int64_t e0, int64_t
     }
     if (tid == 0) sh.zeros = 0;
     __syncthreads();
-    const T* cf = static_cast<const T*>(d.coef) + (int64_t)comp * d.ncs;
+    const T* cf = gmem(static_cast<const T*>(d.coef)) + (int64_t)comp * d.ncs;
     const uint64_t klo = st.klo, khi = st.khi;
     const int shf = (int)st.width;
     unsigned long long nz = 0;
@@ -271,10 +271,10 @@ __device__ void sure_hist_range(const CubeDesc& d, int comp, int64_t e0, int64_t
     const int64_t base = (int64_t)comp * kSureBins;
     for (int b = tid; b < kSureBins; b += kSureThreads) {
         if (lc[b]) {
-            atomicAdd(&d.hcnt[base + b], lc[b]);
-            atomicAdd(&d.hsum[base + b], ls[b]);
-            atomicMin(&d.hmin[base + b], (unsigned long long)lmin[b]);
-            atomicMax(&d.hmax[base + b], (unsigned long long)lmax[b]);
+            atomicAdd(&gmem(d.hcnt)[base + b], lc[b]);
+            atomicAdd(&gmem(d.hsum)[base + b], ls[b]);
+            atomicMin(&gmem(d.hmin)[base + b], (unsigned long long)lmin[b]);
+            atomicMax(&gmem(d.hmax)[base + b], (unsigned long long)lmax[b]);
         }
     }
     if (tid == 0 && sh.zeros) atomicAdd(sure_zeros(d, comp), sh.zeros);
@@ -289,7 +289,7 @@ __device__ void sure_gather_chunk(const CubeDesc& d, int comp, int64_t e0, int64
     typedef KeyTraits<T> KT;
     typedef typename KT::K K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const T* cf = static_cast<const T*>(d.coef) + (int64_t)comp * d.ncs;
+    const T* cf = gmem(static_cast<const T*>(d.coef)) + (int64_t)comp * d.ncs;
     const uint64_t klo = st.klo, khi = st.khi;
     const int shf = (int)st.width;
     K kv[kGatherPer];
@@ -318,9 +318,9 @@ __device__ void sure_gather_chunk(const CubeDesc& d, int comp, int64_t e0, int64
         if (w < wave) off += sh.wc[w];
         tot += sh.wc[w];
     }
-    if (tid == 0) sh.base = tot ? atomicAdd(&d.sctr[4 * comp + 1], tot) : 0u;
+    if (tid == 0) sh.base = tot ? atomicAdd(&gmem(d.sctr)[4 * comp + 1], tot) : 0u;
     __syncthreads();
-    uint64_t* out = d.cand + (int64_t)comp * kSureCap;
+    uint64_t* out = gmem(d.cand) + (int64_t)comp * kSureCap;
     uint32_t pos = sh.base + off;
 #pragma unroll
     for (int j = 0; j < kGatherPer; ++j) {
@@ -344,11 +344,11 @@ __device__ void sure_finish(const CubeDesc& d, int comp, double N, unsigned char
     const SureState st = sh.st;
     // the gather re-reads the values the last histogram counted, so the
     // surviving bins hold exactly nsurv (<= kSureCap) values
-    const uint32_t got = d.sctr[4 * comp + 1];
+    const uint32_t got = gmem(d.sctr)[4 * comp + 1];
     const int nc = (int)(got < (uint32_t)kSureCap ? got : (uint32_t)kSureCap);
     const uint64_t klo = st.klo;
     const int shf = (int)st.width;
-    const uint64_t* src = d.cand + (int64_t)comp * kSureCap;
+    const uint64_t* src = gmem(d.cand) + (int64_t)comp * kSureCap;
     for (int b = tid; b < kSureBins; b += kSureThreads) bcnt[b] = 0u;
     __syncthreads();
     for (int i = tid; i < nc; i += kSureThreads) atomicAdd(&bcnt[(int)((src[i] - klo) >> shf)], 1u);
@@ -464,10 +464,10 @@ __device__ void sure_select(const CubeDesc& d, int comp, double N, SureShared& s
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int b = tid * PER + j;
-        cnt[j] = d.hcnt[base + b];
-        sum[j] = d.hsum[base + b];
-        kmin[j] = d.hmin[base + b];
-        kmax[j] = d.hmax[base + b];
+        cnt[j] = gmem(d.hcnt)[base + b];
+        sum[j] = gmem(d.hsum)[base + b];
+        kmin[j] = gmem(d.hmin)[base + b];
+        kmax[j] = gmem(d.hmax)[base + b];
         tc += cnt[j];
         ts += sum[j];
     }
@@ -631,15 +631,15 @@ __device__ void sure_select(const CubeDesc& d, int comp, double N, SureShared& s
             if (ns.inexact) set_status(d.status, HYRES_DEV_SURE_INEXACT);
         }
         put_state(&d.sst[comp], ns);
-        d.sctr[4 * comp] = 0u;        // block counter of the next pass
-        d.sctr[4 * comp + 1] = 0u;    // gathered values
+        gmem(d.sctr)[4 * comp] = 0u;        // block counter of the next pass
+        gmem(d.sctr)[4 * comp + 1] = 0u;    // gathered values
     }
     // clear the bins for the next pass
     for (int b = tid; b < kSureBins; b += kSureThreads) {
-        d.hcnt[base + b] = 0;
-        d.hsum[base + b] = 0.0;
-        d.hmin[base + b] = ~0ull;
-        d.hmax[base + b] = 0;
+        gmem(d.hcnt)[base + b] = 0;
+        gmem(d.hsum)[base + b] = 0.0;
+        gmem(d.hmin)[base + b] = ~0ull;
+        gmem(d.hmax)[base + b] = 0;
     }
 }
 
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(kSureThreads) void k_sure_round(const CubeDesc* __r
         __syncthreads();
         if (tid == 0) {
             __threadfence();
-            const bool last = atomicAdd(&d.sctr[4 * comp], 1u) == (unsigned)(nch - 1);
+            const bool last = atomicAdd(&gmem(d.sctr)[4 * comp], 1u) == (unsigned)(nch - 1);
             if (last) __threadfence();
             sh.last = last;
         }

@@ -1648,6 +1648,12 @@ HYRES_API hyres_status hyres_hyminor(hyres_handle* h, const void* Y, int H, int 
 // ------------------------------------------------------------- WSRRR
 namespace {
 // The HyRes workspace of the cube, then Y^T Zh (r x p) and its per-slot partial sums.
+// Slots (blocks, partial sums) of the pixel cross products Y^T Zh and the
+// adjoint's: about 256 pixels each, at most two blocks per compute unit of a
+// 256-unit device (each block runs its tiles in turn; fewer partials make the
+// sum over slots cheaper).
+int cross_slots(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, cdiv(n, 256))); }
+
 struct WsrrrPlan {
     Exec x;
     int slots = 1;
@@ -1665,7 +1671,7 @@ hyres_status plan_wsrrr(WsrrrPlan& w, hyres_handle* h, int H, int W, int p, cons
     one_cube(w.x, h, H, W, p, opt->rank, opt->levels, dtype, opt->scope, opt->precision);
     if ((st = plan_cubes(w.x, kAllParts))) return st;
     const CubePlan& c = w.x.plan[0];
-    w.slots = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(c.n, 256)));
+    w.slots = cross_slots(c.n);
     w.o_M = w.x.lay.add((size_t)c.r * p * 8);
     w.o_part = w.x.lay.add((size_t)w.slots * c.r * p * 8);
     return HYRES_OK;
@@ -2097,7 +2103,7 @@ hyres_status plan_backward(BwdPlan& b, hyres_handle* h, int H, int W, int p, con
     b.o_A = L.add((size_t)r * c.nz * es);
     b.o_dB = L.add((size_t)r * c.ncs * es);
     b.o_tmp = L.add((size_t)std::max<int64_t>(1, r * c.tps) * es);
-    b.slots = (int)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(c.n, 256)));
+    b.slots = cross_slots(c.n);
     b.o_part = L.add((size_t)b.slots * r * p * 8);
     b.o_dQ = L.add((size_t)r * p * 8);
     b.o_dPt = L.add((size_t)r * p * 8);

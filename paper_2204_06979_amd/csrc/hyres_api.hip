@@ -36,13 +36,14 @@ hipError_t launch_backproject_f32(int T, const CubeDesc*, const int*, int, int, 
 hipError_t launch_blend_f32(int T, const CubeDesc*, const BlendGrid&, int, hipStream_t);
 hipError_t launch_project_f64(const CubeDesc*, int, int64_t, hipStream_t);
 hipError_t launch_backproject_f64(const CubeDesc*, int, int64_t, hipStream_t);
+hipError_t launch_dwt_level1_rot(int tx, int ty, const CubeDesc*, const int*, int, int, int, hipStream_t);
 hipError_t launch_dwt_level(int dtype, int tx, int ty, bool inverse, const CubeDesc*, const int*, int, int,
                             int, hipStream_t);
 hipError_t launch_sure_init(int dtype, const CubeDesc*, const int*, int, int, hipStream_t);
 hipError_t launch_sure_round(int dtype, const CubeDesc*, const int*, int, int, hipStream_t);
 int sure_rounds(int dtype);
 int64_t sure_chunk_for(int64_t total_coef, int num_cu);
-hipError_t launch_ritz(const CubeDesc*, const int*, const int*, int, const int*, int, int, int, hipStream_t);
+hipError_t launch_ritz(const CubeDesc*, const int*, const int*, int, int, int, hipStream_t);
 hipError_t launch_adjoint_pre(const AdjDesc&, int dtype, hipStream_t);
 hipError_t launch_adjoint_thresh(const AdjDesc&, int dtype, hipStream_t);
 hipError_t launch_adjoint_post(const AdjDesc&, int dtype, hipStream_t);
@@ -484,19 +485,28 @@ int tile_of(const hyres_handle* h, int dtype, bool inverse, int w) {
 
 bool in_group(const Exec& x, int i, int grp) { return grp < 0 || x.ngroups <= 1 || x.group_of[i] == grp; }
 
-void add_dwt(Exec& x, bool inverse, int grp) {
+void add_dwt(Exec& x, bool inverse, int grp, bool rotate_l1 = false) {
     int Lmax = 0;
     for (int i = 0; i < x.count; ++i)
         if (in_group(x, i, grp)) Lmax = std::max(Lmax, x.plan[i].L);
     for (int k = 0; k < Lmax; ++k) {
         const int l = inverse ? Lmax - k : k + 1;
+        // the first analysis level of a mixed FP32 solve applies the
+        // Rayleigh-Ritz rotation as it loads Z: one item per tile of all components
+        // (one launch per rank class, at most 8 or more: the kernel keeps the
+        // rotation of the lower class in registers)
+        const bool rot = rotate_l1 && !inverse && l == 1;
+        for (int cls = 0; cls < (rot ? 2 : 1); ++cls)
         for (int cand = 0; cand < kTileCands; ++cand) {
             std::vector<int64_t> cnt(x.count, 0);
             bool any = false;
+            int rmax = 0;
             for (int i = 0; i < x.count; ++i) {
                 const CubePlan& c = x.plan[i];
                 if (!in_group(x, i, grp) || c.L < l || tile_of(x.h, x.dtype, inverse, c.lw[l]) != cand) continue;
-                cnt[i] = c.r * cdiv(c.lw[l], kTileTX[cand]) * cdiv(c.lh[l], kTileTY[cand]);
+                if (rot && (c.r > 8) != (cls == 1)) continue;
+                cnt[i] = (rot ? 1 : c.r) * cdiv(c.lw[l], kTileTX[cand]) * cdiv(c.lh[l], kTileTY[cand]);
+                rmax = std::max(rmax, c.r);
                 any = true;
             }
             if (!any) continue;
@@ -509,6 +519,7 @@ void add_dwt(Exec& x, bool inverse, int grp) {
             L.n = x.count;
             L.level = l;
             L.grid = x.grid(tot, 8);
+            L.grid2 = rot ? rmax : 0;
             L.grp = grp;
             x.prog.push_back(L);
         }
@@ -617,29 +628,28 @@ void build_group(Exec& x, int stages, int grp) {
         else per_T(K_PROJ_F32, HYRES_STAGE_PROJECT, 8, [](const CubePlan& c) { return cdiv(c.n, kPixTile); });
         if (x.precision == HYRES_PREC_MIXED && !f64) {
             // the FP32 refinement of the subspace (Rayleigh-Ritz on T^T T)
-            std::vector<int64_t> slots(N, 0), pix(N, 0);
+            // (the rotation of Z by the Ritz vectors is applied by the first
+            // analysis level as it loads Z)
+            std::vector<int64_t> slots(N, 0);
             std::vector<int> ids;
             for (int i = 0; i < N; ++i) {
                 if (!in_group(x, i, grp)) continue;
                 slots[i] = x.plan[i].rgroups;
-                pix[i] = cdiv(x.plan[i].nz, kRotPix);
                 ids.push_back(i);
             }
-            int64_t ns, np;
+            int64_t ns;
             Launch R{};
             R.kind = K_RITZ;
             R.stage = HYRES_STAGE_PROJECT;
             R.a = x.counts(slots, &ns);
-            R.b = x.counts(pix, &np);
             R.key = x.list(ids);
             R.n = N;
             R.nlist = (int)ids.size();
             R.grid = x.grid(ns, 4);
-            R.grid2 = x.grid(np, 8);
             x.prog.push_back(R);
         }
     }
-    if (stages & S_DWT) add_dwt(x, false, grp);
+    if (stages & S_DWT) add_dwt(x, false, grp, x.precision == HYRES_PREC_MIXED && !f64 && (stages & S_PROJ));
     if (stages & S_SURE) {
         std::vector<int64_t> comp(N, 0), hist(N, 0);
         // one work-item size for the whole program: about one item per compute unit
@@ -744,6 +754,10 @@ hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
         case K_PROJ_F32: return launch_project_f32(L.key, L.b, D, x.table(L.a), L.n, L.grid, s);
         case K_PROJ_F64: return launch_project_f64(D, L.a, L.n64, s);
         case K_DWT:
+            if (L.grid2)
+                return launch_dwt_level1_rot(kTileTX[L.key], kTileTY[L.key], D, x.table(L.a), L.n, L.grid, L.grid2, s);
+            return launch_dwt_level(x.dtype, kTileTX[L.key], kTileTY[L.key], false, D, x.table(L.a), L.n, L.level,
+                                    L.grid, s);
         case K_IDWT:
             return launch_dwt_level(x.dtype, kTileTX[L.key], kTileTY[L.key], L.kind == K_IDWT, D, x.table(L.a),
                                     L.n, L.level, L.grid, s);
@@ -757,7 +771,7 @@ hipError_t launch_one(const Exec& x, const Launch& L, hipStream_t s) {
         case K_BP_F64: return launch_backproject_f64(D, L.a, L.n64, s);
         case K_BLEND_F32: return launch_blend_f32(L.key, D, x.bg, L.grid, s);
         case K_RITZ:
-            return launch_ritz(D, x.table(L.a), x.table(L.key), L.nlist, x.table(L.b), L.n, L.grid, L.grid2, s);
+            return launch_ritz(D, x.table(L.a), x.table(L.key), L.nlist, L.n, L.grid, s);
     }
     return hipErrorInvalidValue;
 }

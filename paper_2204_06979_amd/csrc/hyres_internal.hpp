@@ -19,7 +19,6 @@ constexpr int kGramThreads = 512;
 constexpr int kSmallThreads = 1024;
 constexpr int kPixTile = 64;          // pixels per projection / back-projection block
 constexpr int kRitzGroup = 128;       // projection tiles per first-level Rayleigh-Ritz sum
-constexpr int kRotPix = 1024;         // pixels per work item of the Rayleigh-Ritz rotation
 
 // Daubechies 4-tap orthonormal scaling filter h = ((1+s3),(3+s3),(3-s3),(1-s3)) / (4 sqrt 2),
 // s3 = sqrt 3, and its quadrature mirror g[m] = (-1)^m h[3-m].

@@ -122,6 +122,115 @@ __global__ __launch_bounds__(TX* TY) void k_dwt_level(const CubeDesc* __restrict
     }
 }
 
+// Level 1 of a mixed-precision solve with the Rayleigh-Ritz rotation applied
+// as Z is loaded: a block takes one TY x TX output tile of every component of
+// a cube.  Each window pixel's r component values are read once, rotated in
+// registers (the pixel's row of Z R, summed in the order of the component
+// index) and staged in LDS, one window per component; then every component's
+// four subbands come from its rotated window.  Z itself stays unrotated (the
+// inverse transform overwrites it), so the rotation costs no pass of its own.
+template <int TX, int TY, int RM>
+__global__ __launch_bounds__(TX* TY) void k_dwt_level1_rot(const CubeDesc* __restrict__ descs,
+                                                          const int* __restrict__ items, int ncubes) {
+    // RM: largest rank of the launch's cubes, 8 or kMaxRank.  At 8 the
+    // rotation stays in registers; at 16 it is read from LDS per use.
+    constexpr int WW = 2 * TX + 2, WH = 2 * TY + 2, WS = WH * (WW + 1);
+    extern __shared__ float dwin[];                 // one WH x (WW + 1) window per component
+    __shared__ __attribute__((aligned(16))) float R[kMaxRank][kMaxRank];   // rows 16-byte aligned
+    using F = Filt<float>;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int total = items[ncubes];
+    int cur = -1;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int c = find_cube(items, ncubes, item);
+        const CubeDesc& d = descs[c];
+        const int h = d.lh[0], w = d.lw[0];
+        const int h2 = d.lh[1], w2 = d.lw[1];
+        const int ntx = (w2 + TX - 1) / TX;
+        const int local = item - items[c];
+        const int oy0 = (local / ntx) * TY, ox0 = (local % ntx) * TX;
+        const int r = d.r;
+        __syncthreads();                            // the previous item's windows and R are read
+        if (c != cur) {
+            for (int e = threadIdx.x; e < 256; e += TX * TY) R[e >> 4][e & 15] = (float)d.rrot[e];
+            __syncthreads();
+            cur = c;
+        }
+        const float* z = gmem(static_cast<const float*>(d.Z));
+        const int he = h + (h & 1), we = w + (w & 1);
+        for (int e = threadIdx.x; e < WH * WW; e += TX * TY) {
+            const int wy = e / WW, wx = e - wy * WW;
+            int ey = 2 * oy0 + wy;
+            ey = ey >= he ? ey - he : ey;
+            ey = ey >= he ? ey % he : ey;
+            ey = ey == h ? h - 1 : ey;
+            int ex = 2 * ox0 + wx;
+            ex = ex >= we ? ex - we : ex;
+            ex = ex >= we ? ex % we : ex;
+            ex = ex == w ? w - 1 : ex;
+            const int64_t off = (int64_t)ey * w + ex;
+            float in[RM];
+#pragma unroll
+            for (int j = 0; j < RM; ++j) in[j] = j < r ? z[(int64_t)j * d.nz + off] : 0.f;
+            if constexpr (RM <= 8) {
+#pragma unroll
+                for (int k = 0; k < RM; ++k) {
+                    if (k < r) {
+                        float v = 0.f;
+#pragma unroll
+                        for (int j = 0; j < RM; ++j)
+                            if (j < r) v = fmaf(in[j], R[j][k], v);
+                        dwin[k * WS + wy * (WW + 1) + wx] = v;
+                    }
+                }
+            } else {
+                // four output components at a time: one 16-byte read of R per input
+#pragma unroll 1
+                for (int k0 = 0; k0 < r; k0 += 4) {
+                    v4f v = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int j = 0; j < RM; ++j)
+                        if (j < r) {
+                            const v4f rk = *reinterpret_cast<const v4f*>(&R[j][k0]);
+#pragma unroll
+                            for (int c4 = 0; c4 < 4; ++c4) v[c4] = fmaf(in[j], rk[c4], v[c4]);
+                        }
+#pragma unroll
+                    for (int c4 = 0; c4 < 4; ++c4)
+                        if (k0 + c4 < r) dwin[(k0 + c4) * WS + wy * (WW + 1) + wx] = v[c4];
+                }
+            }
+        }
+        __syncthreads();
+        const int oy = oy0 + ty, ox = ox0 + tx;
+        if (oy < h2 && ox < w2) {
+            const int64_t blk = (int64_t)h2 * w2;
+            const int64_t o = (int64_t)oy * w2 + ox;
+            for (int k = 0; k < r; ++k) {
+                const float* wk = dwin + k * WS;
+                float lo[4], hi[4];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const float* x = wk + (2 * ty + rr) * (WW + 1) + 2 * tx;
+                    lo[rr] = F::h0 * x[0] + F::h1 * x[1] + F::h2 * x[2] + F::h3 * x[3];
+                    hi[rr] = F::g0 * x[0] + F::g1 * x[1] + F::g2 * x[2] + F::g3 * x[3];
+                }
+                const float ll = F::h0 * lo[0] + F::h1 * lo[1] + F::h2 * lo[2] + F::h3 * lo[3];
+                const float hl = F::g0 * lo[0] + F::g1 * lo[1] + F::g2 * lo[2] + F::g3 * lo[3];
+                const float lh = F::h0 * hi[0] + F::h1 * hi[1] + F::h2 * hi[2] + F::h3 * hi[3];
+                const float hh = F::g0 * hi[0] + F::g1 * hi[1] + F::g2 * hi[2] + F::g3 * hi[3];
+                float* cf = gmem(static_cast<float*>(d.coef)) + (int64_t)k * d.ncs + d.loff[1];
+                cf[o] = lh;
+                cf[blk + o] = hl;
+                cf[2 * blk + o] = hh;
+                float* llo = d.L == 1 ? gmem(static_cast<float*>(d.coef)) + (int64_t)k * d.ncs + d.ll_off
+                                      : ll_buf<float>(d, k, 1);
+                llo[o] = ll;
+            }
+        }
+    }
+}
+
 template <typename T, int TX, int TY>
 __global__ __launch_bounds__(TX* TY) void k_idwt_level(const CubeDesc* __restrict__ descs,
                                                       const int* __restrict__ items, int ncubes, int level) {
@@ -245,6 +354,37 @@ static hipError_t dwt_dispatch(int tx, int ty, bool inverse, const CubeDesc* des
     }
     HYRES_DWT_SHAPES(HYRES_D)
 #undef HYRES_D
+    return hipErrorInvalidValue;
+}
+
+// Level 1 with the rotation (FP32): rmax is the largest rank of the launch's
+// cubes (one LDS window per component).
+template <int TX, int TY, int RM>
+static hipError_t launch_rot_k(const CubeDesc* descs, const int* items, int ncubes, int grid, size_t bytes,
+                               hipStream_t s) {
+    if (bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dwt_level1_rot<TX, TY, RM>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_dwt_level1_rot<TX, TY, RM>), dim3(grid), dim3(TX * TY), bytes, s, descs, items, ncubes);
+    return hipGetLastError();
+}
+
+template <int TX, int TY>
+static hipError_t launch_rot_t(const CubeDesc* descs, const int* items, int ncubes, int grid, int rmax,
+                               hipStream_t s) {
+    const size_t bytes = (size_t)rmax * (2 * TY + 2) * (2 * TX + 3) * sizeof(float);
+    if (rmax <= 8) return launch_rot_k<TX, TY, 8>(descs, items, ncubes, grid, bytes, s);
+    return launch_rot_k<TX, TY, kMaxRank>(descs, items, ncubes, grid, bytes, s);
+}
+
+hipError_t launch_dwt_level1_rot(int tx, int ty, const CubeDesc* descs, const int* items, int ncubes, int grid,
+                                 int rmax, hipStream_t s) {
+#define HYRES_R(TX, TY) \
+    if (tx == TX && ty == TY) return launch_rot_t<TX, TY>(descs, items, ncubes, grid, rmax, s);
+    HYRES_DWT_SHAPES(HYRES_R)
+#undef HYRES_R
     return hipErrorInvalidValue;
 }
 

@@ -14,7 +14,7 @@
 //   k_ritz         one workgroup per cube: group sums in FP64, cyclic Jacobi
 //                  (parallel pair ordering), sort, sign rule, new V, evals,
 //                  projection matrices and the r x r rotation
-//   k_ritz_rotate  Z <- Z R in place, one pixel per thread
+//   (the first analysis level applies Z <- Z R as it loads Z)
 #include "hyres_internal.hpp"
 
 namespace hyres {
@@ -360,49 +360,10 @@ hipError_t launch_polar(const CubeDesc* descs, const double* M, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Z <- Z R (r x r rotation), in place: four pixels per thread (16-byte
-// accesses; the planes are padded to whole 64-pixel tiles, so an item never
-// reads or writes past a plane).
-__global__ __launch_bounds__(256) void k_ritz_rotate(const CubeDesc* __restrict__ descs,
-                                                     const int* __restrict__ items, int ncubes) {
-    __shared__ float R[kMaxRank][kMaxRank + 1];
-    const int total = items[ncubes];
-    int cur = -1;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int c = find_cube(items, ncubes, item);
-        const CubeDesc& d = descs[c];
-        if (c != cur) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < 256; e += 256) R[e >> 4][e & 15] = (float)d.rrot[e];
-            __syncthreads();
-            cur = c;
-        }
-        const int64_t q = (int64_t)(item - items[c]) * kRotPix + 4 * threadIdx.x;
-        if (q >= d.nz) continue;
-        const int r = d.r;
-        float* z = gmem(static_cast<float*>(d.Z)) + q;
-        v4f in[kMaxRank];
-#pragma unroll
-        for (int k = 0; k < kMaxRank; ++k)
-            in[k] = k < r ? *reinterpret_cast<const v4f*>(z + (int64_t)k * d.nz) : v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < kMaxRank; ++k) {
-            if (k < r) {
-                v4f s = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int jj = 0; jj < kMaxRank; ++jj)
-                    if (jj < r) s += in[jj] * R[jj][k];
-                *reinterpret_cast<v4f*>(z + (int64_t)k * d.nz) = s;
-            }
-        }
-    }
-}
-
-hipError_t launch_ritz(const CubeDesc* descs, const int* group_items, const int* cube_list, int ncls,
-                       const int* rot_items, int ncubes, int grid_sum, int grid_rot, hipStream_t s) {
+hipError_t launch_ritz(const CubeDesc* descs, const int* group_items, const int* cube_list, int ncls, int ncubes,
+                       int grid_sum, hipStream_t s) {
     hipLaunchKernelGGL(k_ritz_reduce, dim3(grid_sum), dim3(256), 0, s, descs, group_items, ncubes);
     hipLaunchKernelGGL(k_ritz, dim3(ncls), dim3(256), 0, s, descs, cube_list, ncls);
-    hipLaunchKernelGGL(k_ritz_rotate, dim3(grid_rot), dim3(256), 0, s, descs, rot_items, ncubes);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ STAGE_OF = [
     ("k_backproject", "backproject"), ("k_blend_axis", "backproject"), ("k_blend_f32", "backproject"),
     ("k_upload", "setup"), ("k_l1l1", "l1l1"), ("k_vdwt", "dwt"), ("k_vidwt", "idwt"),
     ("k_forpdn_filter", "smoother"), ("k_forpdn_lambda", "threshold"),
+    ("k_adj_", "adjoint"), ("k_chunk_reduce", "adjoint"), ("k_polar", "polar"),
 ]
 
 

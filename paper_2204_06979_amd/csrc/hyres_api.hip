@@ -822,8 +822,18 @@ void group_tiles(Exec& x) {
 hyres_status upload_exec(const Exec& x, hipStream_t s) {
     // the last table of the region is the tuner's
     if (x.tab.size() > table_ints(x.count) - (size_t)(x.count + 1)) return HYRES_E_UNSUPPORTED;
-    HIPCHK(upload(x.ws, x.o_desc, x.desc.data(), sizeof(CubeDesc) * x.count, s));
-    if (!x.tab.empty()) HIPCHK(upload(x.ws, x.o_tab, x.tab.data(), sizeof(int) * x.tab.size(), s));
+    const size_t db = sizeof(CubeDesc) * x.count, tb = sizeof(int) * x.tab.size();
+    if (!x.tab.empty() && x.o_tab >= x.o_desc + db && x.o_tab - (x.o_desc + db) < kAlign) {
+        // descriptors and tables adjacent (up to the alignment gap): one
+        // upload covers both (a single launch for one cube)
+        std::vector<unsigned char> buf(x.o_tab - x.o_desc + tb, 0);
+        std::memcpy(buf.data(), x.desc.data(), db);
+        std::memcpy(buf.data() + (x.o_tab - x.o_desc), x.tab.data(), tb);
+        HIPCHK(upload(x.ws, x.o_desc, buf.data(), buf.size(), s));
+        return HYRES_OK;
+    }
+    HIPCHK(upload(x.ws, x.o_desc, x.desc.data(), db, s));
+    if (!x.tab.empty()) HIPCHK(upload(x.ws, x.o_tab, x.tab.data(), tb, s));
     return HYRES_OK;
 }
 
@@ -1733,12 +1743,17 @@ HYRES_API hyres_status hyres_wsrrr(hyres_handle* h, const void* Y, int H, int W,
     a.slots = w.slots;
     a.part = at<double>(workspace, w.o_part);
     double* M = at<double>(workspace, w.o_M);
+    if (iters > 0) {
+        // every alternation runs the same program: its tables go up once
+        // (stream-ordered after the program above, which has read its own)
+        build_program(x, S_PROJ | S_DWT | S_IDWT);
+        if ((st = upload_exec(x, s))) return st;
+    }
     for (int it = 0; it < iters; ++it) {
         // V <- polar factor of Yw^T Zh, then F <- soft(W^T Yw V, lambda) with the thresholds held
         HIPCHK(launch_planes_cube(dtype, a, d.Z, Y, pitch, row_pitch, M, s));
         HIPCHK(launch_polar(x.descs(), M, s));
-        build_program(x, S_PROJ | S_DWT | S_IDWT);
-        if ((st = upload_exec(x, s)) || (st = run_program(x, s, false))) return st;
+        if ((st = run_program(x, s, false))) return st;
     }
     build_program(x, S_BP);
     if ((st = upload_exec(x, s))) return st;

@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
     __shared__ double sgn[16];
     __shared__ double s_off, s_diag;
     __shared__ double s_part[256];
+    __shared__ double s_sig[kMaxBands];           // the noise, read once (the output loop stores to global memory)
     const int cube = cubes[blockIdx.x];
     const CubeDesc& d = descs[cube];
     const int r = d.r, p = d.p, tid = threadIdx.x;
@@ -193,6 +194,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
         const int row = e / r, k = e - row * r;
         v0[row][k] = d.V[(int64_t)k * p + row];
     }
+    for (int b = tid; b < p; b += 256) s_sig[b] = d.sigma[b];
     __syncthreads();
     const int cb = jacobi16(Mb, Ub, cs, sn, m, &s_off, &s_diag);
     const double (*M)[17] = Mb[cb];
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
         double v = 0.0;
         for (int jj = 0; jj < r; ++jj) v = fma(v0[row][jj], U[jj][col], v);
         v *= sgn[k];
-        const double s = d.sigma[row];
+        const double s = s_sig[row];
         d.V[(int64_t)k * p + row] = v;
         d.P64[(int64_t)row * r + k] = v / s;
         d.Q64[(int64_t)k * p + row] = v * s;
@@ -268,14 +270,17 @@ __global__ __launch_bounds__(256) void k_polar(const CubeDesc* __restrict__ desc
     __shared__ double cs[16], sn[16];
     __shared__ double mw[kMaxBands][kMaxRank], vold[kMaxBands][kMaxRank], vnew[kMaxBands][kMaxRank];
     __shared__ double S[16][17];
+    __shared__ double s_sig[kMaxBands];           // the noise, read once (the output loop stores to global memory)
     __shared__ double s_off, s_diag, s_nmax;
     __shared__ int live[16];
     const CubeDesc& d = descs[0];
     const int r = d.r, p = d.p, tid = threadIdx.x, i = tid >> 4, j = tid & 15, lane = tid & 63;
     const int m = (r + 1) & ~1;
+    for (int b = tid; b < p; b += 256) s_sig[b] = d.sigma[b];
+    __syncthreads();
     for (int e = tid; e < r * p; e += 256) {
         const int k = e / p, b = e - k * p;
-        mw[b][k] = M[e] / d.sigma[b];
+        mw[b][k] = M[e] / s_sig[b];
         vold[b][k] = d.V[e];
     }
     __syncthreads();
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(256) void k_polar(const CubeDesc* __restrict__ desc
         const int row = e >> 4, k = e & 15;
         const bool ok = row < p && k < r;
         const double v = ok ? vnew[row][k] : 0.0;
-        const double sg = row < p ? d.sigma[row] : 1.0;
+        const double sg = row < p ? s_sig[row] : 1.0;
         d.P32[e] = (float)(v / sg);
         d.Q32[(int64_t)k * P16 + row] = (float)(v * sg);
         if (ok) {

@@ -117,9 +117,14 @@ __device__ __forceinline__ int jacobi16(double (*Mb)[16][17], double (*Ub)[16][1
                 double c = 1.0, s = 0.0;
                 const double apq = M[lo][hi];
                 if (apq != 0.0) {
-                    const double tau = (M[hi][hi] - M[lo][lo]) / (2.0 * apq);
-                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    // t = sgn(tau) / (|tau| + sqrt(1 + tau^2)), tau = dd / hh, written
+                    // without the quotient tau: one square root, one division and
+                    // one reciprocal square root on the chain instead of two square
+                    // roots and three divisions
+                    const double dd = M[hi][hi] - M[lo][lo], hh = 2.0 * apq;
+                    const double sg = (dd == 0.0 || (dd > 0.0) == (hh > 0.0)) ? 1.0 : -1.0;
+                    const double tt = sg * fabs(hh) / (fabs(dd) + sqrt(fma(dd, dd, hh * hh)));
+                    c = rsqrt(fma(tt, tt, 1.0));
                     s = tt * c;
                 }
                 cs[x] = c;

@@ -237,6 +237,14 @@ def test_denoise_config2_mixed_full_size():
     assert e_v <= 1e-3
 
 
+def test_denoise_mixed_largest_rank():
+    """Rank 16, the largest (16 sources, so the subspace is well separated):
+    the rotated first analysis level then holds 16 component windows per block,
+    more than 64 KB of LDS."""
+    cube = synth.mixing_cube(7016, 70, 150, 48, 16, 15.0, 2, dtype=np.float32, keep_clean=False)
+    _check_denoise(cube.Y, 16, 2, 1e-3, name="mixed-r16", precision="mixed")
+
+
 @pytest.mark.parametrize("H,W,p,r,L", [(97, 133, 40, 5, 3), (128, 128, 100, 12, 4), (64, 96, 191, 6, 3)])
 def test_denoise_mixed_ragged(H, W, p, r, L):
     cube = synth.mixing_cube(H * W + p, H, W, p, min(r, 6), 12.0, L, dtype=np.float32, keep_clean=False)

@@ -77,6 +77,26 @@ __device__ __forceinline__ int ritz_partner(int x, int t, int m) {
     return y == x ? 0 : y;
 }
 
+// The rotation of pair (x, y) that zeroes M[x][y]: c, and s signed as
+// J[y][x], stored by index x.  t = sgn(tau) / (|tau| + sqrt(1 + tau^2)),
+// tau = dd / hh, is written without the quotient tau: one square root, one
+// division and one reciprocal square root on the chain instead of two square
+// roots and three divisions.
+__device__ __forceinline__ void jacobi_params(const double (*M)[17], int x, int y, double* cs, double* sn) {
+    const int lo = x < y ? x : y, hi = x < y ? y : x;
+    double c = 1.0, s = 0.0;
+    const double apq = M[lo][hi];
+    if (apq != 0.0) {
+        const double dd = M[hi][hi] - M[lo][lo], hh = 2.0 * apq;
+        const double sg = (dd == 0.0 || (dd > 0.0) == (hh > 0.0)) ? 1.0 : -1.0;
+        const double tt = sg * fabs(hh) / (fabs(dd) + sqrt(fma(dd, dd, hh * hh)));
+        c = rsqrt(fma(tt, tt, 1.0));
+        s = tt * c;
+    }
+    cs[x] = c;
+    sn[x] = x == lo ? -s : s;
+}
+
 // Cyclic Jacobi on the symmetric m x m matrix Mb[0] (m even, at most 16;
 // Ub[0] the identity): the pairs of each round come from the circle schedule,
 // every rotation of a round is applied at once, and the two buffers
@@ -113,22 +133,7 @@ __device__ __forceinline__ int jacobi16(double (*Mb)[16][17], double (*Ub)[16][1
             // rotation of every pair (x, y), x < y: [c s; -s c] diagonalises the 2 x 2 block
             if (tid < m) {
                 const int x = tid, y = ritz_partner(x, t, m);
-                const int lo = x < y ? x : y, hi = x < y ? y : x;
-                double c = 1.0, s = 0.0;
-                const double apq = M[lo][hi];
-                if (apq != 0.0) {
-                    // t = sgn(tau) / (|tau| + sqrt(1 + tau^2)), tau = dd / hh, written
-                    // without the quotient tau: one square root, one division and
-                    // one reciprocal square root on the chain instead of two square
-                    // roots and three divisions
-                    const double dd = M[hi][hi] - M[lo][lo], hh = 2.0 * apq;
-                    const double sg = (dd == 0.0 || (dd > 0.0) == (hh > 0.0)) ? 1.0 : -1.0;
-                    const double tt = sg * fabs(hh) / (fabs(dd) + sqrt(fma(dd, dd, hh * hh)));
-                    c = rsqrt(fma(tt, tt, 1.0));
-                    s = tt * c;
-                }
-                cs[x] = c;
-                sn[x] = x == lo ? -s : s;   // J[partner][x]
+                jacobi_params(M, x, y, cs, sn);
             }
             __syncthreads();
             // the rotated matrices go to the other buffer: no barrier between reads and writes
@@ -148,6 +153,59 @@ __device__ __forceinline__ int jacobi16(double (*Mb)[16][17], double (*Ub)[16][1
     return cb;
 }
 
+// LDS written by some lanes of a wave, then read by others of the same wave:
+// the wave's LDS operations are done in order; this keeps the compiler from
+// moving them across (no barrier of the block).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// jacobi16 for m <= 8, run by the first wave alone (lane (i, j) = (lane / 8,
+// lane % 8) owns entry (i, j) of the m x m block, the only part read
+// afterwards): the same rounds and arithmetic, its steps passed through LDS
+// within the wave instead of through block barriers.
+__device__ int jacobi8_wave(double (*Mb)[16][17], double (*Ub)[16][17], double* cs, double* sn, int m) {
+    const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
+    const bool in = i < m && j < m;
+    int cb = 0;
+    for (int sweep = 0; sweep < 12 && m > 1; ++sweep) {
+        const double v = Mb[cb][i][j];
+        const double off = wave_sum(in && i != j ? v * v : 0.0);
+        const double dg = wave_sum(in && i == j ? v * v : 0.0);
+        if (!(off > 1e-26 * dg)) break;
+        for (int t = 0; t < m - 1; ++t) {
+            const double (*M)[17] = Mb[cb];
+            const double (*U)[17] = Ub[cb];
+            if (lane < m) jacobi_params(M, lane, ritz_partner(lane, t, m), cs, sn);
+            wave_lds_sync();
+            if (in) {
+                const int pi = ritz_partner(i, t, m), pj = ritz_partner(j, t, m);
+                const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
+                Mb[cb ^ 1][i][j] = ci * (M[i][j] * cj + M[i][pj] * sj) + si * (M[pi][j] * cj + M[pi][pj] * sj);
+                Ub[cb ^ 1][i][j] = U[i][j] * cj + U[i][pj] * sj;
+            }
+            cb ^= 1;
+            wave_lds_sync();
+        }
+    }
+    return cb;
+}
+
+// jacobi16 or, for m <= 8, jacobi8_wave in the first wave; called by every
+// thread of the block, returns the buffer index to all.
+__device__ __forceinline__ int jacobi_any(double (*Mb)[16][17], double (*Ub)[16][17], double* cs, double* sn, int m,
+                                          double* s_off, double* s_diag, int* s_cb) {
+    if (m > 8) return jacobi16(Mb, Ub, cs, sn, m, s_off, s_diag);
+    if (threadIdx.x < 64) {
+        const int cb = jacobi8_wave(Mb, Ub, cs, sn, m);
+        if (threadIdx.x == 0) *s_cb = cb;
+    }
+    __syncthreads();
+    return *s_cb;
+}
+
 __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs, const int* __restrict__ cubes,
                                               int ncls) {
     __shared__ double Mb[2][16][17], Ub[2][16][17];   // Jacobi rounds alternate between the two
@@ -156,6 +214,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
     __shared__ int perm[16];
     __shared__ double sgn[16];
     __shared__ double s_off, s_diag;
+    __shared__ int s_cb;
     __shared__ double s_part[256];
     __shared__ double s_sig[kMaxBands];           // the noise, read once (the output loop stores to global memory)
     const int cube = cubes[blockIdx.x];
@@ -201,7 +260,7 @@ __global__ __launch_bounds__(256) void k_ritz(const CubeDesc* __restrict__ descs
     }
     for (int b = tid; b < p; b += 256) s_sig[b] = d.sigma[b];
     __syncthreads();
-    const int cb = jacobi16(Mb, Ub, cs, sn, m, &s_off, &s_diag);
+    const int cb = jacobi_any(Mb, Ub, cs, sn, m, &s_off, &s_diag, &s_cb);
     const double (*M)[17] = Mb[cb];
     const double (*U)[17] = Ub[cb];
     // descending order of the Ritz values (ties: lower index first)
@@ -277,6 +336,7 @@ __global__ __launch_bounds__(256) void k_polar(const CubeDesc* __restrict__ desc
     __shared__ double S[16][17];
     __shared__ double s_sig[kMaxBands];           // the noise, read once (the output loop stores to global memory)
     __shared__ double s_off, s_diag, s_nmax;
+    __shared__ int s_cb;
     __shared__ int live[16];
     const CubeDesc& d = descs[0];
     const int r = d.r, p = d.p, tid = threadIdx.x, i = tid >> 4, j = tid & 15, lane = tid & 63;
@@ -305,7 +365,7 @@ __global__ __launch_bounds__(256) void k_polar(const CubeDesc* __restrict__ desc
     __syncthreads();
     if (!(live[i] && live[j])) Mb[0][i][j] = 0.0;      // the zero components stay decoupled
     __syncthreads();
-    const int cb = jacobi16(Mb, Ub, cs, sn, m, &s_off, &s_diag);
+    const int cb = jacobi_any(Mb, Ub, cs, sn, m, &s_off, &s_diag, &s_cb);
     double sv = 0.0;
     if (i < r && j < r)
         for (int k = 0; k < r; ++k)

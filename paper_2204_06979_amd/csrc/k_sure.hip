@@ -53,7 +53,7 @@ template <> struct KeyTraits<double> {
 constexpr int kSureThreads = 1024;                    // threads of a pass block
 constexpr int kSureWaves = kSureThreads / 64;
 constexpr int kSureChunk = 16 * kSureThreads;         // smallest work item (coefficients)
-constexpr int kGatherPer = 32;                        // gathered coefficients per thread and step
+constexpr int kGatherPer = 16;                        // gathered coefficients per thread and step
 constexpr int kBinsPer = kSureBins / kSureThreads;    // bins per thread in the select
 constexpr int kSureGroup = 4;   // chunks per block after the first pass (fewer partial merges)
 constexpr int64_t kSureGroupSpan = 65536;   // ... while a block's range stays within this many values
